@@ -1,0 +1,548 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these retypes the oracle's own formula: each compares the oracle with
+a closed form, a library routine (scipy), a brute-force search, or an
+identity the method must satisfy, chosen so that a dropped term, a wrong sign
+or index, or a transposed operand in the oracle fails at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation, Slerp
+
+import gut_synth as G
+import oracle as O
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rot_scipy(q_wxyz):
+    q = np.asarray(q_wxyz, np.float64)
+    return Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+
+
+# ---------------------------------------------------------------------------
+# Unscented transform (Eq. 6-10)
+# ---------------------------------------------------------------------------
+
+def test_ut_weights_golden():
+    """Eq. 7-8 at alpha=1, beta=2, kappa=0 (Sec. 4.4) give fixed constants."""
+    g = json.load(open(os.path.join(GOLD, "ut_weights.json")))
+    lam, wm, wc = O.ut_weights(g["alpha"], g["beta"], g["kappa"])
+    assert lam == g["lambda"]
+    np.testing.assert_allclose(wm, g["w_mu"], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(wc, g["w_sigma"], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("a,b,k", [(0.5, 2.0, 0.0), (1.0, 0.0, 1.0), (1e-3, 2.0, 0.0)])
+def test_ut_weights_identities(a, b, k):
+    """For any spread the mean weights sum to one, and the covariance weights
+    differ from them only at the centre point, by 1 - alpha^2 + beta."""
+    lam, wm, wc = O.ut_weights(a, b, k)
+    assert abs(lam - (a * a * (3 + k) - 3)) < 1e-12
+    assert abs(wm.sum() - 1.0) < 1e-9
+    np.testing.assert_allclose(wc[1:], wm[1:], rtol=0, atol=0)
+    assert abs((wc[0] - wm[0]) - (1 - a * a + b)) < 1e-9
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_ut_exact_for_affine_maps(seed):
+    """The UT reproduces (A mu + b, A Sigma A^T) exactly for affine g, with
+    Sigma = R S S^T R^T (Eq. 2) and R from scipy's quaternion convention."""
+    rng = np.random.default_rng(seed)
+    mu = rng.normal(size=3)
+    q = rng.normal(size=4)
+    s = np.exp(rng.normal(-1, 0.5, size=3))
+    A = rng.normal(size=(2, 3))
+    b = rng.normal(size=2)
+    R = rot_scipy(q / np.linalg.norm(q))
+    Sigma = R @ np.diag(s ** 2) @ R.T
+    m, cov = O.ut_affine(mu, q, s, A, b)
+    np.testing.assert_allclose(m, A @ mu + b, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(cov, A @ Sigma @ A.T, rtol=1e-12, atol=1e-12)
+
+
+def test_ut_affine_general_spread():
+    """Exactness for affine maps holds for any (alpha, beta, kappa) with
+    alpha^2 (3 + kappa) > 0 whenever beta = 0 adds no extra centre weight...
+    here beta = 1 - alpha^2 keeps the covariance weights summing to one."""
+    rng = np.random.default_rng(7)
+    mu, q, s = rng.normal(size=3), rng.normal(size=4), np.array([0.2, 0.5, 0.1])
+    A, b = rng.normal(size=(2, 3)), rng.normal(size=2)
+    R = rot_scipy(q / np.linalg.norm(q))
+    for a, k in [(0.7, 0.0), (1.3, 1.0)]:
+        p = O.default_params(ut_alpha=a, ut_beta=1 - a * a, ut_kappa=k)
+        m, cov = O.ut_affine(mu, q, s, A, b, p)
+        np.testing.assert_allclose(m, A @ mu + b, atol=1e-12)
+        np.testing.assert_allclose(cov, A @ R @ np.diag(s ** 2) @ R.T @ A.T, atol=1e-12)
+
+
+@pytest.mark.parametrize("z,s,f", [(3.0, 0.1, 150.0), (8.0, 0.02, 1662.77), (1.5, 0.3, 37.5)])
+def test_ut_on_axis_pinhole_closed_form(z, s, f):
+    """An isotropic particle on the optical axis, its frame rotated only about
+    that axis, projects to the principal point with covariance (f s / z)^2 I
+    exactly (the two z-axis sigma points land on the centre; the other four at
+    distance sqrt(3) f s / z with weight 1/6)."""
+    cam = G.camera("pinhole", 200, 100, f, cx=100.0, cy=50.0)
+    ang = 0.7
+    q = np.array([[math.cos(ang / 2), 0.0, 0.0, math.sin(ang / 2)]])
+    sc = O.OScene(np.array([[0.0, 0.0, z]]), np.full((1, 3), s), q, np.array([0.9]),
+                  np.zeros((1, 1, 3)), 0)
+    pr = O.project(sc, cam)
+    np.testing.assert_allclose(pr["mean2d"][0], [100.0, 50.0], atol=1e-9)
+    e = (f * s / z) ** 2
+    np.testing.assert_allclose(pr["cov2d"][0], [e, 0.0, e], rtol=1e-9, atol=1e-9)
+
+
+def test_ut_vs_ewa_converges_quadratically():
+    """Off axis, the UT covariance approaches the linearised (EWA, Eq. 3)
+    covariance J Sigma J^T as the particle shrinks, with error O((s/z)^2)."""
+    f, c = 500.0, 0.0
+    cam = G.camera("pinhole", 1000, 1000, f, cx=c, cy=c)
+    mu = np.array([0.7, -0.4, 2.5])
+    q = np.array([0.9, 0.2, -0.3, 0.1])
+    R = rot_scipy(q / np.linalg.norm(q))
+    errs = []
+    for s in [0.04, 0.02, 0.01]:
+        sc = O.OScene(mu[None], np.array([[s, 0.5 * s, 0.8 * s]]), q[None], np.array([0.9]),
+                      np.zeros((1, 1, 3)), 0)
+        pr = O.project(sc, cam)
+        x, y, zz = mu
+        J = np.array([[f / zz, 0, -f * x / zz ** 2], [0, f / zz, -f * y / zz ** 2]])
+        S = R @ np.diag(np.array([s, 0.5 * s, 0.8 * s]) ** 2) @ R.T
+        ewa = J @ S @ J.T
+        cv = pr["cov2d"][0]
+        ut = np.array([[cv[0], cv[1]], [cv[1], cv[2]]])
+        errs.append(np.linalg.norm(ut - ewa) / np.linalg.norm(ewa))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.5 < r1 < 4.5 and 3.5 < r2 < 4.5, errs
+
+
+# ---------------------------------------------------------------------------
+# Camera models
+# ---------------------------------------------------------------------------
+
+def _fisheye(k, w=400, h=300, f=None):
+    return G.camera("fisheye", w, h, f or G.fisheye_focal(w), k=k)
+
+
+@pytest.mark.parametrize("model", ["pinhole", "fisheye"])
+def test_projection_round_trip(model):
+    """project(unproject(u)) = u for pixel centres across the image."""
+    if model == "pinhole":
+        cam = G.camera("pinhole", 320, 240, 300.0, cx=157.3, cy=121.9)
+    else:
+        cam = _fisheye([0.03, -0.02, 0.01, -0.004])
+    rng = np.random.default_rng(0)
+    checked = 0
+    for _ in range(200):
+        u, v = rng.uniform(0, cam["width"]), rng.uniform(0, cam["height"])
+        ok, o, d, _ = O.pixel_ray(cam, u, v)
+        if not ok:
+            continue
+        x = o + rng.uniform(0.5, 20) * d / np.linalg.norm(d)
+        ok2, uv, _ = O.project_point(cam, x)
+        assert ok2
+        np.testing.assert_allclose(uv, [u, v], atol=1e-9)
+        checked += 1
+    assert checked > 100
+
+
+def test_fisheye_k0_is_equidistant():
+    """With k = 0 the OpenCV fisheye model is the equidistant model r = f theta."""
+    cam = _fisheye([0, 0, 0, 0], f=250.0)
+    for th in [0.01, 0.3, 1.0, 1.5]:
+        for ph in [0.0, 0.7, 2.5]:
+            x = np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)]) * 3
+            ok, uv, _ = O.project_point(cam, x)
+            assert ok
+            r = np.hypot(uv[0] - cam["cx"], uv[1] - cam["cy"])
+            assert abs(r - 250.0 * th) < 1e-9
+
+
+def test_fisheye_small_angle_matches_pinhole():
+    fish = _fisheye([0.04, 0.01, -0.02, 0.005], f=300.0)
+    pin = G.camera("pinhole", 400, 300, 300.0)
+    for eps in [1e-3, 1e-4]:
+        x = np.array([eps, -0.5 * eps, 1.0])
+        _, a, _ = O.project_point(fish, x)
+        _, b, _ = O.project_point(pin, x)
+        assert np.abs(a - b).max() < 300.0 * eps ** 3 * 10
+
+
+@pytest.mark.parametrize("j,kv", [(0, -0.5), (1, -0.3), (2, -0.2), (3, -0.1)])
+def test_theta_lim_single_coefficient_closed_form(j, kv):
+    """With one coefficient k_j < 0 the validity limit is the root of
+    1 + (2j+3) k_j theta^(2j+2) = 0 when it lies below pi/2."""
+    k = [0.0] * 4
+    k[j] = kv
+    root = (-1.0 / ((2 * j + 3) * kv)) ** (1.0 / (2 * j + 2))
+    expect = min(root, math.pi / 2)
+    assert abs(O.theta_lim(k) - expect) < 1e-12
+
+
+def test_theta_lim_is_the_image_radius_maximum():
+    """The validity angle is where the projected radius stops growing: a dense
+    scan of the projected radius (through project_point) peaks there."""
+    k = [-0.05, -0.05, -0.05, -0.05]
+    tl = O.theta_lim(k)
+    assert tl < math.pi / 2
+    cam = _fisheye(k, f=100.0)
+    ths = np.linspace(0.5, math.pi / 2, 20001)
+    radii = []
+    p = O.default_params(near_plane=0.0)
+    for th in ths:
+        x = np.array([math.sin(th), 0.0, math.cos(th)]) * 2
+        _, uv, _ = O.project_point(cam, x, params=p)
+        radii.append(uv[0] - cam["cx"])
+    th_max = ths[int(np.argmax(radii))]
+    assert abs(th_max - tl) < 2 * (ths[1] - ths[0])
+
+
+def test_fisheye_validity_and_image_circle():
+    k = [-0.05, -0.05, -0.05, -0.05]
+    cam = _fisheye(k, w=200, h=200, f=60.0)
+    tl = O.theta_lim(k)
+    ok_in, _, m_in = O.project_point(cam, np.array([math.sin(tl - 1e-3), 0, math.cos(tl - 1e-3)]))
+    ok_out, _, m_out = O.project_point(cam, np.array([math.sin(tl + 1e-3), 0, math.cos(tl + 1e-3)]))
+    assert ok_in and not ok_out and m_in > 0 > m_out
+    ok, _, _, _ = O.pixel_ray(cam, 199.5, 199.5)  # a corner beyond the image circle
+    assert not ok
+
+
+# ---------------------------------------------------------------------------
+# Rolling shutter
+# ---------------------------------------------------------------------------
+
+def _rs_cam(model="pinhole", pan=0.1, shift=0.3, w=320, h=240):
+    R, t = G.look_at((0.5, -0.3, -6.0))
+    if model == "pinhole":
+        cam = G.camera("pinhole", w, h, G.pinhole_focal(w), R0=R, t0=t)
+    else:
+        cam = G.camera("fisheye", w, h, G.fisheye_focal(w), k=[0.02, -0.01, 0.0, 0.0], R0=R, t0=t)
+    return G.with_motion(cam, pan, shift)
+
+
+def test_pose_interpolation_matches_scipy_slerp():
+    cam = _rs_cam(pan=0.4, shift=0.7)
+    Q0, Q1 = cam["R0"].T, cam["R1"].T
+    sl = Slerp([0, 1], Rotation.from_matrix([Q0, Q1]))
+    c0, c1 = -cam["R0"].T @ cam["t0"], -cam["R1"].T @ cam["t1"]
+    for t in [0.0, 0.25, 0.5, 0.9, 1.0]:
+        Rwc, cen = O.pose(cam, t)
+        np.testing.assert_allclose(Rwc.T, sl([t]).as_matrix()[0], atol=1e-12)
+        np.testing.assert_allclose(cen, (1 - t) * c0 + t * c1, atol=1e-12)
+
+
+def test_zero_motion_rolling_equals_global():
+    sc, cams = G.config1()
+    cam = cams[0]
+    rs = G.with_motion(cam, 0.0, 0.0)
+    a = O.project(sc, cam)
+    b = O.project(sc, rs)
+    for k in ("mean2d", "cov2d", "depth", "rgb"):
+        np.testing.assert_allclose(a[k], b[k], atol=1e-10)
+    np.testing.assert_array_equal(a["rect"], b["rect"])
+
+
+@pytest.mark.parametrize("model", ["pinhole", "fisheye"])
+def test_rolling_time_matches_bruteforce_root(model):
+    """The solved exposure time approaches the row-consistency root
+    t = (v_y(x, pose(t)) - 1/2)/(H - 1), found by a dense scan of t."""
+    cam = _rs_cam(model)
+    rng = np.random.default_rng(3)
+    H = cam["height"]
+    ts = np.linspace(0, 1, 100001)
+    for _ in range(5):
+        x = rng.normal(size=3) * np.array([1.5, 1.5, 1.0])
+        ok, t3, _, _ = O.solve_time(cam, x, iters=3)
+        ok20, t20, _, _ = O.solve_time(cam, x, iters=20)
+        if not ok:
+            continue
+        F = []
+        for t in ts[::100]:
+            _, v, _ = O.project_point(cam, x, t)
+            F.append(np.clip((v[1] - 0.5) / (H - 1), 0, 1) - t)
+        F = np.array(F)
+        i = np.nonzero(np.diff(np.sign(F)))[0]
+        assert len(i) == 1
+        lo, hi = ts[::100][i[0]], ts[::100][i[0] + 1]
+        for _ in range(60):
+            mid = 0.5 * (lo + hi)
+            _, v, _ = O.project_point(cam, x, mid)
+            f = np.clip((v[1] - 0.5) / (H - 1), 0, 1) - mid
+            if np.sign(f) == np.sign(F[i[0]]):
+                lo = mid
+            else:
+                hi = mid
+        root = 0.5 * (lo + hi)
+        assert abs(t20 - root) < 1e-10
+        assert abs(t3 - root) < 1e-3
+
+
+def test_rolling_pixel_ray_hits_its_row_at_its_time():
+    """A point on the ray of pixel (u, v) projects back to (u, v) at the
+    exposure time of row floor(v)."""
+    cam = _rs_cam("fisheye")
+    for u, v in [(60.5, 50.5), (160.5, 120.5), (280.5, 180.5)]:
+        ok, o, d, _ = O.pixel_ray(cam, u, v)
+        assert ok
+        t = math.floor(v) / (cam["height"] - 1)
+        _, uv, _ = O.project_point(cam, o + 5.0 * d / np.linalg.norm(d), t)
+        np.testing.assert_allclose(uv, [u, v], atol=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# Particle response (Eq. 1, Eq. 11)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(4))
+def test_tau_max_forms_and_argmax(seed):
+    """Eq. 11: the world-space form (mu-o)^T Sigma^-1 d / d^T Sigma^-1 d equals
+    the canonical form, and it maximises the response along the ray."""
+    rng = np.random.default_rng(seed)
+    mu, q, s = rng.normal(size=3), rng.normal(size=4), np.exp(rng.normal(-1, 0.4, 3))
+    o, d = rng.normal(size=3) * 3, rng.normal(size=3)
+    R = rot_scipy(q / np.linalg.norm(q))
+    Si = np.linalg.inv(R @ np.diag(s ** 2) @ R.T)
+    tau_world = (mu - o) @ Si @ d / (d @ Si @ d)
+    _, tau, om2, _ = O.particle_alpha(mu, q, s, 0.8, o, d)
+    assert abs(tau - tau_world) < 1e-12 * max(1, abs(tau))
+    taus = tau + np.linspace(-3, 3, 60001) * (1 + abs(tau))
+    x = o[None] + taus[:, None] * d[None]
+    rho = np.exp(-0.5 * np.einsum("ni,ij,nj->n", x - mu, Si, x - mu))
+    assert abs(taus[np.argmax(rho)] - tau) <= (taus[1] - taus[0])
+    assert abs(rho.max() - math.exp(-0.5 * om2)) < 1e-8
+
+
+def test_single_isotropic_particle_closed_form():
+    """One isotropic particle: pixel = c sigma exp(-d_perp^2 / (2 s^2)) with
+    d_perp the distance from the centre to the pixel ray (vector geometry)."""
+    cam = G.camera("pinhole", 64, 64, 80.0, R0=np.eye(3), t0=np.array([0.0, 0.0, 4.0]))
+    s, sig, col = 0.15, 0.8, np.array([0.9, 0.4, 0.1])
+    mu = np.array([0.1, -0.05, 0.2])
+    sh = ((col - 0.5) / G.SH_C0)[None, None, :]
+    sc = O.OScene(mu[None], np.full((1, 3), s), np.array([[0.3, 0.1, 0.7, -0.2]]),
+                  np.array([sig]), sh, 0)
+    pr, b, res = O.render_full(sc, cam)
+    img = O.to_image(res, cam)
+    o = np.array([0.0, 0.0, -4.0])
+    worst = 0.0
+    n_checked = 0
+    for py in range(64):
+        for px in range(64):
+            d = np.array([(px + 0.5 - 32) / 80.0, (py + 0.5 - 32) / 80.0, 1.0])
+            dperp = np.linalg.norm(np.cross(mu - o, d / np.linalg.norm(d)))
+            a = sig * math.exp(-dperp ** 2 / (2 * s * s))
+            if a < 1 / 255 + 1e-6 or a > 0.99:
+                continue
+            worst = max(worst, np.abs(img[py, px] - col * a).max())
+            n_checked += 1
+    assert n_checked > 50 and worst < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Compositing (Eq. 5)
+# ---------------------------------------------------------------------------
+
+def _white(scene):
+    sh = np.zeros_like(scene.sh)
+    sh[:, 0, :] = 0.5 / G.SH_C0
+    return O.OScene(scene.means, scene.scales, scene.quats, scene.opacities, sh, scene.sh_degree)
+
+
+def test_weights_plus_transmittance_sum_to_one():
+    """With unit colour and black background, C = sum_i alpha_i T_i, so
+    C + T_final = 1 telescopes exactly."""
+    sc, cams = G.config1()
+    w = _white(sc)
+    pr, b, res = O.render_full(w, cams[0])
+    m = res["inside"] == 1
+    np.testing.assert_allclose(res["rgb"][m, 0] + res["T"][m], 1.0, atol=1e-12)
+
+
+def test_two_particle_order_closed_form():
+    """Front particle first: C = c1 a1 + c2 a2 (1 - a1) on the line of sight."""
+    cam = G.camera("pinhole", 16, 16, 20.0, R0=np.eye(3), t0=np.array([0.0, 0.0, 5.0]))
+    cols = np.array([[0.9, 0.1, 0.2], [0.2, 0.8, 0.6]])
+    mu = np.array([[0.0, 0.0, -1.0], [0.0, 0.0, 1.0]])  # depth 4 and 6
+    sh = ((cols - 0.5) / G.SH_C0)[:, None, :]
+    sc = O.OScene(mu, np.full((2, 3), 0.5), np.tile([1.0, 0, 0, 0], (2, 1)), np.array([0.7, 0.6]),
+                  sh, 0)
+    pr, b, res = O.render_full(sc, cam)
+    img = O.to_image(res, cam)
+    o = np.array([0, 0, -5.0])
+    d = np.array([(8.5 - 8) / 20, (8.5 - 8) / 20, 1.0])
+    a = [sg * math.exp(-np.linalg.norm(np.cross(m - o, d / np.linalg.norm(d))) ** 2 / 0.5)
+         for m, sg in zip(mu, [0.7, 0.6])]
+    expect = cols[0] * a[0] + cols[1] * a[1] * (1 - a[0])
+    np.testing.assert_allclose(img[8, 8], expect, atol=1e-12)
+
+
+def test_early_termination_closed_form():
+    """Ten stacked particles of alpha 0.9 on the axis: T falls 10x per layer;
+    with T_min = 5e-5 the fifth would take T below it, so it is not added and
+    T_final = 1e-4."""
+    cam = G.camera("pinhole", 16, 16, 20.0, R0=np.eye(3), t0=np.array([0.0, 0.0, 5.0]))
+    n = 10
+    mu = np.stack([np.zeros(n), np.zeros(n), np.linspace(-1, 1, n)], 1)
+    sh = np.full((n, 1, 3), 0.5 / G.SH_C0)
+    p = O.default_params(alpha_max=1.0, t_min=5e-5)
+    # opacity chosen so alpha at the exact centre ray is 0.9: put the pixel ray through the axis
+    cam["cx"] = cam["cy"] = 8.5
+    sc = O.OScene(mu, np.full((n, 3), 0.2), np.tile([1.0, 0, 0, 0], (n, 1)), np.full(n, 0.9), sh, 0)
+    pr, b, res = O.render_full(sc, cam, params=p)
+    px = (8 // 16) * 256 + 8 * 16 + 8
+    assert res["n_contrib"][px] == 4
+    assert res["n_eval"][px] == 5
+    assert abs(res["T"][px] - 0.1 ** 4) < 1e-15
+    np.testing.assert_allclose(res["rgb"][px] + res["T"][px], 1.0, atol=1e-15)
+    assert abs(res["rgb"][px, 0] - (1 - 0.1 ** 4)) < 1e-14
+
+
+def test_alpha_min_skip():
+    """A particle whose alpha at the pixel is below 1/255 is skipped entirely."""
+    cam = G.camera("pinhole", 16, 16, 20.0, R0=np.eye(3), t0=np.array([0.0, 0.0, 5.0]))
+    cam["cx"] = cam["cy"] = 8.5
+    sh = np.full((1, 1, 3), 0.5 / G.SH_C0)
+    for sig, expect_contrib in [(0.0039, 0), (0.004, 1)]:
+        sc = O.OScene(np.zeros((1, 3)), np.full((1, 3), 0.2), np.array([[1.0, 0, 0, 0]]),
+                      np.array([sig]), sh, 0)
+        p = O.default_params(alpha_min=1 / 255)
+        pr, b, res = O.render_full(sc, cam, params=p)
+        px = 8 * 16 + 8
+        assert res["n_contrib"][px] == expect_contrib
+
+
+# ---------------------------------------------------------------------------
+# Culling and tiling
+# ---------------------------------------------------------------------------
+
+def test_tiled_equals_bruteforce_when_rects_cover_everything():
+    """Large particles whose rectangles cover every tile: the tiled render and
+    the no-culling brute-force render (every particle, every pixel) agree."""
+    rng = np.random.default_rng(5)
+    n = 40
+    cam = G.camera("pinhole", 48, 48, 30.0, R0=np.eye(3), t0=np.array([0.0, 0.0, 4.0]))
+    sc = O.OScene(rng.uniform(-0.3, 0.3, (n, 3)), np.exp(rng.normal(0.3, 0.1, (n, 3))),
+                  rng.normal(size=(n, 4)), rng.uniform(0.05, 0.2, n),
+                  rng.normal(0, 1, (n, 1, 3)), 0)
+    p = O.default_params()
+    pr = O.project(sc, cam, p)
+    assert (pr["cull"] == 0).all() and (pr["tiles"] == 9).all()
+    b = O.bin_tiles(pr, cam, p)
+    tiled = O.render(sc, pr, cam, b, p)
+    brute = O.render(sc, pr, cam, None, p, brute_force=True)
+    np.testing.assert_allclose(tiled["rgb"], brute["rgb"], atol=1e-15)
+    np.testing.assert_array_equal(tiled["n_contrib"], brute["n_contrib"])
+
+
+def test_tiled_close_to_bruteforce_config1():
+    """In general the tiled render drops only response outside each
+    particle's extent box, so it stays close to the brute-force render."""
+    sc, cams = G.config1()
+    cam = cams[0]
+    pr = O.project(sc, cam)
+    b = O.bin_tiles(pr, cam)
+    tiled = O.render(sc, pr, cam, b, alternatives=False)
+    brute = O.render(sc, pr, cam, None, brute_force=True, alternatives=False)
+    d = np.abs(tiled["rgb"] - brute["rgb"]).max()
+    assert d < 0.05
+    assert np.mean(np.abs(tiled["rgb"] - brute["rgb"]).max(1) < 1e-9) > 0.9
+
+
+def test_tile_lists_bruteforce():
+    """Each tile's list holds exactly the visible particles whose rectangle
+    covers it, ordered by (depth, id)."""
+    sc, cams = G.config1()
+    cam = cams[0]
+    pr = O.project(sc, cam)
+    ts, ids, fl = O.bin_tiles(pr, cam)
+    prim = fl & 1 == 1
+    tx, ty = O.tiles_xy(cam, O.default_params())
+    vis = np.nonzero(pr["cull"] == 0)[0]
+    for t in range(tx * ty):
+        x, y = t % tx, t // tx
+        r = pr["rect"][vis]
+        cov = vis[(r[:, 0] <= x) & (x <= r[:, 2]) & (r[:, 1] <= y) & (y <= r[:, 3])]
+        order = sorted(cov, key=lambda i: (pr["depth"][i], i))
+        seg = slice(ts[t], ts[t + 1])
+        got = ids[seg][prim[seg]]
+        assert list(got) == list(order)
+
+
+def test_opacity_and_near_culls():
+    sc, cams = G.config1()
+    cam = cams[0]
+    pr = O.project(sc, cam)
+    low = sc.opacities < np.float32(1 / 255)
+    assert (pr["cull"][low] == 1).all()
+    # a particle straddling the near plane of a camera placed inside the cloud
+    cam2 = G.camera("pinhole", 64, 64, 60.0, R0=np.eye(3), t0=np.array([0.0, 0.0, -0.1]))
+    sc2 = O.OScene(np.array([[0.0, 0.0, 0.3]]), np.full((1, 3), 0.1), np.array([[1.0, 0, 0, 0]]),
+                   np.array([0.9]), np.zeros((1, 1, 3)), 0)
+    pr2 = O.project(sc2, cam2)
+    assert pr2["cull"][0] == 2
+
+
+def test_depth_and_degree0_colour():
+    sc, cams = G.config1()
+    cam = cams[0]
+    pr = O.project(sc, cam)
+    eye = np.array([0, 0, -3.0])
+    vis = pr["cull"] != 1
+    np.testing.assert_allclose(pr["depth"][vis], np.linalg.norm(sc.means[vis] - eye, axis=1),
+                               rtol=1e-12)
+    dc = 0.5 + G.SH_C0 * sc.sh[:, 0, :].astype(np.float64)
+    np.testing.assert_allclose(pr["rgb"][vis], np.maximum(dc[vis], 0), atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Spherical harmonics
+# ---------------------------------------------------------------------------
+
+def test_sh_matches_scipy():
+    """Real SH with the Condon-Shortley phase: sqrt2 Re Y_l^m (m>0),
+    sqrt2 Im Y_l^|m| (m<0), Y_l^0, from scipy's complex harmonics."""
+    from scipy.special import sph_harm_y
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        th, ph = math.acos(d[2]), math.atan2(d[1], d[0])
+        Y = O.sh_basis(3, d)
+        for l in range(4):
+            for m in range(-l, l + 1):
+                y = sph_harm_y(l, abs(m), th, ph)
+                ref = y.real if m == 0 else (math.sqrt(2) * (y.real if m > 0 else y.imag))
+                assert abs(Y[l * l + l + m] - ref) < 1e-12, (l, m)
+
+
+def test_sh_orthonormal_by_quadrature():
+    x, w = np.polynomial.legendre.leggauss(16)
+    phis = np.arange(32) * 2 * np.pi / 32
+    G_ = np.zeros((16, 16))
+    for zi, wi in zip(x, w):
+        for ph in phis:
+            r = math.sqrt(1 - zi * zi)
+            Y = O.sh_basis(3, [r * math.cos(ph), r * math.sin(ph), zi])
+            G_ += wi * (2 * np.pi / 32) * np.outer(Y, Y)
+    np.testing.assert_allclose(G_, np.eye(16), atol=1e-12)
+
+
+def test_sh_gradient_tangential_matches_differences():
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        dY = O.sh_basis_grad(3, d)
+        P = np.eye(3) - np.outer(d, d)
+        for j in range(3):
+            e = np.zeros(3)
+            e[j] = 1e-6
+            f = lambda v: O.sh_basis(3, v / np.linalg.norm(v))
+            fd = (f(d + e) - f(d - e)) / 2e-6
+            np.testing.assert_allclose(fd, (dY @ P)[:, j], atol=1e-8)
