@@ -1,0 +1,186 @@
+// Internal definitions shared by the libgut HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <cstdio>
+
+#include "gut.h"
+
+namespace gut {
+
+constexpr int kTile = 16;
+constexpr int kTilePix = kTile * kTile;
+constexpr int kMaxCams = 64;
+
+// A camera prepared on the host in FP64.  The projection kernel reads the
+// FP32 copies; the render kernels build per-tile ray frames from the FP64
+// values so that pixel rays are exact to well below FP32 resolution.
+struct DevCam {
+  int model, shutter, W, H;
+  int tiles_x, tiles_y, tile_base, pad0;
+  long long pixel_base;
+  // FP64
+  double fx, fy, cx, cy;
+  double k[4];
+  double theta_lim, thetad_lim;
+  double Q0[9];        // camera->world rotation at t = 0, row-major
+  double c0[3], dc[3]; // camera centre at t = 0, and c1 - c0
+  double axis[3];      // Q0^T Q1 = exp(angle [axis]x)  (camera-0 frame)
+  double angle;
+  double inv_hm1;      // 1/(H-1), 0 if H == 1
+  // FP32
+  float fxf, fyf, cxf, cyf;
+  float kf[4];
+  float theta_limf, inv_hm1f, anglef, pad1;
+  float R0f[9];    // world->camera at t = 0
+  float c0f[3];
+  float deltaf[3]; // R0 (c1 - c0): centre motion in camera-0 coordinates
+  float axisf[3];
+  float dcf[3];    // c1 - c0 in world coordinates
+};
+
+// UT weights and spread, prepared on the host from (alpha, beta, kappa).
+struct UTConst {
+  float gamma;  // sqrt(3 + lambda)
+  float wm0, wmi, wc0, wci;
+};
+
+struct Thresholds {
+  float alpha_min, alpha_max, t_min, near_plane, k_sigma_max;
+  float bg[3];
+  int rs_iters;
+};
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+const char* status_name(gut_status s);
+
+#define GUT_HIP(call)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      ::gut::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),  \
+                       __FILE__, __LINE__);                                    \
+      return GUT_E_HIP;                                                        \
+    }                                                                          \
+  } while (0)
+
+#define GUT_LAUNCH_CHECK()                                                     \
+  do {                                                                         \
+    hipError_t e_ = hipGetLastError();                                         \
+    if (e_ != hipSuccess) {                                                    \
+      ::gut::set_error("kernel launch failed: %s (%s:%d)",                     \
+                       hipGetErrorString(e_), __FILE__, __LINE__);             \
+      return GUT_E_HIP;                                                        \
+    }                                                                          \
+  } while (0)
+
+// ---------------------------------------------------------------- host prep
+gut_status make_devcam(const gut_camera& c, const gut_params& p, int tile_base,
+                       long long pixel_base, DevCam* out);
+gut_status check_params(const gut_params* p);
+UTConst make_ut(const gut_params& p);
+Thresholds make_thresholds(const gut_params& p);
+gut_status check_scene(const gut_scene* s, bool need_sh);
+gut_status prepare_cams(const gut_camera* cams, int n_cams, const gut_params& p,
+                        DevCam* out, int64_t* total_tiles, int64_t* total_pixels);
+
+gut_status fill_u32(uint32_t* p, int64_t m, uint32_t v, hipStream_t st);
+
+// Radix sort / scan building blocks (sort.hip).
+size_t scan_temp_bytes(int64_t n);
+gut_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* temp,
+                              hipStream_t st);
+int64_t radix_blocks(int64_t n);
+size_t radix_temp_bytes(int64_t n);
+// Stable LSD sort of (key, value) pairs over key bits [0, bits), 8 bits per
+// pass, ping-ponging between (kA, vA) and (kB, vB) starting from A;
+// *result_in_b tells which pair holds the sorted result.
+gut_status radix_sort_pairs_pp(uint32_t* kA, uint32_t* vA, uint32_t* kB, uint32_t* vB, int64_t n,
+                               int bits, void* temp, hipStream_t st, int* result_in_b);
+
+// ---------------------------------------------------------------- device math
+__host__ __device__ inline float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
+__device__ inline float dot3f(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ inline float3 cross3f(float3 a, float3 b) {
+  return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+struct d3 { double x, y, z; };
+__host__ __device__ inline d3 mk3(double x, double y, double z) { d3 r = {x, y, z}; return r; }
+__host__ __device__ inline double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__host__ __device__ inline d3 cross(d3 a, d3 b) {
+  return mk3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline d3 add(d3 a, d3 b) { return mk3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__host__ __device__ inline d3 sub(d3 a, d3 b) { return mk3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__host__ __device__ inline d3 scl(d3 a, double s) { return mk3(a.x * s, a.y * s, a.z * s); }
+__host__ __device__ inline d3 mv(const double* M, d3 v) {
+  return mk3(M[0] * v.x + M[1] * v.y + M[2] * v.z, M[3] * v.x + M[4] * v.y + M[5] * v.z,
+             M[6] * v.x + M[7] * v.y + M[8] * v.z);
+}
+
+// Fisheye distortion polynomial theta_d(theta) (OpenCV fisheye model).
+__host__ __device__ inline double thetad_poly(const double* k, double th) {
+  double t2 = th * th;
+  return th * (1.0 + t2 * (k[0] + t2 * (k[1] + t2 * (k[2] + t2 * k[3]))));
+}
+__host__ __device__ inline double thetad_deriv(const double* k, double th) {
+  double t2 = th * th;
+  return 1.0 + t2 * (3.0 * k[0] + t2 * (5.0 * k[1] + t2 * (7.0 * k[2] + t2 * 9.0 * k[3])));
+}
+
+// Rotate v by angle a about unit axis u (Rodrigues), FP64.
+__host__ __device__ inline d3 rodrigues(d3 u, double a, d3 v) {
+  double s = sin(a), c = cos(a);
+  d3 uxv = cross(u, v);
+  d3 uxuxv = cross(u, uxv);
+  return add(v, add(scl(uxv, s), scl(uxuxv, 1.0 - c)));
+}
+
+// Camera-frame direction of image point (u, v) (a pixel centre or any point),
+// FP64.  Fisheye: theta from theta_d by safeguarded Newton on [0, theta_lim];
+// points beyond the image circle are clamped to it and reported invalid.
+__device__ inline d3 unproject_dir(const DevCam& c, double u, double v, bool* valid) {
+  double mx = (u - c.cx) / c.fx, my = (v - c.cy) / c.fy;
+  if (c.model == GUT_PINHOLE) {
+    *valid = true;
+    return mk3(mx, my, 1.0);
+  }
+  double td = sqrt(mx * mx + my * my);
+  *valid = td <= c.thetad_lim;
+  double target = td < c.thetad_lim ? td : c.thetad_lim;
+  double lo = 0.0, hi = c.theta_lim, th = target < hi ? target : hi;
+  for (int it = 0; it < 60; it++) {  // Newton on the bracket [lo, hi], bisecting when it leaves
+    double f = thetad_poly(c.k, th) - target;
+    if (f == 0.0) break;
+    if (f > 0) hi = th; else lo = th;
+    double nt = th - f / thetad_deriv(c.k, th);
+    if (!(nt >= lo && nt <= hi)) nt = 0.5 * (lo + hi);
+    if (fabs(nt - th) <= 1e-16 * th || hi - lo <= 1e-16 * hi) { th = nt; break; }
+    th = nt;
+  }
+  double st = sin(th), ct = cos(th);
+  if (td > 0) return mk3(st * mx / td, st * my / td, ct);
+  return mk3(0.0, 0.0, 1.0);
+}
+
+// World-space ray (origin, direction) of camera-frame direction dc exposed at
+// time t: Q(t) = Q0 exp(t angle [axis]x), centre c0 + t (c1 - c0).
+__device__ inline void ray_at(const DevCam& c, double t, d3 dc, d3* o, d3* d) {
+  d3 r = dc;
+  if (c.shutter == GUT_ROLLING_TOP_TO_BOTTOM && c.angle != 0.0)
+    r = rodrigues(mk3(c.axis[0], c.axis[1], c.axis[2]), t * c.angle, dc);
+  *d = mv(c.Q0, r);
+  *o = mk3(c.c0[0] + t * c.dc[0], c.c0[1] + t * c.dc[1], c.c0[2] + t * c.dc[2]);
+  if (c.shutter != GUT_ROLLING_TOP_TO_BOTTOM) *o = mk3(c.c0[0], c.c0[1], c.c0[2]);
+}
+
+__device__ inline double row_time(const DevCam& c, int row) {
+  return c.shutter == GUT_ROLLING_TOP_TO_BOTTOM ? row * c.inv_hm1 : 0.0;
+}
+
+}  // namespace gut

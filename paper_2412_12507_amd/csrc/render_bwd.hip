@@ -1,0 +1,325 @@
+// K6 + K7 -- backward of the compositing and of the per-particle colour
+// (Supp. B).  No gradient flows through the sigma-point projection, the
+// rectangles or the sort order (Sec. 4.1: the UT only selects particles).
+//
+// K6 (per tile, same layout as the forward): each pixel recomputes its
+// contributors front to back with the forward's exact arithmetic, up to its
+// stored n_contrib.  For contributor j with transmittance T_j before it,
+//   dL/dalpha_j = sum_ch gC (c_j T_j - (S_after + T_N bg) / (1 - alpha_j))
+//                 - gT T_N / (1 - alpha_j),   S_after = C - T_N bg - C_<=j,
+//   dL/dc_j     = alpha_j T_j gC,
+// and through alpha = sigma exp(-omega^2/2) (unclamped only):
+//   dL/dsigma += dL/dalpha exp(-omega^2/2),
+//   dL/domega^2 = -alpha/2 dL/dalpha.
+// With p = o_g + tau d_g = (d_g x (o_g x d_g)) / |d_g|^2 the closest point
+// in canonical space, d omega^2/d o_g = 2p and d omega^2/d d_g = 2 tau p
+// (Supp. B), so with M = S^-1 R^T the per-pixel gradients are
+//   dL/dmu = -M^T c p,   dL/dM = c p (M^-1 p)^T,   c = 2 dL/domega^2.
+// They only depend on G = sum c p p^T (6 values) and h = sum c p (3): each
+// wave sums those plus dL/dsigma and dL/dc over its lanes and issues one FP32
+// atomic per value per (wave, particle).
+//
+// K7 (per particle) then applies M = S^-1 R^T:
+//   dL/ds_k = -G_kk / s_k,   dL/dR = R S G S^-1,   dL/dmu = -R S^-1 h,
+// the quaternion normalisation Jacobian, and (per camera) the SH colour:
+//   dL/dbeta_k = dL/dc Y_k(d),  dL/dmu += (I - d d^T)/|mu - o| sum beta grad Y.
+#include "camera_dev.h"
+#include "tile_eval.h"
+
+namespace gut {
+
+constexpr int kAcc = 10;  // G xx,xy,xz,yy,yz,zz ; h x,y,z ; dL/dsigma
+
+__device__ inline float wave_sum(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+template <bool RS>
+__global__ void __launch_bounds__(kTilePix) render_bwd_kernel(
+    DevCam cam, Thresholds th, int n, int cam_idx, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ ids, const float4* __restrict__ record,
+    const float* __restrict__ rgb, const float* __restrict__ out_rgb,
+    const float* __restrict__ out_T, const uint32_t* __restrict__ out_nc,
+    const float* __restrict__ d_rgb, const float* __restrict__ d_T, float* __restrict__ acc,
+    float* __restrict__ acc_rgb) {
+  constexpr int S = Slots<RS>::N;
+  __shared__ float4 pd[kTilePix * S];
+  __shared__ uint32_t pe[kTilePix];
+  __shared__ TileFrameD F;
+  __shared__ float red[12];
+  __shared__ uint32_t maxlast_s;
+
+  const int tile = blockIdx.x;
+  const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+  const int t = threadIdx.x, lane = t & 63;
+  const int px = tx * kTile + (t & (kTile - 1)), py = ty * kTile + t / kTile;
+  if (t == 0) { tile_frame(cam, tx, ty, &F); maxlast_s = 0; }
+  __syncthreads();
+  const bool inside = px < cam.W && py < cam.H;
+  float u = 0.0f, v = 0.0f, dt = 0.0f;
+  bool active = inside && pixel_ray(cam, F, px, py, &u, &v, &dt);
+  float umax, vmax, dtmax;
+  tile_bounds(u, v, dt, active, red, &umax, &vmax, &dtmax);
+
+  uint32_t last = 0;
+  float TN = 1.0f, gC0 = 0, gC1 = 0, gC2 = 0, gT = 0;
+  double Co0 = 0, Co1 = 0, Co2 = 0;  // the output colour C = sum_j c_j alpha_j T_j + T_N bg
+  if (active) {
+    long long pix = cam.pixel_base + (long long)py * cam.W + px;
+    last = out_nc[pix];
+    TN = out_T[pix];
+    gC0 = d_rgb[3 * pix]; gC1 = d_rgb[3 * pix + 1]; gC2 = d_rgb[3 * pix + 2];
+    gT = d_T ? d_T[pix] : 0.0f;
+    Co0 = out_rgb[3 * pix]; Co1 = out_rgb[3 * pix + 1]; Co2 = out_rgb[3 * pix + 2];
+  }
+  atomicMax(&maxlast_s, last);
+  __syncthreads();
+  const uint2 rg = ranges[cam.tile_base + tile];
+  const uint32_t maxlast = min(maxlast_s, rg.y - rg.x);  // never past the tile's list
+
+  float T = 1.0f;
+  double A0 = 0.0, A1 = 0.0, A2 = 0.0;  // running colour C_<=j, accumulated as in the forward
+  for (uint32_t b = 0; b < maxlast; b += kTilePix) {
+    __syncthreads();
+    if (b + t < maxlast) {
+      uint32_t e = ids[rg.x + b + t];
+      pe[t] = e;
+      pair_setup<RS>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n), F, cam, umax,
+                     vmax, dtmax, &pd[t * S]);
+    }
+    __syncthreads();
+    const uint32_t cnt = min((uint32_t)kTilePix, maxlast - b);
+    for (uint32_t q = 0; q < cnt; q++) {
+      float g[kAcc + 3];
+#pragma unroll
+      for (int k = 0; k < kAcc + 3; k++) g[k] = 0.0f;
+      bool hit = false;
+      Eval ev;
+      if (b + q < last && eval_pair<RS>(&pd[q * S], u, v, dt, th.alpha_min, th.alpha_max, &ev)) {
+        hit = true;
+        const float4* P = &pd[q * S];
+        const float c0 = P[1].w, c1 = P[2].w, c2 = P[3].w;
+        const float wgt = ev.a * T;
+        A0 = fma((double)wgt, (double)c0, A0);
+        A1 = fma((double)wgt, (double)c1, A1);
+        A2 = fma((double)wgt, (double)c2, A2);
+        const float inv1m = 1.0f / (1.0f - ev.a);
+        // (S_after + T_N bg) = C - C_<=j, formed in FP64
+        const float r0 = (float)(Co0 - A0), r1 = (float)(Co1 - A1), r2 = (float)(Co2 - A2);
+        float gA = gC0 * (c0 * T - r0 * inv1m) + gC1 * (c1 * T - r1 * inv1m) +
+                   gC2 * (c2 * T - r2 * inv1m) - gT * TN * inv1m;
+        g[kAcc] = wgt * gC0;
+        g[kAcc + 1] = wgt * gC1;
+        g[kAcc + 2] = wgt * gC2;
+        if (!ev.clamped) {
+          g[9] = gA * ev.ex;
+          const float c = -ev.a * gA;  // 2 dL/domega^2
+          float3 p = cross3f(ev.dg, ev.cr);
+          p = f3(p.x * ev.idd, p.y * ev.idd, p.z * ev.idd);
+          const float3 cp = f3(c * p.x, c * p.y, c * p.z);
+          g[0] = cp.x * p.x; g[1] = cp.x * p.y; g[2] = cp.x * p.z;
+          g[3] = cp.y * p.y; g[4] = cp.y * p.z; g[5] = cp.z * p.z;
+          g[6] = cp.x; g[7] = cp.y; g[8] = cp.z;
+        }
+        T = T * (1.0f - ev.a);
+      }
+      if (__ballot(hit) == 0ull) continue;  // wave-uniform
+#pragma unroll
+      for (int k = 0; k < kAcc + 3; k++) g[k] = wave_sum(g[k]);
+      if (lane == 0) {
+        uint32_t e = pe[q];
+        int i = (int)(e - (uint32_t)cam_idx * (uint32_t)n);
+#pragma unroll
+        for (int k = 0; k < kAcc; k++)
+          if (g[k] != 0.0f) atomicAdd(&acc[(long long)i * kAcc + k], g[k]);
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+          if (g[kAcc + k] != 0.0f) atomicAdd(&acc_rgb[3 * (long long)e + k], g[kAcc + k]);
+      }
+    }
+  }
+}
+
+// K7a: camera-independent part of the per-particle chain; also zeroes g_sh.
+__global__ void particle_grad_kernel(int n, int K, const float* __restrict__ scales,
+                                     const float* __restrict__ quats, const float* __restrict__ acc,
+                                     float* __restrict__ g_means, float* __restrict__ g_scales,
+                                     float* __restrict__ g_quats, float* __restrict__ g_opac,
+                                     float* __restrict__ g_sh) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* a = acc + (long long)i * kAcc;
+  const float G[9] = {a[0], a[1], a[2], a[1], a[3], a[4], a[2], a[4], a[5]};
+  const float h[3] = {a[6], a[7], a[8]};
+  float s[3] = {scales[3 * i], scales[3 * i + 1], scales[3 * i + 2]};
+  float4 q = reinterpret_cast<const float4*>(quats)[i];
+  float R[9];
+  quat_to_rot(q, R);
+  // dL/ds_k = -G_kk / s_k
+  g_scales[3 * i] = -G[0] / s[0];
+  g_scales[3 * i + 1] = -G[4] / s[1];
+  g_scales[3 * i + 2] = -G[8] / s[2];
+  // dL/dmu = -R S^-1 h
+  float hs[3] = {h[0] / s[0], h[1] / s[1], h[2] / s[2]};
+  for (int r = 0; r < 3; r++) g_means[3 * i + r] = -(R[3 * r] * hs[0] + R[3 * r + 1] * hs[1] + R[3 * r + 2] * hs[2]);
+  // dL/dR = R S G S^-1
+  float X[9];  // S G S^-1
+  for (int l = 0; l < 3; l++)
+    for (int k = 0; k < 3; k++) X[3 * l + k] = s[l] * G[3 * l + k] / s[k];
+  float gR[9];
+  for (int j = 0; j < 3; j++)
+    for (int k = 0; k < 3; k++)
+      gR[3 * j + k] = R[3 * j] * X[k] + R[3 * j + 1] * X[3 + k] + R[3 * j + 2] * X[6 + k];
+  // through R(q/|q|):  R entries are quadratic in (w, x, y, z)
+  float qn = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w), iq = 1.0f / qn;
+  float w = q.x * iq, x = q.y * iq, y = q.z * iq, z = q.w * iq;
+  float gw = 2.f * (x * (gR[7] - gR[5]) + y * (gR[2] - gR[6]) + z * (gR[3] - gR[1]));
+  float gx = 2.f * (w * (gR[7] - gR[5]) + y * (gR[1] + gR[3]) + z * (gR[2] + gR[6]) - 2.f * x * (gR[4] + gR[8]));
+  float gy = 2.f * (w * (gR[2] - gR[6]) + x * (gR[1] + gR[3]) + z * (gR[5] + gR[7]) - 2.f * y * (gR[0] + gR[8]));
+  float gz = 2.f * (w * (gR[3] - gR[1]) + x * (gR[2] + gR[6]) + y * (gR[5] + gR[7]) - 2.f * z * (gR[0] + gR[4]));
+  float pdot = w * gw + x * gx + y * gy + z * gz;
+  reinterpret_cast<float4*>(g_quats)[i] =
+      make_float4((gw - w * pdot) * iq, (gx - x * pdot) * iq, (gy - y * pdot) * iq, (gz - z * pdot) * iq);
+  g_opac[i] = a[9];
+  float* gs = g_sh + (long long)i * K * 3;
+  for (int k = 0; k < K * 3; k++) gs[k] = 0.0f;
+}
+
+// K7b: SH colour of one camera -> dL/dbeta and dL/dmu through the view direction.
+template <int DEG>
+__global__ void sh_grad_kernel(int n, int cam_idx, DevCam cam, Thresholds th,
+                               const float* __restrict__ means, const float* __restrict__ sh,
+                               const float* __restrict__ rgb, const float* __restrict__ acc_rgb,
+                               float* __restrict__ g_means, float* __restrict__ g_sh) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  long long e = (long long)cam_idx * n + i;
+  float gr[3] = {acc_rgb[3 * e], acc_rgb[3 * e + 1], acc_rgb[3 * e + 2]};
+  bool live[3];
+  for (int c = 0; c < 3; c++) live[c] = gr[c] != 0.0f && rgb[3 * e + c] > 0.0f;
+  if (!live[0] && !live[1] && !live[2]) return;
+  float3 mu = f3(means[3 * i], means[3 * i + 1], means[3 * i + 2]);
+  float t0 = 0.0f;
+  if (cam.shutter == GUT_ROLLING_TOP_TO_BOTTOM) {  // exposure time of the mean, as in K1
+    float2 vv;
+    bool ok;
+    t0 = solve_project(cam, cam0_coords(cam, mu), th, &vv, &ok);
+  }
+  float3 ctr = centre_at(cam, t0);
+  float3 dv = f3(mu.x - ctr.x, mu.y - ctr.y, mu.z - ctr.z);
+  float dist = sqrtf(dot3f(dv, dv)), id = 1.0f / dist;
+  float3 d = f3(dv.x * id, dv.y * id, dv.z * id);
+  float Y[K];
+  float3 dY[K];
+  sh_basis<DEG>(d.x, d.y, d.z, Y);
+  sh_basis_grad<DEG>(d.x, d.y, d.z, dY);
+  const float* b = sh + (long long)i * K * 3;
+  float* gs = g_sh + (long long)i * K * 3;
+  float3 gd = f3(0.f, 0.f, 0.f);
+  for (int c = 0; c < 3; c++) {
+    if (!live[c]) continue;
+    for (int k = 0; k < K; k++) {
+      gs[3 * k + c] += gr[c] * Y[k];
+      float bb = gr[c] * b[3 * k + c];
+      gd = f3(gd.x + bb * dY[k].x, gd.y + bb * dY[k].y, gd.z + bb * dY[k].z);
+    }
+  }
+  float pdd = dot3f(gd, d);
+  g_means[3 * i] += (gd.x - d.x * pdd) * id;
+  g_means[3 * i + 1] += (gd.y - d.y * pdd) * id;
+  g_means[3 * i + 2] += (gd.z - d.z * pdd) * id;
+}
+
+__global__ void zero_f32_kernel(float* __restrict__ p, long long m) {
+  long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < m) p[j] = 0.0f;
+}
+
+}  // namespace gut
+
+using namespace gut;
+
+extern "C" size_t gut_render_bwd_workspace_bytes(int64_t n, int32_t n_cams) {
+  if (n < 0 || n_cams <= 0) return 0;
+  size_t a = ((size_t)n * kAcc * 4 + 255) & ~size_t(255);
+  return a + (size_t)n * n_cams * 3 * 4 + 256;
+}
+
+extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected* proj,
+                                     const uint32_t* tile_ranges, const uint32_t* sorted_ids,
+                                     const gut_camera* cams, int32_t n_cams, const gut_params* p,
+                                     const float* rgb, const float* T_final,
+                                     const uint32_t* n_contrib, const float* d_rgb,
+                                     const float* d_T, float* g_means, float* g_scales,
+                                     float* g_quats, float* g_opacities, float* g_sh, void* ws,
+                                     size_t ws_bytes, void* stream) {
+  gut_status st = check_params(p);
+  if (st != GUT_OK) return st;
+  if ((st = check_scene(scene, true)) != GUT_OK) return st;
+  if (!proj || !proj->record || !proj->rgb || !tile_ranges || !rgb || !T_final || !n_contrib ||
+      !d_rgb || !g_means || !g_scales || !g_quats || !g_opacities || !g_sh) {
+    set_error("gut_render_bwd: a required pointer is NULL");
+    return GUT_E_INVALID;
+  }
+  if (((uintptr_t)proj->record & 15) || ((uintptr_t)scene->quats & 15) ||
+      ((uintptr_t)g_quats & 15) || ((uintptr_t)tile_ranges & 7)) {
+    set_error("record, quats, g_quats must be 16-byte and tile_ranges 8-byte aligned");
+    return GUT_E_INVALID;
+  }
+  const int64_t n = scene->n;
+  if (n * (int64_t)n_cams >= (int64_t(1) << 31)) {
+    set_error("n * n_cams must be below 2^31");
+    return GUT_E_INVALID;
+  }
+  size_t need = gut_render_bwd_workspace_bytes(n, n_cams);
+  if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) {
+    set_error("workspace must be 256-byte aligned and hold %zu bytes", need);
+    return GUT_E_INVALID;
+  }
+  DevCam dc[kMaxCams];
+  if ((st = prepare_cams(cams, n_cams, *p, dc, nullptr, nullptr)) != GUT_OK) return st;
+  if (n == 0) return GUT_OK;
+  hipStream_t s = (hipStream_t)stream;
+  float* acc = (float*)ws;
+  float* acc_rgb = (float*)((char*)ws + (((size_t)n * kAcc * 4 + 255) & ~size_t(255)));
+  long long m1 = n * kAcc, m2 = n * n_cams * 3;
+  zero_f32_kernel<<<(unsigned)((m1 + 255) / 256), 256, 0, s>>>(acc, m1);
+  GUT_LAUNCH_CHECK();
+  zero_f32_kernel<<<(unsigned)((m2 + 255) / 256), 256, 0, s>>>(acc_rgb, m2);
+  GUT_LAUNCH_CHECK();
+  Thresholds th = make_thresholds(*p);
+  for (int c = 0; c < n_cams; c++) {
+    dim3 grid(dc[c].tiles_x * dc[c].tiles_y), block(kTilePix);
+    if (dc[c].shutter == GUT_ROLLING_TOP_TO_BOTTOM)
+      render_bwd_kernel<true><<<grid, block, 0, s>>>(
+          dc[c], th, (int)n, c, (const uint2*)tile_ranges, sorted_ids,
+          (const float4*)proj->record, proj->rgb, rgb, T_final, n_contrib, d_rgb, d_T, acc, acc_rgb);
+    else
+      render_bwd_kernel<false><<<grid, block, 0, s>>>(
+          dc[c], th, (int)n, c, (const uint2*)tile_ranges, sorted_ids,
+          (const float4*)proj->record, proj->rgb, rgb, T_final, n_contrib, d_rgb, d_T, acc, acc_rgb);
+    GUT_LAUNCH_CHECK();
+  }
+  const int K = (scene->sh_degree + 1) * (scene->sh_degree + 1);
+  dim3 g1((unsigned)((n + 255) / 256)), b1(256);
+  particle_grad_kernel<<<g1, b1, 0, s>>>((int)n, K, scene->scales, scene->quats, acc, g_means,
+                                         g_scales, g_quats, g_opacities, g_sh);
+  GUT_LAUNCH_CHECK();
+  for (int c = 0; c < n_cams; c++) {
+#define GUT_SHG(D)                                                                          \
+  sh_grad_kernel<D><<<g1, b1, 0, s>>>((int)n, c, dc[c], th, scene->means, scene->sh, proj->rgb, \
+                                      acc_rgb, g_means, g_sh)
+    switch (scene->sh_degree) {
+      case 0: GUT_SHG(0); break;
+      case 1: GUT_SHG(1); break;
+      case 2: GUT_SHG(2); break;
+      default: GUT_SHG(3); break;
+    }
+#undef GUT_SHG
+    GUT_LAUNCH_CHECK();
+  }
+  return GUT_OK;
+}

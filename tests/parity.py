@@ -1,0 +1,180 @@
+"""Helpers that compare the HIP path with the FP64 oracle (test infrastructure).
+
+Decisions that FP32 and FP64 may take differently (a particle's alpha within
+1e-6 of alpha_min, a transmittance within 1e-4 relative of t_min, a
+rectangle edge within 2e-3 px of a tile boundary, a sigma point on the
+validity boundary, a depth near-tie, a pixel on the fisheye image circle) are
+reported by the oracle as alternatives: the render it gets when that one
+decision goes the other way.  A GPU pixel passes if it matches the oracle's
+primary render or one of those alternatives within the tolerance, so no pixel
+is excluded from the check.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle as O
+from paper_2412_12507_amd import raster as R
+
+TOL_PIX = 1e-4   # max abs error per pixel channel, RGB in [0, 1] (and for T_final)
+
+
+def to_torch_scene(scene):
+    return R.GaussianScene.from_host(scene)
+
+
+def gpu_forward(scene, cams, params=None, with_eval=True, debug=True):
+    gs = to_torch_scene(scene)
+    proj = R.project(gs, cams, params, debug=debug)
+    bins = R.bin_tiles(proj, cams, params)
+    img = R.render(proj, bins, cams, params, with_eval=with_eval)
+    torch.cuda.synchronize()
+    return gs, proj, bins, img
+
+
+def image_np(img, cam_index=0):
+    rgb = img.images("rgb")[cam_index].cpu().numpy().astype(np.float64)
+    T = img.images("T")[cam_index].cpu().numpy().astype(np.float64)
+    nc = img.images("n_contrib")[cam_index].cpu().numpy()
+    ne = img.images("n_eval")[cam_index].cpu().numpy() if img.n_eval is not None else None
+    return rgb, T, nc, ne
+
+
+def compare_pixels(gpu, ora, cam, params=None, tol=TOL_PIX):
+    """gpu: (rgb[H,W,3], T[H,W], nc[H,W], ne[H,W]); ora: oracle render result
+    (any tile list).  Returns a report dict."""
+    p = params or O.default_params()
+    ts = p["tile"]
+    tx, _ = O.tiles_xy(cam, p)
+    rgb, T, nc, ne = gpu
+    tiles = ora["tiles"]
+    H, W = cam["height"], cam["width"]
+    n_fail = n_alt_used = n_checked = 0
+    worst_primary = 0.0
+    fails = []
+    for slot, t in enumerate(tiles):
+        ty, txi = divmod(int(t), tx)
+        for ly in range(ts):
+            py = ty * ts + ly
+            if py >= H:
+                continue
+            for lx in range(ts):
+                px = txi * ts + lx
+                if px >= W:
+                    continue
+                k = slot * ts * ts + ly * ts + lx
+                n_checked += 1
+                g = (rgb[py, px], T[py, px], int(nc[py, px]), int(ne[py, px]) if ne is not None else None)
+
+                def match(orgb, oT, onc, one):
+                    err = max(np.abs(g[0] - orgb).max(), abs(g[1] - oT))
+                    ok = err <= tol and g[2] == onc and (g[3] is None or g[3] == one)
+                    return ok, err
+
+                ok, err = match(ora["rgb"][k], ora["T"][k], ora["n_contrib"][k], ora["n_eval"][k])
+                if ok:
+                    worst_primary = max(worst_primary, err)
+                    continue
+                found = False
+                for a in range(int(ora["n_alt"][k]) if "n_alt" in ora else 0):
+                    ok2, _ = match(ora["alt_rgb"][k, a], ora["alt_T"][k, a], ora["alt_nc"][k, a],
+                                   ora["alt_ne"][k, a])
+                    if ok2:
+                        found = True
+                        break
+                if found:
+                    n_alt_used += 1
+                else:
+                    n_fail += 1
+                    if len(fails) < 10:
+                        fails.append(dict(px=px, py=py, err=float(err), gpu_nc=g[2],
+                                          ora_nc=int(ora["n_contrib"][k]), gpu_ne=g[3],
+                                          ora_ne=int(ora["n_eval"][k]), n_alt=int(ora["n_alt"][k]),
+                                          n_amb=int(ora["n_amb"][k])))
+    return dict(n_checked=n_checked, n_fail=n_fail, n_alt_used=n_alt_used,
+                worst_primary=worst_primary, fails=fails)
+
+
+def compare_projection(gproj, pr, cam_index, n, amb=None, params=None):
+    """Per-particle parity of gut_project against the oracle's projection."""
+    a = amb or O.default_amb()
+    p = params or O.default_params()
+    sl = slice(cam_index * n, (cam_index + 1) * n)
+    tiles = gproj.tiles[sl].cpu().numpy().astype(np.int64)
+    rect = gproj.rect[sl].cpu().numpy().astype(np.int64)
+    depth = gproj.depth[sl].cpu().numpy().astype(np.float64)
+    rgb = gproj.rgb[sl].cpu().numpy().astype(np.float64)
+    vis_g = tiles > 0
+    vis_o = pr["cull"] == 0
+    e = pr["edge"]
+    ts = p["tile"]
+    frac = np.abs(e / ts - np.round(e / ts)) * ts
+    edge_amb = (frac < a["edge"]).any(axis=1)
+    valid_amb = np.abs(pr["valid_margin"]) < a["valid"]
+    amb_any = edge_amb | valid_amb
+    rep = {}
+    mism = vis_g != vis_o
+    rep["cull_mismatch_unexplained"] = int((mism & ~amb_any).sum())
+    rep["cull_mismatch_ambiguous"] = int((mism & amb_any).sum())
+    both = vis_g & vis_o
+    rect_bad = (rect[both] != pr["rect"][both]).any(axis=1)
+    rep["rect_mismatch_unexplained"] = int((rect_bad & ~edge_amb[both]).sum())
+    rep["tiles_mismatch_unexplained"] = int(((tiles[both] != pr["tiles"][both]) & ~edge_amb[both]).sum())
+    rep["depth_rel_err"] = float((np.abs(depth[both] - pr["depth"][both]) / pr["depth"][both]).max()) if both.any() else 0.0
+    rep["rgb_abs_err"] = float(np.abs(rgb[both] - pr["rgb"][both]).max()) if both.any() else 0.0
+    if gproj.mean2d is not None:
+        m = gproj.mean2d[sl].cpu().numpy().astype(np.float64)
+        c = gproj.cov2d[sl].cpu().numpy().astype(np.float64)
+        rep["mean_abs_err_px"] = float(np.abs(m[both] - pr["mean2d"][both]).max()) if both.any() else 0.0
+        scale = np.maximum(pr["cov2d"][both][:, [0, 2]].max(axis=1), 1e-12)
+        rep["cov_rel_err"] = float((np.abs(c[both] - pr["cov2d"][both]).max(axis=1) / scale).max()) if both.any() else 0.0
+        # implied error of the rectangle edges v +/- k sqrt(cov), k <= k_sigma_max
+        k = p["k_sigma_max"]
+        dh = np.abs(np.sqrt(np.maximum(c[both][:, [0, 2]], 0)) - np.sqrt(pr["cov2d"][both][:, [0, 2]]))
+        rep["edge_err_px"] = float((np.abs(m[both] - pr["mean2d"][both]) + k * dh).max()) if both.any() else 0.0
+    rep["n_visible"] = int(vis_o.sum())
+    return rep
+
+
+def compare_bins(bins, ob, pr, cam_index, n, tile_base, n_tiles, depth_tol=1e-6):
+    """Per-tile lists: the GPU list must hold every decided member of the
+    oracle's list, nothing outside it, and be ordered by (depth, id) up to
+    depth near-ties."""
+    ranges = bins.ranges.cpu().numpy().astype(np.int64)
+    ids = bins.ids[: max(bins.n_pairs, 1)].cpu().numpy().astype(np.int64)
+    ts, oids, ofl = ob
+    bad = []
+    for t in range(n_tiles):
+        g0, g1 = ranges[tile_base + t]
+        glist = ids[g0:g1] - cam_index * n if g1 > g0 else np.zeros(0, np.int64)
+        olist = oids[ts[t]:ts[t + 1]]
+        ofl_t = ofl[ts[t]:ts[t + 1]]
+        decided = set(olist[(ofl_t & 2) == 0][(ofl_t[(ofl_t & 2) == 0] & 1) == 1].tolist())
+        allowed = set(olist.tolist())
+        gs = set(glist.tolist())
+        if not decided <= gs or not gs <= allowed or len(gs) != len(glist):
+            bad.append((t, "membership"))
+            continue
+        d = pr["depth"][glist]
+        inv = d[1:] < d[:-1] * (1 - depth_tol)
+        if inv.any():
+            bad.append((t, "order"))
+    return bad
+
+
+def grad_compare(g_gpu, g_ora):
+    """Per tensor: max |dg| / max |g_ora|, and the element-wise check
+    |dg_i| <= 1e-3 max(|g_i|, 1e-3 max|g|)."""
+    out = {}
+    for k in g_ora:
+        a = g_gpu[k].detach().cpu().numpy().astype(np.float64).reshape(g_ora[k].shape)
+        b = g_ora[k]
+        m = np.abs(b).max()
+        rel = np.abs(a - b).max() / m if m > 0 else np.abs(a).max()
+        elem = np.abs(a - b) <= 1e-3 * np.maximum(np.abs(b), 1e-3 * m) + 1e-30
+        bad = np.argsort(-(np.abs(a - b) / np.maximum(np.abs(b), 1e-3 * m)).reshape(-1))[:4]
+        worst = [(int(i), float(a.reshape(-1)[i]), float(b.reshape(-1)[i])) for i in bad
+                 if not elem.reshape(-1)[i]]
+        out[k] = dict(rel=float(rel), elem_fail=int((~elem).sum()), max=float(m), worst=worst)
+    return out

@@ -1,0 +1,125 @@
+"""The C ABI on the host: the library loads, exports every symbol the header
+declares, and rejects bad arguments before touching the GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gut_synth as G
+from paper_2412_12507_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "gut.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gut_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    lib = L.load()
+    syms = header_symbols()
+    assert len(syms) >= 18
+    missing = [s for s in syms if not hasattr(lib, s)]
+    assert not missing, missing
+    assert set(syms) == set(L.EXPORTS)
+
+
+def test_default_params_and_helpers():
+    lib = L.load()
+    p = L.params_struct()
+    assert p.ut_alpha == 1.0 and p.ut_beta == 2.0 and p.ut_kappa == 0.0
+    assert p.alpha_min == np.float32(1 / 255) and p.alpha_max == np.float32(0.99)
+    assert p.t_min == np.float32(1e-4) and p.tile == 16 and p.rs_iters == 3
+    cams = G.config2_cameras()
+    arr = L.camera_array(cams)
+    assert lib.gut_num_tiles(arr, 2, L.ref(p)) == 2 * 120 * 68
+    assert lib.gut_num_pixels(arr, 2) == 2 * 1920 * 1080
+    assert lib.gut_bin_workspace_bytes(1000, 1, 5000) > 5000 * 12
+    assert lib.gut_render_bwd_workspace_bytes(1000, 2) >= 1000 * 40 + 2000 * 12
+    assert lib.gut_status_string(2) == b"GUT_E_CAPACITY"
+
+
+def _scene_struct(n=10):
+    s = L.Scene()
+    s.n, s.sh_degree = n, 0
+    s.means = s.scales = s.quats = s.opacities = s.sh = 4096  # never dereferenced
+    return s
+
+
+def test_argument_validation_without_launch():
+    lib = L.load()
+    p = L.params_struct()
+    sc = _scene_struct()
+    out = L.Projected()
+    out.rect = out.tiles = out.depth = out.rgb = out.record = 4096
+    cam = G.config1()[1][0]
+    arr = L.camera_array([cam])
+    # NULL outputs
+    assert lib.gut_project(L.ref(sc), arr, 1, L.ref(p), L.ref(L.Projected()), None) == L.GUT_E_INVALID
+    # bad camera sizes / models / poses / intrinsics
+    for mut in (dict(width=0), dict(height=-3), dict(fx=0.0), dict(model="pinhole", fy=-1.0)):
+        bad = dict(cam, **mut)
+        st = lib.gut_project(L.ref(sc), L.camera_array([bad]), 1, L.ref(p), L.ref(out), None)
+        assert st == L.GUT_E_INVALID, mut
+    bad = dict(cam, R0=np.eye(3) * 2)
+    assert lib.gut_project(L.ref(sc), L.camera_array([bad]), 1, L.ref(p), L.ref(out), None) == L.GUT_E_INVALID
+    bad = dict(cam, t0=np.array([np.nan, 0, 0]))
+    assert lib.gut_project(L.ref(sc), L.camera_array([bad]), 1, L.ref(p), L.ref(out), None) == L.GUT_E_INVALID
+    c = L.camera_struct(cam)
+    c.model = 7
+    arr7 = (L.Camera * 1)(c)
+    assert lib.gut_project(L.ref(sc), arr7, 1, L.ref(p), L.ref(out), None) == L.GUT_E_INVALID
+    # fisheye with no valid field of view
+    fe = G.camera("fisheye", 64, 64, 20.0, k=[-1e14, 0, 0, 0])
+    assert lib.gut_project(L.ref(sc), L.camera_array([fe]), 1, L.ref(p), L.ref(out), None) == L.GUT_E_INVALID
+    # bad params
+    p2 = L.params_struct(dict(tile=8))
+    assert lib.gut_project(L.ref(sc), arr, 1, L.ref(p2), L.ref(out), None) == L.GUT_E_UNSUPPORTED
+    p3 = L.params_struct(dict(alpha_min=0.0))
+    assert lib.gut_project(L.ref(sc), arr, 1, L.ref(p3), L.ref(out), None) == L.GUT_E_INVALID
+    p4 = L.params_struct(dict(ut_alpha=0.0))
+    assert lib.gut_project(L.ref(sc), arr, 1, L.ref(p4), L.ref(out), None) == L.GUT_E_INVALID
+    # too many cameras, bad scene
+    assert lib.gut_project(L.ref(sc), arr, 0, L.ref(p), L.ref(out), None) == L.GUT_E_INVALID
+    sc.sh_degree = 4
+    assert lib.gut_project(L.ref(sc), arr, 1, L.ref(p), L.ref(out), None) == L.GUT_E_INVALID
+    sc.sh_degree = 0
+    sc.n = -1
+    assert lib.gut_project(L.ref(sc), arr, 1, L.ref(p), L.ref(out), None) == L.GUT_E_INVALID
+    msg = lib.gut_last_error().decode()
+    assert "scene size" in msg
+    # misaligned record
+    sc.n = 10
+    out.record = 4100
+    assert lib.gut_project(L.ref(sc), arr, 1, L.ref(p), L.ref(out), None) == L.GUT_E_INVALID
+
+
+def test_bin_and_render_validation_without_launch():
+    lib = L.load()
+    p = L.params_struct()
+    cam = G.config1()[1][0]
+    arr = L.camera_array([cam])
+    pj = L.Projected()
+    pj.rect = pj.tiles = pj.depth = pj.rgb = pj.record = 4096
+    # workspace too small / misaligned
+    st = lib.gut_bin(L.ref(pj), 10, arr, 1, L.ref(p), C.c_void_p(4096), 16, 100, C.c_void_p(4096),
+                     C.c_void_p(4096), None, None)
+    assert st == L.GUT_E_INVALID
+    need = lib.gut_bin_workspace_bytes(10, 1, 100)
+    st = lib.gut_bin(L.ref(pj), 10, arr, 1, L.ref(p), C.c_void_p(4097), need, 100, C.c_void_p(4096),
+                     C.c_void_p(4096), None, None)
+    assert st == L.GUT_E_INVALID
+    # render: NULL outputs
+    st = lib.gut_render(L.ref(pj), 10, C.c_void_p(4096), C.c_void_p(4096), arr, 1, L.ref(p), None,
+                        None, None, None, None)
+    assert st == L.GUT_E_INVALID
+    # bwd: workspace too small
+    sc = _scene_struct()
+    z = C.c_void_p(4096)
+    st = lib.gut_render_bwd(L.ref(sc), L.ref(pj), z, z, arr, 1, L.ref(p), z, z, z, z, None, z, z, z,
+                            z, z, z, 16, None)
+    assert st == L.GUT_E_INVALID
