@@ -1,0 +1,247 @@
+"""Benchmark of the 3DGUT rasterizer hot path on one MI355X.
+
+Step = one forward pass of the whole path (project -> bin -> render) over the
+1M-Gaussian clustered scene (SH degree 3) seen by two 1920x1080 cameras, a
+60-degree pinhole and a 180-degree OpenCV fisheye, issued as one two-camera
+batch.  value = rendered megapixels per second (2 x 1920 x 1080 per step),
+with the scene and all buffers resident in HBM; the step includes gut_bin's
+one host read-back of the pair count.
+
+Also reported on the same line:
+  roofline      the compositing kernel (the dominant one): algorithmic FP32
+                FLOPs (E_eval x 55, E_eval = list entries evaluated per pixel
+                up to its stop, counted by the kernel itself) per launch over
+                its average duration from HIP events on its stream, against
+                the chip's FP32 vector peak; plus HBM traffic from rocprofv3
+                counters when given (--traffic-json)
+  stages_ms     per-stage averages (events), Table-2 style
+  fwd_bwd_ms_per_view   forward + L1 loss + backward on the fisheye view
+                against a target rendered from parameters perturbed by
+                N(0, 0.01) (the differentiation workload)
+  cpu_baseline  the FP64 oracle on this host's cores, on a bounded sample
+                (full projection and binning, a time-boxed share of the tiles
+                rendered), extrapolated to Mpix/s
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+F_EVAL = 55            # FP32 FLOPs per (pixel, particle) evaluation (mul and add counted apart)
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bench_forward(gs, cams, steps, warmup, R, torch):
+    proj = R.alloc_projection(gs.n, len(cams), gs.means.device)
+    R.project(gs, cams, out=proj)
+    bins = R.bin_tiles(proj, cams)
+    img = R.alloc_image(cams, gs.means.device)
+    n_ev = 4
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(n_ev)] for _ in range(steps)]
+
+    def step(e=None):
+        if e: e[0].record()
+        R.project(gs, cams, out=proj)
+        if e: e[1].record()
+        R.bin_tiles(proj, cams, bins=bins)
+        if e: e[2].record()
+        R.render(proj, bins, cams, out=img)
+        if e: e[3].record()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(ev[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = np.array([[ev[k][i].elapsed_time(ev[k][i + 1]) for i in range(n_ev - 1)] for k in range(steps)])
+    # one extra, untimed render that counts evaluations per pixel
+    img_eval = R.render(proj, bins, cams, with_eval=True)
+    torch.cuda.synchronize()
+    e_eval = int(img_eval.n_eval.to(torch.int64).sum().item())
+    return dict(ms_per_step=(t1 - t0) * 1e3 / steps, stage_ms=st.mean(0), stage_p10=np.percentile(st, 10, 0),
+                stage_p90=np.percentile(st, 90, 0), e_eval=e_eval, n_pairs=bins.n_pairs,
+                n_visible=int((proj.tiles > 0).sum().item()), img=img)
+
+
+def bench_fwd_bwd(scene, cam, steps, warmup, R, G, torch):
+    """Forward + L1 loss + backward on one view, the differentiation workload."""
+    gs = R.GaussianScene.from_host(scene)
+    tgt_scene = R.GaussianScene.from_host(G.perturb_raw(scene, seed=3004))
+    _, _, timg = R.forward(tgt_scene, [cam])
+    target = timg.rgb.clone()
+    del tgt_scene, timg
+    proj = R.alloc_projection(gs.n, 1, gs.means.device)
+    R.project(gs, [cam], out=proj)
+    bins = R.bin_tiles(proj, [cam])
+    img = R.alloc_image([cam], gs.means.device)
+    grads = dict(means=torch.empty_like(gs.means), scales=torch.empty_like(gs.scales),
+                 quats=torch.empty_like(gs.quats), opacities=torch.empty_like(gs.opacities),
+                 sh=torch.empty_like(gs.sh))
+    ws = None
+    npx = target.shape[0] * 3
+
+    def step():
+        nonlocal ws
+        R.project(gs, [cam], out=proj)
+        R.bin_tiles(proj, [cam], bins=bins)
+        R.render(proj, bins, [cam], out=img)
+        d_rgb = torch.sign(img.rgb - target) / npx          # dL/dC of mean |C - C_target|
+        if ws is None:
+            from paper_2412_12507_amd import _lib as L
+            need = L.load().gut_render_bwd_workspace_bytes(gs.n, 1)
+            ws = torch.empty(need, dtype=torch.uint8, device=gs.means.device)
+        R.render_backward(gs, proj, bins, [cam], img, d_rgb, None, grads=grads, workspace=ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def cpu_baseline(scene, cam, budget_s, O):
+    """The FP64 oracle on this host: full projection and binning of the
+    pinhole view, then tiles rendered until the time budget is spent;
+    extrapolated to a full frame."""
+    p = O.default_params()
+    osc = O.OScene.from_scene(scene)
+    t0 = time.perf_counter()
+    pr = O.project(osc, cam, p)
+    t1 = time.perf_counter()
+    ob = O.bin_tiles(pr, cam, p)
+    t2 = time.perf_counter()
+    tx, ty = O.tiles_xy(cam, p)
+    order = np.random.default_rng(0).permutation(tx * ty).astype(np.int32)
+    done, t_render = 0, 0.0
+    while done < len(order) and t_render < budget_s:
+        chunk = order[done:done + 256]
+        a = time.perf_counter()
+        O.render(osc, pr, cam, ob, p, tiles=chunk, alternatives=False)
+        t_render += time.perf_counter() - a
+        done += len(chunk)
+    frac = done / len(order)
+    t_frame = (t1 - t0) + (t2 - t1) + t_render / frac
+    mpix = cam["width"] * cam["height"] / t_frame / 1e6
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=mpix, unit="Mpix/s", cores=threads, kind="oracle",
+                sample=f"1M-Gaussian pinhole 1920x1080 view: full FP64 projection "
+                       f"({t1 - t0:.1f} s) and binning ({t2 - t1:.1f} s), {done}/{len(order)} "
+                       f"tiles rendered ({t_render:.1f} s), extrapolated to one frame "
+                       f"({t_frame:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle rendering")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fwd-bwd", action="store_true")
+    ap.add_argument("--traffic-json", default=None,
+                    help="JSON with per-launch HBM bytes of the render kernel from rocprofv3 counters")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a 1 GiB device copy first (counter calibration)")
+    ap.add_argument("--n", type=int, default=1_000_000)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build renders on a single MI355X "
+              "(multi-GPU sharding is a design note, not implemented); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import gut_synth as G
+    from paper_2412_12507_amd import raster as R, _lib
+    _lib.load()
+    torch.cuda.set_device(0)
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    log("[bench] generating the 1M-Gaussian scene")
+    scene = G.config2_scene(args.n)
+    cams = G.config2_cameras()
+    gs = R.GaussianScene.from_host(scene)
+    torch.cuda.synchronize()
+    log("[bench] forward steps")
+    fw = bench_forward(gs, cams, args.steps, args.warmup, R, torch)
+    npx = sum(c["width"] * c["height"] for c in cams)
+    value = npx / (fw["ms_per_step"] * 1e-3) / 1e6
+    render_ms_per_launch = fw["stage_ms"][2] / len(cams)
+    flops_per_launch = fw["e_eval"] * F_EVAL / len(cams)
+    achieved = flops_per_launch / (render_ms_per_launch * 1e-3) / 1e12
+    traffic = None
+    if args.traffic_json and os.path.exists(args.traffic_json):
+        traffic = json.load(open(args.traffic_json)).get("render_kernel_bytes_per_launch")
+    roofline = dict(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                    frac=achieved / PEAK_FP32_TFLOPS, traffic=traffic,
+                    kernel="render_kernel (gut_render)",
+                    e_eval_per_launch=fw["e_eval"] / len(cams), flops_per_eval=F_EVAL,
+                    ms_per_launch=render_ms_per_launch)
+    del fw["img"]
+
+    fwd_bwd = None
+    if not args.no_fwd_bwd:
+        log("[bench] fwd+bwd on the fisheye view")
+        fwd_bwd = bench_fwd_bwd(scene, cams[1], max(3, args.steps // 2), 2, R, G, torch)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] oracle CPU baseline")
+        import oracle as O
+        cpu = cpu_baseline(scene, cams[0], args.cpu_budget, O)
+
+    out = {
+        "metric": "Mpix/s fwd, fwd+bwd ms/view @1M Gaussians; serving p50/p99 ms",
+        "value": value,
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": fw["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1M clustered Gaussians (SH degree 3), pinhole + 180-deg fisheye "
+                               "1920x1080, one two-camera batch per step",
+                   "n_gaussians": args.n, "views": 2, "width": 1920, "height": 1080},
+        "roofline": roofline,
+        "stages_ms": {"project": fw["stage_ms"][0], "bin": fw["stage_ms"][1],
+                      "render": fw["stage_ms"][2]},
+        "n_pairs": fw["n_pairs"],
+        "n_visible": fw["n_visible"],
+        "fwd_bwd_ms_per_view": fwd_bwd,
+        "serving": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
