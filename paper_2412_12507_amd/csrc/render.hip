@@ -1,83 +1,114 @@
 // K5 -- per-tile front-to-back compositing (Eq. 5) with each particle's
 // response evaluated in 3D at its maximum along the pixel ray (Eq. 11).
 //
-// One 256-thread block (4 wave64s) per 16x16 tile, one pixel per thread.  The
-// tile's sorted list is consumed in batches of 256: each thread gathers one
-// pair's 64-byte render record, forms the pair's FP64 tile-frame terms
-// (tile_eval.h) and stores them in LDS; then every thread walks the batch,
-// reading each pair as an LDS broadcast.  A thread stops when its
-// transmittance would fall below t_min; the block stops when no thread is
-// still going (__syncthreads_count).
+// One 128-thread block (2 wave64s) per 16x16 tile; each thread owns two
+// pixels, (x, y) and (x, y + 8), so every pair read from LDS serves two
+// evaluations.  The tile's sorted list is consumed in batches of 128: each
+// thread gathers one pair's 64-byte render record, forms the pair's FP64
+// tile-frame terms (tile_eval.h) and stores them in LDS; then every thread
+// walks the batch, reading each pair as an LDS broadcast.  The walk is
+// branch-free per pixel (predicated updates); a wave leaves the batch as soon
+// as all its pixels have stopped, and the block stops when no pixel is still
+// going.  Blocks are mapped to tiles so that each XCD gets a contiguous band.
 #include "tile_eval.h"
 
 namespace gut {
 
+constexpr int kRThreads = 128;
+constexpr int kRBatch = kRThreads;
+
 template <bool RS>
-__global__ void __launch_bounds__(kTilePix) render_kernel(
+__global__ void __launch_bounds__(kRThreads) render_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ ids, const float4* __restrict__ record,
     const float* __restrict__ rgb, float* __restrict__ out_rgb, float* __restrict__ out_T,
     uint32_t* __restrict__ out_nc, uint32_t* __restrict__ out_ne) {
   constexpr int S = Slots<RS>::N;
-  __shared__ float4 pd[kTilePix * S];
+  __shared__ float4 pd[kRBatch * S];
   __shared__ TileFrameD F;
-  __shared__ float red[12];
+  __shared__ float red[6];
 
-  const int tile = blockIdx.x;
+  const int ntiles = cam.tiles_x * cam.tiles_y;
+  const int tile = xcd_tile(blockIdx.x, ntiles);
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
   const int t = threadIdx.x;
-  const int px = tx * kTile + (t & (kTile - 1)), py = ty * kTile + t / kTile;
+  const int px = tx * kTile + (t & (kTile - 1));
+  const int py0 = ty * kTile + t / kTile;
   if (t == 0) tile_frame(cam, tx, ty, &F);
   __syncthreads();
-  const bool inside = px < cam.W && py < cam.H;
-  float u = 0.0f, v = 0.0f, dt = 0.0f;
-  bool active = inside && pixel_ray(cam, F, px, py, &u, &v, &dt);
+
+  bool inside[2], active[2];
+  float u[2] = {0.f, 0.f}, v[2] = {0.f, 0.f}, dt[2] = {0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < 2; k++) {
+    const int py = py0 + 8 * k;
+    inside[k] = px < cam.W && py < cam.H;
+    active[k] = inside[k] && pixel_ray(cam, F, px, py, &u[k], &v[k], &dt[k]);
+  }
   float umax, vmax, dtmax;
-  tile_bounds(u, v, dt, active, red, &umax, &vmax, &dtmax);
+  tile_bounds<2>(u, v, dt, active, red, &umax, &vmax, &dtmax);
 
   const uint2 rg = ranges[cam.tile_base + tile];
   const uint32_t len = rg.y - rg.x;
-  // Colour accumulates in FP64 (three FMAs per contributor) so that the
-  // backward can form suffix sums C - C_<=j without FP32 cancellation.
-  float T = 1.0f;
-  double C0 = 0.0, C1 = 0.0, C2 = 0.0;
-  uint32_t last = 0, nev = active ? len : 0u;
-  bool done = !active;
-  for (uint32_t b = 0; b < len; b += kTilePix) {
-    if (__syncthreads_count(!done) == 0) break;
+  // Colour accumulates in FP64 (three FMAs per contributing entry) so that
+  // the backward can form suffix sums C - C_<=j without FP32 cancellation.
+  float T[2] = {1.0f, 1.0f};
+  double C[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  uint32_t last[2] = {0u, 0u}, nev[2] = {active[0] ? len : 0u, active[1] ? len : 0u};
+  bool done[2] = {!active[0], !active[1]};
+  for (uint32_t b = 0; b < len; b += kRBatch) {
+    if (__syncthreads_count(!(done[0] && done[1])) == 0) break;
     if (b + t < len) {
       uint32_t e = ids[rg.x + b + t];
       pair_setup<RS>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n), F, cam, umax,
                      vmax, dtmax, &pd[t * S]);
     }
     __syncthreads();
-    const uint32_t cnt = min((uint32_t)kTilePix, len - b);
-    for (uint32_t q = 0; q < cnt && !done; q++) {
-      Eval ev;
-      if (!eval_pair<RS>(&pd[q * S], u, v, dt, th.alpha_min, th.alpha_max, &ev)) continue;
-      float Tn = T * (1.0f - ev.a);
-      if (Tn < th.t_min) {  // stop before adding (would leave T below t_min)
-        done = true;
-        nev = b + q + 1;
-        break;
-      }
-      const double wgt = (double)(ev.a * T);
+    const uint32_t cnt = min((uint32_t)kRBatch, len - b);
+    for (uint32_t q = 0; q < cnt; q++) {
+      if (__ballot(!(done[0] && done[1])) == 0ull) break;  // wave-uniform exit
       const float4* P = &pd[q * S];
-      C0 = fma(wgt, (double)P[1].w, C0);
-      C1 = fma(wgt, (double)P[2].w, C1);
-      C2 = fma(wgt, (double)P[3].w, C2);
-      T = Tn;
-      last = b + q + 1;
+      PairRegs<RS> r;
+      load_pair<RS>(P, r);
+      bool contrib[2];
+      float wgt[2];
+#pragma unroll
+      for (int k = 0; k < 2; k++) {
+        Eval ev;
+        eval_pair<RS>(r, P, u[k], v[k], dt[k], th.alpha_min, th.alpha_max, &ev);
+        const float Tn = T[k] * (1.0f - ev.a);
+        const bool live = ev.ok && !done[k];
+        const bool stop = live && Tn < th.t_min;  // stop before adding this particle
+        contrib[k] = live && !stop;
+        wgt[k] = contrib[k] ? ev.a * T[k] : 0.0f;
+        T[k] = contrib[k] ? Tn : T[k];
+        last[k] = contrib[k] ? b + q + 1 : last[k];
+        nev[k] = stop ? b + q + 1 : nev[k];
+        done[k] = done[k] || stop;
+      }
+      if (__ballot(contrib[0] || contrib[1]) != 0ull) {
+        const double c0 = r.p1.w, c1 = r.p2.w, c2 = r.p3.w;
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+          const double w = (double)wgt[k];
+          C[k][0] = fma(w, c0, C[k][0]);
+          C[k][1] = fma(w, c1, C[k][1]);
+          C[k][2] = fma(w, c2, C[k][2]);
+        }
+      }
     }
   }
-  if (inside) {
+#pragma unroll
+  for (int k = 0; k < 2; k++) {
+    if (!inside[k]) continue;
+    const int py = py0 + 8 * k;
     long long pix = cam.pixel_base + (long long)py * cam.W + px;
-    out_rgb[3 * pix] = (float)fma((double)T, (double)th.bg[0], C0);
-    out_rgb[3 * pix + 1] = (float)fma((double)T, (double)th.bg[1], C1);
-    out_rgb[3 * pix + 2] = (float)fma((double)T, (double)th.bg[2], C2);
-    out_T[pix] = T;
-    out_nc[pix] = last;
-    if (out_ne) out_ne[pix] = nev;
+    out_rgb[3 * pix] = (float)fma((double)T[k], (double)th.bg[0], C[k][0]);
+    out_rgb[3 * pix + 1] = (float)fma((double)T[k], (double)th.bg[1], C[k][1]);
+    out_rgb[3 * pix + 2] = (float)fma((double)T[k], (double)th.bg[2], C[k][2]);
+    out_T[pix] = T[k];
+    out_nc[pix] = last[k];
+    if (out_ne) out_ne[pix] = nev[k];
   }
 }
 
@@ -85,7 +116,7 @@ gut_status launch_render(const DevCam& cam, const Thresholds& th, int n, int cam
                          const uint32_t* ranges, const uint32_t* ids, const float* record,
                          const float* rgb, float* out_rgb, float* out_T, uint32_t* out_nc,
                          uint32_t* out_ne, hipStream_t s) {
-  dim3 grid(cam.tiles_x * cam.tiles_y), block(kTilePix);
+  dim3 grid(cam.tiles_x * cam.tiles_y), block(kRThreads);
   if (cam.shutter == GUT_ROLLING_TOP_TO_BOTTOM)
     render_kernel<true><<<grid, block, 0, s>>>(cam, th, n, cam_idx, (const uint2*)ranges, ids,
                                                (const float4*)record, rgb, out_rgb, out_T, out_nc,

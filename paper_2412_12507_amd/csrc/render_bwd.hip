@@ -36,8 +36,11 @@ __device__ inline float wave_sum(float x) {
   return x;
 }
 
+constexpr int kBwThreads = 128;
+constexpr int kBwBatch = kBwThreads;
+
 template <bool RS>
-__global__ void __launch_bounds__(kTilePix) render_bwd_kernel(
+__global__ void __launch_bounds__(kBwThreads) render_bwd_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ ids, const float4* __restrict__ record,
     const float* __restrict__ rgb, const float* __restrict__ out_rgb,
@@ -45,43 +48,51 @@ __global__ void __launch_bounds__(kTilePix) render_bwd_kernel(
     const float* __restrict__ d_rgb, const float* __restrict__ d_T, float* __restrict__ acc,
     float* __restrict__ acc_rgb) {
   constexpr int S = Slots<RS>::N;
-  __shared__ float4 pd[kTilePix * S];
-  __shared__ uint32_t pe[kTilePix];
+  __shared__ float4 pd[kBwBatch * S];
+  __shared__ uint32_t pe[kBwBatch];
   __shared__ TileFrameD F;
-  __shared__ float red[12];
+  __shared__ float red[6];
   __shared__ uint32_t maxlast_s;
 
-  const int tile = blockIdx.x;
+  const int ntiles = cam.tiles_x * cam.tiles_y;
+  const int tile = xcd_tile(blockIdx.x, ntiles);
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
   const int t = threadIdx.x, lane = t & 63;
-  const int px = tx * kTile + (t & (kTile - 1)), py = ty * kTile + t / kTile;
+  const int px = tx * kTile + (t & (kTile - 1));
+  const int py0 = ty * kTile + t / kTile;
   if (t == 0) { tile_frame(cam, tx, ty, &F); maxlast_s = 0; }
   __syncthreads();
-  const bool inside = px < cam.W && py < cam.H;
-  float u = 0.0f, v = 0.0f, dt = 0.0f;
-  bool active = inside && pixel_ray(cam, F, px, py, &u, &v, &dt);
-  float umax, vmax, dtmax;
-  tile_bounds(u, v, dt, active, red, &umax, &vmax, &dtmax);
 
-  uint32_t last = 0;
-  float TN = 1.0f, gC0 = 0, gC1 = 0, gC2 = 0, gT = 0;
-  double Co0 = 0, Co1 = 0, Co2 = 0;  // the output colour C = sum_j c_j alpha_j T_j + T_N bg
-  if (active) {
-    long long pix = cam.pixel_base + (long long)py * cam.W + px;
-    last = out_nc[pix];
-    TN = out_T[pix];
-    gC0 = d_rgb[3 * pix]; gC1 = d_rgb[3 * pix + 1]; gC2 = d_rgb[3 * pix + 2];
-    gT = d_T ? d_T[pix] : 0.0f;
-    Co0 = out_rgb[3 * pix]; Co1 = out_rgb[3 * pix + 1]; Co2 = out_rgb[3 * pix + 2];
+  bool active[2];
+  float u[2] = {0.f, 0.f}, v[2] = {0.f, 0.f}, dt[2] = {0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < 2; k++) {
+    const int py = py0 + 8 * k;
+    active[k] = px < cam.W && py < cam.H && pixel_ray(cam, F, px, py, &u[k], &v[k], &dt[k]);
   }
-  atomicMax(&maxlast_s, last);
+  float umax, vmax, dtmax;
+  tile_bounds<2>(u, v, dt, active, red, &umax, &vmax, &dtmax);
+
+  uint32_t last[2] = {0u, 0u};
+  float TN[2] = {1.f, 1.f}, gC[2][3] = {{0, 0, 0}, {0, 0, 0}}, gT[2] = {0.f, 0.f};
+  double Co[2][3] = {{0, 0, 0}, {0, 0, 0}};  // output colour C = sum c alpha T + T_N bg
+#pragma unroll
+  for (int k = 0; k < 2; k++) {
+    if (!active[k]) continue;
+    const long long pix = cam.pixel_base + (long long)(py0 + 8 * k) * cam.W + px;
+    last[k] = out_nc[pix];
+    TN[k] = out_T[pix];
+    for (int c = 0; c < 3; c++) { gC[k][c] = d_rgb[3 * pix + c]; Co[k][c] = out_rgb[3 * pix + c]; }
+    gT[k] = d_T ? d_T[pix] : 0.0f;
+  }
+  atomicMax(&maxlast_s, max(last[0], last[1]));
   __syncthreads();
   const uint2 rg = ranges[cam.tile_base + tile];
   const uint32_t maxlast = min(maxlast_s, rg.y - rg.x);  // never past the tile's list
 
-  float T = 1.0f;
-  double A0 = 0.0, A1 = 0.0, A2 = 0.0;  // running colour C_<=j, accumulated as in the forward
-  for (uint32_t b = 0; b < maxlast; b += kTilePix) {
+  float T[2] = {1.0f, 1.0f};
+  double A[2][3] = {{0, 0, 0}, {0, 0, 0}};  // running colour C_<=j, accumulated as in the forward
+  for (uint32_t b = 0; b < maxlast; b += kBwBatch) {
     __syncthreads();
     if (b + t < maxlast) {
       uint32_t e = ids[rg.x + b + t];
@@ -90,53 +101,69 @@ __global__ void __launch_bounds__(kTilePix) render_bwd_kernel(
                      vmax, dtmax, &pd[t * S]);
     }
     __syncthreads();
-    const uint32_t cnt = min((uint32_t)kTilePix, maxlast - b);
+    const uint32_t cnt = min((uint32_t)kBwBatch, maxlast - b);
     for (uint32_t q = 0; q < cnt; q++) {
+      const uint32_t idx = b + q;
+      if (__ballot(idx < last[0] || idx < last[1]) == 0ull) break;  // wave-uniform exit
+      const float4* P = &pd[q * S];
+      PairRegs<RS> r;
+      load_pair<RS>(P, r);
+      const float col[3] = {r.p1.w, r.p2.w, r.p3.w};
       float g[kAcc + 3];
 #pragma unroll
-      for (int k = 0; k < kAcc + 3; k++) g[k] = 0.0f;
-      bool hit = false;
-      Eval ev;
-      if (b + q < last && eval_pair<RS>(&pd[q * S], u, v, dt, th.alpha_min, th.alpha_max, &ev)) {
-        hit = true;
-        const float4* P = &pd[q * S];
-        const float c0 = P[1].w, c1 = P[2].w, c2 = P[3].w;
-        const float wgt = ev.a * T;
-        A0 = fma((double)wgt, (double)c0, A0);
-        A1 = fma((double)wgt, (double)c1, A1);
-        A2 = fma((double)wgt, (double)c2, A2);
-        const float inv1m = 1.0f / (1.0f - ev.a);
-        // (S_after + T_N bg) = C - C_<=j, formed in FP64
-        const float r0 = (float)(Co0 - A0), r1 = (float)(Co1 - A1), r2 = (float)(Co2 - A2);
-        float gA = gC0 * (c0 * T - r0 * inv1m) + gC1 * (c1 * T - r1 * inv1m) +
-                   gC2 * (c2 * T - r2 * inv1m) - gT * TN * inv1m;
-        g[kAcc] = wgt * gC0;
-        g[kAcc + 1] = wgt * gC1;
-        g[kAcc + 2] = wgt * gC2;
-        if (!ev.clamped) {
-          g[9] = gA * ev.ex;
-          const float c = -ev.a * gA;  // 2 dL/domega^2
-          float3 p = cross3f(ev.dg, ev.cr);
-          p = f3(p.x * ev.idd, p.y * ev.idd, p.z * ev.idd);
-          const float3 cp = f3(c * p.x, c * p.y, c * p.z);
-          g[0] = cp.x * p.x; g[1] = cp.x * p.y; g[2] = cp.x * p.z;
-          g[3] = cp.y * p.y; g[4] = cp.y * p.z; g[5] = cp.z * p.z;
-          g[6] = cp.x; g[7] = cp.y; g[8] = cp.z;
-        }
-        T = T * (1.0f - ev.a);
-      }
-      if (__ballot(hit) == 0ull) continue;  // wave-uniform
+      for (int j = 0; j < kAcc + 3; j++) g[j] = 0.0f;
+      bool hit[2];
+      float wgt[2], Tb[2];
 #pragma unroll
-      for (int k = 0; k < kAcc + 3; k++) g[k] = wave_sum(g[k]);
+      for (int k = 0; k < 2; k++) {
+        Eval ev;
+        eval_pair<RS>(r, P, u[k], v[k], dt[k], th.alpha_min, th.alpha_max, &ev);
+        hit[k] = ev.ok && idx < last[k];
+        Tb[k] = T[k];
+        wgt[k] = hit[k] ? ev.a * T[k] : 0.0f;
+        const float Tn = T[k] * (1.0f - ev.a);
+        T[k] = hit[k] ? Tn : T[k];
+        g[kAcc] += wgt[k] * gC[k][0];
+        g[kAcc + 1] += wgt[k] * gC[k][1];
+        g[kAcc + 2] += wgt[k] * gC[k][2];
+        // A_j includes this contributor: (S_after + T_N bg) = C - C_<=j, in FP64
+        double R0 = Co[k][0] - fma((double)wgt[k], (double)col[0], A[k][0]);
+        double R1 = Co[k][1] - fma((double)wgt[k], (double)col[1], A[k][1]);
+        double R2 = Co[k][2] - fma((double)wgt[k], (double)col[2], A[k][2]);
+        const float inv1m = 1.0f / (1.0f - ev.a);
+        float gA = gC[k][0] * (col[0] * Tb[k] - (float)R0 * inv1m) +
+                   gC[k][1] * (col[1] * Tb[k] - (float)R1 * inv1m) +
+                   gC[k][2] * (col[2] * Tb[k] - (float)R2 * inv1m) - gT[k] * TN[k] * inv1m;
+        const bool geo = hit[k] && !ev.clamped;  // alpha = alpha_max carries no gradient
+        gA = geo ? gA : 0.0f;
+        g[9] += gA * ev.ex;
+        const float c = -ev.a * gA;  // 2 dL/domega^2
+        float3 p = cross3f(ev.dg, ev.cr);
+        p = f3(p.x * ev.idd, p.y * ev.idd, p.z * ev.idd);
+        const float3 cp = f3(c * p.x, c * p.y, c * p.z);
+        g[0] += cp.x * p.x; g[1] += cp.x * p.y; g[2] += cp.x * p.z;
+        g[3] += cp.y * p.y; g[4] += cp.y * p.z; g[5] += cp.z * p.z;
+        g[6] += cp.x; g[7] += cp.y; g[8] += cp.z;
+      }
+      if (__ballot(hit[0] || hit[1]) == 0ull) continue;  // wave-uniform
+#pragma unroll
+      for (int k = 0; k < 2; k++) {
+        const double w = (double)wgt[k];
+        A[k][0] = fma(w, (double)col[0], A[k][0]);
+        A[k][1] = fma(w, (double)col[1], A[k][1]);
+        A[k][2] = fma(w, (double)col[2], A[k][2]);
+      }
+#pragma unroll
+      for (int j = 0; j < kAcc + 3; j++) g[j] = wave_sum(g[j]);
       if (lane == 0) {
         uint32_t e = pe[q];
         int i = (int)(e - (uint32_t)cam_idx * (uint32_t)n);
 #pragma unroll
-        for (int k = 0; k < kAcc; k++)
-          if (g[k] != 0.0f) atomicAdd(&acc[(long long)i * kAcc + k], g[k]);
+        for (int j = 0; j < kAcc; j++)
+          if (g[j] != 0.0f) atomicAdd(&acc[(long long)i * kAcc + j], g[j]);
 #pragma unroll
-        for (int k = 0; k < 3; k++)
-          if (g[kAcc + k] != 0.0f) atomicAdd(&acc_rgb[3 * (long long)e + k], g[kAcc + k]);
+        for (int j = 0; j < 3; j++)
+          if (g[kAcc + j] != 0.0f) atomicAdd(&acc_rgb[3 * (long long)e + j], g[kAcc + j]);
       }
     }
   }
@@ -292,7 +319,7 @@ extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected
   GUT_LAUNCH_CHECK();
   Thresholds th = make_thresholds(*p);
   for (int c = 0; c < n_cams; c++) {
-    dim3 grid(dc[c].tiles_x * dc[c].tiles_y), block(kTilePix);
+    dim3 grid(dc[c].tiles_x * dc[c].tiles_y), block(kBwThreads);
     if (dc[c].shutter == GUT_ROLLING_TOP_TO_BOTTOM)
       render_bwd_kernel<true><<<grid, block, 0, s>>>(
           dc[c], th, (int)n, c, (const uint2*)tile_ranges, sorted_ids,

@@ -129,57 +129,82 @@ __device__ inline void pair_setup(const float4* __restrict__ record, const float
 }
 
 struct Eval {
-  float a;      // alpha after the alpha_max clamp
+  float a;      // alpha after the alpha_max clamp (0 when the pair is skipped)
   float ex;     // exp(-omega^2 / 2)
-  float sig;    // opacity
+  bool ok;      // tau_max > 0 and alpha >= alpha_min
   bool clamped; // sigma * ex > alpha_max
   float3 dg, cr;
   float idd;    // 1 / |d_g|^2
 };
 
-// alpha of one pair on one pixel ray; false if tau_max <= 0 or alpha < alpha_min.
+// One pair's terms, loaded from LDS once and shared by the pixels a thread owns.
 template <bool RS>
-__device__ __forceinline__ bool eval_pair(const float4* P, float u, float v, float dt,
-                                          float amin, float amax, Eval* o) {
-  const float4 p0 = P[0], p1 = P[1], p2 = P[2], p3 = P[3], p4 = P[4], p5 = P[5];
-  float3 dg = f3(fmaf(v, p2.x, fmaf(u, p1.x, p0.x)), fmaf(v, p2.y, fmaf(u, p1.y, p0.y)),
-                 fmaf(v, p2.z, fmaf(u, p1.z, p0.z)));
-  float3 cr = f3(fmaf(v, p5.x, fmaf(u, p4.x, p3.x)), fmaf(v, p5.y, fmaf(u, p4.y, p3.y)),
-                 fmaf(v, p5.z, fmaf(u, p4.z, p3.z)));
-  float sig = p0.w;
+struct PairRegs {
+  float4 p0, p1, p2, p3, p4, p5;
+  float4 p7, p8, p9;
+  bool mixed;  // sign of o_g . d_g varies across the tile (wave-uniform)
+};
+
+template <bool RS>
+__device__ __forceinline__ void load_pair(const float4* P, PairRegs<RS>& r) {
+  r.p0 = P[0]; r.p1 = P[1]; r.p2 = P[2]; r.p3 = P[3]; r.p4 = P[4]; r.p5 = P[5];
+  if (RS) { r.p7 = P[7]; r.p8 = P[8]; r.p9 = P[9]; }
+  // every lane reads the same pair: move the flag to a scalar register
+  r.mixed = __builtin_amdgcn_readfirstlane(__float_as_int(r.p0.w)) < 0;
+}
+
+// alpha of one pair on one pixel ray (Eq. 11 and alpha = sigma rho), with no
+// divergent branches; o->ok is false if tau_max <= 0 or alpha < alpha_min.
+template <bool RS>
+__device__ __forceinline__ void eval_pair(const PairRegs<RS>& r, const float4* P, float u, float v,
+                                          float dt, float amin, float amax, Eval* o) {
+  float3 dg = f3(fmaf(v, r.p2.x, fmaf(u, r.p1.x, r.p0.x)), fmaf(v, r.p2.y, fmaf(u, r.p1.y, r.p0.y)),
+                 fmaf(v, r.p2.z, fmaf(u, r.p1.z, r.p0.z)));
+  float3 cr = f3(fmaf(v, r.p5.x, fmaf(u, r.p4.x, r.p3.x)), fmaf(v, r.p5.y, fmaf(u, r.p4.y, r.p3.y)),
+                 fmaf(v, r.p5.z, fmaf(u, r.p4.z, r.p3.z)));
   if (RS) {
-    const float4 p7 = P[7], p8 = P[8], p9 = P[9];
-    float3 m = f3(fmaf(v, p9.x, fmaf(u, p8.x, p7.x)), fmaf(v, p9.y, fmaf(u, p8.y, p7.y)),
-                  fmaf(v, p9.z, fmaf(u, p8.z, p7.z)));
+    float3 m = f3(fmaf(v, r.p9.x, fmaf(u, r.p8.x, r.p7.x)), fmaf(v, r.p9.y, fmaf(u, r.p8.y, r.p7.y)),
+                  fmaf(v, r.p9.z, fmaf(u, r.p8.z, r.p7.z)));
     cr = f3(fmaf(dt, m.x, cr.x), fmaf(dt, m.y, cr.y), fmaf(dt, m.z, cr.z));
   }
-  if (sig < 0.0f) {  // rare: the sign of o_g . d_g varies across the tile
-    float sg = fmaf(v, P[6].x, fmaf(u, p5.w, p4.w));
-    if (RS) sg = fmaf(dt, fmaf(v, P[9].w, fmaf(u, P[8].w, P[7].w)), sg);
-    if (sg >= 0.0f) return false;
-    sig = -sig;
+  bool ok = true;
+  if (r.mixed) {  // rare, and uniform across the wave
+    float sg = fmaf(v, P[6].x, fmaf(u, r.p5.w, r.p4.w));
+    if (RS) sg = fmaf(dt, fmaf(v, r.p9.w, fmaf(u, r.p8.w, r.p7.w)), sg);
+    ok = sg < 0.0f;
   }
+  const float sig = fabsf(r.p0.w);
   float dd = fmaf(dg.z, dg.z, fmaf(dg.y, dg.y, dg.x * dg.x));
   float cc = fmaf(cr.z, cr.z, fmaf(cr.y, cr.y, cr.x * cr.x));
   float idd = __builtin_amdgcn_rcpf(dd);
-  float ex = __expf(-0.5f * (cc * idd));
+  // exp(-omega^2/2) = 2^(-omega^2 log2(e) / 2)
+  float ex = __builtin_amdgcn_exp2f((cc * idd) * -0.72134752044448170f);
   float araw = sig * ex;
   float a = fminf(araw, amax);
-  if (!(a >= amin)) return false;
-  o->a = a;
+  ok = ok && (a >= amin);
+  o->a = ok ? a : 0.0f;
   o->ex = ex;
-  o->sig = sig;
+  o->ok = ok;
   o->clamped = araw > amax;
   o->dg = dg;
   o->cr = cr;
   o->idd = idd;
-  return true;
 }
 
-// Block-wide maxima of |u|, |v|, |dt| over the tile's valid pixels.
-__device__ inline void tile_bounds(float u, float v, float dt, bool valid, float* red,
-                                   float* umax, float* vmax, float* dtmax) {
-  float a = valid ? fabsf(u) : 0.0f, b = valid ? fabsf(v) : 0.0f, c = valid ? fabsf(dt) : 0.0f;
+// Block-wide maxima of |u|, |v|, |dt| over the tile's valid pixels (NP per thread).
+template <int NP>
+__device__ inline void tile_bounds(const float* u, const float* v, const float* dt,
+                                   const bool* valid, float* red, float* umax, float* vmax,
+                                   float* dtmax) {
+  float a = 0.0f, b = 0.0f, c = 0.0f;
+#pragma unroll
+  for (int k = 0; k < NP; k++) {
+    if (valid[k]) {
+      a = fmaxf(a, fabsf(u[k]));
+      b = fmaxf(b, fabsf(v[k]));
+      c = fmaxf(c, fabsf(dt[k]));
+    }
+  }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     a = fmaxf(a, __shfl_xor(a, o, 64));
@@ -199,6 +224,17 @@ __device__ inline void tile_bounds(float u, float v, float dt, bool valid, float
   *umax = A * 1.0001f + 1e-7f;
   *vmax = B * 1.0001f + 1e-7f;
   *dtmax = Cc * 1.0001f + 1e-7f;
+}
+
+// Tile visited by block b: blocks are dealt round-robin to the 8 XCDs, so
+// give each XCD a contiguous run of tiles (neighbouring tiles share most of
+// their particles, and each XCD has its own L2).
+__device__ inline int xcd_tile(int b, int n) {
+  const int nx = 8;
+  int x = b % nx, j = b / nx;
+  int q = n / nx, r = n % nx;
+  int start = x * q + min(x, r);
+  return start + j;
 }
 
 }  // namespace gut
