@@ -119,6 +119,69 @@ def bench_fwd_bwd(scene, cam, steps, warmup, R, G, torch):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
+def bench_serving(n_requests, rates, R, G, torch, n_particles=3_000_000, warm=8):
+    """Serving workload: the 3M-Gaussian scene resident in HBM, Poisson
+    arrivals of requests with 1-8 cameras (half pinhole 640x480..3840x2160,
+    half 1600x1200 rolling-shutter fisheye).  The baseline renders the same
+    trace one request at a time, cameras one after another, synchronously;
+    its latencies at a given arrival rate follow from its measured service
+    times by the FIFO recursion start = max(arrival, previous finish)."""
+    from paper_2412_12507_amd.serve import Server, render_sequential
+    scene = G.config3_scene(n_particles)
+    gs = R.GaussianScene.from_host(scene)
+    reqs = G.config5_requests(n_requests + warm, seed=3005)
+    warm_reqs, reqs = reqs[:warm], reqs[warm:]
+    for cams in warm_reqs:
+        render_sequential(gs, cams)
+    service = []
+    for cams in reqs:
+        t = time.perf_counter()
+        render_sequential(gs, cams)
+        service.append(time.perf_counter() - t)
+    service = np.array(service)
+    cap = 1.0 / service.mean()
+    n_cams = np.array([len(c) for c in reqs])
+    out = dict(capacity_req_per_s=cap, mean_cameras_per_request=float(n_cams.mean()), rates=[])
+    srv = Server(gs, mem_budget_bytes=48 << 30, max_slots=4, max_batch_cams=8)
+    try:
+        for cams in warm_reqs:
+            rid, _ = srv.submit(cams)
+            srv.wait(rid)
+        for f in rates:
+            lam = f * cap
+            arr = G.poisson_arrivals(len(reqs), lam, seed=3005 + int(100 * f))
+            # sequential server at these arrivals
+            fin, lat = 0.0, []
+            for a, sv in zip(arr, service):
+                start = max(a, fin)
+                fin = start + sv
+                lat.append(fin - a)
+            lat = np.array(lat) * 1e3
+            seq = dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                       frames_per_s=float(n_cams.sum() / fin))
+            srv.reset_stats()
+            t0 = time.perf_counter()
+            ids = []
+            for a, cams in zip(arr, reqs):
+                d = t0 + a - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                ids.append(srv.submit(cams)[0])
+            for rid in ids:
+                srv.wait(rid)
+            st = srv.stats()
+            out["rates"].append(dict(load=f, arrival_req_per_s=lam,
+                                     server=dict(p50_ms=st["p50_ms"], p99_ms=st["p99_ms"],
+                                                 frames_per_s=st["frames_per_s"],
+                                                 batches=st["batches"]),
+                                     sequential=seq))
+            log(f"[bench] serving load {f}: server p50 {st['p50_ms']:.1f} p99 {st['p99_ms']:.1f} ms, "
+                f"{st['frames_per_s']:.0f} fps; sequential p50 {seq['p50_ms']:.1f} p99 {seq['p99_ms']:.1f}")
+    finally:
+        srv.close()
+    return out
+
+
 def cpu_baseline(scene, cam, budget_s, O):
     """The FP64 oracle on this host: full projection and binning of the
     pinhole view, then tiles rendered until the time budget is spent;
@@ -163,6 +226,10 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration)")
     ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-loads", default="0.5,0.9,1.5,3.0",
+                    help="arrival rates as fractions of the sequential baseline's capacity")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build renders on a single MI355X "
@@ -209,6 +276,17 @@ def main():
         log("[bench] fwd+bwd on the fisheye view")
         fwd_bwd = bench_fwd_bwd(scene, cams[1], max(3, args.steps // 2), 2, R, G, torch)
 
+    serving = None
+    if not args.no_serve:
+        log("[bench] serving")
+        del gs
+        torch.cuda.empty_cache()
+        serving = bench_serving(args.serve_requests, [float(x) for x in args.serve_loads.split(",")],
+                                R, G, torch)
+        top = max(serving["rates"], key=lambda r: r["load"])
+        serving["p50_ms"] = top["server"]["p50_ms"]
+        serving["p99_ms"] = top["server"]["p99_ms"]
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] oracle CPU baseline")
@@ -237,7 +315,7 @@ def main():
         "n_pairs": fw["n_pairs"],
         "n_visible": fw["n_visible"],
         "fwd_bwd_ms_per_view": fwd_bwd,
-        "serving": None,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

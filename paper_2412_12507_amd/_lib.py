@@ -114,10 +114,9 @@ def load():
         "gut_serve_destroy": [vp],
     }
     for name, args in serve_sigs.items():
-        if hasattr(L, name):
-            f = getattr(L, name)
-            f.argtypes = args
-            f.restype = st
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = st
     L.gut_status_string.argtypes = [st]
     L.gut_status_string.restype = C.c_char_p
     L.gut_last_error.argtypes = []

@@ -31,14 +31,18 @@ struct CamTiles {
 
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Workspace layout of gut_bin.
-struct BinLayout {
-  size_t vis_part, vis_scan, vis_tmp, scalars, dkA, dvA, dkB, dvB, cnt, offs, offs_tmp, pkA,
-      pkB, pvB, radix_tmp, total;
+// Workspace of the entry phase (sized by E = n_cams * n) and of the pair
+// phase (sized by the pair capacity).
+struct EntryLayout {
+  size_t vis_part, vis_scan, vis_tmp, scalars, dkA, dvA, dkB, dvB, cnt, offs, offs_tmp, radix_tmp,
+      total;
+};
+struct PairLayout {
+  size_t pkA, pkB, pvB, radix_tmp, total;
 };
 
-static BinLayout bin_layout(int64_t E, int64_t cap) {
-  BinLayout L;
+static EntryLayout entry_layout(int64_t E) {
+  EntryLayout L;
   int64_t nb = (E + kBChunk - 1) / kBChunk;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o += al(bytes); return r; };
@@ -53,14 +57,25 @@ static BinLayout bin_layout(int64_t E, int64_t cap) {
   L.cnt = take(E * 4);
   L.offs = take(E * 4);
   L.offs_tmp = take(scan_temp_bytes(E));
-  L.pkA = take(cap * 4);
-  L.pkB = take(cap * 4);
-  L.pvB = take(cap * 4);
-  int64_t mx = E > cap ? E : cap;
-  L.radix_tmp = take(radix_temp_bytes(mx));
+  L.radix_tmp = take(radix_temp_bytes(E));
   L.total = o;
   return L;
 }
+
+static PairLayout pair_layout(int64_t cap) {
+  PairLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += al(bytes); return r; };
+  L.pkA = take(cap * 4);
+  L.pkB = take(cap * 4);
+  L.pvB = take(cap * 4);
+  L.radix_tmp = take(radix_temp_bytes(cap));
+  L.total = o;
+  return L;
+}
+
+size_t bin_entry_bytes(int64_t E) { return entry_layout(E).total; }
+size_t bin_pair_bytes(int64_t cap) { return pair_layout(cap).total; }
 
 __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t* total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -204,13 +219,83 @@ gut_status fill_u32(uint32_t* p, int64_t m, uint32_t v, hipStream_t st) {
   return GUT_OK;
 }
 
+// Phase 1: compaction of the visible entries into (depth bits, id) and the
+// pair total; reads back (N_vis, P) -- the one host synchronisation.
+gut_status bin_count(const gut_projected* proj, int64_t E, char* ews, uint32_t* nvis_out,
+                     uint64_t* P_out, hipStream_t s) {
+  EntryLayout L = entry_layout(E);
+  auto P32 = [&](size_t off) { return (uint32_t*)(ews + off); };
+  uint32_t* scal = P32(L.scalars);
+  unsigned long long* ptotal = (unsigned long long*)(scal + 2);
+  *nvis_out = 0;
+  *P_out = 0;
+  if (E == 0) return GUT_OK;
+  gut_status st;
+  if ((st = fill_u32(scal, 16, 0u, s)) != GUT_OK) return st;
+  int64_t nb = (E + kBChunk - 1) / kBChunk;
+  vis_reduce_kernel<<<(unsigned)nb, kBThreads, 0, s>>>(proj->tiles, E, P32(L.vis_part), ptotal);
+  GUT_LAUNCH_CHECK();
+  if ((st = exclusive_scan_u32(P32(L.vis_part), P32(L.vis_scan), nb, ews + L.vis_tmp, s)) != GUT_OK)
+    return st;
+  vis_emit_kernel<<<(unsigned)nb, kBThreads, 0, s>>>(proj->tiles, proj->depth, E, P32(L.vis_scan),
+                                                      P32(L.dkA), P32(L.dvA), scal, nb);
+  GUT_LAUNCH_CHECK();
+  if (!g_pinned.p) GUT_HIP(hipHostMalloc(&g_pinned.p, 64, hipHostMallocDefault));
+  GUT_HIP(hipMemcpyAsync(g_pinned.p, scal, 16, hipMemcpyDeviceToHost, s));
+  GUT_HIP(hipStreamSynchronize(s));
+  uint32_t nvis;
+  unsigned long long P;
+  std::memcpy(&nvis, g_pinned.p, 4);
+  std::memcpy(&P, (char*)g_pinned.p + 8, 8);
+  *nvis_out = nvis;
+  *P_out = P;
+  return GUT_OK;
+}
+
+// Phase 2: depth sort, duplicate, tile sort, ranges.  tile_ranges must
+// already be zero; sorted_ids and the pair workspace hold at least P pairs.
+gut_status bin_sort(const gut_projected* proj, int n, const DevCam* dc, int n_cams, int64_t T,
+                    int64_t E, char* ews, uint32_t nvis, uint64_t P, char* pws,
+                    uint32_t* tile_ranges, uint32_t* sorted_ids, hipStream_t s) {
+  if (nvis == 0 || P == 0) return GUT_OK;
+  EntryLayout L = entry_layout(E);
+  PairLayout Lp = pair_layout((int64_t)P);
+  auto E32 = [&](size_t off) { return (uint32_t*)(ews + off); };
+  auto Q32 = [&](size_t off) { return (uint32_t*)(pws + off); };
+  gut_status st;
+  int inB = 0;
+  if ((st = radix_sort_pairs_pp(E32(L.dkA), E32(L.dvA), E32(L.dkB), E32(L.dvB), nvis, 32,
+                                ews + L.radix_tmp, s, &inB)) != GUT_OK)
+    return st;
+  uint32_t* ent = inB ? E32(L.dvB) : E32(L.dvA);
+  gather_tiles_kernel<<<grid_for(nvis, 256), 256, 0, s>>>(ent, proj->tiles, nvis, E32(L.cnt));
+  GUT_LAUNCH_CHECK();
+  if ((st = exclusive_scan_u32(E32(L.cnt), E32(L.offs), nvis, ews + L.offs_tmp, s)) != GUT_OK)
+    return st;
+  CamTiles ct;
+  for (int c = 0; c < n_cams; c++) { ct.base[c] = dc[c].tile_base; ct.tx[c] = dc[c].tiles_x; }
+  duplicate_kernel<<<grid_for(nvis, 128), 128, 0, s>>>(ent, E32(L.offs), (const short4*)proj->rect,
+                                                       n, ct, nvis, Q32(Lp.pkA), sorted_ids);
+  GUT_LAUNCH_CHECK();
+  int bits = 1;
+  while ((int64_t(1) << bits) < T) bits++;
+  if ((st = radix_sort_pairs_pp(Q32(Lp.pkA), sorted_ids, Q32(Lp.pkB), Q32(Lp.pvB), (int64_t)P,
+                                bits, pws + Lp.radix_tmp, s, &inB)) != GUT_OK)
+    return st;
+  uint32_t* keys = inB ? Q32(Lp.pkB) : Q32(Lp.pkA);
+  if (inB) GUT_HIP(hipMemcpyAsync(sorted_ids, Q32(Lp.pvB), P * 4, hipMemcpyDeviceToDevice, s));
+  ranges_kernel<<<grid_for((int64_t)P, 256), 256, 0, s>>>(keys, (int64_t)P, (uint2*)tile_ranges);
+  GUT_LAUNCH_CHECK();
+  return GUT_OK;
+}
+
 }  // namespace gut
 
 using namespace gut;
 
 extern "C" size_t gut_bin_workspace_bytes(int64_t n, int32_t n_cams, int64_t pair_capacity) {
   if (n < 0 || n_cams <= 0 || pair_capacity < 0) return 0;
-  return bin_layout(n * n_cams, pair_capacity).total;
+  return bin_entry_bytes(n * n_cams) + bin_pair_bytes(pair_capacity);
 }
 
 extern "C" gut_status gut_bin(const gut_projected* proj, int64_t n, const gut_camera* cams,
@@ -236,71 +321,22 @@ extern "C" gut_status gut_bin(const gut_projected* proj, int64_t n, const gut_ca
   if ((st = prepare_cams(cams, n_cams, *p, dc, &T, nullptr)) != GUT_OK) return st;
   const int64_t E = n * n_cams;
   if (E >= (int64_t(1) << 31)) { set_error("n * n_cams must be below 2^31"); return GUT_E_INVALID; }
-  BinLayout L = bin_layout(E, pair_capacity);
-  if (!ws || ws_bytes < L.total || ((uintptr_t)ws & 255)) {
-    set_error("workspace must be 256-byte aligned and hold %zu bytes (got %zu)", L.total, ws_bytes);
+  const size_t eb = bin_entry_bytes(E), need = eb + bin_pair_bytes(pair_capacity);
+  if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) {
+    set_error("workspace must be 256-byte aligned and hold %zu bytes (got %zu)", need, ws_bytes);
     return GUT_E_INVALID;
   }
   hipStream_t s = (hipStream_t)stream;
-  char* base = (char*)ws;
-  auto P32 = [&](size_t off) { return (uint32_t*)(base + off); };
-  uint32_t* scal = P32(L.scalars);
-  unsigned long long* ptotal = (unsigned long long*)(scal + 2);
-
-  if ((st = fill_u32((uint32_t*)tile_ranges, 2 * T, 0u, s)) != GUT_OK) return st;
-  if (E == 0) {
-    if (n_pairs) *n_pairs = 0;
-    return GUT_OK;
-  }
-  // 1. compaction of visible entries + pair total
-  if ((st = fill_u32(scal, 16, 0u, s)) != GUT_OK) return st;
-  int64_t nb = (E + kBChunk - 1) / kBChunk;
-  vis_reduce_kernel<<<(unsigned)nb, kBThreads, 0, s>>>(proj->tiles, E, P32(L.vis_part), ptotal);
-  GUT_LAUNCH_CHECK();
-  if ((st = exclusive_scan_u32(P32(L.vis_part), P32(L.vis_scan), nb, base + L.vis_tmp, s)) != GUT_OK) return st;
-  vis_emit_kernel<<<(unsigned)nb, kBThreads, 0, s>>>(proj->tiles, proj->depth, E, P32(L.vis_scan),
-                                                      P32(L.dkA), P32(L.dvA), scal, nb);
-  GUT_LAUNCH_CHECK();
-  // 2. read back N_vis and P
-  if (!g_pinned.p) GUT_HIP(hipHostMalloc(&g_pinned.p, 64, hipHostMallocDefault));
-  GUT_HIP(hipMemcpyAsync(g_pinned.p, scal, 16, hipMemcpyDeviceToHost, s));
-  GUT_HIP(hipStreamSynchronize(s));
-  uint32_t nvis;
-  unsigned long long P;
-  std::memcpy(&nvis, g_pinned.p, 4);
-  std::memcpy(&P, (char*)g_pinned.p + 8, 8);
+  char* ews = (char*)ws;
+  char* pws = ews + eb;
+  if ((st = fill_u32(tile_ranges, 2 * T, 0u, s)) != GUT_OK) return st;
+  uint32_t nvis = 0;
+  uint64_t P = 0;
+  if ((st = bin_count(proj, E, ews, &nvis, &P, s)) != GUT_OK) return st;
   if (n_pairs) *n_pairs = (int64_t)P;
   if ((int64_t)P > pair_capacity) {
-    set_error("pair capacity %lld < required %llu", (long long)pair_capacity, P);
+    set_error("pair capacity %lld < required %llu", (long long)pair_capacity, (unsigned long long)P);
     return GUT_E_CAPACITY;
   }
-  if (nvis == 0 || P == 0) return GUT_OK;
-  // 3. depth sort of the visible entries
-  int inB = 0;
-  if ((st = radix_sort_pairs_pp(P32(L.dkA), P32(L.dvA), P32(L.dkB), P32(L.dvB), nvis, 32,
-                                base + L.radix_tmp, s, &inB)) != GUT_OK)
-    return st;
-  uint32_t* ent = inB ? P32(L.dvB) : P32(L.dvA);
-  // 4. pair offsets in depth order
-  gather_tiles_kernel<<<grid_for(nvis, 256), 256, 0, s>>>(ent, proj->tiles, nvis, P32(L.cnt));
-  GUT_LAUNCH_CHECK();
-  if ((st = exclusive_scan_u32(P32(L.cnt), P32(L.offs), nvis, base + L.offs_tmp, s)) != GUT_OK) return st;
-  // 5. duplicate
-  CamTiles ct;
-  for (int c = 0; c < n_cams; c++) { ct.base[c] = dc[c].tile_base; ct.tx[c] = dc[c].tiles_x; }
-  duplicate_kernel<<<grid_for(nvis, 128), 128, 0, s>>>(ent, P32(L.offs), (const short4*)proj->rect,
-                                                       (int)n, ct, nvis, P32(L.pkA), sorted_ids);
-  GUT_LAUNCH_CHECK();
-  // 6. stable sort of the pairs by tile id
-  int bits = 1;
-  while ((int64_t(1) << bits) < T) bits++;
-  if ((st = radix_sort_pairs_pp(P32(L.pkA), sorted_ids, P32(L.pkB), P32(L.pvB), (int64_t)P, bits,
-                                base + L.radix_tmp, s, &inB)) != GUT_OK)
-    return st;
-  uint32_t* keys = inB ? P32(L.pkB) : P32(L.pkA);
-  if (inB) GUT_HIP(hipMemcpyAsync(sorted_ids, P32(L.pvB), P * 4, hipMemcpyDeviceToDevice, s));
-  // 7. ranges
-  ranges_kernel<<<grid_for((int64_t)P, 256), 256, 0, s>>>(keys, (int64_t)P, (uint2*)tile_ranges);
-  GUT_LAUNCH_CHECK();
-  return GUT_OK;
+  return bin_sort(proj, (int)n, dc, n_cams, T, E, ews, nvis, P, pws, tile_ranges, sorted_ids, s);
 }

@@ -90,6 +90,24 @@ gut_status prepare_cams(const gut_camera* cams, int n_cams, const gut_params& p,
 
 gut_status fill_u32(uint32_t* p, int64_t m, uint32_t v, hipStream_t st);
 
+// Internal stage launchers shared by the C entry points and the server.
+gut_status project_launch(const gut_scene* scene, const DevCam* dc, int n_cams, const UTConst& ut,
+                          const Thresholds& th, const gut_projected* out, bool write_record,
+                          hipStream_t s);
+gut_status render_batch_launch(const DevCam* d_cams, const DevCam* h_cams, int n_cams,
+                               const Thresholds& th, int n, const uint32_t* ranges,
+                               const uint32_t* ids, const float* record, const float* rgb,
+                               float* const* d_outs, unsigned* d_counters, int* d_lists,
+                               int* h_lists, int n_blocks, hipStream_t s);
+gut_status record_launch(const gut_scene* scene, float* record, hipStream_t s);
+size_t bin_entry_bytes(int64_t E);
+size_t bin_pair_bytes(int64_t cap);
+gut_status bin_count(const gut_projected* proj, int64_t E, char* ews, uint32_t* nvis_out,
+                     uint64_t* P_out, hipStream_t s);
+gut_status bin_sort(const gut_projected* proj, int n, const DevCam* dc, int n_cams, int64_t T,
+                    int64_t E, char* ews, uint32_t nvis, uint64_t P, char* pws,
+                    uint32_t* tile_ranges, uint32_t* sorted_ids, hipStream_t s);
+
 // Radix sort / scan building blocks (sort.hip).
 size_t scan_temp_bytes(int64_t n);
 gut_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* temp,

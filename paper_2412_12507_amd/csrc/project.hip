@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(256) project_kernel(
   float sig = opac[i];
   float R[9];
   quat_to_rot(q, R);
-  if (record && cam_idx == 0) {  // render record: mu, sigma, M = S^-1 R^T
+  if (record) {  // render record: mu, sigma, M = S^-1 R^T (written by one launch per scene)
     float4* rec = reinterpret_cast<float4*>(record) + 4 * (long long)i;
     float is0 = 1.0f / s.x, is1 = 1.0f / s.y, is2 = 1.0f / s.z;
     rec[0] = make_float4(mu.x, mu.y, mu.z, sig);
@@ -124,6 +124,56 @@ __global__ void __launch_bounds__(256) project_kernel(
   if (cov2d) { cov2d[3 * e] = cxx; cov2d[3 * e + 1] = cxy; cov2d[3 * e + 2] = cyy; }
 }
 
+// Render records only (mu, sigma, M = S^-1 R^T), for a resident scene.
+__global__ void record_kernel(int n, const float* __restrict__ means,
+                              const float* __restrict__ scales, const float* __restrict__ quats,
+                              const float* __restrict__ opac, float* __restrict__ record) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float R[9];
+  quat_to_rot(reinterpret_cast<const float4*>(quats)[i], R);
+  float is0 = 1.0f / scales[3 * i], is1 = 1.0f / scales[3 * i + 1], is2 = 1.0f / scales[3 * i + 2];
+  float4* rec = reinterpret_cast<float4*>(record) + 4 * (long long)i;
+  rec[0] = make_float4(means[3 * i], means[3 * i + 1], means[3 * i + 2], opac[i]);
+  rec[1] = make_float4(R[0] * is0, R[3] * is0, R[6] * is0, 0.0f);
+  rec[2] = make_float4(R[1] * is1, R[4] * is1, R[7] * is1, 0.0f);
+  rec[3] = make_float4(R[2] * is2, R[5] * is2, R[8] * is2, 0.0f);
+}
+
+gut_status record_launch(const gut_scene* scene, float* record, hipStream_t s) {
+  const int n = (int)scene->n;
+  if (n == 0) return GUT_OK;
+  record_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, scene->means, scene->scales, scene->quats,
+                                                scene->opacities, record);
+  GUT_LAUNCH_CHECK();
+  return GUT_OK;
+}
+
+gut_status project_launch(const gut_scene* scene, const DevCam* dc, int n_cams, const UTConst& ut,
+                          const Thresholds& th, const gut_projected* out, bool write_record,
+                          hipStream_t s) {
+  const int n = (int)scene->n;
+  if (n == 0) return GUT_OK;
+  dim3 grid((n + 255) / 256), block(256);
+  for (int c = 0; c < n_cams; c++) {
+    float* rec = (write_record && c == 0) ? out->record : nullptr;
+#define GUT_PROJ(D)                                                                          \
+  project_kernel<D><<<grid, block, 0, s>>>(n, c, dc[c], ut, th, scene->means, scene->scales, \
+                                           scene->quats, scene->opacities, scene->sh,        \
+                                           out->rect, out->tiles, out->depth, out->rgb, rec, \
+                                           out->mean2d, out->cov2d)
+    switch (scene->sh_degree) {
+      case 0: GUT_PROJ(0); break;
+      case 1: GUT_PROJ(1); break;
+      case 2: GUT_PROJ(2); break;
+      default: GUT_PROJ(3); break;
+    }
+#undef GUT_PROJ
+    GUT_LAUNCH_CHECK();
+  }
+  return GUT_OK;
+}
+
 }  // namespace gut
 
 using namespace gut;
@@ -152,26 +202,6 @@ extern "C" gut_status gut_project(const gut_scene* scene, const gut_camera* cams
     set_error("n * n_cams must be below 2^31");
     return GUT_E_INVALID;
   }
-  const int n = (int)scene->n;
-  if (n == 0) return GUT_OK;
-  UTConst ut = make_ut(*p);
-  Thresholds th = make_thresholds(*p);
-  hipStream_t s = (hipStream_t)stream;
-  dim3 grid((n + 255) / 256), block(256);
-  for (int c = 0; c < n_cams; c++) {
-#define GUT_PROJ(D)                                                                          \
-  project_kernel<D><<<grid, block, 0, s>>>(n, c, dc[c], ut, th, scene->means, scene->scales, \
-                                           scene->quats, scene->opacities, scene->sh,        \
-                                           out->rect, out->tiles, out->depth, out->rgb,      \
-                                           out->record, out->mean2d, out->cov2d)
-    switch (scene->sh_degree) {
-      case 0: GUT_PROJ(0); break;
-      case 1: GUT_PROJ(1); break;
-      case 2: GUT_PROJ(2); break;
-      default: GUT_PROJ(3); break;
-    }
-#undef GUT_PROJ
-    GUT_LAUNCH_CHECK();
-  }
-  return GUT_OK;
+  return project_launch(scene, dc, n_cams, make_ut(*p), make_thresholds(*p), out, true,
+                        (hipStream_t)stream);
 }

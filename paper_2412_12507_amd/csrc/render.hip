@@ -17,19 +17,16 @@ namespace gut {
 constexpr int kRThreads = 128;
 constexpr int kRBatch = kRThreads;
 
+// One tile of one camera.  pd, F and red are the block's LDS; out_* are
+// indexed by pix_base + y * W + x.
 template <bool RS>
-__global__ void __launch_bounds__(kRThreads) render_kernel(
-    DevCam cam, Thresholds th, int n, int cam_idx, const uint2* __restrict__ ranges,
-    const uint32_t* __restrict__ ids, const float4* __restrict__ record,
-    const float* __restrict__ rgb, float* __restrict__ out_rgb, float* __restrict__ out_T,
-    uint32_t* __restrict__ out_nc, uint32_t* __restrict__ out_ne) {
+__device__ __forceinline__ void render_tile(
+    const DevCam& cam, const Thresholds& th, int n, int cam_idx, int tile,
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
+    const float4* __restrict__ record, const float* __restrict__ rgb, float* __restrict__ out_rgb,
+    float* __restrict__ out_T, uint32_t* __restrict__ out_nc, uint32_t* __restrict__ out_ne,
+    long long pix_base, float4* pd, TileFrameD& F, float* red) {
   constexpr int S = Slots<RS>::N;
-  __shared__ float4 pd[kRBatch * S];
-  __shared__ TileFrameD F;
-  __shared__ float red[6];
-
-  const int ntiles = cam.tiles_x * cam.tiles_y;
-  const int tile = xcd_tile(blockIdx.x, ntiles);
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
   const int t = threadIdx.x;
   const int px = tx * kTile + (t & (kTile - 1));
@@ -102,14 +99,118 @@ __global__ void __launch_bounds__(kRThreads) render_kernel(
   for (int k = 0; k < 2; k++) {
     if (!inside[k]) continue;
     const int py = py0 + 8 * k;
-    long long pix = cam.pixel_base + (long long)py * cam.W + px;
+    long long pix = pix_base + (long long)py * cam.W + px;
     out_rgb[3 * pix] = (float)fma((double)T[k], (double)th.bg[0], C[k][0]);
     out_rgb[3 * pix + 1] = (float)fma((double)T[k], (double)th.bg[1], C[k][1]);
     out_rgb[3 * pix + 2] = (float)fma((double)T[k], (double)th.bg[2], C[k][2]);
-    out_T[pix] = T[k];
-    out_nc[pix] = last[k];
+    if (out_T) out_T[pix] = T[k];
+    if (out_nc) out_nc[pix] = last[k];
     if (out_ne) out_ne[pix] = nev[k];
   }
+}
+
+template <bool RS>
+__global__ void __launch_bounds__(kRThreads) render_kernel(
+    DevCam cam, Thresholds th, int n, int cam_idx, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ ids, const float4* __restrict__ record,
+    const float* __restrict__ rgb, float* __restrict__ out_rgb, float* __restrict__ out_T,
+    uint32_t* __restrict__ out_nc, uint32_t* __restrict__ out_ne) {
+  __shared__ float4 pd[kRBatch * Slots<RS>::N];
+  __shared__ TileFrameD F;
+  __shared__ float red[6];
+  const int tile = xcd_tile(blockIdx.x, cam.tiles_x * cam.tiles_y);
+  render_tile<RS>(cam, th, n, cam_idx, tile, ranges, ids, record, rgb, out_rgb, out_T, out_nc,
+                  out_ne, cam.pixel_base, pd, F, red);
+}
+
+// Persistent render of the cameras of one shutter type in a multi-camera
+// batch.  Items are (camera, tile) over the listed cameras, in order; the
+// item range is cut into 8 contiguous chunks, one per XCD (blocks are dealt
+// to XCDs round-robin), each with its own counter; a block that drains its
+// XCD's chunk steals from the others, and leaves once every counter is past
+// its chunk.  Images go to outs[camera] ([H, W, 3]).
+template <bool RS>
+__global__ void __launch_bounds__(kRThreads) render_batch_kernel(
+    const DevCam* __restrict__ cams, const int* __restrict__ cam_list,
+    const int* __restrict__ item_start, int n_list, int n_items, unsigned* __restrict__ counters,
+    Thresholds th, int n, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
+    const float4* __restrict__ record, const float* __restrict__ rgb, float* const* __restrict__ outs) {
+  __shared__ float4 pd[kRBatch * Slots<RS>::N];
+  __shared__ TileFrameD F;
+  __shared__ float red[6];
+  __shared__ int item_s;
+  __shared__ DevCam cam_s;  // the current item's camera, staged in LDS
+  const int nx = 8;
+  const int my = blockIdx.x % nx;
+  const int q = n_items / nx, r = n_items % nx;
+  int probe = 0;  // which XCD chunk this block is draining (its own first)
+  while (true) {
+    if (threadIdx.x == 0) {
+      int it = -1;
+      while (probe < nx) {
+        int x = (my + probe) % nx;
+        int start = x * q + min(x, r), len = q + (x < r ? 1 : 0);
+        unsigned k = atomicAdd(&counters[x], 1u);
+        if ((int)k < len) { it = start + (int)k; break; }
+        probe++;
+      }
+      item_s = it;
+    }
+    __syncthreads();
+    const int item = item_s;
+    __syncthreads();
+    if (item < 0) break;
+    int j = 0;
+    while (j + 1 < n_list && item_start[j + 1] <= item) j++;
+    const int c = cam_list[j];
+    {
+      const int* src = reinterpret_cast<const int*>(&cams[c]);
+      int* dst = reinterpret_cast<int*>(&cam_s);
+      for (int w = threadIdx.x; w < (int)(sizeof(DevCam) / sizeof(int)); w += blockDim.x) dst[w] = src[w];
+    }
+    __syncthreads();
+    render_tile<RS>(cam_s, th, n, c, item - item_start[j], ranges, ids, record, rgb, outs[c],
+                    nullptr, nullptr, nullptr, 0, pd, F, red);
+  }
+}
+
+// Launch the batch render: one persistent kernel per shutter type present.
+// d_lists holds, per type, the camera indices and item prefix sums
+// (2 x (kMaxCams + kMaxCams + 1) ints); d_counters 16 counters.
+gut_status render_batch_launch(const DevCam* d_cams, const DevCam* h_cams, int n_cams,
+                               const Thresholds& th, int n, const uint32_t* ranges,
+                               const uint32_t* ids, const float* record, const float* rgb,
+                               float* const* d_outs, unsigned* d_counters, int* d_lists,
+                               int* h_lists, int n_blocks, hipStream_t s) {
+  gut_status st = fill_u32(d_counters, 16, 0u, s);
+  if (st != GUT_OK) return st;
+  for (int type = 0; type < 2; type++) {
+    int* hl = h_lists + type * (2 * kMaxCams + 1);
+    int* cl = hl;
+    int* is = hl + kMaxCams;
+    int m = 0, items = 0;
+    for (int c = 0; c < n_cams; c++) {
+      if ((h_cams[c].shutter == GUT_ROLLING_TOP_TO_BOTTOM) != (type == 1)) continue;
+      cl[m] = c;
+      is[m] = items;
+      items += h_cams[c].tiles_x * h_cams[c].tiles_y;
+      m++;
+    }
+    is[m] = items;
+    if (m == 0) continue;
+    int* dl = d_lists + type * (2 * kMaxCams + 1);
+    GUT_HIP(hipMemcpyAsync(dl, hl, (2 * kMaxCams + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    if (type == 1)
+      render_batch_kernel<true><<<n_blocks, kRThreads, 0, s>>>(
+          d_cams, dl, dl + kMaxCams, m, items, d_counters + 8 * type, th, n, (const uint2*)ranges,
+          ids, (const float4*)record, rgb, d_outs);
+    else
+      render_batch_kernel<false><<<n_blocks, kRThreads, 0, s>>>(
+          d_cams, dl, dl + kMaxCams, m, items, d_counters + 8 * type, th, n, (const uint2*)ranges,
+          ids, (const float4*)record, rgb, d_outs);
+    GUT_LAUNCH_CHECK();
+  }
+  return GUT_OK;
 }
 
 gut_status launch_render(const DevCam& cam, const Thresholds& th, int n, int cam_idx,

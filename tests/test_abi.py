@@ -123,3 +123,21 @@ def test_bin_and_render_validation_without_launch():
     st = lib.gut_render_bwd(L.ref(sc), L.ref(pj), z, z, arr, 1, L.ref(p), z, z, z, z, None, z, z, z,
                             z, z, z, 16, None)
     assert st == L.GUT_E_INVALID
+
+
+def test_serve_validation_without_launch():
+    lib = L.load()
+    p = L.params_struct()
+    sc = _scene_struct()
+    h = C.c_void_p()
+    # bad slot counts / batch sizes
+    assert lib.gut_serve_create(L.ref(sc), L.ref(p), 1 << 30, 0, 8, C.byref(h)) == L.GUT_E_INVALID
+    assert lib.gut_serve_create(L.ref(sc), L.ref(p), 1 << 30, 2, 0, C.byref(h)) == L.GUT_E_INVALID
+    assert lib.gut_serve_create(L.ref(sc), L.ref(p), 1 << 30, 2, 65, C.byref(h)) == L.GUT_E_INVALID
+    # budget below the resident records of the scene
+    big = _scene_struct(n=10_000_000)
+    assert lib.gut_serve_create(L.ref(big), L.ref(p), 1 << 20, 2, 8, C.byref(h)) == L.GUT_E_ADMISSION
+    # NULL server handles
+    done = C.c_int32()
+    assert lib.gut_serve_poll(None, 1, C.byref(done)) == L.GUT_E_INVALID
+    assert lib.gut_serve_destroy(None) == L.GUT_E_INVALID
