@@ -123,7 +123,11 @@ gut_status make_devcam(const gut_camera& c, const gut_params& p, int tile_base,
   }
   const int ts = p.tile;
   o->model = c.model;
-  o->shutter = c.shutter;
+  // a rolling shutter whose two poses are identical images exactly as a
+  // global shutter: use the global-shutter kernels for it
+  const bool still = rolling && std::memcmp(c.R0, c.R1, sizeof(c.R0)) == 0 &&
+                     std::memcmp(c.t0, c.t1, sizeof(c.t0)) == 0;
+  o->shutter = still ? GUT_GLOBAL_SHUTTER : c.shutter;
   o->W = c.width;
   o->H = c.height;
   o->tiles_x = (c.width + ts - 1) / ts;

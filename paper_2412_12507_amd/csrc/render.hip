@@ -1,15 +1,19 @@
 // K5 -- per-tile front-to-back compositing (Eq. 5) with each particle's
 // response evaluated in 3D at its maximum along the pixel ray (Eq. 11).
 //
-// One 128-thread block (2 wave64s) per 16x16 tile; each thread owns two
-// pixels, (x, y) and (x, y + 8), so every pair read from LDS serves two
-// evaluations.  The tile's sorted list is consumed in batches of 128: each
-// thread gathers one pair's 64-byte render record, forms the pair's FP64
-// tile-frame terms (tile_eval.h) and stores them in LDS; then every thread
-// walks the batch, reading each pair as an LDS broadcast.  The walk is
-// branch-free per pixel (predicated updates); a wave leaves the batch as soon
-// as all its pixels have stopped, and the block stops when no pixel is still
-// going.  Blocks are mapped to tiles so that each XCD gets a contiguous band.
+// One 128-thread block (2 wave64s) per 16x16 tile; each wave owns a 16x8
+// half-tile and each thread two pixels of one column, 4 rows apart, so every
+// pair read from LDS serves two evaluations.  The tile's sorted list is
+// consumed in batches of 128: each thread gathers one pair's 64-byte render
+// record, forms the pair's FP64 tile-frame terms (tile_eval.h), including
+// which half-tiles the particle's alpha_min ellipse can reach, and stores
+// them in LDS.  Each wave then walks only the pairs flagged for its half
+// (a scalar bit loop), reading each pair as an LDS broadcast; per pixel the
+// cheap test omega^2 <= K comes first and the reciprocal and exponential run
+// only when some lane of the wave passes it.  The walk is branch-free per
+// pixel (predicated updates); a wave leaves the batch as soon as all its
+// pixels have stopped, and the block stops when no pixel is still going.
+// Blocks are mapped to tiles so that each XCD gets a contiguous band.
 #include "tile_eval.h"
 
 namespace gut {
@@ -17,20 +21,22 @@ namespace gut {
 constexpr int kRThreads = 128;
 constexpr int kRBatch = kRThreads;
 
-// One tile of one camera.  pd, F and red are the block's LDS; out_* are
-// indexed by pix_base + y * W + x.
+// One tile of one camera.  pd, pf, F, wb and red are the block's LDS; out_*
+// are indexed by pix_base + y * W + x.
 template <bool RS>
 __device__ __forceinline__ void render_tile(
     const DevCam& cam, const Thresholds& th, int n, int cam_idx, int tile,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
     const float4* __restrict__ record, const float* __restrict__ rgb, float* __restrict__ out_rgb,
     float* __restrict__ out_T, uint32_t* __restrict__ out_nc, uint32_t* __restrict__ out_ne,
-    long long pix_base, float4* pd, TileFrameD& F, float* red) {
-  constexpr int S = Slots<RS>::N;
+    long long pix_base, float4* pd, uint32_t* pf, TileFrameD& F, WaveBoxes& wb, float* red) {
+  constexpr int S = Slots<RS, false>::N;
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-  const int t = threadIdx.x;
-  const int px = tx * kTile + (t & (kTile - 1));
-  const int py0 = ty * kTile + t / kTile;
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  // wave wv owns the 16 x 8 half-tile of rows 8 wv .. 8 wv + 7; a thread
+  // owns the pixels (px, py0) and (px, py0 + 4)
+  const int px = tx * kTile + (lane & (kTile - 1));
+  const int py0 = ty * kTile + 8 * wv + (lane >> 4);
   if (t == 0) tile_frame(cam, tx, ty, &F);
   __syncthreads();
 
@@ -38,12 +44,13 @@ __device__ __forceinline__ void render_tile(
   float u[2] = {0.f, 0.f}, v[2] = {0.f, 0.f}, dt[2] = {0.f, 0.f};
 #pragma unroll
   for (int k = 0; k < 2; k++) {
-    const int py = py0 + 8 * k;
+    const int py = py0 + 4 * k;
     inside[k] = px < cam.W && py < cam.H;
     active[k] = inside[k] && pixel_ray(cam, F, px, py, &u[k], &v[k], &dt[k]);
   }
   float umax, vmax, dtmax;
   tile_bounds<2>(u, v, dt, active, red, &umax, &vmax, &dtmax);
+  wave_box<2>(u, v, active, &wb);
 
   const uint2 rg = ranges[cam.tile_base + tile];
   const uint32_t len = rg.y - rg.x;
@@ -54,43 +61,59 @@ __device__ __forceinline__ void render_tile(
   uint32_t last[2] = {0u, 0u}, nev[2] = {active[0] ? len : 0u, active[1] ? len : 0u};
   bool done[2] = {!active[0], !active[1]};
   for (uint32_t b = 0; b < len; b += kRBatch) {
+    // (also publishes wb before the first setup)
     if (__syncthreads_count(!(done[0] && done[1])) == 0) break;
+    uint32_t fl = 0u;
     if (b + t < len) {
       uint32_t e = ids[rg.x + b + t];
-      pair_setup<RS>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n), F, cam, umax,
-                     vmax, dtmax, &pd[t * S]);
+      fl = pair_setup<RS, false>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n), F, cam,
+                          umax, vmax, dtmax, th.alpha_min, wb, kRThreads / 64, &pd[t * S]);
     }
+    pf[t] = fl;
     __syncthreads();
-    const uint32_t cnt = min((uint32_t)kRBatch, len - b);
-    for (uint32_t q = 0; q < cnt; q++) {
-      if (__ballot(!(done[0] && done[1])) == 0ull) break;  // wave-uniform exit
-      const float4* P = &pd[q * S];
-      PairRegs<RS> r;
-      load_pair<RS>(P, r);
-      bool contrib[2];
-      float wgt[2];
+    // the batch's pairs that may reach alpha_min somewhere in this wave's half-tile
+    const unsigned long long m0 = __ballot((pf[lane] >> wv) & 1u);
+    const unsigned long long m1 = __ballot((pf[lane + 64] >> wv) & 1u);
+    bool wave_done = false;
+    for (int h = 0; h < 2 && !wave_done; h++) {
+      unsigned long long m = h ? m1 : m0;
+      while (m) {
+        if (__ballot(!(done[0] && done[1])) == 0ull) { wave_done = true; break; }
+        const uint32_t q = 64u * h + (uint32_t)__builtin_ctzll(m);
+        m &= m - 1ull;
+        const float4* P = &pd[q * S];
+        PairRegs<RS> r;
+        load_pair<RS>(P, r);
+        Eval ev[2];
 #pragma unroll
-      for (int k = 0; k < 2; k++) {
-        Eval ev;
-        eval_pair<RS>(r, P, u[k], v[k], dt[k], th.alpha_min, th.alpha_max, &ev);
-        const float Tn = T[k] * (1.0f - ev.a);
-        const bool live = ev.ok && !done[k];
-        const bool stop = live && Tn < th.t_min;  // stop before adding this particle
-        contrib[k] = live && !stop;
-        wgt[k] = contrib[k] ? ev.a * T[k] : 0.0f;
-        T[k] = contrib[k] ? Tn : T[k];
-        last[k] = contrib[k] ? b + q + 1 : last[k];
-        nev[k] = stop ? b + q + 1 : nev[k];
-        done[k] = done[k] || stop;
-      }
-      if (__ballot(contrib[0] || contrib[1]) != 0ull) {
-        const double c0 = r.p1.w, c1 = r.p2.w, c2 = r.p3.w;
+        for (int k = 0; k < 2; k++) eval_test<RS>(r, P, u[k], v[k], dt[k], &ev[k]);
+        const bool live0 = ev[0].ok && !done[0], live1 = ev[1].ok && !done[1];
+        if (__ballot(live0 || live1) == 0ull) continue;  // nothing reaches alpha_min here
+        bool contrib[2];
+        float wgt[2];
 #pragma unroll
         for (int k = 0; k < 2; k++) {
-          const double w = (double)wgt[k];
-          C[k][0] = fma(w, c0, C[k][0]);
-          C[k][1] = fma(w, c1, C[k][1]);
-          C[k][2] = fma(w, c2, C[k][2]);
+          eval_alpha<RS>(r, th.alpha_max, &ev[k]);
+          const bool live = k ? live1 : live0;
+          const float Tn = T[k] * (1.0f - ev[k].a);
+          const bool stop = live && Tn < th.t_min;  // stop before adding this particle
+          contrib[k] = live && !stop;
+          wgt[k] = contrib[k] ? ev[k].a * T[k] : 0.0f;
+          T[k] = contrib[k] ? Tn : T[k];
+          last[k] = contrib[k] ? b + q + 1 : last[k];
+          nev[k] = stop ? b + q + 1 : nev[k];
+          done[k] = done[k] || stop;
+        }
+        if (__ballot(contrib[0] || contrib[1]) != 0ull) {
+          const float4 col = pair_colour<RS>(P);
+          const double c0 = col.x, c1 = col.y, c2 = col.z;
+#pragma unroll
+          for (int k = 0; k < 2; k++) {
+            const double w = (double)wgt[k];
+            C[k][0] = fma(w, c0, C[k][0]);
+            C[k][1] = fma(w, c1, C[k][1]);
+            C[k][2] = fma(w, c2, C[k][2]);
+          }
         }
       }
     }
@@ -98,7 +121,7 @@ __device__ __forceinline__ void render_tile(
 #pragma unroll
   for (int k = 0; k < 2; k++) {
     if (!inside[k]) continue;
-    const int py = py0 + 8 * k;
+    const int py = py0 + 4 * k;
     long long pix = pix_base + (long long)py * cam.W + px;
     out_rgb[3 * pix] = (float)fma((double)T[k], (double)th.bg[0], C[k][0]);
     out_rgb[3 * pix + 1] = (float)fma((double)T[k], (double)th.bg[1], C[k][1]);
@@ -115,12 +138,14 @@ __global__ void __launch_bounds__(kRThreads) render_kernel(
     const uint32_t* __restrict__ ids, const float4* __restrict__ record,
     const float* __restrict__ rgb, float* __restrict__ out_rgb, float* __restrict__ out_T,
     uint32_t* __restrict__ out_nc, uint32_t* __restrict__ out_ne) {
-  __shared__ float4 pd[kRBatch * Slots<RS>::N];
+  __shared__ float4 pd[kRBatch * Slots<RS, false>::N];
+  __shared__ uint32_t pf[kRBatch];
   __shared__ TileFrameD F;
+  __shared__ WaveBoxes wb;
   __shared__ float red[6];
   const int tile = xcd_tile(blockIdx.x, cam.tiles_x * cam.tiles_y);
   render_tile<RS>(cam, th, n, cam_idx, tile, ranges, ids, record, rgb, out_rgb, out_T, out_nc,
-                  out_ne, cam.pixel_base, pd, F, red);
+                  out_ne, cam.pixel_base, pd, pf, F, wb, red);
 }
 
 // Persistent render of the cameras of one shutter type in a multi-camera
@@ -135,8 +160,10 @@ __global__ void __launch_bounds__(kRThreads) render_batch_kernel(
     const int* __restrict__ item_start, int n_list, int n_items, unsigned* __restrict__ counters,
     Thresholds th, int n, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
     const float4* __restrict__ record, const float* __restrict__ rgb, float* const* __restrict__ outs) {
-  __shared__ float4 pd[kRBatch * Slots<RS>::N];
+  __shared__ float4 pd[kRBatch * Slots<RS, false>::N];
+  __shared__ uint32_t pf[kRBatch];
   __shared__ TileFrameD F;
+  __shared__ WaveBoxes wb;
   __shared__ float red[6];
   __shared__ int item_s;
   __shared__ DevCam cam_s;  // the current item's camera, staged in LDS
@@ -170,7 +197,7 @@ __global__ void __launch_bounds__(kRThreads) render_batch_kernel(
     }
     __syncthreads();
     render_tile<RS>(cam_s, th, n, c, item - item_start[j], ranges, ids, record, rgb, outs[c],
-                    nullptr, nullptr, nullptr, 0, pd, F, red);
+                    nullptr, nullptr, nullptr, 0, pd, pf, F, wb, red);
   }
 }
 

@@ -16,8 +16,9 @@
 // (Supp. B), so with M = S^-1 R^T the per-pixel gradients are
 //   dL/dmu = -M^T c p,   dL/dM = c p (M^-1 p)^T,   c = 2 dL/domega^2.
 // They only depend on G = sum c p p^T (6 values) and h = sum c p (3): each
-// wave sums those plus dL/dsigma and dL/dc over its lanes and issues one FP32
-// atomic per value per (wave, particle).
+// wave sums those plus dL/dsigma and dL/dc over its lanes (FP32) and issues
+// one FP64 atomic per value per (wave, particle), so the per-particle totals
+// carry no order-dependent FP32 rounding.
 //
 // K7 (per particle) then applies M = S^-1 R^T:
 //   dL/ds_k = -G_kk / s_k,   dL/dR = R S G S^-1,   dL/dmu = -R S^-1 h,
@@ -45,21 +46,24 @@ __global__ void __launch_bounds__(kBwThreads) render_bwd_kernel(
     const uint32_t* __restrict__ ids, const float4* __restrict__ record,
     const float* __restrict__ rgb, const float* __restrict__ out_rgb,
     const float* __restrict__ out_T, const uint32_t* __restrict__ out_nc,
-    const float* __restrict__ d_rgb, const float* __restrict__ d_T, float* __restrict__ acc,
-    float* __restrict__ acc_rgb) {
-  constexpr int S = Slots<RS>::N;
+    const float* __restrict__ d_rgb, const float* __restrict__ d_T, double* __restrict__ acc,
+    double* __restrict__ acc_rgb) {
+  constexpr int S = Slots<RS, true>::N;
   __shared__ float4 pd[kBwBatch * S];
   __shared__ uint32_t pe[kBwBatch];
+  __shared__ uint32_t pf[kBwBatch];
   __shared__ TileFrameD F;
+  __shared__ WaveBoxes wb;
   __shared__ float red[6];
   __shared__ uint32_t maxlast_s;
 
   const int ntiles = cam.tiles_x * cam.tiles_y;
   const int tile = xcd_tile(blockIdx.x, ntiles);
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-  const int t = threadIdx.x, lane = t & 63;
-  const int px = tx * kTile + (t & (kTile - 1));
-  const int py0 = ty * kTile + t / kTile;
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  // the forward's pixel layout: wave wv owns rows 8 wv .. 8 wv + 7
+  const int px = tx * kTile + (lane & (kTile - 1));
+  const int py0 = ty * kTile + 8 * wv + (lane >> 4);
   if (t == 0) { tile_frame(cam, tx, ty, &F); maxlast_s = 0; }
   __syncthreads();
 
@@ -67,11 +71,12 @@ __global__ void __launch_bounds__(kBwThreads) render_bwd_kernel(
   float u[2] = {0.f, 0.f}, v[2] = {0.f, 0.f}, dt[2] = {0.f, 0.f};
 #pragma unroll
   for (int k = 0; k < 2; k++) {
-    const int py = py0 + 8 * k;
+    const int py = py0 + 4 * k;
     active[k] = px < cam.W && py < cam.H && pixel_ray(cam, F, px, py, &u[k], &v[k], &dt[k]);
   }
   float umax, vmax, dtmax;
   tile_bounds<2>(u, v, dt, active, red, &umax, &vmax, &dtmax);
+  wave_box<2>(u, v, active, &wb);
 
   uint32_t last[2] = {0u, 0u};
   float TN[2] = {1.f, 1.f}, gC[2][3] = {{0, 0, 0}, {0, 0, 0}}, gT[2] = {0.f, 0.f};
@@ -79,14 +84,14 @@ __global__ void __launch_bounds__(kBwThreads) render_bwd_kernel(
 #pragma unroll
   for (int k = 0; k < 2; k++) {
     if (!active[k]) continue;
-    const long long pix = cam.pixel_base + (long long)(py0 + 8 * k) * cam.W + px;
+    const long long pix = cam.pixel_base + (long long)(py0 + 4 * k) * cam.W + px;
     last[k] = out_nc[pix];
     TN[k] = out_T[pix];
     for (int c = 0; c < 3; c++) { gC[k][c] = d_rgb[3 * pix + c]; Co[k][c] = out_rgb[3 * pix + c]; }
     gT[k] = d_T ? d_T[pix] : 0.0f;
   }
   atomicMax(&maxlast_s, max(last[0], last[1]));
-  __syncthreads();
+  __syncthreads();  // (also publishes wb)
   const uint2 rg = ranges[cam.tile_base + tile];
   const uint32_t maxlast = min(maxlast_s, rg.y - rg.x);  // never past the tile's list
 
@@ -94,122 +99,151 @@ __global__ void __launch_bounds__(kBwThreads) render_bwd_kernel(
   double A[2][3] = {{0, 0, 0}, {0, 0, 0}};  // running colour C_<=j, accumulated as in the forward
   for (uint32_t b = 0; b < maxlast; b += kBwBatch) {
     __syncthreads();
+    uint32_t fl = 0u;
     if (b + t < maxlast) {
       uint32_t e = ids[rg.x + b + t];
       pe[t] = e;
-      pair_setup<RS>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n), F, cam, umax,
-                     vmax, dtmax, &pd[t * S]);
+      fl = pair_setup<RS, true>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n), F, cam,
+                          umax, vmax, dtmax, th.alpha_min, wb, kBwThreads / 64, &pd[t * S]);
     }
+    pf[t] = fl;
     __syncthreads();
-    const uint32_t cnt = min((uint32_t)kBwBatch, maxlast - b);
-    for (uint32_t q = 0; q < cnt; q++) {
-      const uint32_t idx = b + q;
-      if (__ballot(idx < last[0] || idx < last[1]) == 0ull) break;  // wave-uniform exit
-      const float4* P = &pd[q * S];
-      PairRegs<RS> r;
-      load_pair<RS>(P, r);
-      const float col[3] = {r.p1.w, r.p2.w, r.p3.w};
-      float g[kAcc + 3];
+    // the same pairs the forward walked for this half-tile
+    const unsigned long long m0 = __ballot((pf[lane] >> wv) & 1u);
+    const unsigned long long m1 = __ballot((pf[lane + 64] >> wv) & 1u);
+    bool wave_done = false;
+    for (int hh = 0; hh < 2 && !wave_done; hh++) {
+      unsigned long long m = hh ? m1 : m0;
+      while (m) {
+        const uint32_t q = 64u * hh + (uint32_t)__builtin_ctzll(m);
+        m &= m - 1ull;
+        const uint32_t idx = b + q;
+        if (__ballot(idx < last[0] || idx < last[1]) == 0ull) { wave_done = true; break; }
+        const float4* P = &pd[q * S];
+        PairRegs<RS> r;
+        load_pair<RS>(P, r);
+        Eval ev[2];
 #pragma unroll
-      for (int j = 0; j < kAcc + 3; j++) g[j] = 0.0f;
-      bool hit[2];
-      float wgt[2], Tb[2];
+        for (int k = 0; k < 2; k++) eval_test<RS>(r, P, u[k], v[k], dt[k], &ev[k]);
+        bool hit[2];
+        hit[0] = ev[0].ok && idx < last[0];
+        hit[1] = ev[1].ok && idx < last[1];
+        if (__ballot(hit[0] || hit[1]) == 0ull) continue;  // wave-uniform
+        const float4 colv = pair_colour<RS>(P);
+        const float col[3] = {colv.x, colv.y, colv.z};
+        float g[kAcc + 3];
 #pragma unroll
-      for (int k = 0; k < 2; k++) {
-        Eval ev;
-        eval_pair<RS>(r, P, u[k], v[k], dt[k], th.alpha_min, th.alpha_max, &ev);
-        hit[k] = ev.ok && idx < last[k];
-        Tb[k] = T[k];
-        wgt[k] = hit[k] ? ev.a * T[k] : 0.0f;
-        const float Tn = T[k] * (1.0f - ev.a);
-        T[k] = hit[k] ? Tn : T[k];
-        g[kAcc] += wgt[k] * gC[k][0];
-        g[kAcc + 1] += wgt[k] * gC[k][1];
-        g[kAcc + 2] += wgt[k] * gC[k][2];
-        // A_j includes this contributor: (S_after + T_N bg) = C - C_<=j, in FP64
-        double R0 = Co[k][0] - fma((double)wgt[k], (double)col[0], A[k][0]);
-        double R1 = Co[k][1] - fma((double)wgt[k], (double)col[1], A[k][1]);
-        double R2 = Co[k][2] - fma((double)wgt[k], (double)col[2], A[k][2]);
-        const float inv1m = 1.0f / (1.0f - ev.a);
-        float gA = gC[k][0] * (col[0] * Tb[k] - (float)R0 * inv1m) +
-                   gC[k][1] * (col[1] * Tb[k] - (float)R1 * inv1m) +
-                   gC[k][2] * (col[2] * Tb[k] - (float)R2 * inv1m) - gT[k] * TN[k] * inv1m;
-        const bool geo = hit[k] && !ev.clamped;  // alpha = alpha_max carries no gradient
-        gA = geo ? gA : 0.0f;
-        g[9] += gA * ev.ex;
-        const float c = -ev.a * gA;  // 2 dL/domega^2
-        float3 p = cross3f(ev.dg, ev.cr);
-        p = f3(p.x * ev.idd, p.y * ev.idd, p.z * ev.idd);
-        const float3 cp = f3(c * p.x, c * p.y, c * p.z);
-        g[0] += cp.x * p.x; g[1] += cp.x * p.y; g[2] += cp.x * p.z;
-        g[3] += cp.y * p.y; g[4] += cp.y * p.z; g[5] += cp.z * p.z;
-        g[6] += cp.x; g[7] += cp.y; g[8] += cp.z;
-      }
-      if (__ballot(hit[0] || hit[1]) == 0ull) continue;  // wave-uniform
+        for (int j = 0; j < kAcc + 3; j++) g[j] = 0.0f;
+        float wgt[2];
 #pragma unroll
-      for (int k = 0; k < 2; k++) {
-        const double w = (double)wgt[k];
-        A[k][0] = fma(w, (double)col[0], A[k][0]);
-        A[k][1] = fma(w, (double)col[1], A[k][1]);
-        A[k][2] = fma(w, (double)col[2], A[k][2]);
-      }
+        for (int k = 0; k < 2; k++) {
+          eval_alpha<RS>(r, th.alpha_max, &ev[k]);
+          const float Tb = T[k];
+          wgt[k] = hit[k] ? ev[k].a * Tb : 0.0f;
+          const float Tn = Tb * (1.0f - ev[k].a);
+          T[k] = hit[k] ? Tn : Tb;
+          g[kAcc] += wgt[k] * gC[k][0];
+          g[kAcc + 1] += wgt[k] * gC[k][1];
+          g[kAcc + 2] += wgt[k] * gC[k][2];
+          // A_j includes this contributor: (S_after + T_N bg) = C - C_<=j, in FP64
+          double R0 = Co[k][0] - fma((double)wgt[k], (double)col[0], A[k][0]);
+          double R1 = Co[k][1] - fma((double)wgt[k], (double)col[1], A[k][1]);
+          double R2 = Co[k][2] - fma((double)wgt[k], (double)col[2], A[k][2]);
+          const float inv1m = 1.0f / (1.0f - ev[k].a);
+          float gA = gC[k][0] * (col[0] * Tb - (float)R0 * inv1m) +
+                     gC[k][1] * (col[1] * Tb - (float)R1 * inv1m) +
+                     gC[k][2] * (col[2] * Tb - (float)R2 * inv1m) - gT[k] * TN[k] * inv1m;
+          const bool geo = hit[k] && !ev[k].clamped;  // alpha = alpha_max carries no gradient
+          gA = geo ? gA : 0.0f;
+          // rho = exp(-omega^2 / 2) = 2^(-omega'^2)
+          const float rho = __builtin_amdgcn_exp2f(-ev[k].cc * ev[k].idd);
+          g[9] += gA * rho;
+          const float c = -ev[k].a * gA;  // 2 dL/domega^2
+          float3 dg, cr;
+          pair_vectors<RS>(P, ev[k], u[k], v[k], &dg, &cr);
+          float3 p = cross3f(dg, cr);
+          p = f3(p.x * ev[k].idd, p.y * ev[k].idd, p.z * ev[k].idd);
+          const float3 cp = f3(c * p.x, c * p.y, c * p.z);
+          g[0] += cp.x * p.x; g[1] += cp.x * p.y; g[2] += cp.x * p.z;
+          g[3] += cp.y * p.y; g[4] += cp.y * p.z; g[5] += cp.z * p.z;
+          g[6] += cp.x; g[7] += cp.y; g[8] += cp.z;
+        }
 #pragma unroll
-      for (int j = 0; j < kAcc + 3; j++) g[j] = wave_sum(g[j]);
-      if (lane == 0) {
-        uint32_t e = pe[q];
-        int i = (int)(e - (uint32_t)cam_idx * (uint32_t)n);
+        for (int k = 0; k < 2; k++) {
+          const double w = (double)wgt[k];
+          A[k][0] = fma(w, (double)col[0], A[k][0]);
+          A[k][1] = fma(w, (double)col[1], A[k][1]);
+          A[k][2] = fma(w, (double)col[2], A[k][2]);
+        }
 #pragma unroll
-        for (int j = 0; j < kAcc; j++)
-          if (g[j] != 0.0f) atomicAdd(&acc[(long long)i * kAcc + j], g[j]);
+        for (int j = 0; j < kAcc + 3; j++) g[j] = wave_sum(g[j]);
+        if (lane == 0) {
+          uint32_t e = pe[q];
+          int i = (int)(e - (uint32_t)cam_idx * (uint32_t)n);
 #pragma unroll
-        for (int j = 0; j < 3; j++)
-          if (g[kAcc + j] != 0.0f) atomicAdd(&acc_rgb[3 * (long long)e + j], g[kAcc + j]);
+          for (int j = 0; j < kAcc; j++)
+            if (g[j] != 0.0f) atomicAdd(&acc[(long long)i * kAcc + j], (double)g[j]);
+#pragma unroll
+          for (int j = 0; j < 3; j++)
+            if (g[kAcc + j] != 0.0f) atomicAdd(&acc_rgb[3 * (long long)e + j], (double)g[kAcc + j]);
+        }
       }
     }
   }
 }
 
-// K7a: camera-independent part of the per-particle chain; also zeroes g_sh.
+// K7a: camera-independent part of the per-particle chain (FP64: the
+// quaternion gradient is a difference of terms of the size of dL/dR); also
+// zeroes g_sh.
 __global__ void particle_grad_kernel(int n, int K, const float* __restrict__ scales,
-                                     const float* __restrict__ quats, const float* __restrict__ acc,
+                                     const float* __restrict__ quats, const double* __restrict__ acc,
                                      float* __restrict__ g_means, float* __restrict__ g_scales,
                                      float* __restrict__ g_quats, float* __restrict__ g_opac,
                                      float* __restrict__ g_sh) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float* a = acc + (long long)i * kAcc;
-  const float G[9] = {a[0], a[1], a[2], a[1], a[3], a[4], a[2], a[4], a[5]};
-  const float h[3] = {a[6], a[7], a[8]};
-  float s[3] = {scales[3 * i], scales[3 * i + 1], scales[3 * i + 2]};
-  float4 q = reinterpret_cast<const float4*>(quats)[i];
-  float R[9];
-  quat_to_rot(q, R);
+  const double* a = acc + (long long)i * kAcc;
+  const double G[9] = {a[0], a[1], a[2], a[1], a[3], a[4], a[2], a[4], a[5]};
+  const double h[3] = {a[6], a[7], a[8]};
+  const double s[3] = {scales[3 * i], scales[3 * i + 1], scales[3 * i + 2]};
+  const float4 qf = reinterpret_cast<const float4*>(quats)[i];
+  // R(q / |q|), q = (w, x, y, z)
+  const double qn = sqrt((double)qf.x * qf.x + (double)qf.y * qf.y + (double)qf.z * qf.z +
+                         (double)qf.w * qf.w);
+  const double iq = 1.0 / qn;
+  const double w = qf.x * iq, x = qf.y * iq, y = qf.z * iq, z = qf.w * iq;
+  const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                       2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                       2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
   // dL/ds_k = -G_kk / s_k
-  g_scales[3 * i] = -G[0] / s[0];
-  g_scales[3 * i + 1] = -G[4] / s[1];
-  g_scales[3 * i + 2] = -G[8] / s[2];
+  g_scales[3 * i] = (float)(-G[0] / s[0]);
+  g_scales[3 * i + 1] = (float)(-G[4] / s[1]);
+  g_scales[3 * i + 2] = (float)(-G[8] / s[2]);
   // dL/dmu = -R S^-1 h
-  float hs[3] = {h[0] / s[0], h[1] / s[1], h[2] / s[2]};
-  for (int r = 0; r < 3; r++) g_means[3 * i + r] = -(R[3 * r] * hs[0] + R[3 * r + 1] * hs[1] + R[3 * r + 2] * hs[2]);
+  const double hs[3] = {h[0] / s[0], h[1] / s[1], h[2] / s[2]};
+  for (int r = 0; r < 3; r++)
+    g_means[3 * i + r] = (float)(-(R[3 * r] * hs[0] + R[3 * r + 1] * hs[1] + R[3 * r + 2] * hs[2]));
   // dL/dR = R S G S^-1
-  float X[9];  // S G S^-1
+  double X[9];  // S G S^-1
   for (int l = 0; l < 3; l++)
     for (int k = 0; k < 3; k++) X[3 * l + k] = s[l] * G[3 * l + k] / s[k];
-  float gR[9];
+  double gR[9];
   for (int j = 0; j < 3; j++)
     for (int k = 0; k < 3; k++)
       gR[3 * j + k] = R[3 * j] * X[k] + R[3 * j + 1] * X[3 + k] + R[3 * j + 2] * X[6 + k];
   // through R(q/|q|):  R entries are quadratic in (w, x, y, z)
-  float qn = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w), iq = 1.0f / qn;
-  float w = q.x * iq, x = q.y * iq, y = q.z * iq, z = q.w * iq;
-  float gw = 2.f * (x * (gR[7] - gR[5]) + y * (gR[2] - gR[6]) + z * (gR[3] - gR[1]));
-  float gx = 2.f * (w * (gR[7] - gR[5]) + y * (gR[1] + gR[3]) + z * (gR[2] + gR[6]) - 2.f * x * (gR[4] + gR[8]));
-  float gy = 2.f * (w * (gR[2] - gR[6]) + x * (gR[1] + gR[3]) + z * (gR[5] + gR[7]) - 2.f * y * (gR[0] + gR[8]));
-  float gz = 2.f * (w * (gR[3] - gR[1]) + x * (gR[2] + gR[6]) + y * (gR[5] + gR[7]) - 2.f * z * (gR[0] + gR[4]));
-  float pdot = w * gw + x * gx + y * gy + z * gz;
+  const double gw = 2 * (x * (gR[7] - gR[5]) + y * (gR[2] - gR[6]) + z * (gR[3] - gR[1]));
+  const double gx = 2 * (w * (gR[7] - gR[5]) + y * (gR[1] + gR[3]) + z * (gR[2] + gR[6]) -
+                         2 * x * (gR[4] + gR[8]));
+  const double gy = 2 * (w * (gR[2] - gR[6]) + x * (gR[1] + gR[3]) + z * (gR[5] + gR[7]) -
+                         2 * y * (gR[0] + gR[8]));
+  const double gz = 2 * (w * (gR[3] - gR[1]) + x * (gR[2] + gR[6]) + y * (gR[5] + gR[7]) -
+                         2 * z * (gR[0] + gR[4]));
+  const double pdot = w * gw + x * gx + y * gy + z * gz;
   reinterpret_cast<float4*>(g_quats)[i] =
-      make_float4((gw - w * pdot) * iq, (gx - x * pdot) * iq, (gy - y * pdot) * iq, (gz - z * pdot) * iq);
-  g_opac[i] = a[9];
+      make_float4((float)((gw - w * pdot) * iq), (float)((gx - x * pdot) * iq),
+                  (float)((gy - y * pdot) * iq), (float)((gz - z * pdot) * iq));
+  g_opac[i] = (float)a[9];
   float* gs = g_sh + (long long)i * K * 3;
   for (int k = 0; k < K * 3; k++) gs[k] = 0.0f;
 }
@@ -218,13 +252,13 @@ __global__ void particle_grad_kernel(int n, int K, const float* __restrict__ sca
 template <int DEG>
 __global__ void sh_grad_kernel(int n, int cam_idx, DevCam cam, Thresholds th,
                                const float* __restrict__ means, const float* __restrict__ sh,
-                               const float* __restrict__ rgb, const float* __restrict__ acc_rgb,
+                               const float* __restrict__ rgb, const double* __restrict__ acc_rgb,
                                float* __restrict__ g_means, float* __restrict__ g_sh) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   long long e = (long long)cam_idx * n + i;
-  float gr[3] = {acc_rgb[3 * e], acc_rgb[3 * e + 1], acc_rgb[3 * e + 2]};
+  const float gr[3] = {(float)acc_rgb[3 * e], (float)acc_rgb[3 * e + 1], (float)acc_rgb[3 * e + 2]};
   bool live[3];
   for (int c = 0; c < 3; c++) live[c] = gr[c] != 0.0f && rgb[3 * e + c] > 0.0f;
   if (!live[0] && !live[1] && !live[2]) return;
@@ -260,9 +294,9 @@ __global__ void sh_grad_kernel(int n, int cam_idx, DevCam cam, Thresholds th,
   g_means[3 * i + 2] += (gd.z - d.z * pdd) * id;
 }
 
-__global__ void zero_f32_kernel(float* __restrict__ p, long long m) {
+__global__ void zero_f64_kernel(double* __restrict__ p, long long m) {
   long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < m) p[j] = 0.0f;
+  if (j < m) p[j] = 0.0;
 }
 
 }  // namespace gut
@@ -271,8 +305,8 @@ using namespace gut;
 
 extern "C" size_t gut_render_bwd_workspace_bytes(int64_t n, int32_t n_cams) {
   if (n < 0 || n_cams <= 0) return 0;
-  size_t a = ((size_t)n * kAcc * 4 + 255) & ~size_t(255);
-  return a + (size_t)n * n_cams * 3 * 4 + 256;
+  size_t a = ((size_t)n * kAcc * 8 + 255) & ~size_t(255);
+  return a + (size_t)n * n_cams * 3 * 8 + 256;
 }
 
 extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected* proj,
@@ -310,12 +344,12 @@ extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected
   if ((st = prepare_cams(cams, n_cams, *p, dc, nullptr, nullptr)) != GUT_OK) return st;
   if (n == 0) return GUT_OK;
   hipStream_t s = (hipStream_t)stream;
-  float* acc = (float*)ws;
-  float* acc_rgb = (float*)((char*)ws + (((size_t)n * kAcc * 4 + 255) & ~size_t(255)));
+  double* acc = (double*)ws;
+  double* acc_rgb = (double*)((char*)ws + (((size_t)n * kAcc * 8 + 255) & ~size_t(255)));
   long long m1 = n * kAcc, m2 = n * n_cams * 3;
-  zero_f32_kernel<<<(unsigned)((m1 + 255) / 256), 256, 0, s>>>(acc, m1);
+  zero_f64_kernel<<<(unsigned)((m1 + 255) / 256), 256, 0, s>>>(acc, m1);
   GUT_LAUNCH_CHECK();
-  zero_f32_kernel<<<(unsigned)((m2 + 255) / 256), 256, 0, s>>>(acc_rgb, m2);
+  zero_f64_kernel<<<(unsigned)((m2 + 255) / 256), 256, 0, s>>>(acc_rgb, m2);
   GUT_LAUNCH_CHECK();
   Thresholds th = make_thresholds(*p);
   for (int c = 0; c < n_cams; c++) {

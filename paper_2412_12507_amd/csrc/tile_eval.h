@@ -70,22 +70,102 @@ __device__ inline bool pixel_ray(const DevCam& cam, const TileFrameD& F, int px,
   return valid;
 }
 
-template <bool RS>
+// log2(e) / 2: omega^2 / 2 in natural units is omega^2 * kHalfLog2e in log2 units.
+constexpr double kHalfLog2e = 0.72134752044448170368;
+
+// Pair slots (float4 each) kept in LDS for one (tile, particle) pair.
+//
+// Global shutter.  The two quadratic forms of a pixel's (u, v) that decide
+// the response are factored in FP64 (QR of the affine maps (u, v) -> vector)
+// into sums of squares,
+//   |o_g x d_g|^2 log2(e)/2 = (f1 + r11 u + r12 v)^2 + (f2 + r22 v)^2 + f3
+//   |d_g|^2                 = (g1 + h11 u + h12 v)^2 + (g2 + h22 v)^2 + g3
+// so a pixel needs 10 FMAs for both and no term cancels beyond what the
+// affine maps themselves carry.
+//   0: f1 r11 r12 Kp    1: f2 r22 f3 lsig    2: g1 h11 h12 mixed
+//   3: g2 h22 g3 -      4: colour r g b -    5: s ta tb -
+// and, for the backward only, the vectors for the closest point p:
+//   6: d_g(n).xyz w.x   7: d_g(e1).xyz w.y   8: d_g(e2).xyz w.z
+//   9: A.xyz B.x       10: B.y B.z - -
+// Rolling shutter.  The origin moves with the row, so the cross product is
+// bilinear in (u, v) and dt and is formed from its vectors per pixel:
+//   0: d_g(n).xyz mixed  1: d_g(e1).xyz lsig  2: d_g(e2).xyz Kp
+//   3: w.xyz ta          4: A.xyz tb          5: B.xyz s
+//   6: colour r g b -    7: (m x d_g(n)).xyz m.d_g(n)
+//   8: (m x d_g(e1)).xyz m.d_g(e1)               9: (m x d_g(e2)).xyz m.d_g(e2)
+// Here w = o_g x d_g(n), A = o_g x d_g(e1), B = o_g x d_g(e2),
+// s, ta, tb = o_g . d_g(.) (the tau_max > 0 test, needed per pixel only when
+// its sign varies over the tile: mixed = -1), lsig = log2(sigma) and
+// Kp = log2(sigma / alpha_min) (-1: never contributes), so that
+//   alpha = min(2^(lsig - omega'^2), alpha_max),  alpha >= alpha_min <=> omega'^2 <= Kp
+// with omega'^2 = omega^2 log2(e) / 2.
+template <bool RS, bool BWD>
 struct Slots {
-  static constexpr int N = RS ? 10 : 7;
+  static constexpr int N = RS ? 10 : (BWD ? 11 : 6);
 };
 
-// Per-pair terms, FP64 -> FP32 slots:
-//   0: d_g(n).xyz, sigma (negated: sign test needed per pixel; 0: never)
-//   1: d_g(e1).xyz, r    2: d_g(e2).xyz, g    3: w.xyz, b
-//   4: A.xyz, s          5: B.xyz, ta          6: tb, -, -, -
-//   RS: 7: (m x d_g(n)).xyz, m.d_g(n)  8: (m x d_g(e1)).xyz, m.d_g(e1)
-//       9: (m x d_g(e2)).xyz, m.d_g(e2)
-// where s, ta, tb are o_g . d_g(.) for the tau_max > 0 test.
-template <bool RS>
-__device__ inline void pair_setup(const float4* __restrict__ record, const float* __restrict__ rgb,
-                                  long long e, int i, const TileFrameD& F, const DevCam& cam,
-                                  float umax, float vmax, float dtmax, float4* out) {
+// QR of the affine map (u, v) -> c0 + u c1 + v c2 (FP64, Gram-Schmidt with
+// one re-orthogonalisation): |c0 + u c1 + v c2|^2 =
+// (q[0] + q[1] u + q[2] v)^2 + (q[3] + q[4] v)^2 + q[5].
+__device__ inline void affine_qr(d3 c0, d3 c1, d3 c2, double q[6]) {
+  const double r11 = sqrt(dot(c1, c1));
+  const d3 a1 = r11 > 0.0 ? scl(c1, 1.0 / r11) : mk3(0, 0, 0);
+  double r12 = dot(c2, a1);
+  d3 b = sub(c2, scl(a1, r12));
+  const double r12b = dot(b, a1);
+  r12 += r12b;
+  b = sub(b, scl(a1, r12b));
+  const double r22 = sqrt(dot(b, b));
+  const d3 a2 = r22 > 0.0 ? scl(b, 1.0 / r22) : mk3(0, 0, 0);
+  double f1 = dot(c0, a1), f2 = dot(c0, a2);
+  d3 rem = sub(sub(c0, scl(a1, f1)), scl(a2, f2));
+  const double e1 = dot(rem, a1), e2 = dot(rem, a2);
+  f1 += e1;
+  f2 += e2;
+  rem = sub(sub(rem, scl(a1, e1)), scl(a2, e2));
+  q[0] = f1; q[1] = r11; q[2] = r12; q[3] = f2; q[4] = r22; q[5] = dot(rem, rem);
+}
+
+// Per-wave culling.  With d_g = D x, D = [d_g(n) d_g(e1) d_g(e2)],
+// x = (1, u, v), the pixels where omega^2 <= K' form {x : x^T N x <= 0} with
+// N_ij = (o_g x D_i).(o_g x D_j) - K' D_i.D_j  (Lagrange's identity on
+// |o_g|^2 |d_g|^2 - (o_g.d_g)^2 - K' |d_g|^2), i.e. an ellipse in (u, v)
+// that is tested exactly against each wave's pixel box.  K' carries a 1e-3
+// relative margin (and, under a rolling shutter, the distance the ray origin
+// moves within the tile, which bounds how far the line moves), so a culled
+// pair fails the per-pixel FP32 test for every pixel of the wave (that
+// test's own rounding is ~1e-6 relative) and culling changes no result.
+// Forward and backward cull identically.
+struct WaveBoxes {
+  float u0[4], u1[4], v0[4], v1[4];
+};
+
+// Does the ellipse qmin + [du dv] [[N11 N12] [N12 N22]] [du dv]^T <= 0
+// (qmin < 0, matrix positive definite; coordinates relative to its centre)
+// meet the box [a0, a1] x [b0, b1]?  The quadratic is convex, so its minimum
+// over the box is at the centre if the centre is inside, else on an edge,
+// where it is a 1D quadratic minimised in closed form and clamped.
+__device__ inline bool ellipse_meets_box(double qmin, double N11, double N12, double N22,
+                                         double a0, double a1, double b0, double b1) {
+  if (a0 <= 0.0 && a1 >= 0.0 && b0 <= 0.0 && b1 >= 0.0) return true;
+  const double slack = -1e-6 * qmin;
+  // edge with one offset x fixed; the other offset y ranges over [lo, hi]
+  auto edge = [&](double x, double lo, double hi, double Nxx, double Nyy) {
+    const double y = fmin(fmax(-N12 * x / Nyy, lo), hi);
+    return qmin + Nxx * x * x + 2.0 * N12 * x * y + Nyy * y * y <= slack;
+  };
+  return edge(a0, b0, b1, N11, N22) || edge(a1, b0, b1, N11, N22) ||
+         edge(b0, a0, a1, N22, N11) || edge(b1, a0, a1, N22, N11);
+}
+
+// Forms a pair's slots (FP64 -> FP32) and returns one bit per wave of the
+// block: bit k set when wave k's pixel box may see alpha >= alpha_min.
+template <bool RS, bool BWD>
+__device__ inline unsigned pair_setup(const float4* __restrict__ record,
+                                      const float* __restrict__ rgb, long long e, int i,
+                                      const TileFrameD& F, const DevCam& cam, float umax,
+                                      float vmax, float dtmax, float amin, const WaveBoxes& wb,
+                                      int nwaves, float4* out) {
   float4 r0 = record[4 * (long long)i], r1 = record[4 * (long long)i + 1];
   float4 r2 = record[4 * (long long)i + 2], r3 = record[4 * (long long)i + 3];
   const double M[9] = {r1.x, r1.y, r1.z, r2.x, r2.y, r2.z, r3.x, r3.y, r3.z};
@@ -98,97 +178,195 @@ __device__ inline void pair_setup(const float4* __restrict__ record, const float
   double s = dot(og, dn), ta = dot(og, da), tb = dot(og, db);
   double spread = umax * fabs(ta) + vmax * fabs(tb);
   d3 w2 = mk3(0, 0, 0), A2 = w2, B2 = w2;
-  double s2 = 0, ta2 = 0, tb2 = 0;
+  double s2 = 0, ta2 = 0, tb2 = 0, mlen = 0;
   if (RS) {
     d3 m = mv(M, mk3(cam.dc[0], cam.dc[1], cam.dc[2]));
     w2 = cross(m, dn); A2 = cross(m, da); B2 = cross(m, db);
     s2 = dot(m, dn); ta2 = dot(m, da); tb2 = dot(m, db);
     spread += dtmax * (fabs(s2) + umax * fabs(ta2) + vmax * fabs(tb2));
+    mlen = sqrt(dot(m, m));
   }
-  float sig = r0.w;
+  const float sigma = r0.w;
+  bool never = false, mixed = false;
   if (s + spread < 0.0) {
     // o_g . d_g < 0 (tau_max > 0) for every ray of the tile
   } else if (s - spread >= 0.0) {
-    sig = 0.0f;  // tau_max <= 0 for every ray: never contributes
+    never = true;  // tau_max <= 0 for every ray
   } else {
-    sig = -sig;  // mixed: decide per pixel
+    mixed = true;  // decide per pixel
+  }
+  const float lsig = log2f(sigma);
+  const float Kp = (!never && sigma >= amin) ? lsig - log2f(amin) : -1.0f;
+  unsigned flags = 0;
+  if (Kp >= 0.0f) {
+    // the per-pixel test uses this FP32 Kp; cull with it in natural units
+    double Kc = (double)Kp / kHalfLog2e * (1.0 + 1e-3) + 1e-5;
+    if (RS) {
+      const double r = sqrt(Kc) + dtmax * mlen * (1.0 + 1e-6);
+      Kc = r * r;
+    }
+    const unsigned all = (1u << nwaves) - 1u;
+    if (dot(og, og) <= Kc) {
+      flags = all;  // the ray origin is inside the particle's alpha_min ellipsoid
+    } else {
+      const double N00 = dot(w, w) - Kc * dot(dn, dn), N01 = dot(w, A) - Kc * dot(dn, da);
+      const double N02 = dot(w, B) - Kc * dot(dn, db), N11 = dot(A, A) - Kc * dot(da, da);
+      const double N12 = dot(A, B) - Kc * dot(da, db), N22 = dot(B, B) - Kc * dot(db, db);
+      const double det = N11 * N22 - N12 * N12;
+      if (!(N11 > 0.0) || !(N22 > 0.0) || !(det > 1e-9 * N11 * N22)) {
+        flags = all;  // not a well-conditioned ellipse in the tile plane: no culling
+      } else {
+        const double idet = 1.0 / det;
+        const double uc = (N02 * N12 - N01 * N22) * idet, vc = (N01 * N12 - N02 * N11) * idet;
+        const double qmin = N00 + N01 * uc + N02 * vc;
+        if (qmin < 0.0) {
+          for (int k = 0; k < nwaves; k++)
+            if (ellipse_meets_box(qmin, N11, N12, N22, wb.u0[k] - uc, wb.u1[k] - uc,
+                                  wb.v0[k] - vc, wb.v1[k] - vc))
+              flags |= 1u << k;
+        }
+      }
+    }
   }
   const float* c = rgb + 3 * e;
-  out[0] = make_float4((float)dn.x, (float)dn.y, (float)dn.z, sig);
-  out[1] = make_float4((float)da.x, (float)da.y, (float)da.z, c[0]);
-  out[2] = make_float4((float)db.x, (float)db.y, (float)db.z, c[1]);
-  out[3] = make_float4((float)w.x, (float)w.y, (float)w.z, c[2]);
-  out[4] = make_float4((float)A.x, (float)A.y, (float)A.z, (float)s);
-  out[5] = make_float4((float)B.x, (float)B.y, (float)B.z, (float)ta);
-  out[6] = make_float4((float)tb, 0.0f, 0.0f, 0.0f);
-  if (RS) {
+  const float mflag = mixed ? -1.0f : 1.0f;
+  if (!RS) {
+    const double sc = sqrt(kHalfLog2e);
+    double qc[6], qd[6];
+    affine_qr(scl(w, sc), scl(A, sc), scl(B, sc), qc);
+    affine_qr(dn, da, db, qd);
+    out[0] = make_float4((float)qc[0], (float)qc[1], (float)qc[2], Kp);
+    out[1] = make_float4((float)qc[3], (float)qc[4], (float)qc[5], lsig);
+    out[2] = make_float4((float)qd[0], (float)qd[1], (float)qd[2], mflag);
+    out[3] = make_float4((float)qd[3], (float)qd[4], (float)qd[5], 0.0f);
+    out[4] = make_float4(c[0], c[1], c[2], 0.0f);
+    out[5] = make_float4((float)s, (float)ta, (float)tb, 0.0f);
+    if (BWD) {
+      out[6] = make_float4((float)dn.x, (float)dn.y, (float)dn.z, (float)w.x);
+      out[7] = make_float4((float)da.x, (float)da.y, (float)da.z, (float)w.y);
+      out[8] = make_float4((float)db.x, (float)db.y, (float)db.z, (float)w.z);
+      out[9] = make_float4((float)A.x, (float)A.y, (float)A.z, (float)B.x);
+      out[10] = make_float4((float)B.y, (float)B.z, 0.0f, 0.0f);
+    }
+  } else {
+    out[0] = make_float4((float)dn.x, (float)dn.y, (float)dn.z, mflag);
+    out[1] = make_float4((float)da.x, (float)da.y, (float)da.z, lsig);
+    out[2] = make_float4((float)db.x, (float)db.y, (float)db.z, Kp);
+    out[3] = make_float4((float)w.x, (float)w.y, (float)w.z, (float)ta);
+    out[4] = make_float4((float)A.x, (float)A.y, (float)A.z, (float)tb);
+    out[5] = make_float4((float)B.x, (float)B.y, (float)B.z, (float)s);
+    out[6] = make_float4(c[0], c[1], c[2], 0.0f);
     out[7] = make_float4((float)w2.x, (float)w2.y, (float)w2.z, (float)s2);
     out[8] = make_float4((float)A2.x, (float)A2.y, (float)A2.z, (float)ta2);
     out[9] = make_float4((float)B2.x, (float)B2.y, (float)B2.z, (float)tb2);
   }
+  return flags;
 }
 
 struct Eval {
-  float a;      // alpha after the alpha_max clamp (0 when the pair is skipped)
-  float ex;     // exp(-omega^2 / 2)
-  bool ok;      // tau_max > 0 and alpha >= alpha_min
-  bool clamped; // sigma * ex > alpha_max
-  float3 dg, cr;
-  float idd;    // 1 / |d_g|^2
+  float a;       // alpha after the alpha_max clamp (0 when the pair is skipped)
+  bool ok;       // tau_max > 0 and omega^2 <= K (alpha >= alpha_min)
+  bool clamped;  // sigma rho > alpha_max
+  float cc;      // omega'^2 |d_g|^2 (omega'^2 = omega^2 log2(e) / 2)
+  float dd;      // |d_g|^2
+  float idd;     // 1 / |d_g|^2
+  float3 dg, cr; // rolling shutter only: d_g and o_g x d_g
 };
 
-// One pair's terms, loaded from LDS once and shared by the pixels a thread owns.
+// One pair's decision terms, loaded from LDS once and shared by the pixels a thread owns.
 template <bool RS>
 struct PairRegs {
   float4 p0, p1, p2, p3, p4, p5;
   float4 p7, p8, p9;
   bool mixed;  // sign of o_g . d_g varies across the tile (wave-uniform)
+  float lsig, Kp;
 };
 
 template <bool RS>
 __device__ __forceinline__ void load_pair(const float4* P, PairRegs<RS>& r) {
-  r.p0 = P[0]; r.p1 = P[1]; r.p2 = P[2]; r.p3 = P[3]; r.p4 = P[4]; r.p5 = P[5];
-  if (RS) { r.p7 = P[7]; r.p8 = P[8]; r.p9 = P[9]; }
-  // every lane reads the same pair: move the flag to a scalar register
-  r.mixed = __builtin_amdgcn_readfirstlane(__float_as_int(r.p0.w)) < 0;
+  r.p0 = P[0]; r.p1 = P[1]; r.p2 = P[2]; r.p3 = P[3];
+  if (RS) {
+    r.p4 = P[4]; r.p5 = P[5]; r.p7 = P[7]; r.p8 = P[8]; r.p9 = P[9];
+    r.lsig = r.p1.w; r.Kp = r.p2.w;
+    // every lane reads the same pair: move the flag to a scalar register
+    r.mixed = __builtin_amdgcn_readfirstlane(__float_as_int(r.p0.w)) < 0;
+  } else {
+    r.lsig = r.p1.w; r.Kp = r.p0.w;
+    r.mixed = __builtin_amdgcn_readfirstlane(__float_as_int(r.p2.w)) < 0;
+  }
 }
 
-// alpha of one pair on one pixel ray (Eq. 11 and alpha = sigma rho), with no
-// divergent branches; o->ok is false if tau_max <= 0 or alpha < alpha_min.
+// Stage 1 of the response on one pixel ray (Eq. 11): omega'^2 |d_g|^2 and
+// |d_g|^2, and the test omega'^2 <= Kp (<=> alpha >= alpha_min) without any
+// transcendental.
 template <bool RS>
-__device__ __forceinline__ void eval_pair(const PairRegs<RS>& r, const float4* P, float u, float v,
-                                          float dt, float amin, float amax, Eval* o) {
-  float3 dg = f3(fmaf(v, r.p2.x, fmaf(u, r.p1.x, r.p0.x)), fmaf(v, r.p2.y, fmaf(u, r.p1.y, r.p0.y)),
-                 fmaf(v, r.p2.z, fmaf(u, r.p1.z, r.p0.z)));
-  float3 cr = f3(fmaf(v, r.p5.x, fmaf(u, r.p4.x, r.p3.x)), fmaf(v, r.p5.y, fmaf(u, r.p4.y, r.p3.y)),
-                 fmaf(v, r.p5.z, fmaf(u, r.p4.z, r.p3.z)));
-  if (RS) {
+__device__ __forceinline__ void eval_test(const PairRegs<RS>& r, const float4* P, float u, float v,
+                                          float dt, Eval* o) {
+  bool ok = true;
+  if (!RS) {
+    const float t1 = fmaf(v, r.p0.z, fmaf(u, r.p0.y, r.p0.x));
+    const float t2 = fmaf(v, r.p1.y, r.p1.x);
+    o->cc = fmaf(t1, t1, fmaf(t2, t2, r.p1.z));
+    const float e1 = fmaf(v, r.p2.z, fmaf(u, r.p2.y, r.p2.x));
+    const float e2 = fmaf(v, r.p3.y, r.p3.x);
+    o->dd = fmaf(e1, e1, fmaf(e2, e2, r.p3.z));
+    if (r.mixed) {  // rare, and uniform across the wave
+      const float4 p5 = P[5];
+      ok = fmaf(v, p5.z, fmaf(u, p5.y, p5.x)) < 0.0f;
+    }
+  } else {
+    float3 dg = f3(fmaf(v, r.p2.x, fmaf(u, r.p1.x, r.p0.x)), fmaf(v, r.p2.y, fmaf(u, r.p1.y, r.p0.y)),
+                   fmaf(v, r.p2.z, fmaf(u, r.p1.z, r.p0.z)));
+    float3 cr = f3(fmaf(v, r.p5.x, fmaf(u, r.p4.x, r.p3.x)), fmaf(v, r.p5.y, fmaf(u, r.p4.y, r.p3.y)),
+                   fmaf(v, r.p5.z, fmaf(u, r.p4.z, r.p3.z)));
     float3 m = f3(fmaf(v, r.p9.x, fmaf(u, r.p8.x, r.p7.x)), fmaf(v, r.p9.y, fmaf(u, r.p8.y, r.p7.y)),
                   fmaf(v, r.p9.z, fmaf(u, r.p8.z, r.p7.z)));
     cr = f3(fmaf(dt, m.x, cr.x), fmaf(dt, m.y, cr.y), fmaf(dt, m.z, cr.z));
+    if (r.mixed) {
+      float sg = fmaf(v, r.p4.w, fmaf(u, r.p3.w, r.p5.w));
+      sg = fmaf(dt, fmaf(v, r.p9.w, fmaf(u, r.p8.w, r.p7.w)), sg);
+      ok = sg < 0.0f;
+    }
+    o->dd = fmaf(dg.z, dg.z, fmaf(dg.y, dg.y, dg.x * dg.x));
+    o->cc = fmaf(cr.z, cr.z, fmaf(cr.y, cr.y, cr.x * cr.x)) * (float)kHalfLog2e;
+    o->dg = dg;
+    o->cr = cr;
   }
-  bool ok = true;
-  if (r.mixed) {  // rare, and uniform across the wave
-    float sg = fmaf(v, P[6].x, fmaf(u, r.p5.w, r.p4.w));
-    if (RS) sg = fmaf(dt, fmaf(v, r.p9.w, fmaf(u, r.p8.w, r.p7.w)), sg);
-    ok = sg < 0.0f;
-  }
-  const float sig = fabsf(r.p0.w);
-  float dd = fmaf(dg.z, dg.z, fmaf(dg.y, dg.y, dg.x * dg.x));
-  float cc = fmaf(cr.z, cr.z, fmaf(cr.y, cr.y, cr.x * cr.x));
-  float idd = __builtin_amdgcn_rcpf(dd);
-  // exp(-omega^2/2) = 2^(-omega^2 log2(e) / 2)
-  float ex = __builtin_amdgcn_exp2f((cc * idd) * -0.72134752044448170f);
-  float araw = sig * ex;
-  float a = fminf(araw, amax);
-  ok = ok && (a >= amin);
-  o->a = ok ? a : 0.0f;
-  o->ex = ex;
-  o->ok = ok;
-  o->clamped = araw > amax;
-  o->dg = dg;
-  o->cr = cr;
+  o->ok = ok && (o->cc <= r.Kp * o->dd);
+}
+
+// Stage 2 (only for waves where some pixel passed): alpha = min(sigma rho, alpha_max)
+// with sigma rho = 2^(lsig - omega'^2).
+template <bool RS>
+__device__ __forceinline__ void eval_alpha(const PairRegs<RS>& r, float amax, Eval* o) {
+  const float idd = __builtin_amdgcn_rcpf(o->dd);
+  const float araw = __builtin_amdgcn_exp2f(fmaf(-o->cc, idd, r.lsig));
   o->idd = idd;
+  o->clamped = araw > amax;
+  o->a = o->ok ? fminf(araw, amax) : 0.0f;
+}
+
+// Colour slot of a pair.
+template <bool RS>
+__device__ __forceinline__ float4 pair_colour(const float4* P) {
+  return RS ? P[6] : P[4];
+}
+
+// Backward only: d_g and o_g x d_g on the pixel ray (unscaled), for the
+// closest point p = d_g x (o_g x d_g) / |d_g|^2.
+template <bool RS>
+__device__ __forceinline__ void pair_vectors(const float4* P, const Eval& ev, float u, float v,
+                                             float3* dg, float3* cr) {
+  if (RS) {
+    *dg = ev.dg;
+    *cr = ev.cr;
+  } else {
+    const float4 q6 = P[6], q7 = P[7], q8 = P[8], q9 = P[9], q10 = P[10];
+    *dg = f3(fmaf(v, q8.x, fmaf(u, q7.x, q6.x)), fmaf(v, q8.y, fmaf(u, q7.y, q6.y)),
+             fmaf(v, q8.z, fmaf(u, q7.z, q6.z)));
+    *cr = f3(fmaf(v, q9.w, fmaf(u, q9.x, q6.w)), fmaf(v, q10.x, fmaf(u, q9.y, q7.w)),
+             fmaf(v, q10.y, fmaf(u, q9.z, q8.w)));
+  }
 }
 
 // Block-wide maxima of |u|, |v|, |dt| over the tile's valid pixels (NP per thread).
@@ -224,6 +402,30 @@ __device__ inline void tile_bounds(const float* u, const float* v, const float* 
   *umax = A * 1.0001f + 1e-7f;
   *vmax = B * 1.0001f + 1e-7f;
   *dtmax = Cc * 1.0001f + 1e-7f;
+}
+
+// Pixel box (u, v) of each wave's pixels, written to LDS by lane 0 of each
+// wave (NP pixels per thread).
+template <int NP>
+__device__ inline void wave_box(const float* u, const float* v, const bool* valid, WaveBoxes* wb) {
+  float a0 = 3e38f, a1 = -3e38f, b0 = 3e38f, b1 = -3e38f;
+#pragma unroll
+  for (int k = 0; k < NP; k++)
+    if (valid[k]) {
+      a0 = fminf(a0, u[k]); a1 = fmaxf(a1, u[k]);
+      b0 = fminf(b0, v[k]); b1 = fmaxf(b1, v[k]);
+    }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a0 = fminf(a0, __shfl_xor(a0, o, 64));
+    a1 = fmaxf(a1, __shfl_xor(a1, o, 64));
+    b0 = fminf(b0, __shfl_xor(b0, o, 64));
+    b1 = fmaxf(b1, __shfl_xor(b1, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    const int w = threadIdx.x >> 6;
+    wb->u0[w] = a0; wb->u1[w] = a1; wb->v0[w] = b0; wb->v1[w] = b1;
+  }
 }
 
 // Tile visited by block b: blocks are dealt round-robin to the 8 XCDs, so

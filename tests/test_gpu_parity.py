@@ -236,11 +236,15 @@ def test_autograd_function_matches_direct_call():
     loss.backward()
     proj, bins, img = R.forward(gs, [cam])
     g = R.render_backward(gs, proj, bins, [cam], img, w.reshape(-1, 3), torch.ones_like(img.T))
+    # per-particle sums are FP32 atomics whose order varies from run to run:
+    # agreement to FP32 summation noise, scaled by each tensor's largest entry
+    def close(a, b):
+        return torch.allclose(a, b, rtol=1e-4, atol=1e-6 * float(b.abs().max()) + 1e-12)
     for leaf, k in zip(leaves, ("means", "scales", "quats", "opacities", "sh")):
-        assert torch.allclose(leaf.grad, g[k], rtol=1e-5, atol=1e-7), k
+        assert close(leaf.grad, g[k]), k
     # recompute_projection gives the same gradients
     leaves2 = [t.clone().requires_grad_(True) for t in (gs.means, gs.scales, gs.quats, gs.opacities, gs.sh)]
     imgs2, Ts2 = R.render_gaussians(*leaves2, gs.sh_degree, [cam], recompute_projection=True)
     ((imgs2[0] * w).sum() + Ts2[0].sum()).backward()
     for a, b in zip(leaves, leaves2):
-        assert torch.allclose(a.grad, b.grad, rtol=1e-5, atol=1e-7)
+        assert close(a.grad, b.grad)
