@@ -140,7 +140,13 @@ size_t gut_bin_workspace_bytes(int64_t n, int32_t n_cams, int64_t pair_capacity)
 /* Global per-tile depth sort (Sec. 4.3): visible entries are sorted by
  * (depth, entry id), duplicated once per touched tile, and stably sorted by
  * global tile id with a hand-written LSD radix sort.
- *   tile_ranges [T,2] uint32  out: [start, end) of each tile in sorted_ids
+ *   tile_ranges [3T] uint32   out: [T,2] [start, end) of each tile in sorted_ids,
+ *                             then [T] the render order: for each camera, its
+ *                             camera-local tile indices with the longest lists
+ *                             first (bucketed by floor(log2(length)); order
+ *                             within a bucket unspecified), at the camera's
+ *                             tile offset.  gut_render and gut_render_bwd take
+ *                             tiles in this order to shorten the tail.
  *   sorted_ids  [pair_capacity] uint32 out: entry ids e = cam*n + i
  *   n_pairs     host int64*   out (nullable): number of pairs P
  * If P > pair_capacity nothing is written past the buffer, *n_pairs holds the

@@ -27,6 +27,7 @@ constexpr int kBChunk = kBThreads * kBItems;
 struct CamTiles {
   int base[kMaxCams];
   int tx[kMaxCams];
+  int count[kMaxCams];
 };
 
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -199,6 +200,35 @@ __global__ void ranges_kernel(const uint32_t* __restrict__ keys, int64_t m, uint
   if (i == m - 1 || keys[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
 }
 
+// Render order of one camera's tiles (one block per camera): a counting sort
+// of the tiles by bucket = bit length of the list length, longest first.
+// Only the schedule depends on it (every tile is rendered independently), so
+// the order within a bucket may vary from call to call.
+constexpr int kOrderThreads = 1024;
+__global__ void __launch_bounds__(kOrderThreads) order_kernel(const uint2* __restrict__ ranges,
+                                                             CamTiles ct, uint32_t* __restrict__ order) {
+  __shared__ unsigned cnt[33], cur[33];
+  const int c = blockIdx.x, base = ct.base[c], nt = ct.count[c];
+  for (int b = threadIdx.x; b < 33; b += blockDim.x) cnt[b] = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+    const uint2 r = ranges[base + t];
+    const int key = __clz(r.y - r.x);  // 32 - bit length: 0 for the longest lists
+    atomicAdd(&cnt[key], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned acc = 0;
+    for (int b = 0; b < 33; b++) { cur[b] = acc; acc += cnt[b]; }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+    const uint2 r = ranges[base + t];
+    const unsigned pos = atomicAdd(&cur[__clz(r.y - r.x)], 1u);
+    order[base + pos] = (uint32_t)t;
+  }
+}
+
 // Pinned host slot for the count read-back, one per host thread.
 struct PinnedSlot {
   void* p = nullptr;
@@ -289,6 +319,19 @@ gut_status bin_sort(const gut_projected* proj, int n, const DevCam* dc, int n_ca
   return GUT_OK;
 }
 
+// Render order after the ranges (tile_ranges[2T .. 3T)).
+gut_status bin_order(const DevCam* dc, int n_cams, int64_t T, uint32_t* tile_ranges, hipStream_t s) {
+  CamTiles ct;
+  for (int c = 0; c < n_cams; c++) {
+    ct.base[c] = dc[c].tile_base;
+    ct.tx[c] = dc[c].tiles_x;
+    ct.count[c] = dc[c].tiles_x * dc[c].tiles_y;
+  }
+  order_kernel<<<n_cams, kOrderThreads, 0, s>>>((const uint2*)tile_ranges, ct, tile_ranges + 2 * T);
+  GUT_LAUNCH_CHECK();
+  return GUT_OK;
+}
+
 }  // namespace gut
 
 using namespace gut;
@@ -338,5 +381,8 @@ extern "C" gut_status gut_bin(const gut_projected* proj, int64_t n, const gut_ca
     set_error("pair capacity %lld < required %llu", (long long)pair_capacity, (unsigned long long)P);
     return GUT_E_CAPACITY;
   }
-  return bin_sort(proj, (int)n, dc, n_cams, T, E, ews, nvis, P, pws, tile_ranges, sorted_ids, s);
+  if ((st = bin_sort(proj, (int)n, dc, n_cams, T, E, ews, nvis, P, pws, tile_ranges, sorted_ids,
+                     s)) != GUT_OK)
+    return st;
+  return bin_order(dc, n_cams, T, tile_ranges, s);
 }

@@ -96,9 +96,9 @@ gut_status project_launch(const gut_scene* scene, const DevCam* dc, int n_cams, 
                           hipStream_t s);
 gut_status render_batch_launch(const DevCam* d_cams, const DevCam* h_cams, int n_cams,
                                const Thresholds& th, int n, const uint32_t* ranges,
-                               const uint32_t* ids, const float* record, const float* rgb,
-                               float* const* d_outs, unsigned* d_counters, int* d_lists,
-                               int* h_lists, int n_blocks, hipStream_t s);
+                               const uint32_t* order, const uint32_t* ids, const float* record,
+                               const float* rgb, float* const* d_outs, unsigned* d_counters,
+                               int* d_lists, int* h_lists, int n_blocks, hipStream_t s);
 gut_status record_launch(const gut_scene* scene, float* record, hipStream_t s);
 size_t bin_entry_bytes(int64_t E);
 size_t bin_pair_bytes(int64_t cap);
@@ -107,6 +107,7 @@ gut_status bin_count(const gut_projected* proj, int64_t E, char* ews, uint32_t* 
 gut_status bin_sort(const gut_projected* proj, int n, const DevCam* dc, int n_cams, int64_t T,
                     int64_t E, char* ews, uint32_t nvis, uint64_t P, char* pws,
                     uint32_t* tile_ranges, uint32_t* sorted_ids, hipStream_t s);
+gut_status bin_order(const DevCam* dc, int n_cams, int64_t T, uint32_t* tile_ranges, hipStream_t s);
 
 // Radix sort / scan building blocks (sort.hip).
 size_t scan_temp_bytes(int64_t n);
@@ -172,7 +173,10 @@ __device__ inline d3 unproject_dir(const DevCam& c, double u, double v, bool* va
   *valid = td <= c.thetad_lim;
   double target = td < c.thetad_lim ? td : c.thetad_lim;
   double lo = 0.0, hi = c.theta_lim, th = target < hi ? target : hi;
-  for (int it = 0; it < 60; it++) {  // Newton on the bracket [lo, hi], bisecting when it leaves
+  // beyond the circle the clamp is theta_lim itself (a double root of
+  // theta_d(theta) - theta_d(theta_lim), where Newton would only crawl)
+  if (!*valid) th = c.theta_lim;
+  for (int it = 0; *valid && it < 60; it++) {  // Newton on [lo, hi], bisecting when it leaves
     double f = thetad_poly(c.k, th) - target;
     if (f == 0.0) break;
     if (f > 0) hi = th; else lo = th;

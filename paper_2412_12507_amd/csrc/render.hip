@@ -13,7 +13,9 @@
 // only when some lane of the wave passes it.  The walk is branch-free per
 // pixel (predicated updates); a wave leaves the batch as soon as all its
 // pixels have stopped, and the block stops when no pixel is still going.
-// Blocks are mapped to tiles so that each XCD gets a contiguous band.
+// Blocks take tiles in the render order from gut_bin (longest lists first)
+// and waves of long lists raise their issue priority, so the longest tiles
+// neither start last nor crawl behind short ones.
 #include "tile_eval.h"
 
 namespace gut {
@@ -50,10 +52,16 @@ __device__ __forceinline__ void render_tile(
   }
   float umax, vmax, dtmax;
   tile_bounds<2>(u, v, dt, active, red, &umax, &vmax, &dtmax);
+  const float l2amin = log2f(th.alpha_min);
   wave_box<2>(u, v, active, &wb);
 
   const uint2 rg = ranges[cam.tile_base + tile];
-  const uint32_t len = rg.y - rg.x;
+  const uint32_t len = __builtin_amdgcn_readfirstlane(rg.y - rg.x);
+  // long lists first in the schedule, and their waves first at issue
+  if (len >= 2048) __builtin_amdgcn_s_setprio(3);
+  else if (len >= 1024) __builtin_amdgcn_s_setprio(2);
+  else if (len >= 256) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
   // Colour accumulates in FP64 (three FMAs per contributing entry) so that
   // the backward can form suffix sums C - C_<=j without FP32 cancellation.
   float T[2] = {1.0f, 1.0f};
@@ -67,7 +75,7 @@ __device__ __forceinline__ void render_tile(
     if (b + t < len) {
       uint32_t e = ids[rg.x + b + t];
       fl = pair_setup<RS, false>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n), F, cam,
-                          umax, vmax, dtmax, th.alpha_min, wb, kRThreads / 64, &pd[t * S]);
+                          umax, vmax, dtmax, th.alpha_min, l2amin, wb, kRThreads / 64, &pd[t * S]);
     }
     pf[t] = fl;
     __syncthreads();
@@ -105,8 +113,9 @@ __device__ __forceinline__ void render_tile(
           done[k] = done[k] || stop;
         }
         if (__ballot(contrib[0] || contrib[1]) != 0ull) {
-          const float4 col = pair_colour<RS>(P);
-          const double c0 = col.x, c1 = col.y, c2 = col.z;
+          double col[3];
+          pair_colour<RS>(P, col);
+          const double c0 = col[0], c1 = col[1], c2 = col[2];
 #pragma unroll
           for (int k = 0; k < 2; k++) {
             const double w = (double)wgt[k];
@@ -132,33 +141,36 @@ __device__ __forceinline__ void render_tile(
   }
 }
 
+// One block per tile, taken in the render order (longest lists first).
 template <bool RS>
-__global__ void __launch_bounds__(kRThreads) render_kernel(
+__global__ void __launch_bounds__(kRThreads, 4) render_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, const uint2* __restrict__ ranges,
-    const uint32_t* __restrict__ ids, const float4* __restrict__ record,
-    const float* __restrict__ rgb, float* __restrict__ out_rgb, float* __restrict__ out_T,
-    uint32_t* __restrict__ out_nc, uint32_t* __restrict__ out_ne) {
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
+    const float4* __restrict__ record, const float* __restrict__ rgb, float* __restrict__ out_rgb,
+    float* __restrict__ out_T, uint32_t* __restrict__ out_nc, uint32_t* __restrict__ out_ne) {
   __shared__ float4 pd[kRBatch * Slots<RS, false>::N];
   __shared__ uint32_t pf[kRBatch];
   __shared__ TileFrameD F;
   __shared__ WaveBoxes wb;
   __shared__ float red[6];
-  const int tile = xcd_tile(blockIdx.x, cam.tiles_x * cam.tiles_y);
+  const int tile = (int)order[cam.tile_base + blockIdx.x];
   render_tile<RS>(cam, th, n, cam_idx, tile, ranges, ids, record, rgb, out_rgb, out_T, out_nc,
                   out_ne, cam.pixel_base, pd, pf, F, wb, red);
 }
 
 // Persistent render of the cameras of one shutter type in a multi-camera
-// batch.  Items are (camera, tile) over the listed cameras, in order; the
-// item range is cut into 8 contiguous chunks, one per XCD (blocks are dealt
-// to XCDs round-robin), each with its own counter; a block that drains its
-// XCD's chunk steals from the others, and leaves once every counter is past
-// its chunk.  Images go to outs[camera] ([H, W, 3]).
+// batch.  Items are (camera, k-th tile of its render order) over the listed
+// cameras, in order.  Item i belongs to XCD i % 8 (blocks are dealt to XCDs
+// round-robin), and each XCD has its own counter, so every XCD walks its
+// share longest-first; a block that drains its XCD's share steals from the
+// others, and leaves once every counter is past its share.  Images go to
+// outs[camera] ([H, W, 3]).
 template <bool RS>
-__global__ void __launch_bounds__(kRThreads) render_batch_kernel(
+__global__ void __launch_bounds__(kRThreads, 3) render_batch_kernel(
     const DevCam* __restrict__ cams, const int* __restrict__ cam_list,
     const int* __restrict__ item_start, int n_list, int n_items, unsigned* __restrict__ counters,
-    Thresholds th, int n, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
+    Thresholds th, int n, const uint2* __restrict__ ranges, const uint32_t* __restrict__ order,
+    const uint32_t* __restrict__ ids,
     const float4* __restrict__ record, const float* __restrict__ rgb, float* const* __restrict__ outs) {
   __shared__ float4 pd[kRBatch * Slots<RS, false>::N];
   __shared__ uint32_t pf[kRBatch];
@@ -170,15 +182,15 @@ __global__ void __launch_bounds__(kRThreads) render_batch_kernel(
   const int nx = 8;
   const int my = blockIdx.x % nx;
   const int q = n_items / nx, r = n_items % nx;
-  int probe = 0;  // which XCD chunk this block is draining (its own first)
+  int probe = 0;  // which XCD share this block is draining (its own first)
   while (true) {
     if (threadIdx.x == 0) {
       int it = -1;
       while (probe < nx) {
         int x = (my + probe) % nx;
-        int start = x * q + min(x, r), len = q + (x < r ? 1 : 0);
+        int len = q + (x < r ? 1 : 0);  // items x, x + 8, x + 16, ...
         unsigned k = atomicAdd(&counters[x], 1u);
-        if ((int)k < len) { it = start + (int)k; break; }
+        if ((int)k < len) { it = x + nx * (int)k; break; }
         probe++;
       }
       item_s = it;
@@ -196,8 +208,9 @@ __global__ void __launch_bounds__(kRThreads) render_batch_kernel(
       for (int w = threadIdx.x; w < (int)(sizeof(DevCam) / sizeof(int)); w += blockDim.x) dst[w] = src[w];
     }
     __syncthreads();
-    render_tile<RS>(cam_s, th, n, c, item - item_start[j], ranges, ids, record, rgb, outs[c],
-                    nullptr, nullptr, nullptr, 0, pd, pf, F, wb, red);
+    const int tile = (int)order[cam_s.tile_base + (item - item_start[j])];
+    render_tile<RS>(cam_s, th, n, c, tile, ranges, ids, record, rgb, outs[c], nullptr, nullptr,
+                    nullptr, 0, pd, pf, F, wb, red);
   }
 }
 
@@ -206,9 +219,9 @@ __global__ void __launch_bounds__(kRThreads) render_batch_kernel(
 // (2 x (kMaxCams + kMaxCams + 1) ints); d_counters 16 counters.
 gut_status render_batch_launch(const DevCam* d_cams, const DevCam* h_cams, int n_cams,
                                const Thresholds& th, int n, const uint32_t* ranges,
-                               const uint32_t* ids, const float* record, const float* rgb,
-                               float* const* d_outs, unsigned* d_counters, int* d_lists,
-                               int* h_lists, int n_blocks, hipStream_t s) {
+                               const uint32_t* order, const uint32_t* ids, const float* record,
+                               const float* rgb, float* const* d_outs, unsigned* d_counters,
+                               int* d_lists, int* h_lists, int n_blocks, hipStream_t s) {
   gut_status st = fill_u32(d_counters, 16, 0u, s);
   if (st != GUT_OK) return st;
   for (int type = 0; type < 2; type++) {
@@ -230,29 +243,29 @@ gut_status render_batch_launch(const DevCam* d_cams, const DevCam* h_cams, int n
     if (type == 1)
       render_batch_kernel<true><<<n_blocks, kRThreads, 0, s>>>(
           d_cams, dl, dl + kMaxCams, m, items, d_counters + 8 * type, th, n, (const uint2*)ranges,
-          ids, (const float4*)record, rgb, d_outs);
+          order, ids, (const float4*)record, rgb, d_outs);
     else
       render_batch_kernel<false><<<n_blocks, kRThreads, 0, s>>>(
           d_cams, dl, dl + kMaxCams, m, items, d_counters + 8 * type, th, n, (const uint2*)ranges,
-          ids, (const float4*)record, rgb, d_outs);
+          order, ids, (const float4*)record, rgb, d_outs);
     GUT_LAUNCH_CHECK();
   }
   return GUT_OK;
 }
 
 gut_status launch_render(const DevCam& cam, const Thresholds& th, int n, int cam_idx,
-                         const uint32_t* ranges, const uint32_t* ids, const float* record,
-                         const float* rgb, float* out_rgb, float* out_T, uint32_t* out_nc,
-                         uint32_t* out_ne, hipStream_t s) {
+                         const uint32_t* ranges, const uint32_t* order, const uint32_t* ids,
+                         const float* record, const float* rgb, float* out_rgb, float* out_T,
+                         uint32_t* out_nc, uint32_t* out_ne, hipStream_t s) {
   dim3 grid(cam.tiles_x * cam.tiles_y), block(kRThreads);
   if (cam.shutter == GUT_ROLLING_TOP_TO_BOTTOM)
-    render_kernel<true><<<grid, block, 0, s>>>(cam, th, n, cam_idx, (const uint2*)ranges, ids,
-                                               (const float4*)record, rgb, out_rgb, out_T, out_nc,
-                                               out_ne);
+    render_kernel<true><<<grid, block, 0, s>>>(cam, th, n, cam_idx, (const uint2*)ranges, order,
+                                               ids, (const float4*)record, rgb, out_rgb, out_T,
+                                               out_nc, out_ne);
   else
-    render_kernel<false><<<grid, block, 0, s>>>(cam, th, n, cam_idx, (const uint2*)ranges, ids,
-                                                (const float4*)record, rgb, out_rgb, out_T, out_nc,
-                                                out_ne);
+    render_kernel<false><<<grid, block, 0, s>>>(cam, th, n, cam_idx, (const uint2*)ranges, order,
+                                                ids, (const float4*)record, rgb, out_rgb, out_T,
+                                                out_nc, out_ne);
   GUT_LAUNCH_CHECK();
   return GUT_OK;
 }
@@ -281,11 +294,13 @@ extern "C" gut_status gut_render(const gut_projected* proj, int64_t n, const uin
     return GUT_E_INVALID;
   }
   DevCam dc[kMaxCams];
-  if ((st = prepare_cams(cams, n_cams, *p, dc, nullptr, nullptr)) != GUT_OK) return st;
+  int64_t T = 0;
+  if ((st = prepare_cams(cams, n_cams, *p, dc, &T, nullptr)) != GUT_OK) return st;
   Thresholds th = make_thresholds(*p);
   for (int c = 0; c < n_cams; c++) {
-    st = launch_render(dc[c], th, (int)n, c, tile_ranges, sorted_ids, proj->record, proj->rgb, rgb,
-                       T_final, n_contrib, n_eval, (hipStream_t)stream);
+    st = launch_render(dc[c], th, (int)n, c, tile_ranges, tile_ranges + 2 * T, sorted_ids,
+                       proj->record, proj->rgb, rgb, T_final, n_contrib, n_eval,
+                       (hipStream_t)stream);
     if (st != GUT_OK) return st;
   }
   return GUT_OK;

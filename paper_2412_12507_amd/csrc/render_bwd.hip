@@ -16,9 +16,10 @@
 // (Supp. B), so with M = S^-1 R^T the per-pixel gradients are
 //   dL/dmu = -M^T c p,   dL/dM = c p (M^-1 p)^T,   c = 2 dL/domega^2.
 // They only depend on G = sum c p p^T (6 values) and h = sum c p (3): each
-// wave sums those plus dL/dsigma and dL/dc over its lanes (FP32) and issues
-// one FP64 atomic per value per (wave, particle), so the per-particle totals
-// carry no order-dependent FP32 rounding.
+// wave sums those plus dL/dsigma and dL/dc over its lanes (FP32, one
+// reduce-scatter for all 13) and issues one FP64 atomic per value per
+// (wave, particle) from 13 lanes at once, so the per-particle totals carry no
+// order-dependent FP32 rounding.
 //
 // K7 (per particle) then applies M = S^-1 R^T:
 //   dL/ds_k = -G_kk / s_k,   dL/dR = R S G S^-1,   dL/dmu = -R S^-1 h,
@@ -31,19 +32,44 @@ namespace gut {
 
 constexpr int kAcc = 10;  // G xx,xy,xz,yy,yz,zz ; h x,y,z ; dL/dsigma
 
-__device__ inline float wave_sum(float x) {
+// Sums 16 per-lane values over the wave as a reduce-scatter: at each of the
+// first four butterfly steps a lane keeps half of its values and adds its
+// partner's copy of that half (8 + 4 + 2 + 1 shuffles), then two plain steps
+// finish the sum; 17 shuffles instead of 16 x 6.  Afterwards lane l holds
+// the total of value (l >> 2) & 15.
+__device__ inline float wave_reduce16(const float* g) {
+  const int lane = threadIdx.x & 63;
+  float h8[8], h4[4], h2[2];
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
+  for (int j = 0; j < 8; j++) {
+    const float keep = b5 ? g[j + 8] : g[j], send = b5 ? g[j] : g[j + 8];
+    h8[j] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    const float keep = b4 ? h8[j + 4] : h8[j], send = b4 ? h8[j] : h8[j + 4];
+    h4[j] = keep + __shfl_xor(send, 16, 64);
+  }
+#pragma unroll
+  for (int j = 0; j < 2; j++) {
+    const float keep = b3 ? h4[j + 2] : h4[j], send = b3 ? h4[j] : h4[j + 2];
+    h2[j] = keep + __shfl_xor(send, 8, 64);
+  }
+  float h = (b2 ? h2[1] : h2[0]) + __shfl_xor(b2 ? h2[0] : h2[1], 4, 64);
+  h += __shfl_xor(h, 2, 64);
+  h += __shfl_xor(h, 1, 64);
+  return h;
 }
 
 constexpr int kBwThreads = 128;
 constexpr int kBwBatch = kBwThreads;
 
 template <bool RS>
-__global__ void __launch_bounds__(kBwThreads) render_bwd_kernel(
+__global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, const uint2* __restrict__ ranges,
-    const uint32_t* __restrict__ ids, const float4* __restrict__ record,
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
+    const float4* __restrict__ record,
     const float* __restrict__ rgb, const float* __restrict__ out_rgb,
     const float* __restrict__ out_T, const uint32_t* __restrict__ out_nc,
     const float* __restrict__ d_rgb, const float* __restrict__ d_T, double* __restrict__ acc,
@@ -57,8 +83,7 @@ __global__ void __launch_bounds__(kBwThreads) render_bwd_kernel(
   __shared__ float red[6];
   __shared__ uint32_t maxlast_s;
 
-  const int ntiles = cam.tiles_x * cam.tiles_y;
-  const int tile = xcd_tile(blockIdx.x, ntiles);
+  const int tile = (int)order[cam.tile_base + blockIdx.x];  // longest lists first
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
   const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
   // the forward's pixel layout: wave wv owns rows 8 wv .. 8 wv + 7
@@ -76,6 +101,7 @@ __global__ void __launch_bounds__(kBwThreads) render_bwd_kernel(
   }
   float umax, vmax, dtmax;
   tile_bounds<2>(u, v, dt, active, red, &umax, &vmax, &dtmax);
+  const float l2amin = log2f(th.alpha_min);
   wave_box<2>(u, v, active, &wb);
 
   uint32_t last[2] = {0u, 0u};
@@ -94,6 +120,9 @@ __global__ void __launch_bounds__(kBwThreads) render_bwd_kernel(
   __syncthreads();  // (also publishes wb)
   const uint2 rg = ranges[cam.tile_base + tile];
   const uint32_t maxlast = min(maxlast_s, rg.y - rg.x);  // never past the tile's list
+  if (maxlast >= 2048) __builtin_amdgcn_s_setprio(3);
+  else if (maxlast >= 1024) __builtin_amdgcn_s_setprio(2);
+  else if (maxlast >= 256) __builtin_amdgcn_s_setprio(1);
 
   float T[2] = {1.0f, 1.0f};
   double A[2][3] = {{0, 0, 0}, {0, 0, 0}};  // running colour C_<=j, accumulated as in the forward
@@ -104,7 +133,7 @@ __global__ void __launch_bounds__(kBwThreads) render_bwd_kernel(
       uint32_t e = ids[rg.x + b + t];
       pe[t] = e;
       fl = pair_setup<RS, true>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n), F, cam,
-                          umax, vmax, dtmax, th.alpha_min, wb, kBwThreads / 64, &pd[t * S]);
+                          umax, vmax, dtmax, th.alpha_min, l2amin, wb, kBwThreads / 64, &pd[t * S]);
     }
     pf[t] = fl;
     __syncthreads();
@@ -129,11 +158,12 @@ __global__ void __launch_bounds__(kBwThreads) render_bwd_kernel(
         hit[0] = ev[0].ok && idx < last[0];
         hit[1] = ev[1].ok && idx < last[1];
         if (__ballot(hit[0] || hit[1]) == 0ull) continue;  // wave-uniform
-        const float4 colv = pair_colour<RS>(P);
-        const float col[3] = {colv.x, colv.y, colv.z};
-        float g[kAcc + 3];
+        double cold[3];
+        pair_colour<RS>(P, cold);
+        const float col[3] = {(float)cold[0], (float)cold[1], (float)cold[2]};
+        float g[16];  // kAcc + 3 values, padded for the reduction
 #pragma unroll
-        for (int j = 0; j < kAcc + 3; j++) g[j] = 0.0f;
+        for (int j = 0; j < 16; j++) g[j] = 0.0f;
         float wgt[2];
 #pragma unroll
         for (int k = 0; k < 2; k++) {
@@ -146,9 +176,9 @@ __global__ void __launch_bounds__(kBwThreads) render_bwd_kernel(
           g[kAcc + 1] += wgt[k] * gC[k][1];
           g[kAcc + 2] += wgt[k] * gC[k][2];
           // A_j includes this contributor: (S_after + T_N bg) = C - C_<=j, in FP64
-          double R0 = Co[k][0] - fma((double)wgt[k], (double)col[0], A[k][0]);
-          double R1 = Co[k][1] - fma((double)wgt[k], (double)col[1], A[k][1]);
-          double R2 = Co[k][2] - fma((double)wgt[k], (double)col[2], A[k][2]);
+          double R0 = Co[k][0] - fma((double)wgt[k], cold[0], A[k][0]);
+          double R1 = Co[k][1] - fma((double)wgt[k], cold[1], A[k][1]);
+          double R2 = Co[k][2] - fma((double)wgt[k], cold[2], A[k][2]);
           const float inv1m = 1.0f / (1.0f - ev[k].a);
           float gA = gC[k][0] * (col[0] * Tb - (float)R0 * inv1m) +
                      gC[k][1] * (col[1] * Tb - (float)R1 * inv1m) +
@@ -171,21 +201,18 @@ __global__ void __launch_bounds__(kBwThreads) render_bwd_kernel(
 #pragma unroll
         for (int k = 0; k < 2; k++) {
           const double w = (double)wgt[k];
-          A[k][0] = fma(w, (double)col[0], A[k][0]);
-          A[k][1] = fma(w, (double)col[1], A[k][1]);
-          A[k][2] = fma(w, (double)col[2], A[k][2]);
+          A[k][0] = fma(w, cold[0], A[k][0]);
+          A[k][1] = fma(w, cold[1], A[k][1]);
+          A[k][2] = fma(w, cold[2], A[k][2]);
         }
-#pragma unroll
-        for (int j = 0; j < kAcc + 3; j++) g[j] = wave_sum(g[j]);
-        if (lane == 0) {
-          uint32_t e = pe[q];
-          int i = (int)(e - (uint32_t)cam_idx * (uint32_t)n);
-#pragma unroll
-          for (int j = 0; j < kAcc; j++)
-            if (g[j] != 0.0f) atomicAdd(&acc[(long long)i * kAcc + j], (double)g[j]);
-#pragma unroll
-          for (int j = 0; j < 3; j++)
-            if (g[kAcc + j] != 0.0f) atomicAdd(&acc_rgb[3 * (long long)e + j], (double)g[kAcc + j]);
+        // one lane per value issues its atomic: lanes 4k hold value k
+        const float tot = wave_reduce16(g);
+        const int k = lane >> 2;
+        if ((lane & 3) == 0 && k < kAcc + 3 && tot != 0.0f) {
+          const uint32_t e = pe[q];
+          const int i = (int)(e - (uint32_t)cam_idx * (uint32_t)n);
+          if (k < kAcc) atomicAdd(&acc[(long long)i * kAcc + k], (double)tot);
+          else atomicAdd(&acc_rgb[3 * (long long)e + (k - kAcc)], (double)tot);
         }
       }
     }
@@ -341,8 +368,10 @@ extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected
     return GUT_E_INVALID;
   }
   DevCam dc[kMaxCams];
-  if ((st = prepare_cams(cams, n_cams, *p, dc, nullptr, nullptr)) != GUT_OK) return st;
+  int64_t T = 0;
+  if ((st = prepare_cams(cams, n_cams, *p, dc, &T, nullptr)) != GUT_OK) return st;
   if (n == 0) return GUT_OK;
+  const uint32_t* order = tile_ranges + 2 * T;
   hipStream_t s = (hipStream_t)stream;
   double* acc = (double*)ws;
   double* acc_rgb = (double*)((char*)ws + (((size_t)n * kAcc * 8 + 255) & ~size_t(255)));
@@ -356,11 +385,11 @@ extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected
     dim3 grid(dc[c].tiles_x * dc[c].tiles_y), block(kBwThreads);
     if (dc[c].shutter == GUT_ROLLING_TOP_TO_BOTTOM)
       render_bwd_kernel<true><<<grid, block, 0, s>>>(
-          dc[c], th, (int)n, c, (const uint2*)tile_ranges, sorted_ids,
+          dc[c], th, (int)n, c, (const uint2*)tile_ranges, order, sorted_ids,
           (const float4*)proj->record, proj->rgb, rgb, T_final, n_contrib, d_rgb, d_T, acc, acc_rgb);
     else
       render_bwd_kernel<false><<<grid, block, 0, s>>>(
-          dc[c], th, (int)n, c, (const uint2*)tile_ranges, sorted_ids,
+          dc[c], th, (int)n, c, (const uint2*)tile_ranges, order, sorted_ids,
           (const float4*)proj->record, proj->rgb, rgb, T_final, n_contrib, d_rgb, d_T, acc, acc_rgb);
     GUT_LAUNCH_CHECK();
   }

@@ -147,7 +147,7 @@ constexpr size_t kStage = 64 * 1024;
 static size_t batch_entry_bytes(int64_t n, const std::vector<DevCam>& dc, int64_t T) {
   const int64_t E = n * (int64_t)dc.size();
   return al256(E * 8) + al256(E * 4) * 2 + al256(E * 12) + al256(bin_entry_bytes(E)) +
-         al256(T * 8) + al256(dc.size() * sizeof(DevCam)) + al256(dc.size() * sizeof(float*)) +
+         al256(T * 12) + al256(dc.size() * sizeof(DevCam)) + al256(dc.size() * sizeof(float*)) +
          al256(2 * (2 * kMaxCams + 1) * sizeof(int)) + al256(16 * sizeof(unsigned)) + 4096;
 }
 
@@ -184,7 +184,7 @@ static gut_status run_batch(gut_server* S, Worker& W, Batch& B) {
   proj.rgb = (float*)take(E * 12);
   proj.record = (float*)(S->base + S->record_off);
   char* ews = take(bin_entry_bytes(E));
-  uint32_t* ranges = (uint32_t*)take(T * 8);
+  uint32_t* ranges = (uint32_t*)take(T * 12);  // [T,2] ranges, then the render order
   DevCam* d_cams = (DevCam*)take(nc * sizeof(DevCam));
   float** d_outs = (float**)take(nc * sizeof(float*));
   int* d_lists = (int*)take(2 * (2 * kMaxCams + 1) * sizeof(int));
@@ -241,8 +241,10 @@ static gut_status run_batch(gut_server* S, Worker& W, Batch& B) {
   char* pws = pb + al256((P > 0 ? P : 1) * 4);
   int* h_lists = (int*)(stage + 49152);
   if ((st = bin_sort(&proj, (int)n, dc.data(), nc, T, E, ews, nvis, P, pws, ranges, ids, s)) != GUT_OK ||
-      (st = render_batch_launch(d_cams, dc.data(), nc, th, (int)n, ranges, ids, proj.record, proj.rgb,
-                                d_outs, d_counters, d_lists, h_lists, S->n_blocks, s)) != GUT_OK) {
+      (st = bin_order(dc.data(), nc, T, ranges, s)) != GUT_OK ||
+      (st = render_batch_launch(d_cams, dc.data(), nc, th, (int)n, ranges, ranges + 2 * T, ids,
+                                proj.record, proj.rgb, d_outs, d_counters, d_lists, h_lists,
+                                S->n_blocks, s)) != GUT_OK) {
     release();
     return st;
   }

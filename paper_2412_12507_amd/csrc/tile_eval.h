@@ -83,16 +83,19 @@ constexpr double kHalfLog2e = 0.72134752044448170368;
 // so a pixel needs 10 FMAs for both and no term cancels beyond what the
 // affine maps themselves carry.
 //   0: f1 r11 r12 Kp    1: f2 r22 f3 lsig    2: g1 h11 h12 mixed
-//   3: g2 h22 g3 -      4: colour r g b -    5: s ta tb -
+//   3: g2 h22 g3 -      4: colour r g (FP64)  5: s ta tb -
+//   6: colour b (FP64), -
 // and, for the backward only, the vectors for the closest point p:
-//   6: d_g(n).xyz w.x   7: d_g(e1).xyz w.y   8: d_g(e2).xyz w.z
-//   9: A.xyz B.x       10: B.y B.z - -
+//   7: d_g(n).xyz w.x   8: d_g(e1).xyz w.y   9: d_g(e2).xyz w.z
+//  10: A.xyz B.x       11: B.y B.z - -
 // Rolling shutter.  The origin moves with the row, so the cross product is
 // bilinear in (u, v) and dt and is formed from its vectors per pixel:
 //   0: d_g(n).xyz mixed  1: d_g(e1).xyz lsig  2: d_g(e2).xyz Kp
 //   3: w.xyz ta          4: A.xyz tb          5: B.xyz s
-//   6: colour r g b -    7: (m x d_g(n)).xyz m.d_g(n)
+//   6: colour r g (FP64) 7: (m x d_g(n)).xyz m.d_g(n)
 //   8: (m x d_g(e1)).xyz m.d_g(e1)               9: (m x d_g(e2)).xyz m.d_g(e2)
+//  10: colour b (FP64), -
+// (colours are kept in FP64 because the compositing accumulates in FP64)
 // Here w = o_g x d_g(n), A = o_g x d_g(e1), B = o_g x d_g(e2),
 // s, ta, tb = o_g . d_g(.) (the tau_max > 0 test, needed per pixel only when
 // its sign varies over the tile: mixed = -1), lsig = log2(sigma) and
@@ -101,22 +104,24 @@ constexpr double kHalfLog2e = 0.72134752044448170368;
 // with omega'^2 = omega^2 log2(e) / 2.
 template <bool RS, bool BWD>
 struct Slots {
-  static constexpr int N = RS ? 10 : (BWD ? 11 : 6);
+  static constexpr int N = RS ? 11 : (BWD ? 12 : 7);
 };
 
 // QR of the affine map (u, v) -> c0 + u c1 + v c2 (FP64, Gram-Schmidt with
 // one re-orthogonalisation): |c0 + u c1 + v c2|^2 =
 // (q[0] + q[1] u + q[2] v)^2 + (q[3] + q[4] v)^2 + q[5].
 __device__ inline void affine_qr(d3 c0, d3 c1, d3 c2, double q[6]) {
-  const double r11 = sqrt(dot(c1, c1));
-  const d3 a1 = r11 > 0.0 ? scl(c1, 1.0 / r11) : mk3(0, 0, 0);
+  const double n11 = dot(c1, c1), i11 = n11 > 0.0 ? rsqrt(n11) : 0.0;
+  const double r11 = n11 * i11;
+  const d3 a1 = scl(c1, i11);
   double r12 = dot(c2, a1);
   d3 b = sub(c2, scl(a1, r12));
   const double r12b = dot(b, a1);
   r12 += r12b;
   b = sub(b, scl(a1, r12b));
-  const double r22 = sqrt(dot(b, b));
-  const d3 a2 = r22 > 0.0 ? scl(b, 1.0 / r22) : mk3(0, 0, 0);
+  const double n22 = dot(b, b), i22 = n22 > 0.0 ? rsqrt(n22) : 0.0;
+  const double r22 = n22 * i22;
+  const d3 a2 = scl(b, i22);
   double f1 = dot(c0, a1), f2 = dot(c0, a2);
   d3 rem = sub(sub(c0, scl(a1, f1)), scl(a2, f2));
   const double e1 = dot(rem, a1), e2 = dot(rem, a2);
@@ -146,16 +151,17 @@ struct WaveBoxes {
 // over the box is at the centre if the centre is inside, else on an edge,
 // where it is a 1D quadratic minimised in closed form and clamped.
 __device__ inline bool ellipse_meets_box(double qmin, double N11, double N12, double N22,
-                                         double a0, double a1, double b0, double b1) {
+                                         double iN11, double iN22, double a0, double a1,
+                                         double b0, double b1) {
   if (a0 <= 0.0 && a1 >= 0.0 && b0 <= 0.0 && b1 >= 0.0) return true;
   const double slack = -1e-6 * qmin;
   // edge with one offset x fixed; the other offset y ranges over [lo, hi]
-  auto edge = [&](double x, double lo, double hi, double Nxx, double Nyy) {
-    const double y = fmin(fmax(-N12 * x / Nyy, lo), hi);
+  auto edge = [&](double x, double lo, double hi, double Nxx, double Nyy, double iNyy) {
+    const double y = fmin(fmax(-N12 * x * iNyy, lo), hi);
     return qmin + Nxx * x * x + 2.0 * N12 * x * y + Nyy * y * y <= slack;
   };
-  return edge(a0, b0, b1, N11, N22) || edge(a1, b0, b1, N11, N22) ||
-         edge(b0, a0, a1, N22, N11) || edge(b1, a0, a1, N22, N11);
+  return edge(a0, b0, b1, N11, N22, iN22) || edge(a1, b0, b1, N11, N22, iN22) ||
+         edge(b0, a0, a1, N22, N11, iN11) || edge(b1, a0, a1, N22, N11, iN11);
 }
 
 // Forms a pair's slots (FP64 -> FP32) and returns one bit per wave of the
@@ -164,8 +170,8 @@ template <bool RS, bool BWD>
 __device__ inline unsigned pair_setup(const float4* __restrict__ record,
                                       const float* __restrict__ rgb, long long e, int i,
                                       const TileFrameD& F, const DevCam& cam, float umax,
-                                      float vmax, float dtmax, float amin, const WaveBoxes& wb,
-                                      int nwaves, float4* out) {
+                                      float vmax, float dtmax, float amin, float log2_amin,
+                                      const WaveBoxes& wb, int nwaves, float4* out) {
   float4 r0 = record[4 * (long long)i], r1 = record[4 * (long long)i + 1];
   float4 r2 = record[4 * (long long)i + 2], r3 = record[4 * (long long)i + 3];
   const double M[9] = {r1.x, r1.y, r1.z, r2.x, r2.y, r2.z, r3.x, r3.y, r3.z};
@@ -196,7 +202,7 @@ __device__ inline unsigned pair_setup(const float4* __restrict__ record,
     mixed = true;  // decide per pixel
   }
   const float lsig = log2f(sigma);
-  const float Kp = (!never && sigma >= amin) ? lsig - log2f(amin) : -1.0f;
+  const float Kp = (!never && sigma >= amin) ? lsig - log2_amin : -1.0f;
   unsigned flags = 0;
   if (Kp >= 0.0f) {
     // the per-pixel test uses this FP32 Kp; cull with it in natural units
@@ -220,8 +226,9 @@ __device__ inline unsigned pair_setup(const float4* __restrict__ record,
         const double uc = (N02 * N12 - N01 * N22) * idet, vc = (N01 * N12 - N02 * N11) * idet;
         const double qmin = N00 + N01 * uc + N02 * vc;
         if (qmin < 0.0) {
+          const double iN11 = 1.0 / N11, iN22 = 1.0 / N22;
           for (int k = 0; k < nwaves; k++)
-            if (ellipse_meets_box(qmin, N11, N12, N22, wb.u0[k] - uc, wb.u1[k] - uc,
+            if (ellipse_meets_box(qmin, N11, N12, N22, iN11, iN22, wb.u0[k] - uc, wb.u1[k] - uc,
                                   wb.v0[k] - vc, wb.v1[k] - vc))
               flags |= 1u << k;
         }
@@ -239,14 +246,15 @@ __device__ inline unsigned pair_setup(const float4* __restrict__ record,
     out[1] = make_float4((float)qc[3], (float)qc[4], (float)qc[5], lsig);
     out[2] = make_float4((float)qd[0], (float)qd[1], (float)qd[2], mflag);
     out[3] = make_float4((float)qd[3], (float)qd[4], (float)qd[5], 0.0f);
-    out[4] = make_float4(c[0], c[1], c[2], 0.0f);
+    reinterpret_cast<double2*>(out + 4)[0] = make_double2(c[0], c[1]);
     out[5] = make_float4((float)s, (float)ta, (float)tb, 0.0f);
+    reinterpret_cast<double2*>(out + 6)[0] = make_double2(c[2], 0.0);
     if (BWD) {
-      out[6] = make_float4((float)dn.x, (float)dn.y, (float)dn.z, (float)w.x);
-      out[7] = make_float4((float)da.x, (float)da.y, (float)da.z, (float)w.y);
-      out[8] = make_float4((float)db.x, (float)db.y, (float)db.z, (float)w.z);
-      out[9] = make_float4((float)A.x, (float)A.y, (float)A.z, (float)B.x);
-      out[10] = make_float4((float)B.y, (float)B.z, 0.0f, 0.0f);
+      out[7] = make_float4((float)dn.x, (float)dn.y, (float)dn.z, (float)w.x);
+      out[8] = make_float4((float)da.x, (float)da.y, (float)da.z, (float)w.y);
+      out[9] = make_float4((float)db.x, (float)db.y, (float)db.z, (float)w.z);
+      out[10] = make_float4((float)A.x, (float)A.y, (float)A.z, (float)B.x);
+      out[11] = make_float4((float)B.y, (float)B.z, 0.0f, 0.0f);
     }
   } else {
     out[0] = make_float4((float)dn.x, (float)dn.y, (float)dn.z, mflag);
@@ -255,10 +263,11 @@ __device__ inline unsigned pair_setup(const float4* __restrict__ record,
     out[3] = make_float4((float)w.x, (float)w.y, (float)w.z, (float)ta);
     out[4] = make_float4((float)A.x, (float)A.y, (float)A.z, (float)tb);
     out[5] = make_float4((float)B.x, (float)B.y, (float)B.z, (float)s);
-    out[6] = make_float4(c[0], c[1], c[2], 0.0f);
+    reinterpret_cast<double2*>(out + 6)[0] = make_double2(c[0], c[1]);
     out[7] = make_float4((float)w2.x, (float)w2.y, (float)w2.z, (float)s2);
     out[8] = make_float4((float)A2.x, (float)A2.y, (float)A2.z, (float)ta2);
     out[9] = make_float4((float)B2.x, (float)B2.y, (float)B2.z, (float)tb2);
+    reinterpret_cast<double2*>(out + 10)[0] = make_double2(c[2], 0.0);
   }
   return flags;
 }
@@ -332,7 +341,7 @@ __device__ __forceinline__ void eval_test(const PairRegs<RS>& r, const float4* P
     o->dg = dg;
     o->cr = cr;
   }
-  o->ok = ok && (o->cc <= r.Kp * o->dd);
+  o->ok = ok & (o->cc <= r.Kp * o->dd);
 }
 
 // Stage 2 (only for waves where some pixel passed): alpha = min(sigma rho, alpha_max)
@@ -346,10 +355,14 @@ __device__ __forceinline__ void eval_alpha(const PairRegs<RS>& r, float amax, Ev
   o->a = o->ok ? fminf(araw, amax) : 0.0f;
 }
 
-// Colour slot of a pair.
+// Colour of a pair (FP64 slots).
 template <bool RS>
-__device__ __forceinline__ float4 pair_colour(const float4* P) {
-  return RS ? P[6] : P[4];
+__device__ __forceinline__ void pair_colour(const float4* P, double c[3]) {
+  const double2 rg = reinterpret_cast<const double2*>(P + (RS ? 6 : 4))[0];
+  const double2 b = reinterpret_cast<const double2*>(P + (RS ? 10 : 6))[0];
+  c[0] = rg.x;
+  c[1] = rg.y;
+  c[2] = b.x;
 }
 
 // Backward only: d_g and o_g x d_g on the pixel ray (unscaled), for the
@@ -361,7 +374,7 @@ __device__ __forceinline__ void pair_vectors(const float4* P, const Eval& ev, fl
     *dg = ev.dg;
     *cr = ev.cr;
   } else {
-    const float4 q6 = P[6], q7 = P[7], q8 = P[8], q9 = P[9], q10 = P[10];
+    const float4 q6 = P[7], q7 = P[8], q8 = P[9], q9 = P[10], q10 = P[11];
     *dg = f3(fmaf(v, q8.x, fmaf(u, q7.x, q6.x)), fmaf(v, q8.y, fmaf(u, q7.y, q6.y)),
              fmaf(v, q8.z, fmaf(u, q7.z, q6.z)));
     *cr = f3(fmaf(v, q9.w, fmaf(u, q9.x, q6.w)), fmaf(v, q10.x, fmaf(u, q9.y, q7.w)),

@@ -78,9 +78,10 @@ class Projection:
 
 @dataclass
 class Bins:
-    ranges: torch.Tensor   # [T,2] int32
+    ranges: torch.Tensor   # [T,2] int32, first 2T entries of the buffer gut_bin writes
     ids: torch.Tensor      # [capacity] int32 (entry ids)
     n_pairs: int
+    order: torch.Tensor = None   # [T] int32 render order (the buffer's last T entries)
     workspace: torch.Tensor = field(repr=False, default=None)
 
 
@@ -147,9 +148,11 @@ def bin_tiles(proj: Projection, cams, params=None, bins: Bins | None = None,
     arr = L.camera_array(cams)
     p = L.params_struct(params)
     if bins is None or bins.ranges.shape[0] != T:
-        ranges = torch.empty(T, 2, dtype=torch.int32, device=dev)
+        # [T,2] ranges followed by the [T] render order, in one buffer
+        rbuf = torch.empty(3 * T, dtype=torch.int32, device=dev)
+        ranges, order = rbuf[:2 * T].view(T, 2), rbuf[2 * T:]
     else:
-        ranges = bins.ranges
+        ranges, order = bins.ranges, bins.order
     cap = capacity if capacity is not None else (
         bins.ids.shape[0] if bins is not None else max(4096, 16 * n * nc))
     ids = bins.ids if (bins is not None and bins.ids.shape[0] >= cap) else None
@@ -169,7 +172,7 @@ def bin_tiles(proj: Projection, cams, params=None, bins: Bins | None = None,
             ids = None
             continue
         L.check(st, "gut_bin")
-        return Bins(ranges=ranges, ids=ids, n_pairs=int(npairs.value), workspace=ws)
+        return Bins(ranges=ranges, ids=ids, n_pairs=int(npairs.value), order=order, workspace=ws)
     raise RuntimeError("gut_bin: pair capacity did not converge")
 
 

@@ -137,6 +137,26 @@ def test_multi_camera_call_equals_single_calls():
         assert torch.equal(multi.images("n_contrib")[c], one.images("n_contrib")[0])
 
 
+def test_render_order_is_longest_first():
+    """gut_bin's render order: per camera a permutation of its tiles whose
+    list lengths have non-increasing bit length."""
+    say("[render order]")
+    scene = G.clustered_scene(20000, seed=1002)
+    cams = G.config2_cameras(320, 180) + [G.config3_camera(200, 150)]
+    _, _, bins, _ = gpu_forward(scene, cams)
+    rng = bins.ranges.cpu().numpy().astype(np.int64)
+    order = bins.order.cpu().numpy().astype(np.int64)
+    base = 0
+    for cam in cams:
+        tx, ty = O.tiles_xy(cam, O.default_params())
+        o = order[base:base + tx * ty]
+        assert np.array_equal(np.sort(o), np.arange(tx * ty))
+        lens = rng[base + o, 1] - rng[base + o, 0]
+        bits = np.array([int(v).bit_length() for v in lens])
+        assert (np.diff(bits) <= 0).all()
+        base += tx * ty
+
+
 def test_edge_cases():
     say("[edge cases]")
     p = O.default_params()
@@ -169,7 +189,7 @@ def test_edge_cases():
     from paper_2412_12507_amd import _lib as L
     lib = L.load()
     arr, ps = L.camera_array([cam2]), L.params_struct()
-    ranges = torch.empty(R.num_tiles([cam2]), 2, dtype=torch.int32, device="cuda")
+    ranges = torch.empty(3 * R.num_tiles([cam2]), dtype=torch.int32, device="cuda")
     ids = torch.empty(1, dtype=torch.int32, device="cuda")
     need = lib.gut_bin_workspace_bytes(gs.n, 1, 1)
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
