@@ -12,15 +12,18 @@ Also reported on the same line:
                 FLOPs (E_eval x 55, E_eval = list entries evaluated per pixel
                 up to its stop, counted by the kernel itself) per launch over
                 its average duration from HIP events on its stream, against
-                the chip's FP32 vector peak; plus HBM traffic from rocprofv3
-                counters when given (--traffic-json)
+                the chip's FP32 vector peak; plus its HBM bytes per launch
+                from rocprofv3 FETCH_SIZE / WRITE_SIZE counters calibrated on
+                kernels of known traffic (profiles/render_traffic.json, made
+                by --pmc-summary; null when the kernel's sources have changed
+                since the counters were taken)
   stages_ms     per-stage averages (events), Table-2 style
   fwd_bwd_ms_per_view   forward + L1 loss + backward on the fisheye view
                 against a target rendered from parameters perturbed by
                 N(0, 0.01) (the differentiation workload)
-  cpu_baseline  the FP64 oracle on this host's cores, on a bounded sample
-                (full projection and binning, a time-boxed share of the tiles
-                rendered), extrapolated to Mpix/s
+  cpu_baseline  the FP64 oracle on this host's cores, timed on whole steps of
+                the same two-view batch (projection, binning, every tile)
+                until its time budget is spent
 """
 from __future__ import annotations
 
@@ -39,6 +42,60 @@ if ROOT not in sys.path:
 F_EVAL = 55            # FP32 FLOPs per (pixel, particle) evaluation (mul and add counted apart)
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "render_traffic.json")
+RENDER_SOURCES = ("render.hip", "tile_eval.h", "common.h")
+CALIB_BYTES = 1 << 30  # the fill writes, and the add reads, exactly this many bytes
+
+
+def render_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in RENDER_SOURCES:
+        with open(os.path.join(ROOT, "paper_2412_12507_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pmc_summary(fetch_dir, write_dir, out_path, command):
+    """Per-launch HBM bytes of render_kernel<false> from two rocprofv3 --pmc
+    runs of `bench.py --calib-copy` (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch).  Each counter is scaled by what it reads for a kernel of known
+    traffic in the same run: the 1 GiB add (reads 1 GiB) for FETCH_SIZE and
+    the 1 GiB fill (writes 1 GiB) for WRITE_SIZE.  The last two render
+    dispatches (the untimed render that also writes n_eval) are left out."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        rows = []
+        for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] == counter:
+                    rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+        rows.sort()
+        return rows
+
+    def pick(rows, *keys):
+        return [v for _, k, v in rows if any(key in k for key in keys)]
+
+    fr, wr = read(fetch_dir, "FETCH_SIZE"), read(write_dir, "WRITE_SIZE")
+    f_add = pick(fr, "CUDAFunctor_add", "CUDAFunctorOnSelf_add")
+    w_fill = pick(wr, "FillFunctor")
+    f_r = pick(fr, "gut::render_kernel<false>")[:-2]
+    w_r = pick(wr, "gut::render_kernel<false>")[:-2]
+    if not (f_add and w_fill and f_r and w_r):
+        raise SystemExit("pmc summary: calibration or render dispatches missing")
+    ff = CALIB_BYTES / (f_add[0] * 1024.0)
+    wf = CALIB_BYTES / (w_fill[0] * 1024.0)
+    fetch = float(np.mean(f_r)) * 1024.0 * ff
+    write = float(np.mean(w_r)) * 1024.0 * wf
+    out = dict(render_kernel_bytes_per_launch=fetch + write, fetch_bytes=fetch, write_bytes=write,
+               fetch_factor=ff, write_factor=wf, raw_fetch_kib=float(np.mean(f_r)),
+               raw_write_kib=float(np.mean(w_r)), dispatches=len(f_r),
+               source_sha256=render_source_hash(), command=command)
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
 
 
 def log(*a):
@@ -219,8 +276,11 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle rendering")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fwd-bwd", action="store_true")
-    ap.add_argument("--traffic-json", default=None,
-                    help="JSON with per-launch HBM bytes of the render kernel from rocprofv3 counters")
+    ap.add_argument("--traffic-json", default=TRAFFIC_JSON,
+                    help="JSON with per-launch HBM bytes of the render kernel (from --pmc-summary)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="write --traffic-json from two rocprofv3 --pmc output folders and exit")
+    ap.add_argument("--pmc-command", default="", help="the profiling command, recorded in the JSON")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run two elementwise kernels of known traffic for counter "
                          "calibration: a 1 GiB fill (writes 1 GiB) and a 1 GiB add "
@@ -231,6 +291,9 @@ def main():
     ap.add_argument("--serve-loads", default="0.5,0.9,1.5,3.0",
                     help="arrival rates as fractions of the sequential baseline's capacity")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.traffic_json, args.pmc_command)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build renders on a single MI355X "
               "(multi-GPU sharding is a design note, not implemented); run with --gpus 1",
@@ -264,7 +327,9 @@ def main():
     achieved = flops_per_launch / (render_ms_per_launch * 1e-3) / 1e12
     traffic = None
     if args.traffic_json and os.path.exists(args.traffic_json):
-        traffic = json.load(open(args.traffic_json)).get("render_kernel_bytes_per_launch")
+        tj = json.load(open(args.traffic_json))
+        if tj.get("source_sha256") == render_source_hash():  # else the kernel changed since
+            traffic = tj.get("render_kernel_bytes_per_launch")
     roofline = dict(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                     frac=achieved / PEAK_FP32_TFLOPS, traffic=traffic,
                     kernel="render_kernel (gut_render)",

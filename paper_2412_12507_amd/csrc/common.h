@@ -182,7 +182,9 @@ __device__ inline d3 unproject_dir(const DevCam& c, double u, double v, bool* va
     if (f > 0) hi = th; else lo = th;
     double nt = th - f / thetad_deriv(c.k, th);
     if (!(nt >= lo && nt <= hi)) nt = 0.5 * (lo + hi);
-    if (fabs(nt - th) <= 1e-16 * th || hi - lo <= 1e-16 * hi) { th = nt; break; }
+    // 1e-14: far below what the FP32 tile coordinates hold, and above the
+    // one-ulp oscillation a tighter test would never leave
+    if (fabs(nt - th) <= 1e-14 * th || hi - lo <= 1e-14 * hi) { th = nt; break; }
     th = nt;
   }
   double st = sin(th), ct = cos(th);

@@ -103,11 +103,12 @@ __device__ __forceinline__ void render_tile(
         for (int k = 0; k < 2; k++) {
           eval_alpha<RS>(r, th.alpha_max, &ev[k]);
           const bool live = k ? live1 : live0;
-          const float Tn = T[k] * (1.0f - ev[k].a);
-          const bool stop = live && Tn < th.t_min;  // stop before adding this particle
+          const float Tn = fmaf(-ev[k].a, T[k], T[k]);  // T (1 - alpha)
+          const bool stop = live && Tn < th.t_min;      // stop before adding this particle
           contrib[k] = live && !stop;
-          wgt[k] = contrib[k] ? ev[k].a * T[k] : 0.0f;
-          T[k] = contrib[k] ? Tn : T[k];
+          const float ae = contrib[k] ? ev[k].a : 0.0f;
+          wgt[k] = ae * T[k];
+          T[k] = fmaf(-ae, T[k], T[k]);  // Tn, or T itself when not contributing
           last[k] = contrib[k] ? b + q + 1 : last[k];
           nev[k] = stop ? b + q + 1 : nev[k];
           done[k] = done[k] || stop;

@@ -169,9 +169,9 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
         for (int k = 0; k < 2; k++) {
           eval_alpha<RS>(r, th.alpha_max, &ev[k]);
           const float Tb = T[k];
-          wgt[k] = hit[k] ? ev[k].a * Tb : 0.0f;
-          const float Tn = Tb * (1.0f - ev[k].a);
-          T[k] = hit[k] ? Tn : Tb;
+          const float ae = hit[k] ? ev[k].a : 0.0f;
+          wgt[k] = ae * Tb;
+          T[k] = fmaf(-ae, Tb, Tb);  // the forward's update, bit for bit
           g[kAcc] += wgt[k] * gC[k][0];
           g[kAcc + 1] += wgt[k] * gC[k][1];
           g[kAcc + 2] += wgt[k] * gC[k][2];
