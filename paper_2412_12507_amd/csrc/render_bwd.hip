@@ -220,13 +220,11 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
 }
 
 // K7a: camera-independent part of the per-particle chain (FP64: the
-// quaternion gradient is a difference of terms of the size of dL/dR); also
-// zeroes g_sh.
-__global__ void particle_grad_kernel(int n, int K, const float* __restrict__ scales,
+// quaternion gradient is a difference of terms of the size of dL/dR).
+__global__ void particle_grad_kernel(int n, const float* __restrict__ scales,
                                      const float* __restrict__ quats, const double* __restrict__ acc,
                                      float* __restrict__ g_means, float* __restrict__ g_scales,
-                                     float* __restrict__ g_quats, float* __restrict__ g_opac,
-                                     float* __restrict__ g_sh) {
+                                     float* __restrict__ g_quats, float* __restrict__ g_opac) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double* a = acc + (long long)i * kAcc;
@@ -271,54 +269,88 @@ __global__ void particle_grad_kernel(int n, int K, const float* __restrict__ sca
       make_float4((float)((gw - w * pdot) * iq), (float)((gx - x * pdot) * iq),
                   (float)((gy - y * pdot) * iq), (float)((gz - z * pdot) * iq));
   g_opac[i] = (float)a[9];
-  float* gs = g_sh + (long long)i * K * 3;
-  for (int k = 0; k < K * 3; k++) gs[k] = 0.0f;
 }
 
-// K7b: SH colour of one camera -> dL/dbeta and dL/dmu through the view direction.
+// K7b: SH colour of one camera -> dL/dbeta and dL/dmu through the view
+// direction.  One wave per 64 particles: their coefficients (3K floats each)
+// are staged through LDS at a padded stride, so global reads and writes are
+// coalesced and per-thread LDS reads hit distinct banks.  The first camera
+// writes g_sh (zeros for particles without colour gradient), later cameras
+// add to it.
+constexpr int kShThreads = 64;
 template <int DEG>
-__global__ void sh_grad_kernel(int n, int cam_idx, DevCam cam, Thresholds th,
-                               const float* __restrict__ means, const float* __restrict__ sh,
-                               const float* __restrict__ rgb, const double* __restrict__ acc_rgb,
-                               float* __restrict__ g_means, float* __restrict__ g_sh) {
-  constexpr int K = (DEG + 1) * (DEG + 1);
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  long long e = (long long)cam_idx * n + i;
-  const float gr[3] = {(float)acc_rgb[3 * e], (float)acc_rgb[3 * e + 1], (float)acc_rgb[3 * e + 2]};
-  bool live[3];
-  for (int c = 0; c < 3; c++) live[c] = gr[c] != 0.0f && rgb[3 * e + c] > 0.0f;
-  if (!live[0] && !live[1] && !live[2]) return;
-  float3 mu = f3(means[3 * i], means[3 * i + 1], means[3 * i + 2]);
-  float t0 = 0.0f;
-  if (cam.shutter == GUT_ROLLING_TOP_TO_BOTTOM) {  // exposure time of the mean, as in K1
-    float2 vv;
-    bool ok;
-    t0 = solve_project(cam, cam0_coords(cam, mu), th, &vv, &ok);
-  }
-  float3 ctr = centre_at(cam, t0);
-  float3 dv = f3(mu.x - ctr.x, mu.y - ctr.y, mu.z - ctr.z);
-  float dist = sqrtf(dot3f(dv, dv)), id = 1.0f / dist;
-  float3 d = f3(dv.x * id, dv.y * id, dv.z * id);
-  float Y[K];
-  float3 dY[K];
-  sh_basis<DEG>(d.x, d.y, d.z, Y);
-  sh_basis_grad<DEG>(d.x, d.y, d.z, dY);
-  const float* b = sh + (long long)i * K * 3;
-  float* gs = g_sh + (long long)i * K * 3;
-  float3 gd = f3(0.f, 0.f, 0.f);
-  for (int c = 0; c < 3; c++) {
-    if (!live[c]) continue;
-    for (int k = 0; k < K; k++) {
-      gs[3 * k + c] += gr[c] * Y[k];
-      float bb = gr[c] * b[3 * k + c];
-      gd = f3(gd.x + bb * dY[k].x, gd.y + bb * dY[k].y, gd.z + bb * dY[k].z);
+__global__ void __launch_bounds__(kShThreads) sh_grad_kernel(
+    int n, int cam_idx, int first, DevCam cam, Thresholds th, const float* __restrict__ means,
+    const float* __restrict__ sh, const float* __restrict__ rgb, const double* __restrict__ acc_rgb,
+    float* __restrict__ g_means, float* __restrict__ g_sh) {
+  constexpr int K = (DEG + 1) * (DEG + 1), C = 3 * K, LD = C + 1;
+  __shared__ float lb[kShThreads * LD];  // coefficients, then gradients
+  const int t = threadIdx.x;
+  const long long i0 = (long long)blockIdx.x * kShThreads;
+  const int cnt = (int)min((long long)kShThreads, (long long)n - i0);
+  const long long i = i0 + t;
+  const float* src = sh + i0 * C;
+  float* dst = g_sh + i0 * C;
+  float gr[3] = {0.f, 0.f, 0.f};
+  bool live[3] = {false, false, false};
+  if (t < cnt) {
+    const long long e = (long long)cam_idx * n + i;
+    for (int c = 0; c < 3; c++) {
+      gr[c] = (float)acc_rgb[3 * e + c];
+      live[c] = gr[c] != 0.0f && rgb[3 * e + c] > 0.0f;  // max(0, .) clamps the rest
     }
   }
-  float pdd = dot3f(gd, d);
-  g_means[3 * i] += (gd.x - d.x * pdd) * id;
-  g_means[3 * i + 1] += (gd.y - d.y * pdd) * id;
-  g_means[3 * i + 2] += (gd.z - d.z * pdd) * id;
+  const bool any = live[0] || live[1] || live[2];
+  const bool wave_any = __ballot(any) != 0ull;
+  if (wave_any) {
+    for (int j = t; j < cnt * C; j += kShThreads) lb[(j / C) * LD + j % C] = src[j];
+  }
+  __syncthreads();
+  float gs[C];
+#pragma unroll
+  for (int k = 0; k < C; k++) gs[k] = 0.0f;
+  if (any) {
+    float3 mu = f3(means[3 * i], means[3 * i + 1], means[3 * i + 2]);
+    float t0 = 0.0f;
+    if (cam.shutter == GUT_ROLLING_TOP_TO_BOTTOM) {  // exposure time of the mean, as in K1
+      float2 vv;
+      bool ok;
+      t0 = solve_project(cam, cam0_coords(cam, mu), th, &vv, &ok);
+    }
+    float3 ctr = centre_at(cam, t0);
+    float3 dv = f3(mu.x - ctr.x, mu.y - ctr.y, mu.z - ctr.z);
+    float dist = sqrtf(dot3f(dv, dv)), id = 1.0f / dist;
+    float3 d = f3(dv.x * id, dv.y * id, dv.z * id);
+    float Y[K];
+    float3 dY[K];
+    sh_basis<DEG>(d.x, d.y, d.z, Y);
+    sh_basis_grad<DEG>(d.x, d.y, d.z, dY);
+    const float* b = lb + t * LD;
+    float3 gd = f3(0.f, 0.f, 0.f);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      if (!live[c]) continue;
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        gs[3 * k + c] = gr[c] * Y[k];
+        const float bb = gr[c] * b[3 * k + c];
+        gd = f3(gd.x + bb * dY[k].x, gd.y + bb * dY[k].y, gd.z + bb * dY[k].z);
+      }
+    }
+    float pdd = dot3f(gd, d);
+    g_means[3 * i] += (gd.x - d.x * pdd) * id;
+    g_means[3 * i + 1] += (gd.y - d.y * pdd) * id;
+    g_means[3 * i + 2] += (gd.z - d.z * pdd) * id;
+  }
+  if (!first && !wave_any) return;  // nothing to add for these particles
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < C; k++) lb[t * LD + k] = gs[k];
+  __syncthreads();
+  for (int j = t; j < cnt * C; j += kShThreads) {
+    const float v = lb[(j / C) * LD + j % C];
+    dst[j] = first ? v : dst[j] + v;
+  }
 }
 
 __global__ void zero_f64_kernel(double* __restrict__ p, long long m) {
@@ -393,15 +425,15 @@ extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected
           (const float4*)proj->record, proj->rgb, rgb, T_final, n_contrib, d_rgb, d_T, acc, acc_rgb);
     GUT_LAUNCH_CHECK();
   }
-  const int K = (scene->sh_degree + 1) * (scene->sh_degree + 1);
   dim3 g1((unsigned)((n + 255) / 256)), b1(256);
-  particle_grad_kernel<<<g1, b1, 0, s>>>((int)n, K, scene->scales, scene->quats, acc, g_means,
-                                         g_scales, g_quats, g_opacities, g_sh);
+  particle_grad_kernel<<<g1, b1, 0, s>>>((int)n, scene->scales, scene->quats, acc, g_means,
+                                         g_scales, g_quats, g_opacities);
   GUT_LAUNCH_CHECK();
+  const dim3 gs_grid((unsigned)((n + kShThreads - 1) / kShThreads));
   for (int c = 0; c < n_cams; c++) {
 #define GUT_SHG(D)                                                                          \
-  sh_grad_kernel<D><<<g1, b1, 0, s>>>((int)n, c, dc[c], th, scene->means, scene->sh, proj->rgb, \
-                                      acc_rgb, g_means, g_sh)
+  sh_grad_kernel<D><<<gs_grid, kShThreads, 0, s>>>((int)n, c, c == 0, dc[c], th, scene->means, \
+                                                   scene->sh, proj->rgb, acc_rgb, g_means, g_sh)
     switch (scene->sh_degree) {
       case 0: GUT_SHG(0); break;
       case 1: GUT_SHG(1); break;
