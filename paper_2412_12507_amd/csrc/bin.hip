@@ -169,22 +169,47 @@ __global__ void gather_tiles_kernel(const uint32_t* __restrict__ ent, const uint
   if (j < m) out[j] = tiles[ent[j]];
 }
 
-__global__ void duplicate_kernel(const uint32_t* __restrict__ ent, const uint32_t* __restrict__ offs,
-                                 const short4* __restrict__ rect, int n, CamTiles ct, int64_t m,
-                                 uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m) return;
-  uint32_t e = ent[j];
-  int cam = (int)(e / (uint32_t)n);
-  short4 r = rect[e];
-  uint32_t k = offs[j];
-  const int base = ct.base[cam], tx = ct.tx[cam];
-  for (int y = r.y; y <= r.w; y++)
-    for (int x = r.x; x <= r.z; x++) {
-      keys[k] = (uint32_t)(base + y * tx + x);
-      vals[k] = e;
-      k++;
+// Expands each visible entry (in depth order) into one (tile, entry) pair per
+// tile of its rectangle, row-major.  A block takes 256 consecutive entries
+// and spreads their contiguous output range evenly over its threads (each
+// output finds its entry by binary search of the block's offsets in LDS), so
+// the writes are coalesced whatever the rectangle sizes.
+constexpr int kDupThreads = 256;
+__global__ void __launch_bounds__(kDupThreads) duplicate_kernel(
+    const uint32_t* __restrict__ ent, const uint32_t* __restrict__ offs,
+    const short4* __restrict__ rect, int n, CamTiles ct, int64_t m, uint64_t P,
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  __shared__ uint32_t so[kDupThreads + 1];
+  __shared__ uint32_t se[kDupThreads];
+  __shared__ int4 sr[kDupThreads];  // x0, y0, width, camera tile base
+  __shared__ int stx[kDupThreads];
+  const int t = threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * kDupThreads;
+  const int cnt = (int)min((int64_t)kDupThreads, m - j0);
+  if (t < cnt) {
+    const uint32_t e = ent[j0 + t];
+    const int cam = (int)(e / (uint32_t)n);
+    const short4 r = rect[e];
+    so[t] = offs[j0 + t];
+    se[t] = e;
+    sr[t] = make_int4(r.x, r.y, r.z - r.x + 1, ct.base[cam]);
+    stx[t] = ct.tx[cam];
+  }
+  if (t == 0) so[cnt] = j0 + cnt < m ? offs[j0 + cnt] : (uint32_t)P;
+  __syncthreads();
+  const uint32_t p1 = so[cnt];
+  for (uint32_t p = so[0] + t; p < p1; p += kDupThreads) {
+    int lo = 0, hi = cnt - 1;  // last entry whose output starts at or before p
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (so[mid] <= p) lo = mid; else hi = mid - 1;
     }
+    const int4 r = sr[lo];
+    const uint32_t k = p - so[lo];
+    const uint32_t y = k / (uint32_t)r.z, x = k - y * (uint32_t)r.z;
+    keys[p] = (uint32_t)(r.w + (r.y + (int)y) * stx[lo] + r.x + (int)x);
+    vals[p] = se[lo];
+  }
 }
 
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t m, uint32_t v) {
@@ -304,8 +329,8 @@ gut_status bin_sort(const gut_projected* proj, int n, const DevCam* dc, int n_ca
     return st;
   CamTiles ct;
   for (int c = 0; c < n_cams; c++) { ct.base[c] = dc[c].tile_base; ct.tx[c] = dc[c].tiles_x; }
-  duplicate_kernel<<<grid_for(nvis, 128), 128, 0, s>>>(ent, E32(L.offs), (const short4*)proj->rect,
-                                                       n, ct, nvis, Q32(Lp.pkA), sorted_ids);
+  duplicate_kernel<<<grid_for(nvis, kDupThreads), kDupThreads, 0, s>>>(
+      ent, E32(L.offs), (const short4*)proj->rect, n, ct, nvis, P, Q32(Lp.pkA), sorted_ids);
   GUT_LAUNCH_CHECK();
   int bits = 1;
   while ((int64_t(1) << bits) < T) bits++;

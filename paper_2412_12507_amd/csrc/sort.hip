@@ -2,12 +2,13 @@
 //
 // Both process 4096-element chunks per 256-thread block (4 wave64s x 16
 // items).  The scan is reduce -> (recursive) scan of chunk sums -> downsweep.
-// Each radix pass (8-bit digits) is histogram -> scan of the digit-major
-// count matrix -> scatter.  The scatter ranks keys inside each wave with
-// ballot-based peer masks (a key's rank among equal digits is the popcount
-// of the lower peer lanes), keeps per-wave running digit counts in LDS, and
-// combines waves with one barrier, so the sort is stable without a local
-// block-wide sort.
+// Each radix pass (8-bit digits) is histogram -> per-digit scan of the
+// digit-major count matrix (one block per digit) -> scatter.  The scatter
+// ranks keys inside each wave with ballot-based peer masks (a key's rank
+// among equal digits is the popcount of the lower peer lanes), keeps
+// per-wave running digit counts in LDS, combines waves with one barrier
+// (so the sort is stable without a block-wide sort), and reorders the chunk
+// by digit in LDS before writing, so each digit's run is one coalesced write.
 #include "common.h"
 
 namespace gut {
@@ -145,17 +146,52 @@ __global__ void __launch_bounds__(kThreads) radix_hist_kernel(const uint32_t* __
   counts[(int64_t)t * nblocks + blockIdx.x] = h[t];
 }
 
+// Per digit (one block each): exclusive scan of that digit's per-block
+// counts in place of the count row, and the digit's total.
+__global__ void __launch_bounds__(kThreads) radix_rowscan_kernel(const uint32_t* __restrict__ counts,
+                                                                 uint32_t* __restrict__ offs,
+                                                                 uint32_t* __restrict__ totals,
+                                                                 int64_t nblocks) {
+  __shared__ uint32_t wsum[kThreads / kWave];
+  const int d = blockIdx.x;
+  const uint32_t* row = counts + (int64_t)d * nblocks;
+  uint32_t* orow = offs + (int64_t)d * nblocks;
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nblocks; b0 += kThreads) {
+    const int64_t b = b0 + threadIdx.x;
+    const uint32_t v = b < nblocks ? row[b] : 0u;
+    uint32_t total;
+    const uint32_t pre = block_exclusive_scan(v, wsum, &total);
+    if (b < nblocks) orow[b] = carry + pre;
+    carry += total;
+    __syncthreads();  // wsum is reused by the next chunk
+  }
+  if (threadIdx.x == 0) totals[d] = carry;
+}
+
+// Stable scatter of one 4096-key chunk.  Keys are ranked inside each wave
+// with ballot peer masks (rank = popcount of lower lanes holding the same
+// digit), waves are combined through per-wave digit counts, and the chunk is
+// first reordered by digit in LDS so that each digit's run leaves the block
+// as one contiguous, coalesced write.
 __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, int64_t n, int shift, int nbits, const uint32_t* __restrict__ offs,
-    int64_t nblocks) {
+    const uint32_t* __restrict__ totals, int64_t nblocks) {
   __shared__ uint32_t wh[kThreads / kWave][kRadix];
-  __shared__ uint32_t goff[kRadix];
+  __shared__ uint32_t goff[kRadix];    // global start of this block's run of digit d
+  __shared__ uint32_t lstart[kRadix];  // start of digit d's run inside the chunk
+  __shared__ uint32_t sk[kChunk], sv[kChunk];
+  __shared__ uint32_t wsum[kThreads / kWave];
   const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
   const uint32_t mask = (1u << nbits) - 1u;
 #pragma unroll
   for (int k = 0; k < kThreads / kWave; k++) wh[k][t] = 0;
-  goff[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+  {  // digit bases: exclusive scan of the digit totals
+    uint32_t tot;
+    const uint32_t base = block_exclusive_scan(totals[t], wsum, &tot);
+    goff[t] = base + offs[(int64_t)t * nblocks + blockIdx.x];
+  }
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)w * (kChunk / 4);
@@ -181,23 +217,34 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     rk[r] = valid ? run + before : 0xffffffffu;
   }
   __syncthreads();
-  {  // exclusive prefix of the per-wave counts for digit t
-    uint32_t s = 0;
+  {  // per digit t: exclusive prefix over the waves, and the chunk's digit total
+    uint32_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kThreads / kWave; k++) {
       uint32_t c = wh[k][t];
-      wh[k][t] = s;
-      s += c;
+      wh[k][t] = sum;
+      sum += c;
     }
+    uint32_t tot;
+    lstart[t] = block_exclusive_scan(sum, wsum, &tot);
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kItems; r++) {
     if (rk[r] == 0xffffffffu) continue;
-    uint32_t d = (kk[r] >> shift) & mask;
-    uint32_t pos = goff[d] + wh[w][d] + rk[r];
-    kout[pos] = kk[r];
-    vout[pos] = vv[r];
+    const uint32_t d = (kk[r] >> shift) & mask;
+    const uint32_t lp = lstart[d] + wh[w][d] + rk[r];
+    sk[lp] = kk[r];
+    sv[lp] = vv[r];
+  }
+  __syncthreads();
+  const int cnt = (int)min((int64_t)kChunk, n - (int64_t)blockIdx.x * kChunk);
+  for (int j = t; j < cnt; j += kThreads) {
+    const uint32_t k = sk[j];
+    const uint32_t d = (k >> shift) & mask;
+    const uint32_t pos = goff[d] + (uint32_t)j - lstart[d];
+    kout[pos] = k;
+    vout[pos] = sv[j];
   }
 }
 
@@ -206,7 +253,7 @@ int64_t radix_blocks(int64_t n) { return ceil_div(n > 0 ? n : 1, kChunk); }
 size_t radix_temp_bytes(int64_t n) {
   int64_t nb = radix_blocks(n);
   size_t cnt = align256((size_t)kRadix * nb * sizeof(uint32_t));
-  return 2 * cnt + scan_temp_bytes((int64_t)kRadix * nb);
+  return 2 * cnt + align256(kRadix * sizeof(uint32_t));
 }
 
 gut_status radix_sort_pairs_pp(uint32_t* kA, uint32_t* vA, uint32_t* kB, uint32_t* vB, int64_t n,
@@ -219,7 +266,7 @@ gut_status radix_sort_pairs_pp(uint32_t* kA, uint32_t* vA, uint32_t* kB, uint32_
   size_t cnt_bytes = align256((size_t)kRadix * nb * sizeof(uint32_t));
   uint32_t* counts = (uint32_t*)temp;
   uint32_t* offs = (uint32_t*)((char*)temp + cnt_bytes);
-  void* scan_tmp = (char*)temp + 2 * cnt_bytes;
+  uint32_t* totals = (uint32_t*)((char*)temp + 2 * cnt_bytes);
   uint32_t *ks = kA, *vs = vA;
   for (int p = 0; p < passes; p++) {
     uint32_t* kd = ks == kA ? kB : kA;
@@ -228,9 +275,10 @@ gut_status radix_sort_pairs_pp(uint32_t* kA, uint32_t* vA, uint32_t* kB, uint32_
     int nbits = bits - shift < kRadixBits ? bits - shift : kRadixBits;
     radix_hist_kernel<<<(unsigned)nb, kThreads, 0, st>>>(ks, n, shift, (1u << nbits) - 1u, counts, nb);
     GUT_LAUNCH_CHECK();
-    gut_status s = exclusive_scan_u32(counts, offs, (int64_t)kRadix * nb, scan_tmp, st);
-    if (s != GUT_OK) return s;
-    radix_scatter_kernel<<<(unsigned)nb, kThreads, 0, st>>>(ks, vs, kd, vd, n, shift, nbits, offs, nb);
+    radix_rowscan_kernel<<<kRadix, kThreads, 0, st>>>(counts, offs, totals, nb);
+    GUT_LAUNCH_CHECK();
+    radix_scatter_kernel<<<(unsigned)nb, kThreads, 0, st>>>(ks, vs, kd, vd, n, shift, nbits, offs,
+                                                            totals, nb);
     GUT_LAUNCH_CHECK();
     ks = kd;
     vs = vd;
