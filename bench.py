@@ -57,12 +57,12 @@ def render_source_hash():
 
 
 def pmc_summary(fetch_dir, write_dir, out_path, command):
-    """Per-launch HBM bytes of render_kernel<false> from two rocprofv3 --pmc
-    runs of `bench.py --calib-copy` (FETCH_SIZE, then WRITE_SIZE, KiB per
-    dispatch).  Each counter is scaled by what it reads for a kernel of known
-    traffic in the same run: the 1 GiB add (reads 1 GiB) for FETCH_SIZE and
-    the 1 GiB fill (writes 1 GiB) for WRITE_SIZE.  The last two render
-    dispatches (the untimed render that also writes n_eval) are left out."""
+    """Per-launch HBM bytes of the timed render kernel (render_kernel<false,
+    false>: global shutter, no n_eval) from two rocprofv3 --pmc runs of
+    `bench.py --calib-copy` (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).
+    Each counter is scaled by what it reads for a kernel of known traffic in
+    the same run: the 1 GiB add (reads 1 GiB) for FETCH_SIZE and the 1 GiB
+    fill (writes 1 GiB) for WRITE_SIZE."""
     import csv
     import glob
 
@@ -81,8 +81,8 @@ def pmc_summary(fetch_dir, write_dir, out_path, command):
     fr, wr = read(fetch_dir, "FETCH_SIZE"), read(write_dir, "WRITE_SIZE")
     f_add = pick(fr, "CUDAFunctor_add", "CUDAFunctorOnSelf_add")
     w_fill = pick(wr, "FillFunctor")
-    f_r = pick(fr, "gut::render_kernel<false>")[:-2]
-    w_r = pick(wr, "gut::render_kernel<false>")[:-2]
+    f_r = pick(fr, "gut::render_kernel<false, false>")
+    w_r = pick(wr, "gut::render_kernel<false, false>")
     if not (f_add and w_fill and f_r and w_r):
         raise SystemExit("pmc summary: calibration or render dispatches missing")
     ff = CALIB_BYTES / (f_add[0] * 1024.0)

@@ -25,7 +25,7 @@ constexpr int kRBatch = kRThreads;
 
 // One tile of one camera.  pd, pf, F, wb and red are the block's LDS; out_*
 // are indexed by pix_base + y * W + x.
-template <bool RS>
+template <bool RS, bool NE>
 __device__ __forceinline__ void render_tile(
     const DevCam& cam, const Thresholds& th, int n, int cam_idx, int tile,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
@@ -67,10 +67,10 @@ __device__ __forceinline__ void render_tile(
   float T[2] = {1.0f, 1.0f};
   double C[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
   uint32_t last[2] = {0u, 0u}, nev[2] = {active[0] ? len : 0u, active[1] ? len : 0u};
-  bool done[2] = {!active[0], !active[1]};
+  bool done0 = !active[0], done1 = !active[1];
   for (uint32_t b = 0; b < len; b += kRBatch) {
     // (also publishes wb before the first setup)
-    if (__syncthreads_count(!(done[0] && done[1])) == 0) break;
+    if (__syncthreads_count(!(done0 && done1)) == 0) break;
     uint32_t fl = 0u;
     if (b + t < len) {
       uint32_t e = ids[rg.x + b + t];
@@ -80,13 +80,13 @@ __device__ __forceinline__ void render_tile(
     pf[t] = fl;
     __syncthreads();
     // the batch's pairs that may reach alpha_min somewhere in this wave's half-tile
-    const unsigned long long m0 = __ballot((pf[lane] >> wv) & 1u);
-    const unsigned long long m1 = __ballot((pf[lane + 64] >> wv) & 1u);
+    const unsigned long long m0 = __builtin_amdgcn_ballot_w64((pf[lane] >> wv) & 1u);
+    const unsigned long long m1 = __builtin_amdgcn_ballot_w64((pf[lane + 64] >> wv) & 1u);
     bool wave_done = false;
     for (int h = 0; h < 2 && !wave_done; h++) {
       unsigned long long m = h ? m1 : m0;
       while (m) {
-        if (__ballot(!(done[0] && done[1])) == 0ull) { wave_done = true; break; }
+        if (!wave_any(!(done0 && done1))) { wave_done = true; break; }
         const uint32_t q = 64u * h + (uint32_t)__builtin_ctzll(m);
         m &= m - 1ull;
         const float4* P = &pd[q * S];
@@ -95,8 +95,8 @@ __device__ __forceinline__ void render_tile(
         Eval ev[2];
 #pragma unroll
         for (int k = 0; k < 2; k++) eval_test<RS>(r, P, u[k], v[k], dt[k], &ev[k]);
-        const bool live0 = ev[0].ok && !done[0], live1 = ev[1].ok && !done[1];
-        if (__ballot(live0 || live1) == 0ull) continue;  // nothing reaches alpha_min here
+        const bool live0 = ev[0].ok && !done0, live1 = ev[1].ok && !done1;
+        if (!wave_any(live0 || live1)) continue;  // nothing reaches alpha_min here
         bool contrib[2];
         float wgt[2];
 #pragma unroll
@@ -104,26 +104,26 @@ __device__ __forceinline__ void render_tile(
           eval_alpha<RS>(r, th.alpha_max, &ev[k]);
           const bool live = k ? live1 : live0;
           const float Tn = fmaf(-ev[k].a, T[k], T[k]);  // T (1 - alpha)
-          const bool stop = live && Tn < th.t_min;      // stop before adding this particle
-          contrib[k] = live && !stop;
+          const bool below = Tn < th.t_min;
+          const bool stop = live & below;  // stop before adding this particle
+          contrib[k] = live & !below;
           const float ae = contrib[k] ? ev[k].a : 0.0f;
           wgt[k] = ae * T[k];
           T[k] = fmaf(-ae, T[k], T[k]);  // Tn, or T itself when not contributing
           last[k] = contrib[k] ? b + q + 1 : last[k];
-          nev[k] = stop ? b + q + 1 : nev[k];
-          done[k] = done[k] || stop;
+          if (NE) nev[k] = stop ? b + q + 1 : nev[k];
+          if (k) done1 = done1 || stop; else done0 = done0 || stop;
         }
-        if (__ballot(contrib[0] || contrib[1]) != 0ull) {
-          double col[3];
-          pair_colour<RS>(P, col);
-          const double c0 = col[0], c1 = col[1], c2 = col[2];
+        // some lane passed the alpha_min test, so almost always some lane
+        // contributes: accumulate unconditionally (zero weights add nothing)
+        double col[3];
+        pair_colour<RS>(P, col);
 #pragma unroll
-          for (int k = 0; k < 2; k++) {
-            const double w = (double)wgt[k];
-            C[k][0] = fma(w, c0, C[k][0]);
-            C[k][1] = fma(w, c1, C[k][1]);
-            C[k][2] = fma(w, c2, C[k][2]);
-          }
+        for (int k = 0; k < 2; k++) {
+          const double w = (double)wgt[k];
+          C[k][0] = fma(w, col[0], C[k][0]);
+          C[k][1] = fma(w, col[1], C[k][1]);
+          C[k][2] = fma(w, col[2], C[k][2]);
         }
       }
     }
@@ -138,12 +138,13 @@ __device__ __forceinline__ void render_tile(
     out_rgb[3 * pix + 2] = (float)fma((double)T[k], (double)th.bg[2], C[k][2]);
     if (out_T) out_T[pix] = T[k];
     if (out_nc) out_nc[pix] = last[k];
-    if (out_ne) out_ne[pix] = nev[k];
+    if (NE) out_ne[pix] = nev[k];
   }
 }
 
-// One block per tile, taken in the render order (longest lists first).
-template <bool RS>
+// One block per tile, taken in the render order (longest lists first).  NE:
+// also count each pixel's evaluated entries (out_ne non-null).
+template <bool RS, bool NE>
 __global__ void __launch_bounds__(kRThreads, 4) render_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
@@ -155,7 +156,7 @@ __global__ void __launch_bounds__(kRThreads, 4) render_kernel(
   __shared__ WaveBoxes wb;
   __shared__ float red[6];
   const int tile = (int)order[cam.tile_base + blockIdx.x];
-  render_tile<RS>(cam, th, n, cam_idx, tile, ranges, ids, record, rgb, out_rgb, out_T, out_nc,
+  render_tile<RS, NE>(cam, th, n, cam_idx, tile, ranges, ids, record, rgb, out_rgb, out_T, out_nc,
                   out_ne, cam.pixel_base, pd, pf, F, wb, red);
 }
 
@@ -210,7 +211,7 @@ __global__ void __launch_bounds__(kRThreads, 3) render_batch_kernel(
     }
     __syncthreads();
     const int tile = (int)order[cam_s.tile_base + (item - item_start[j])];
-    render_tile<RS>(cam_s, th, n, c, tile, ranges, ids, record, rgb, outs[c], nullptr, nullptr,
+    render_tile<RS, false>(cam_s, th, n, c, tile, ranges, ids, record, rgb, outs[c], nullptr, nullptr,
                     nullptr, 0, pd, pf, F, wb, red);
   }
 }
@@ -259,14 +260,14 @@ gut_status launch_render(const DevCam& cam, const Thresholds& th, int n, int cam
                          const float* record, const float* rgb, float* out_rgb, float* out_T,
                          uint32_t* out_nc, uint32_t* out_ne, hipStream_t s) {
   dim3 grid(cam.tiles_x * cam.tiles_y), block(kRThreads);
-  if (cam.shutter == GUT_ROLLING_TOP_TO_BOTTOM)
-    render_kernel<true><<<grid, block, 0, s>>>(cam, th, n, cam_idx, (const uint2*)ranges, order,
-                                               ids, (const float4*)record, rgb, out_rgb, out_T,
-                                               out_nc, out_ne);
-  else
-    render_kernel<false><<<grid, block, 0, s>>>(cam, th, n, cam_idx, (const uint2*)ranges, order,
-                                                ids, (const float4*)record, rgb, out_rgb, out_T,
-                                                out_nc, out_ne);
+#define GUT_RK(RS, NE)                                                                        \
+  render_kernel<RS, NE><<<grid, block, 0, s>>>(cam, th, n, cam_idx, (const uint2*)ranges, order, \
+                                               ids, (const float4*)record, rgb, out_rgb, out_T,   \
+                                               out_nc, out_ne)
+  const bool rs = cam.shutter == GUT_ROLLING_TOP_TO_BOTTOM;
+  if (rs) { if (out_ne) GUT_RK(true, true); else GUT_RK(true, false); }
+  else { if (out_ne) GUT_RK(false, true); else GUT_RK(false, false); }
+#undef GUT_RK
   GUT_LAUNCH_CHECK();
   return GUT_OK;
 }

@@ -138,8 +138,8 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
     pf[t] = fl;
     __syncthreads();
     // the same pairs the forward walked for this half-tile
-    const unsigned long long m0 = __ballot((pf[lane] >> wv) & 1u);
-    const unsigned long long m1 = __ballot((pf[lane + 64] >> wv) & 1u);
+    const unsigned long long m0 = __builtin_amdgcn_ballot_w64((pf[lane] >> wv) & 1u);
+    const unsigned long long m1 = __builtin_amdgcn_ballot_w64((pf[lane + 64] >> wv) & 1u);
     bool wave_done = false;
     for (int hh = 0; hh < 2 && !wave_done; hh++) {
       unsigned long long m = hh ? m1 : m0;
@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
         const uint32_t q = 64u * hh + (uint32_t)__builtin_ctzll(m);
         m &= m - 1ull;
         const uint32_t idx = b + q;
-        if (__ballot(idx < last[0] || idx < last[1]) == 0ull) { wave_done = true; break; }
+        if (!wave_any(idx < last[0] || idx < last[1])) { wave_done = true; break; }
         const float4* P = &pd[q * S];
         PairRegs<RS> r;
         load_pair<RS>(P, r);
@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
         bool hit[2];
         hit[0] = ev[0].ok && idx < last[0];
         hit[1] = ev[1].ok && idx < last[1];
-        if (__ballot(hit[0] || hit[1]) == 0ull) continue;  // wave-uniform
+        if (!wave_any(hit[0] || hit[1])) continue;  // wave-uniform
         double cold[3];
         pair_colour<RS>(P, cold);
         const float col[3] = {(float)cold[0], (float)cold[1], (float)cold[2]};
@@ -301,8 +301,8 @@ __global__ void __launch_bounds__(kShThreads) sh_grad_kernel(
     }
   }
   const bool any = live[0] || live[1] || live[2];
-  const bool wave_any = __ballot(any) != 0ull;
-  if (wave_any) {
+  const bool some = wave_any(any);
+  if (some) {
     for (int j = t; j < cnt * C; j += kShThreads) lb[(j / C) * LD + j % C] = src[j];
   }
   __syncthreads();
@@ -342,7 +342,7 @@ __global__ void __launch_bounds__(kShThreads) sh_grad_kernel(
     g_means[3 * i + 1] += (gd.y - d.y * pdd) * id;
     g_means[3 * i + 2] += (gd.z - d.z * pdd) * id;
   }
-  if (!first && !wave_any) return;  // nothing to add for these particles
+  if (!first && !some) return;  // nothing to add for these particles
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < C; k++) lb[t * LD + k] = gs[k];

@@ -137,10 +137,16 @@ __global__ void __launch_bounds__(kThreads) radix_hist_kernel(const uint32_t* __
   h[t] = 0;
   __syncthreads();
   int64_t base = (int64_t)blockIdx.x * kChunk;
+  uint32_t kk[kItems];  // all loads first, then the LDS atomics
 #pragma unroll
   for (int j = 0; j < kItems; j++) {
     int64_t g = base + j * kThreads + t;
-    if (g < n) atomicAdd(&h[(keys[g] >> shift) & mask], 1u);
+    kk[j] = g < n ? keys[g] : 0xffffffffu;
+  }
+#pragma unroll
+  for (int j = 0; j < kItems; j++) {
+    int64_t g = base + j * kThreads + t;
+    if (g < n) atomicAdd(&h[(kk[j] >> shift) & mask], 1u);
   }
   __syncthreads();
   counts[(int64_t)t * nblocks + blockIdx.x] = h[t];
@@ -197,11 +203,16 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
   int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)w * (kChunk / 4);
   uint32_t kk[kItems], vv[kItems], rk[kItems];
 #pragma unroll
+  for (int r = 0; r < kItems; r++) {  // all loads first
+    int64_t g = base + r * kWave + lane;
+    kk[r] = g < n ? kin[g] : 0u;
+    vv[r] = g < n ? vin[g] : 0u;
+  }
+#pragma unroll
   for (int r = 0; r < kItems; r++) {
     int64_t g = base + r * kWave + lane;
     bool valid = g < n;
-    uint32_t k = valid ? kin[g] : 0u;
-    uint32_t v = valid ? vin[g] : 0u;
+    uint32_t k = kk[r];
     uint32_t d = (k >> shift) & mask;
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < nbits; b++) {
@@ -212,8 +223,6 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     uint32_t before = (uint32_t)__popcll(peers & lt);
     uint32_t run = valid ? wh[w][d] : 0u;
     if (valid && before == 0) wh[w][d] = run + (uint32_t)__popcll(peers);
-    kk[r] = k;
-    vv[r] = v;
     rk[r] = valid ? run + before : 0xffffffffu;
   }
   __syncthreads();

@@ -352,7 +352,8 @@ __device__ __forceinline__ void eval_alpha(const PairRegs<RS>& r, float amax, Ev
   const float araw = __builtin_amdgcn_exp2f(fmaf(-o->cc, idd, r.lsig));
   o->idd = idd;
   o->clamped = araw > amax;
-  o->a = o->ok ? fminf(araw, amax) : 0.0f;
+  // araw >= 0, so med3(araw, 0, amax) = min(araw, amax) in one instruction
+  o->a = o->ok ? __builtin_amdgcn_fmed3f(araw, 0.0f, amax) : 0.0f;
 }
 
 // Colour of a pair (FP64 slots).
@@ -439,6 +440,12 @@ __device__ inline void wave_box(const float* u, const float* v, const bool* vali
     const int w = threadIdx.x >> 6;
     wb->u0[w] = a0; wb->u1[w] = a1; wb->v0[w] = b0; wb->v1[w] = b1;
   }
+}
+
+// True when pred holds on some active lane (the wave's lane mask, without a
+// round trip through a vector register).
+__device__ __forceinline__ bool wave_any(bool pred) {
+  return __builtin_amdgcn_ballot_w64(pred) != 0ull;
 }
 
 // Tile visited by block b: blocks are dealt round-robin to the 8 XCDs, so
