@@ -104,17 +104,23 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
   const float l2amin = log2f(th.alpha_min);
   wave_box<2>(u, v, active, &wb);
 
+  // Per pixel: the loss gradients, T_N gT, and Z = sum_c gC_c (C_c - C_<=j,c)
+  // in FP64 (C the output colour, C_<=j the running colour including entry
+  // j), which is all the suffix sums S_after enter the gradient through.
   uint32_t last[2] = {0u, 0u};
-  float TN[2] = {1.f, 1.f}, gC[2][3] = {{0, 0, 0}, {0, 0, 0}}, gT[2] = {0.f, 0.f};
-  double Co[2][3] = {{0, 0, 0}, {0, 0, 0}};  // output colour C = sum c alpha T + T_N bg
+  float gC[2][3] = {{0, 0, 0}, {0, 0, 0}}, gTT[2] = {0.f, 0.f};
+  double gCd[2][3] = {{0, 0, 0}, {0, 0, 0}}, Z[2] = {0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < 2; k++) {
     if (!active[k]) continue;
     const long long pix = cam.pixel_base + (long long)(py0 + 4 * k) * cam.W + px;
     last[k] = out_nc[pix];
-    TN[k] = out_T[pix];
-    for (int c = 0; c < 3; c++) { gC[k][c] = d_rgb[3 * pix + c]; Co[k][c] = out_rgb[3 * pix + c]; }
-    gT[k] = d_T ? d_T[pix] : 0.0f;
+    gTT[k] = (d_T ? d_T[pix] : 0.0f) * out_T[pix];
+    for (int c = 0; c < 3; c++) {
+      gC[k][c] = d_rgb[3 * pix + c];
+      gCd[k][c] = gC[k][c];
+      Z[k] = fma(gCd[k][c], (double)out_rgb[3 * pix + c], Z[k]);
+    }
   }
   atomicMax(&maxlast_s, max(last[0], last[1]));
   __syncthreads();  // (also publishes wb)
@@ -125,7 +131,6 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
   else if (maxlast >= 256) __builtin_amdgcn_s_setprio(1);
 
   float T[2] = {1.0f, 1.0f};
-  double A[2][3] = {{0, 0, 0}, {0, 0, 0}};  // running colour C_<=j, accumulated as in the forward
   for (uint32_t b = 0; b < maxlast; b += kBwBatch) {
     __syncthreads();
     uint32_t fl = 0u;
@@ -160,51 +165,43 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
         if (!wave_any(hit[0] || hit[1])) continue;  // wave-uniform
         double cold[3];
         pair_colour<RS>(P, cold);
-        const float col[3] = {(float)cold[0], (float)cold[1], (float)cold[2]};
-        float g[16];  // kAcc + 3 values, padded for the reduction
-#pragma unroll
-        for (int j = 0; j < 16; j++) g[j] = 0.0f;
-        float wgt[2];
+        float gk[2][kAcc + 3];
 #pragma unroll
         for (int k = 0; k < 2; k++) {
           eval_alpha<RS>(r, th.alpha_max, &ev[k]);
           const float Tb = T[k];
           const float ae = hit[k] ? ev[k].a : 0.0f;
-          wgt[k] = ae * Tb;
+          const float wgt = ae * Tb;
           T[k] = fmaf(-ae, Tb, Tb);  // the forward's update, bit for bit
-          g[kAcc] += wgt[k] * gC[k][0];
-          g[kAcc + 1] += wgt[k] * gC[k][1];
-          g[kAcc + 2] += wgt[k] * gC[k][2];
-          // A_j includes this contributor: (S_after + T_N bg) = C - C_<=j, in FP64
-          double R0 = Co[k][0] - fma((double)wgt[k], cold[0], A[k][0]);
-          double R1 = Co[k][1] - fma((double)wgt[k], cold[1], A[k][1]);
-          double R2 = Co[k][2] - fma((double)wgt[k], cold[2], A[k][2]);
-          const float inv1m = 1.0f / (1.0f - ev[k].a);
-          float gA = gC[k][0] * (col[0] * Tb - (float)R0 * inv1m) +
-                     gC[k][1] * (col[1] * Tb - (float)R1 * inv1m) +
-                     gC[k][2] * (col[2] * Tb - (float)R2 * inv1m) - gT[k] * TN[k] * inv1m;
+          gk[k][kAcc] = wgt * gC[k][0];
+          gk[k][kAcc + 1] = wgt * gC[k][1];
+          gk[k][kAcc + 2] = wgt * gC[k][2];
+          // D = gC . c_j; after this entry Z = sum_c gC_c (C_c - C_<=j,c)
+          const double D = fma(gCd[k][0], cold[0], fma(gCd[k][1], cold[1], gCd[k][2] * cold[2]));
+          Z[k] = fma(-(double)wgt, D, Z[k]);
+          // dL/dalpha = T_j gC.c_j - (gC.(C - C_<=j) + gT T_N) / (1 - alpha_j)
+          const float inv1m = __builtin_amdgcn_rcpf(1.0f - ev[k].a);
+          float gA = fmaf(Tb, (float)D, -inv1m * ((float)Z[k] + gTT[k]));
           const bool geo = hit[k] && !ev[k].clamped;  // alpha = alpha_max carries no gradient
           gA = geo ? gA : 0.0f;
           // rho = exp(-omega^2 / 2) = 2^(-omega'^2)
           const float rho = __builtin_amdgcn_exp2f(-ev[k].cc * ev[k].idd);
-          g[9] += gA * rho;
+          gk[k][9] = gA * rho;
           const float c = -ev[k].a * gA;  // 2 dL/domega^2
           float3 dg, cr;
           pair_vectors<RS>(P, ev[k], u[k], v[k], &dg, &cr);
           float3 p = cross3f(dg, cr);
           p = f3(p.x * ev[k].idd, p.y * ev[k].idd, p.z * ev[k].idd);
           const float3 cp = f3(c * p.x, c * p.y, c * p.z);
-          g[0] += cp.x * p.x; g[1] += cp.x * p.y; g[2] += cp.x * p.z;
-          g[3] += cp.y * p.y; g[4] += cp.y * p.z; g[5] += cp.z * p.z;
-          g[6] += cp.x; g[7] += cp.y; g[8] += cp.z;
+          gk[k][0] = cp.x * p.x; gk[k][1] = cp.x * p.y; gk[k][2] = cp.x * p.z;
+          gk[k][3] = cp.y * p.y; gk[k][4] = cp.y * p.z; gk[k][5] = cp.z * p.z;
+          gk[k][6] = cp.x; gk[k][7] = cp.y; gk[k][8] = cp.z;
         }
+        float g[16];  // kAcc + 3 values, padded for the reduction
 #pragma unroll
-        for (int k = 0; k < 2; k++) {
-          const double w = (double)wgt[k];
-          A[k][0] = fma(w, cold[0], A[k][0]);
-          A[k][1] = fma(w, cold[1], A[k][1]);
-          A[k][2] = fma(w, cold[2], A[k][2]);
-        }
+        for (int j = 0; j < kAcc + 3; j++) g[j] = gk[0][j] + gk[1][j];
+#pragma unroll
+        for (int j = kAcc + 3; j < 16; j++) g[j] = 0.0f;
         // one lane per value issues its atomic: lanes 4k hold value k
         const float tot = wave_reduce16(g);
         const int k = lane >> 2;
