@@ -20,7 +20,9 @@ Also reported on the same line:
   stages_ms     per-stage averages (events), Table-2 style
   fwd_bwd_ms_per_view   forward + L1 loss + backward on the fisheye view
                 against a target rendered from parameters perturbed by
-                N(0, 0.01) (the differentiation workload)
+                N(0, 0.01) (the differentiation workload): wall-clock mean
+                over the steps, plus the median of per-step HIP-event times
+                (fwd_bwd_step_ms_median)
   cpu_baseline  the FP64 oracle on this host's cores, timed on whole steps of
                 the same two-view batch (projection, binning, every tile)
                 until its time budget is spent
@@ -169,11 +171,17 @@ def bench_fwd_bwd(scene, cam, steps, warmup, R, G, torch):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
+        ev[k][0].record()
         step()
+        ev[k][1].record()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) * 1e3 / steps
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    per = sorted(a.elapsed_time(b) for a, b in ev)
+    return wall, per[len(per) // 2]
 
 
 def bench_serving(n_requests, rates, R, G, torch, n_particles=3_000_000, warm=8):
@@ -337,10 +345,11 @@ def main():
                     ms_per_launch=render_ms_per_launch)
     del fw["img"]
 
-    fwd_bwd = None
+    fwd_bwd = fwd_bwd_med = None
     if not args.no_fwd_bwd:
         log("[bench] fwd+bwd on the fisheye view")
-        fwd_bwd = bench_fwd_bwd(scene, cams[1], max(3, args.steps // 2), 2, R, G, torch)
+        fwd_bwd, fwd_bwd_med = bench_fwd_bwd(scene, cams[1], max(3, args.steps // 2), 2, R, G,
+                                             torch)
 
     serving = None
     if not args.no_serve:
@@ -381,6 +390,7 @@ def main():
         "n_pairs": fw["n_pairs"],
         "n_visible": fw["n_visible"],
         "fwd_bwd_ms_per_view": fwd_bwd,
+        "fwd_bwd_step_ms_median": fwd_bwd_med,
         "serving": serving,
         "cpu_baseline": cpu,
     }
