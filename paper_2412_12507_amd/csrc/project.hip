@@ -14,6 +14,23 @@
 
 namespace gut {
 
+// Render record of one particle: mu, sigma and the rows of M = S^-1 R^T,
+// formed in FP64 from the FP32 parameters and rounded once, so that the
+// compositing kernels see M to half an ulp.
+__device__ inline void write_record(float3 mu, float3 s, float4 q, float sig, float4* rec) {
+  const double qw = q.x, qx = q.y, qy = q.z, qz = q.w;
+  const double iq = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  const double w = qw * iq, x = qx * iq, y = qy * iq, z = qz * iq;
+  const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                       2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                       2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+  const double is0 = 1.0 / s.x, is1 = 1.0 / s.y, is2 = 1.0 / s.z;
+  rec[0] = make_float4(mu.x, mu.y, mu.z, sig);
+  rec[1] = make_float4((float)(R[0] * is0), (float)(R[3] * is0), (float)(R[6] * is0), 0.0f);
+  rec[2] = make_float4((float)(R[1] * is1), (float)(R[4] * is1), (float)(R[7] * is1), 0.0f);
+  rec[3] = make_float4((float)(R[2] * is2), (float)(R[5] * is2), (float)(R[8] * is2), 0.0f);
+}
+
 template <int DEG>
 __global__ void __launch_bounds__(256) project_kernel(
     int n, int cam_idx, DevCam cam, UTConst ut, Thresholds th, const float* __restrict__ means,
@@ -32,14 +49,8 @@ __global__ void __launch_bounds__(256) project_kernel(
   float sig = opac[i];
   float R[9];
   quat_to_rot(q, R);
-  if (record) {  // render record: mu, sigma, M = S^-1 R^T (written by one launch per scene)
-    float4* rec = reinterpret_cast<float4*>(record) + 4 * (long long)i;
-    float is0 = 1.0f / s.x, is1 = 1.0f / s.y, is2 = 1.0f / s.z;
-    rec[0] = make_float4(mu.x, mu.y, mu.z, sig);
-    rec[1] = make_float4(R[0] * is0, R[3] * is0, R[6] * is0, 0.0f);
-    rec[2] = make_float4(R[1] * is1, R[4] * is1, R[7] * is1, 0.0f);
-    rec[3] = make_float4(R[2] * is2, R[5] * is2, R[8] * is2, 0.0f);
-  }
+  if (record)  // render record (written by one launch per scene)
+    write_record(mu, s, q, sig, reinterpret_cast<float4*>(record) + 4 * (long long)i);
 
   uint32_t ntiles = 0;
   short4 rc = make_short4(0, 0, 0, 0);
@@ -130,14 +141,10 @@ __global__ void record_kernel(int n, const float* __restrict__ means,
                               const float* __restrict__ opac, float* __restrict__ record) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  float R[9];
-  quat_to_rot(reinterpret_cast<const float4*>(quats)[i], R);
-  float is0 = 1.0f / scales[3 * i], is1 = 1.0f / scales[3 * i + 1], is2 = 1.0f / scales[3 * i + 2];
-  float4* rec = reinterpret_cast<float4*>(record) + 4 * (long long)i;
-  rec[0] = make_float4(means[3 * i], means[3 * i + 1], means[3 * i + 2], opac[i]);
-  rec[1] = make_float4(R[0] * is0, R[3] * is0, R[6] * is0, 0.0f);
-  rec[2] = make_float4(R[1] * is1, R[4] * is1, R[7] * is1, 0.0f);
-  rec[3] = make_float4(R[2] * is2, R[5] * is2, R[8] * is2, 0.0f);
+  write_record(f3(means[3 * i], means[3 * i + 1], means[3 * i + 2]),
+               f3(scales[3 * i], scales[3 * i + 1], scales[3 * i + 2]),
+               reinterpret_cast<const float4*>(quats)[i], opac[i],
+               reinterpret_cast<float4*>(record) + 4 * (long long)i);
 }
 
 gut_status record_launch(const gut_scene* scene, float* record, hipStream_t s) {
