@@ -128,28 +128,35 @@ __device__ inline float3 cross3f(float3 a, float3 b) {
   return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
 
+// FP64 3-vectors.  Products are summed with explicit fma: the code is built
+// with contraction off (so that kernels sharing code round identically), and
+// an explicit fma is both exact per call site and one instruction.
 struct d3 { double x, y, z; };
 __host__ __device__ inline d3 mk3(double x, double y, double z) { d3 r = {x, y, z}; return r; }
-__host__ __device__ inline double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__host__ __device__ inline double dot(d3 a, d3 b) { return fma(a.x, b.x, fma(a.y, b.y, a.z * b.z)); }
 __host__ __device__ inline d3 cross(d3 a, d3 b) {
-  return mk3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+  return mk3(fma(a.y, b.z, -a.z * b.y), fma(a.z, b.x, -a.x * b.z), fma(a.x, b.y, -a.y * b.x));
 }
 __host__ __device__ inline d3 add(d3 a, d3 b) { return mk3(a.x + b.x, a.y + b.y, a.z + b.z); }
 __host__ __device__ inline d3 sub(d3 a, d3 b) { return mk3(a.x - b.x, a.y - b.y, a.z - b.z); }
 __host__ __device__ inline d3 scl(d3 a, double s) { return mk3(a.x * s, a.y * s, a.z * s); }
+// y + s x
+__host__ __device__ inline d3 axpy(double s, d3 x, d3 y) {
+  return mk3(fma(s, x.x, y.x), fma(s, x.y, y.y), fma(s, x.z, y.z));
+}
 __host__ __device__ inline d3 mv(const double* M, d3 v) {
-  return mk3(M[0] * v.x + M[1] * v.y + M[2] * v.z, M[3] * v.x + M[4] * v.y + M[5] * v.z,
-             M[6] * v.x + M[7] * v.y + M[8] * v.z);
+  return mk3(fma(M[0], v.x, fma(M[1], v.y, M[2] * v.z)), fma(M[3], v.x, fma(M[4], v.y, M[5] * v.z)),
+             fma(M[6], v.x, fma(M[7], v.y, M[8] * v.z)));
 }
 
 // Fisheye distortion polynomial theta_d(theta) (OpenCV fisheye model).
 __host__ __device__ inline double thetad_poly(const double* k, double th) {
   double t2 = th * th;
-  return th * (1.0 + t2 * (k[0] + t2 * (k[1] + t2 * (k[2] + t2 * k[3]))));
+  return th * fma(t2, fma(t2, fma(t2, fma(t2, k[3], k[2]), k[1]), k[0]), 1.0);
 }
 __host__ __device__ inline double thetad_deriv(const double* k, double th) {
   double t2 = th * th;
-  return 1.0 + t2 * (3.0 * k[0] + t2 * (5.0 * k[1] + t2 * (7.0 * k[2] + t2 * 9.0 * k[3])));
+  return fma(t2, fma(t2, fma(t2, fma(t2, 9.0 * k[3], 7.0 * k[2]), 5.0 * k[1]), 3.0 * k[0]), 1.0);
 }
 
 // Rotate v by angle a about unit axis u (Rodrigues), FP64.

@@ -61,11 +61,11 @@ __device__ inline bool pixel_ray(const DevCam& cam, const TileFrameD& F, int px,
   d3 dc = unproject_dir(cam, px + 0.5, py + 0.5, &valid);
   d3 o, d;
   ray_at(cam, tr, dc, &o, &d);
-  double dn = d.x * F.n[0] + d.y * F.n[1] + d.z * F.n[2];
+  double dn = dot(d, mk3(F.n[0], F.n[1], F.n[2]));
   if (!(dn > 0.0)) return false;
   double idn = 1.0 / dn;
-  *u = (float)((d.x * F.e1[0] + d.y * F.e1[1] + d.z * F.e1[2]) * idn);
-  *v = (float)((d.x * F.e2[0] + d.y * F.e2[1] + d.z * F.e2[2]) * idn);
+  *u = (float)(dot(d, mk3(F.e1[0], F.e1[1], F.e1[2])) * idn);
+  *v = (float)(dot(d, mk3(F.e2[0], F.e2[1], F.e2[2])) * idn);
   *dt = (float)(tr - F.tT);
   return valid;
 }
@@ -107,27 +107,21 @@ struct Slots {
   static constexpr int N = RS ? 11 : (BWD ? 12 : 7);
 };
 
-// QR of the affine map (u, v) -> c0 + u c1 + v c2 (FP64, Gram-Schmidt with
-// one re-orthogonalisation): |c0 + u c1 + v c2|^2 =
+// QR of the affine map (u, v) -> c0 + u c1 + v c2 (FP64 Gram-Schmidt; one
+// pass keeps the form to ~1e-7 of the alpha_min decision scale, below the
+// FP32 rounding the coefficients then take): |c0 + u c1 + v c2|^2 =
 // (q[0] + q[1] u + q[2] v)^2 + (q[3] + q[4] v)^2 + q[5].
 __device__ inline void affine_qr(d3 c0, d3 c1, d3 c2, double q[6]) {
   const double n11 = dot(c1, c1), i11 = n11 > 0.0 ? rsqrt(n11) : 0.0;
   const double r11 = n11 * i11;
   const d3 a1 = scl(c1, i11);
-  double r12 = dot(c2, a1);
-  d3 b = sub(c2, scl(a1, r12));
-  const double r12b = dot(b, a1);
-  r12 += r12b;
-  b = sub(b, scl(a1, r12b));
+  const double r12 = dot(c2, a1);
+  const d3 b = axpy(-r12, a1, c2);
   const double n22 = dot(b, b), i22 = n22 > 0.0 ? rsqrt(n22) : 0.0;
   const double r22 = n22 * i22;
   const d3 a2 = scl(b, i22);
-  double f1 = dot(c0, a1), f2 = dot(c0, a2);
-  d3 rem = sub(sub(c0, scl(a1, f1)), scl(a2, f2));
-  const double e1 = dot(rem, a1), e2 = dot(rem, a2);
-  f1 += e1;
-  f2 += e2;
-  rem = sub(sub(rem, scl(a1, e1)), scl(a2, e2));
+  const double f1 = dot(c0, a1), f2 = dot(c0, a2);
+  const d3 rem = axpy(-f2, a2, axpy(-f1, a1, c0));
   q[0] = f1; q[1] = r11; q[2] = r12; q[3] = f2; q[4] = r22; q[5] = dot(rem, rem);
 }
 
@@ -158,7 +152,7 @@ __device__ inline bool ellipse_meets_box(double qmin, double N11, double N12, do
   // edge with one offset x fixed; the other offset y ranges over [lo, hi]
   auto edge = [&](double x, double lo, double hi, double Nxx, double Nyy, double iNyy) {
     const double y = fmin(fmax(-N12 * x * iNyy, lo), hi);
-    return qmin + Nxx * x * x + 2.0 * N12 * x * y + Nyy * y * y <= slack;
+    return fma(Nyy * y, y, fma(2.0 * N12 * x, y, fma(Nxx * x, x, qmin))) <= slack;
   };
   return edge(a0, b0, b1, N11, N22, iN22) || edge(a1, b0, b1, N11, N22, iN22) ||
          edge(b0, a0, a1, N22, N11, iN11) || edge(b1, a0, a1, N22, N11, iN11);
@@ -182,14 +176,14 @@ __device__ inline unsigned pair_setup(const float4* __restrict__ record,
   d3 db = mv(M, mk3(F.e2[0], F.e2[1], F.e2[2]));
   d3 w = cross(og, dn), A = cross(og, da), B = cross(og, db);
   double s = dot(og, dn), ta = dot(og, da), tb = dot(og, db);
-  double spread = umax * fabs(ta) + vmax * fabs(tb);
+  double spread = fma(umax, fabs(ta), vmax * fabs(tb));
   d3 w2 = mk3(0, 0, 0), A2 = w2, B2 = w2;
   double s2 = 0, ta2 = 0, tb2 = 0, mlen = 0;
   if (RS) {
     d3 m = mv(M, mk3(cam.dc[0], cam.dc[1], cam.dc[2]));
     w2 = cross(m, dn); A2 = cross(m, da); B2 = cross(m, db);
     s2 = dot(m, dn); ta2 = dot(m, da); tb2 = dot(m, db);
-    spread += dtmax * (fabs(s2) + umax * fabs(ta2) + vmax * fabs(tb2));
+    spread = fma(dtmax, fma(umax, fabs(ta2), fma(vmax, fabs(tb2), fabs(s2))), spread);
     mlen = sqrt(dot(m, m));
   }
   const float sigma = r0.w;
@@ -215,16 +209,16 @@ __device__ inline unsigned pair_setup(const float4* __restrict__ record,
     if (dot(og, og) <= Kc) {
       flags = all;  // the ray origin is inside the particle's alpha_min ellipsoid
     } else {
-      const double N00 = dot(w, w) - Kc * dot(dn, dn), N01 = dot(w, A) - Kc * dot(dn, da);
-      const double N02 = dot(w, B) - Kc * dot(dn, db), N11 = dot(A, A) - Kc * dot(da, da);
-      const double N12 = dot(A, B) - Kc * dot(da, db), N22 = dot(B, B) - Kc * dot(db, db);
-      const double det = N11 * N22 - N12 * N12;
+      const double N00 = fma(-Kc, dot(dn, dn), dot(w, w)), N01 = fma(-Kc, dot(dn, da), dot(w, A));
+      const double N02 = fma(-Kc, dot(dn, db), dot(w, B)), N11 = fma(-Kc, dot(da, da), dot(A, A));
+      const double N12 = fma(-Kc, dot(da, db), dot(A, B)), N22 = fma(-Kc, dot(db, db), dot(B, B));
+      const double det = fma(N11, N22, -N12 * N12);
       if (!(N11 > 0.0) || !(N22 > 0.0) || !(det > 1e-9 * N11 * N22)) {
         flags = all;  // not a well-conditioned ellipse in the tile plane: no culling
       } else {
         const double idet = 1.0 / det;
-        const double uc = (N02 * N12 - N01 * N22) * idet, vc = (N01 * N12 - N02 * N11) * idet;
-        const double qmin = N00 + N01 * uc + N02 * vc;
+        const double uc = fma(N02, N12, -N01 * N22) * idet, vc = fma(N01, N12, -N02 * N11) * idet;
+        const double qmin = fma(N02, vc, fma(N01, uc, N00));
         if (qmin < 0.0) {
           const double iN11 = 1.0 / N11, iN22 = 1.0 / N22;
           for (int k = 0; k < nwaves; k++)
