@@ -34,31 +34,41 @@ constexpr int kAcc = 10;  // G xx,xy,xz,yy,yz,zz ; h x,y,z ; dL/dsigma
 
 // Sums 16 per-lane values over the wave as a reduce-scatter: at each of the
 // first four butterfly steps a lane keeps half of its values and adds its
-// partner's copy of that half (8 + 4 + 2 + 1 shuffles), then two plain steps
-// finish the sum; 17 shuffles instead of 16 x 6.  Afterwards lane l holds
-// the total of value (l >> 2) & 15.
+// partner's copy of that half, then two plain steps finish the sum.  The
+// 32- and 16-lane steps use the half-wave and row swaps (one instruction
+// exchanges a lane's kept and sent values with its partner's), the 8- and
+// 4-lane steps DPP row rotate and half-mirror, the last two DPP quad
+// permutes: no LDS traffic.  Afterwards lane l holds the total of value
+// (l >> 2) & 15.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
 __device__ inline float wave_reduce16(const float* g) {
   const int lane = threadIdx.x & 63;
   float h8[8], h4[4], h2[2];
-  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
 #pragma unroll
-  for (int j = 0; j < 8; j++) {
-    const float keep = b5 ? g[j + 8] : g[j], send = b5 ? g[j] : g[j + 8];
-    h8[j] = keep + __shfl_xor(send, 32, 64);
+  for (int j = 0; j < 8; j++) {  // lanes 0-31 keep g[j], lanes 32-63 keep g[j + 8]
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(g[j]), __float_as_uint(g[j + 8]),
+                                                   false, false);
+    h8[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
 #pragma unroll
-  for (int j = 0; j < 4; j++) {
-    const float keep = b4 ? h8[j + 4] : h8[j], send = b4 ? h8[j] : h8[j + 4];
-    h4[j] = keep + __shfl_xor(send, 16, 64);
+  for (int j = 0; j < 4; j++) {  // even rows keep h8[j], odd rows h8[j + 4]
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(h8[j]), __float_as_uint(h8[j + 4]),
+                                                   false, false);
+    h4[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
+  const bool b3 = lane & 8, b2 = lane & 4;
 #pragma unroll
-  for (int j = 0; j < 2; j++) {
+  for (int j = 0; j < 2; j++) {  // partner lane ^ 8 (row rotate by 8)
     const float keep = b3 ? h4[j + 2] : h4[j], send = b3 ? h4[j] : h4[j + 2];
-    h2[j] = keep + __shfl_xor(send, 8, 64);
+    h2[j] = keep + dpp<0x128>(send);
   }
-  float h = (b2 ? h2[1] : h2[0]) + __shfl_xor(b2 ? h2[0] : h2[1], 4, 64);
-  h += __shfl_xor(h, 2, 64);
-  h += __shfl_xor(h, 1, 64);
+  // partner 7 - (lane mod 8) within each 8 (row half-mirror): differs in bit 2
+  float h = (b2 ? h2[1] : h2[0]) + dpp<0x141>(b2 ? h2[0] : h2[1]);
+  h += dpp<0x1B>(h);  // quad mirror (0,3) (1,2)
+  h += dpp<0xB1>(h);  // quad xor 1
   return h;
 }
 
