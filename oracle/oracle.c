@@ -896,11 +896,13 @@ int ora_backward(const ora_scene* s, const ora_proj* pr, const ora_camera* c, co
         for (int lx = 0; lx < ts; lx++) {
           int px = txi * ts + lx, py = tyi * ts + ly;
           if (px >= c->width || py >= c->height) continue;
-          double o[3], d[3], pm;
-          if (!pixel_ray_ctx(&CX, px + 0.5, py + 0.5, o, d, &pm)) continue;
           int64_t pix = (int64_t)py * c->width + px;
           const double* gC = &dL_drgb[3 * pix];
           double gT = dL_dT ? dL_dT[pix] : 0.0;
+          /* a pixel whose loss weights are all zero contributes nothing */
+          if (gC[0] == 0.0 && gC[1] == 0.0 && gC[2] == 0.0 && gT == 0.0) continue;
+          double o[3], d[3], pm;
+          if (!pixel_ray_ctx(&CX, px + 0.5, py + 0.5, o, d, &pm)) continue;
           /* forward pass, keeping each contributor (Eq. 5) */
           double T = 1.0;
           int m = 0;

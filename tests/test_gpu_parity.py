@@ -112,6 +112,54 @@ def test_full_size_sampled(which):
     assert rep["n_fail"] == 0
 
 
+@pytest.mark.parametrize("which", ["c2-pinhole", "c2-fisheye", "c3-rolling"])
+def test_full_size_backward_sampled(which):
+    """Backward parity on the full workloads in the benchmark's launch
+    configuration: the loss weights are random on sampled tiles (the longest
+    lists plus random ones) and zero elsewhere, so the oracle's backward only
+    has those pixels to differentiate; every particle's gradient is compared."""
+    say(f"[full size backward] {which}")
+    if which == "c3-rolling":
+        scene, cam = G.config3_scene(), G.config3_camera()
+    else:
+        scene = G.config2_scene()
+        cam = G.config2_cameras()[0 if which == "c2-pinhole" else 1]
+    p = O.default_params()
+    gs, proj, bins, img = gpu_forward(scene, [cam])
+    pr = O.project(scene, cam, p)
+    ob = O.bin_tiles(pr, cam, p)
+    tx, ty = O.tiles_xy(cam, p)
+    ts = p["tile"]
+    lens = np.diff(ob[0])
+    rng = np.random.default_rng(17)
+    tiles = np.unique(np.concatenate([np.argsort(lens)[-4:], rng.choice(tx * ty, 12, replace=False)]))
+    res = O.render(scene, pr, cam, ob, p, tiles=tiles.astype(np.int32))
+    H, W = cam["height"], cam["width"]
+    wC = np.zeros((H, W, 3))
+    n_amb = 0
+    for slot, t in enumerate(tiles):
+        y0, x0 = (int(t) // tx) * ts, (int(t) % tx) * ts
+        for ly in range(ts):
+            for lx in range(ts):
+                py, px = y0 + ly, x0 + lx
+                if py >= H or px >= W:
+                    continue
+                if res["n_alt"][slot * ts * ts + ly * ts + lx] > 0:
+                    n_amb += 1  # a flipped decision changes which particles get gradient
+                    continue
+                wC[py, px] = rng.normal(size=3)
+    say("  sampled tiles", len(tiles), "ambiguous pixels zeroed", n_amb)
+    g_ora = O.backward(scene, pr, cam, ob, wC, None, p)
+    d_rgb = torch.as_tensor(wC.reshape(-1, 3), dtype=torch.float32, device="cuda")
+    g = R.render_backward(gs, proj, bins, [cam], img, d_rgb, None, p)
+    torch.cuda.synchronize()
+    rep = grad_compare(g, g_ora)
+    say("  grads", {k: (v["rel"], v["elem_fail"]) for k, v in rep.items()})
+    for k, v in rep.items():
+        assert v["rel"] <= 1e-3, (k, v)
+        assert v["elem_fail"] == 0, (k, v)
+
+
 def test_forward_deterministic_and_zero_motion():
     say("[determinism]")
     scene, cam = small_c3()
