@@ -43,6 +43,9 @@ if ROOT not in sys.path:
 
 F_EVAL = 55            # FP32 FLOPs per (pixel, particle) evaluation (mul and add counted apart)
 PEAK_FP32_TFLOPS = 157.3
+# the FP32 ceiling without packed-math instructions (256 CUs x 64 lanes x 2 FLOPs x 2.4 GHz),
+# which this build does not emit
+PEAK_FP32_NONPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "render_traffic.json")
 RENDER_SOURCES = ("render.hip", "tile_eval.h", "common.h")
@@ -340,10 +343,25 @@ def main():
             traffic = tj.get("render_kernel_bytes_per_launch")
     roofline = dict(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                     frac=achieved / PEAK_FP32_TFLOPS, traffic=traffic,
+                    peak_nonpacked=PEAK_FP32_NONPACKED_TFLOPS,
+                    frac_nonpacked=achieved / PEAK_FP32_NONPACKED_TFLOPS,
                     kernel="render_kernel (gut_render)",
                     e_eval_per_launch=fw["e_eval"] / len(cams), flops_per_eval=F_EVAL,
                     ms_per_launch=render_ms_per_launch)
     del fw["img"]
+    # HBM rooflines of the other stages, on their algorithmic bytes per step:
+    # project reads each particle (236 B at SH degree 3) and writes 28 B per
+    # (camera, particle) plus the 64 B render record; binning moves 8 B per
+    # entry (compaction), 20 B per visible entry + 8 B per pair (expansion), 20 B
+    # per key per radix pass (histogram read 4, scatter read 8 + write 8) over
+    # 4 depth passes and 2 tile passes, and 8 B per pair for the ranges.
+    n, nc, nvis, P = args.n, len(cams), fw["n_visible"], fw["n_pairs"]
+    proj_bytes = nc * (236 + 28) * n + 64 * n
+    bin_bytes = 8 * nc * n + 20 * nvis + 8 * P + 20 * 4 * nvis + 20 * 2 * P + 8 * P
+    stage_roofline = {
+        k: dict(bound="hbm", bytes=b, achieved_gbs=b / (ms * 1e-3) / 1e9, peak_gbs=PEAK_HBM_GBS,
+                frac=b / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS)
+        for k, b, ms in (("project", proj_bytes, fw["stage_ms"][0]), ("bin", bin_bytes, fw["stage_ms"][1]))}
 
     fwd_bwd = fwd_bwd_med = None
     if not args.no_fwd_bwd:
@@ -387,6 +405,7 @@ def main():
         "roofline": roofline,
         "stages_ms": {"project": fw["stage_ms"][0], "bin": fw["stage_ms"][1],
                       "render": fw["stage_ms"][2]},
+        "stage_roofline": stage_roofline,
         "n_pairs": fw["n_pairs"],
         "n_visible": fw["n_visible"],
         "fwd_bwd_ms_per_view": fwd_bwd,

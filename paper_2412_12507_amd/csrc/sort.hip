@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
   __shared__ uint32_t wh[kThreads / kWave][kRadix];
   __shared__ uint32_t goff[kRadix];    // global start of this block's run of digit d
   __shared__ uint32_t lstart[kRadix];  // start of digit d's run inside the chunk
-  __shared__ uint32_t sk[kChunk], sv[kChunk];
+  __shared__ uint32_t sk[kChunk];     // the chunk reordered by digit: keys, then values
   __shared__ uint32_t wsum[kThreads / kWave];
   const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
   const uint32_t mask = (1u << nbits) - 1u;
@@ -238,22 +238,35 @@ __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     lstart[t] = block_exclusive_scan(sum, wsum, &tot);
   }
   __syncthreads();
+  uint32_t lp[kItems];  // each key's place in the chunk's digit order
 #pragma unroll
   for (int r = 0; r < kItems; r++) {
-    if (rk[r] == 0xffffffffu) continue;
+    if (rk[r] == 0xffffffffu) { lp[r] = 0xffffffffu; continue; }
     const uint32_t d = (kk[r] >> shift) & mask;
-    const uint32_t lp = lstart[d] + wh[w][d] + rk[r];
-    sk[lp] = kk[r];
-    sv[lp] = vv[r];
+    lp[r] = lstart[d] + wh[w][d] + rk[r];
+    sk[lp[r]] = kk[r];
   }
   __syncthreads();
   const int cnt = (int)min((int64_t)kChunk, n - (int64_t)blockIdx.x * kChunk);
-  for (int j = t; j < cnt; j += kThreads) {
+  uint32_t pos[kItems];  // output position of the chunk's j-th key, j = t + 256 i
+#pragma unroll
+  for (int i = 0; i < kItems; i++) {
+    const int j = t + i * kThreads;
+    if (j >= cnt) continue;
     const uint32_t k = sk[j];
     const uint32_t d = (k >> shift) & mask;
-    const uint32_t pos = goff[d] + (uint32_t)j - lstart[d];
-    kout[pos] = k;
-    vout[pos] = sv[j];
+    pos[i] = goff[d] + (uint32_t)j - lstart[d];
+    kout[pos[i]] = k;
+  }
+  __syncthreads();  // the same LDS now stages the values
+#pragma unroll
+  for (int r = 0; r < kItems; r++)
+    if (lp[r] != 0xffffffffu) sk[lp[r]] = vv[r];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kItems; i++) {
+    const int j = t + i * kThreads;
+    if (j < cnt) vout[pos[i]] = sk[j];
   }
 }
 
@@ -271,6 +284,9 @@ gut_status radix_sort_pairs_pp(uint32_t* kA, uint32_t* vA, uint32_t* kB, uint32_
   if (n <= 0) return GUT_OK;
   int passes = (bits + kRadixBits - 1) / kRadixBits;
   if (passes < 1) passes = 1;
+  // spread the bits evenly over the passes (14 bits: 7 + 7, not 8 + 6), so
+  // no pass scatters into more digit runs than it must
+  const int per = (bits + passes - 1) / passes;
   int64_t nb = radix_blocks(n);
   size_t cnt_bytes = align256((size_t)kRadix * nb * sizeof(uint32_t));
   uint32_t* counts = (uint32_t*)temp;
@@ -280,8 +296,8 @@ gut_status radix_sort_pairs_pp(uint32_t* kA, uint32_t* vA, uint32_t* kB, uint32_
   for (int p = 0; p < passes; p++) {
     uint32_t* kd = ks == kA ? kB : kA;
     uint32_t* vd = ks == kA ? vB : vA;
-    int shift = p * kRadixBits;
-    int nbits = bits - shift < kRadixBits ? bits - shift : kRadixBits;
+    int shift = p * per;
+    int nbits = bits - shift < per ? bits - shift : per;
     radix_hist_kernel<<<(unsigned)nb, kThreads, 0, st>>>(ks, n, shift, (1u << nbits) - 1u, counts, nb);
     GUT_LAUNCH_CHECK();
     radix_rowscan_kernel<<<kRadix, kThreads, 0, st>>>(counts, offs, totals, nb);
