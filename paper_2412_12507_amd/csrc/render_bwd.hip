@@ -175,7 +175,8 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
         if (!wave_any(hit[0] || hit[1])) continue;  // wave-uniform
         double cold[3];
         pair_colour<RS>(P, cold);
-        float gk[2][kAcc + 3];
+        const float isig = __builtin_amdgcn_exp2f(-r.lsig);  // 1 / sigma, shared by both pixels
+        float gk[2][9], wfk[2], gAk[2], rhok[2];
 #pragma unroll
         for (int k = 0; k < 2; k++) {
           eval_alpha<RS>(r, th.alpha_max, &ev[k]);
@@ -183,9 +184,7 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
           const float ae = hit[k] ? ev[k].a : 0.0f;
           const float wgt = ae * Tb;
           T[k] = fmaf(-ae, Tb, Tb);  // the forward's update, bit for bit
-          gk[k][kAcc] = wgt * gC[k][0];
-          gk[k][kAcc + 1] = wgt * gC[k][1];
-          gk[k][kAcc + 2] = wgt * gC[k][2];
+          wfk[k] = wgt;
           // D = gC . c_j; after this entry Z = sum_c gC_c (C_c - C_<=j,c)
           const double D = fma(gCd[k][0], cold[0], fma(gCd[k][1], cold[1], gCd[k][2] * cold[2]));
           Z[k] = fma(-(double)wgt, D, Z[k]);
@@ -194,22 +193,33 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
           float gA = fmaf(Tb, (float)D, -inv1m * ((float)Z[k] + gTT[k]));
           const bool geo = hit[k] && !ev[k].clamped;  // alpha = alpha_max carries no gradient
           gA = geo ? gA : 0.0f;
-          // rho = exp(-omega^2 / 2) = 2^(-omega'^2)
-          const float rho = __builtin_amdgcn_exp2f(-ev[k].cc * ev[k].idd);
-          gk[k][9] = gA * rho;
+          // rho = exp(-omega^2 / 2) = (sigma rho) / sigma
+          gAk[k] = gA;
+          rhok[k] = ev[k].araw * isig;
           const float c = -ev[k].a * gA;  // 2 dL/domega^2
           float3 dg, cr;
           pair_vectors<RS>(P, ev[k], u[k], v[k], &dg, &cr);
           float3 p = cross3f(dg, cr);
           p = f3(p.x * ev[k].idd, p.y * ev[k].idd, p.z * ev[k].idd);
           const float3 cp = f3(c * p.x, c * p.y, c * p.z);
-          gk[k][0] = cp.x * p.x; gk[k][1] = cp.x * p.y; gk[k][2] = cp.x * p.z;
-          gk[k][3] = cp.y * p.y; gk[k][4] = cp.y * p.z; gk[k][5] = cp.z * p.z;
+          // G terms are cp p^T: kept as factors so the two pixels combine in fmas
+          gk[k][0] = p.x; gk[k][1] = p.y; gk[k][2] = p.z;
           gk[k][6] = cp.x; gk[k][7] = cp.y; gk[k][8] = cp.z;
         }
         float g[16];  // kAcc + 3 values, padded for the reduction
+        // G (symmetric, 6), h = sum c p (3), dL/dsigma, dL/dc (3)
+        g[0] = fmaf(gk[0][6], gk[0][0], gk[1][6] * gk[1][0]);
+        g[1] = fmaf(gk[0][6], gk[0][1], gk[1][6] * gk[1][1]);
+        g[2] = fmaf(gk[0][6], gk[0][2], gk[1][6] * gk[1][2]);
+        g[3] = fmaf(gk[0][7], gk[0][1], gk[1][7] * gk[1][1]);
+        g[4] = fmaf(gk[0][7], gk[0][2], gk[1][7] * gk[1][2]);
+        g[5] = fmaf(gk[0][8], gk[0][2], gk[1][8] * gk[1][2]);
+        g[6] = gk[0][6] + gk[1][6];
+        g[7] = gk[0][7] + gk[1][7];
+        g[8] = gk[0][8] + gk[1][8];
+        g[9] = fmaf(gAk[0], rhok[0], gAk[1] * rhok[1]);
 #pragma unroll
-        for (int j = 0; j < kAcc + 3; j++) g[j] = gk[0][j] + gk[1][j];
+        for (int c = 0; c < 3; c++) g[kAcc + c] = fmaf(wfk[0], gC[0][c], wfk[1] * gC[1][c]);
 #pragma unroll
         for (int j = kAcc + 3; j < 16; j++) g[j] = 0.0f;
         // one lane per value issues its atomic: lanes 4k hold value k

@@ -273,6 +273,7 @@ struct Eval {
   float cc;      // omega'^2 |d_g|^2 (omega'^2 = omega^2 log2(e) / 2)
   float dd;      // |d_g|^2
   float idd;     // 1 / |d_g|^2
+  float araw;    // sigma rho before the alpha_max clamp
   float3 dg, cr; // rolling shutter only: d_g and o_g x d_g
 };
 
@@ -345,6 +346,7 @@ __device__ __forceinline__ void eval_alpha(const PairRegs<RS>& r, float amax, Ev
   const float idd = __builtin_amdgcn_rcpf(o->dd);
   const float araw = __builtin_amdgcn_exp2f(fmaf(-o->cc, idd, r.lsig));
   o->idd = idd;
+  o->araw = araw;
   o->clamped = araw > amax;
   // araw >= 0, so med3(araw, 0, amax) = min(araw, amax) in one instruction
   o->a = o->ok ? __builtin_amdgcn_fmed3f(araw, 0.0f, amax) : 0.0f;
