@@ -20,9 +20,11 @@ Also reported on the same line:
   stages_ms     per-stage averages (events), Table-2 style
   fwd_bwd_ms_per_view   forward + L1 loss + backward on the fisheye view
                 against a target rendered from parameters perturbed by
-                N(0, 0.01) (the differentiation workload): wall-clock mean
-                over the steps, plus the median of per-step HIP-event times
-                (fwd_bwd_step_ms_median)
+                N(0, 0.01) (the differentiation workload): median over the
+                steps of each step's wall time between synchronisations; the
+                mean, max and HIP-event median are in fwd_bwd_detail
+  rolling_shutter_3m   stage times of the same forward step on the 3M-particle
+                rolling-shutter fisheye 1600x1200 view (context, not the metric)
   cpu_baseline  the FP64 oracle on this host's cores, timed on whole steps of
                 the same two-view batch (projection, binning, every tile)
                 until its time budget is spent
@@ -176,15 +178,17 @@ def bench_fwd_bwd(scene, cam, steps, warmup, R, G, torch):
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
-    t0 = time.perf_counter()
-    for k in range(steps):
+    walls = []
+    for k in range(steps):  # each step bracketed by synchronisations
+        t0 = time.perf_counter()
         ev[k][0].record()
         step()
         ev[k][1].record()
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) * 1e3 / steps
+        torch.cuda.synchronize()
+        walls.append((time.perf_counter() - t0) * 1e3)
     per = sorted(a.elapsed_time(b) for a, b in ev)
-    return wall, per[len(per) // 2]
+    return dict(ms_per_view=float(np.median(walls)), ms_mean=float(np.mean(walls)),
+                ms_max=float(np.max(walls)), gpu_ms_median=per[len(per) // 2])
 
 
 def bench_serving(n_requests, rates, R, G, torch, n_particles=3_000_000, warm=8):
@@ -298,6 +302,8 @@ def main():
                          "(reads 1 GiB, writes 1 GiB)")
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the 3M-particle rolling-shutter fisheye stage timings")
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-loads", default="0.5,0.9,1.5,3.0",
                     help="arrival rates as fractions of the sequential baseline's capacity")
@@ -363,16 +369,31 @@ def main():
                 frac=b / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS)
         for k, b, ms in (("project", proj_bytes, fw["stage_ms"][0]), ("bin", bin_bytes, fw["stage_ms"][1]))}
 
-    fwd_bwd = fwd_bwd_med = None
+    fwd_bwd = None
     if not args.no_fwd_bwd:
         log("[bench] fwd+bwd on the fisheye view")
-        fwd_bwd, fwd_bwd_med = bench_fwd_bwd(scene, cams[1], max(3, args.steps // 2), 2, R, G,
-                                             torch)
+        fwd_bwd = bench_fwd_bwd(scene, cams[1], max(3, args.steps // 2), 2, R, G, torch)
+
+    c3 = None
+    if not args.no_c3:
+        log("[bench] 3M-particle rolling-shutter fisheye view")
+        del gs
+        torch.cuda.empty_cache()
+        gs3 = R.GaussianScene.from_host(G.config3_scene())
+        cam3 = [G.config3_camera()]
+        f3 = bench_forward(gs3, cam3, max(3, args.steps // 2), 2, R, torch)
+        c3 = dict(workload="3M clustered Gaussians, rolling-shutter OpenCV fisheye 1600x1200",
+                  mpix_per_s=1600 * 1200 / (f3["ms_per_step"] * 1e-3) / 1e6,
+                  stages_ms={"project": f3["stage_ms"][0], "bin": f3["stage_ms"][1],
+                             "render": f3["stage_ms"][2]},
+                  n_pairs=f3["n_pairs"], n_visible=f3["n_visible"])
+        del gs3, f3
+        torch.cuda.empty_cache()
 
     serving = None
     if not args.no_serve:
         log("[bench] serving")
-        del gs
+        gs = None
         torch.cuda.empty_cache()
         serving = bench_serving(args.serve_requests, [float(x) for x in args.serve_loads.split(",")],
                                 R, G, torch)
@@ -408,8 +429,9 @@ def main():
         "stage_roofline": stage_roofline,
         "n_pairs": fw["n_pairs"],
         "n_visible": fw["n_visible"],
-        "fwd_bwd_ms_per_view": fwd_bwd,
-        "fwd_bwd_step_ms_median": fwd_bwd_med,
+        "fwd_bwd_ms_per_view": fwd_bwd["ms_per_view"] if fwd_bwd else None,
+        "fwd_bwd_detail": fwd_bwd,
+        "rolling_shutter_3m": c3,
         "serving": serving,
         "cpu_baseline": cpu,
     }
