@@ -191,6 +191,9 @@ static gut_status run_batch(gut_server* S, Worker& W, Batch& B) {
   unsigned* d_counters = (unsigned*)take(16 * sizeof(unsigned));
 
   auto release = [&]() {
+    // queued work may still use the memory (bin_count returns while the
+    // depth sort runs)
+    (void)hipStreamSynchronize(s);
     std::lock_guard<std::mutex> lk(S->mu);
     S->arena.release(off_entry);
     if (off_pair != SIZE_MAX) S->arena.release(off_pair);
@@ -212,10 +215,14 @@ static gut_status run_batch(gut_server* S, Worker& W, Batch& B) {
   uint32_t nvis = 0;
   uint64_t P = 0;
   if ((st = project_launch(&S->scene, dc.data(), nc, ut, th, &proj, false, s)) != GUT_OK ||
-      (st = fill_u32(ranges, 2 * T, 0u, s)) != GUT_OK ||
-      (st = bin_count(&proj, E, ews, &nvis, &P, s)) != GUT_OK) {
+      (st = bin_count(&proj, (int)n, dc.data(), nc, T, ews, ranges, &nvis, &P, s)) != GUT_OK) {
     release();
     return st;
+  }
+  if (P >= (uint64_t(1) << 32)) {  // pair offsets are 32-bit
+    release();
+    set_error("batch needs %llu pairs, more than 2^32 - 1", (unsigned long long)P);
+    return GUT_E_CAPACITY;
   }
   if ((int64_t)P > P_reserved) {  // grow the pair buffers, waiting for memory if needed
     std::unique_lock<std::mutex> lk(S->mu);

@@ -2,87 +2,56 @@
 //
 // Both process 4096-element chunks per 256-thread block (4 wave64s x 16
 // items).  The scan is reduce -> (recursive) scan of chunk sums -> downsweep.
-// Each radix pass (8-bit digits) is histogram -> per-digit scan of the
-// digit-major count matrix (one block per digit) -> scatter.  The scatter
-// ranks keys inside each wave with ballot-based peer masks (a key's rank
-// among equal digits is the popcount of the lower peer lanes), keeps
-// per-wave running digit counts in LDS, combines waves with one barrier
-// (so the sort is stable without a block-wide sort), and reorders the chunk
-// by digit in LDS before writing, so each digit's run is one coalesced write.
-#include "common.h"
+// The radix passes (histogram -> per-digit scan -> scatter) are built from
+// the blocks in radix.h; a pass may take its item count from device memory,
+// so a sort can be queued before the host knows how many items it will see
+// (the grid covers the upper bound and the blocks past the count stay idle).
+#include "radix.h"
 
 namespace gut {
 
-constexpr int kThreads = 256;
-constexpr int kItems = 16;
-constexpr int kChunk = kThreads * kItems;  // 4096
-constexpr int kWave = 64;
-
 __device__ inline int lds_pad(int i) { return i + (i >> 5); }
 
-// Exclusive scan of one value per thread across the block; returns the
-// exclusive prefix and writes the block total.
-__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum, uint32_t* total) {
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  uint32_t x = v;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    uint32_t y = __shfl_up(x, o, kWave);
-    if (lane >= o) x += y;
-  }
-  if (lane == kWave - 1) wsum[w] = x;
-  __syncthreads();
-  uint32_t pre = 0, tot = 0;
-#pragma unroll
-  for (int k = 0; k < kThreads / kWave; k++) {
-    uint32_t s = wsum[k];
-    if (k < w) pre += s;
-    tot += s;
-  }
-  *total = tot;
-  return pre + x - v;
-}
-
-__global__ void __launch_bounds__(kThreads) scan_reduce_kernel(const uint32_t* __restrict__ in,
-                                                               int64_t n, uint32_t* __restrict__ sums) {
-  __shared__ uint32_t wsum[kThreads / kWave];
-  int64_t base = (int64_t)blockIdx.x * kChunk;
+__global__ void __launch_bounds__(kRThreadsSort) scan_reduce_kernel(const uint32_t* __restrict__ in,
+                                                                    int64_t n, uint32_t* __restrict__ sums) {
+  __shared__ uint32_t wsum[kRWaves];
+  int64_t base = (int64_t)blockIdx.x * kRChunk;
   uint32_t acc = 0;
 #pragma unroll
-  for (int j = 0; j < kItems; j++) {
-    int64_t g = base + j * kThreads + threadIdx.x;
+  for (int j = 0; j < kRItems; j++) {
+    int64_t g = base + j * kRThreadsSort + threadIdx.x;
     if (g < n) acc += in[g];
   }
   uint32_t total;
-  block_exclusive_scan(acc, wsum, &total);
+  radix_block_scan(acc, wsum, &total);
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-__global__ void __launch_bounds__(kThreads) scan_down_kernel(const uint32_t* __restrict__ in,
-                                                             uint32_t* __restrict__ out, int64_t n,
-                                                             const uint32_t* __restrict__ offs) {
-  __shared__ uint32_t sm[kChunk + kChunk / 32];
-  __shared__ uint32_t wsum[kThreads / kWave];
-  int64_t base = (int64_t)blockIdx.x * kChunk;
+__global__ void __launch_bounds__(kRThreadsSort) scan_down_kernel(const uint32_t* __restrict__ in,
+                                                                  uint32_t* __restrict__ out, int64_t n,
+                                                                  const uint32_t* __restrict__ offs) {
+  __shared__ uint32_t sm[kRChunk + kRChunk / 32];
+  __shared__ uint32_t wsum[kRWaves];
+  int64_t base = (int64_t)blockIdx.x * kRChunk;
   const int t = threadIdx.x;
 #pragma unroll
-  for (int j = 0; j < kItems; j++) {
-    int idx = j * kThreads + t;
+  for (int j = 0; j < kRItems; j++) {
+    int idx = j * kRThreadsSort + t;
     int64_t g = base + idx;
     sm[lds_pad(idx)] = g < n ? in[g] : 0u;
   }
   __syncthreads();
-  uint32_t v[kItems], s = 0;
+  uint32_t v[kRItems], s = 0;
 #pragma unroll
-  for (int j = 0; j < kItems; j++) { v[j] = sm[lds_pad(t * kItems + j)]; s += v[j]; }
+  for (int j = 0; j < kRItems; j++) { v[j] = sm[lds_pad(t * kRItems + j)]; s += v[j]; }
   uint32_t total;
-  uint32_t run = block_exclusive_scan(s, wsum, &total) + (offs ? offs[blockIdx.x] : 0u);
+  uint32_t run = radix_block_scan(s, wsum, &total) + (offs ? offs[blockIdx.x] : 0u);
 #pragma unroll
-  for (int j = 0; j < kItems; j++) { sm[lds_pad(t * kItems + j)] = run; run += v[j]; }
+  for (int j = 0; j < kRItems; j++) { sm[lds_pad(t * kRItems + j)] = run; run += v[j]; }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kItems; j++) {
-    int idx = j * kThreads + t;
+  for (int j = 0; j < kRItems; j++) {
+    int idx = j * kRThreadsSort + t;
     int64_t g = base + idx;
     if (g < n) out[g] = sm[lds_pad(idx)];
   }
@@ -93,184 +62,151 @@ static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 size_t scan_temp_bytes(int64_t n) {
   size_t bytes = 0;
-  while (n > kChunk) {
-    int64_t nb = ceil_div(n, kChunk);
+  while (n > kRChunk) {
+    int64_t nb = ceil_div(n, kRChunk);
     bytes += 2 * align256(nb * sizeof(uint32_t));
     n = nb;
   }
   return bytes + 256;
 }
 
-gut_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* temp,
-                              hipStream_t st) {
+gut_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* temp, hipStream_t st,
+                              bool have_sums) {
   if (n <= 0) return GUT_OK;
-  if (n <= kChunk) {
-    scan_down_kernel<<<1, kThreads, 0, st>>>(in, out, n, nullptr);
+  if (n <= kRChunk) {
+    scan_down_kernel<<<1, kRThreadsSort, 0, st>>>(in, out, n, nullptr);
     GUT_LAUNCH_CHECK();
     return GUT_OK;
   }
-  int64_t nb = ceil_div(n, kChunk);
+  int64_t nb = ceil_div(n, kRChunk);
   char* tp = (char*)temp;
   uint32_t* sums = (uint32_t*)tp;
   uint32_t* scanned = (uint32_t*)(tp + align256(nb * sizeof(uint32_t)));
   char* rest = tp + 2 * align256(nb * sizeof(uint32_t));
-  scan_reduce_kernel<<<(unsigned)nb, kThreads, 0, st>>>(in, n, sums);
-  GUT_LAUNCH_CHECK();
-  gut_status s = exclusive_scan_u32(sums, scanned, nb, rest, st);
+  if (!have_sums) {
+    scan_reduce_kernel<<<(unsigned)nb, kRThreadsSort, 0, st>>>(in, n, sums);
+    GUT_LAUNCH_CHECK();
+  }
+  gut_status s = exclusive_scan_u32(sums, scanned, nb, rest, st, false);
   if (s != GUT_OK) return s;
-  scan_down_kernel<<<(unsigned)nb, kThreads, 0, st>>>(in, out, n, scanned);
+  scan_down_kernel<<<(unsigned)nb, kRThreadsSort, 0, st>>>(in, out, n, scanned);
   GUT_LAUNCH_CHECK();
   return GUT_OK;
 }
 
 // ------------------------------------------------------------------ radix sort
 
-constexpr int kRadixBits = 8;
-constexpr int kRadix = 1 << kRadixBits;
-
-__global__ void __launch_bounds__(kThreads) radix_hist_kernel(const uint32_t* __restrict__ keys,
-                                                              int64_t n, int shift, uint32_t mask,
-                                                              uint32_t* __restrict__ counts,
-                                                              int64_t nblocks) {
+__global__ void __launch_bounds__(kRThreadsSort) radix_hist_kernel(const uint32_t* __restrict__ keys,
+                                                                   int64_t n_max, const uint32_t* n_dev,
+                                                                   int shift, uint32_t mask,
+                                                                   uint32_t* __restrict__ counts,
+                                                                   int64_t nblocks) {
   __shared__ uint32_t h[kRadix];
-  const int t = threadIdx.x;
-  h[t] = 0;
-  __syncthreads();
-  int64_t base = (int64_t)blockIdx.x * kChunk;
-  uint32_t kk[kItems];  // all loads first, then the LDS atomics
-#pragma unroll
-  for (int j = 0; j < kItems; j++) {
-    int64_t g = base + j * kThreads + t;
-    kk[j] = g < n ? keys[g] : 0xffffffffu;
-  }
-#pragma unroll
-  for (int j = 0; j < kItems; j++) {
-    int64_t g = base + j * kThreads + t;
-    if (g < n) atomicAdd(&h[(kk[j] >> shift) & mask], 1u);
-  }
-  __syncthreads();
-  counts[(int64_t)t * nblocks + blockIdx.x] = h[t];
+  const int64_t n = n_dev ? (int64_t)*n_dev : n_max;
+  uint32_t kk[kRItems], vv[kRItems], pp[kRItems];
+  const uint32_t vmask = radix_load_kv(keys, nullptr, nullptr, n, kk, vv, pp);
+  radix_hist_store(kk, vmask, shift, mask, h, counts, nblocks);
 }
 
-// Per digit (one block each): exclusive scan of that digit's per-block
-// counts in place of the count row, and the digit's total.
-__global__ void __launch_bounds__(kThreads) radix_rowscan_kernel(const uint32_t* __restrict__ counts,
-                                                                 uint32_t* __restrict__ offs,
-                                                                 uint32_t* __restrict__ totals,
-                                                                 int64_t nblocks) {
-  __shared__ uint32_t wsum[kThreads / kWave];
-  const int d = blockIdx.x;
+constexpr int kRowItems = 16;  // counts per thread held in registers
+
+// Blocks 0 .. kRadix-1: one digit each.  Each thread takes a run of up to
+// kRowItems consecutive per-block counts, loaded before any arithmetic so the
+// row costs one memory round trip (longer rows loop over 4096-count pieces).
+// Block kRadix (launched with a tail only) reduces the per-block totals.
+__global__ void __launch_bounds__(kRThreadsSort) radix_rowscan_kernel(const uint32_t* __restrict__ counts,
+                                                                      uint32_t* __restrict__ offs,
+                                                                      uint32_t* __restrict__ totals,
+                                                                      int64_t nblocks, RowscanTail tail) {
+  __shared__ uint32_t wsum[kRWaves];
+  __shared__ unsigned long long wp[kRWaves];
+  const int d = blockIdx.x, t = threadIdx.x;
+  if (d == kRadix) {
+    uint32_t sn = 0;
+    unsigned long long sp = 0;
+    for (int64_t b = t; b < tail.count; b += kRThreadsSort) {
+      sn += tail.part_n[b];
+      sp += tail.part_p[b];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      sn += __shfl_xor(sn, o, 64);
+      sp += __shfl_xor(sp, o, 64);
+    }
+    if ((t & 63) == 0) { wsum[t >> 6] = sn; wp[t >> 6] = sp; }
+    __syncthreads();
+    if (t == 0) {
+      sn = 0;
+      sp = 0;
+      for (int k = 0; k < kRWaves; k++) { sn += wsum[k]; sp += wp[k]; }
+      tail.dev[0] = sn;
+      *(unsigned long long*)(tail.dev + 2) = sp;
+      volatile uint32_t* h = (volatile uint32_t*)tail.host;
+      h[0] = sn;
+      h[2] = (uint32_t)sp;
+      h[3] = (uint32_t)(sp >> 32);
+    }
+    return;
+  }
   const uint32_t* row = counts + (int64_t)d * nblocks;
   uint32_t* orow = offs + (int64_t)d * nblocks;
   uint32_t carry = 0;
-  for (int64_t b0 = 0; b0 < nblocks; b0 += kThreads) {
-    const int64_t b = b0 + threadIdx.x;
-    const uint32_t v = b < nblocks ? row[b] : 0u;
+  for (int64_t p0 = 0; p0 < nblocks; p0 += (int64_t)kRThreadsSort * kRowItems) {
+    const int64_t len = nblocks - p0 < (int64_t)kRThreadsSort * kRowItems
+                            ? nblocks - p0 : (int64_t)kRThreadsSort * kRowItems;
+    const int q = (int)((len + kRThreadsSort - 1) / kRThreadsSort);  // counts per thread
+    const int64_t b0 = p0 + (int64_t)t * q;
+    uint32_t v[kRowItems], sum = 0;
+#pragma unroll
+    for (int i = 0; i < kRowItems; i++) {
+      v[i] = (i < q && b0 + i < p0 + len) ? row[b0 + i] : 0u;
+      sum += v[i];
+    }
     uint32_t total;
-    const uint32_t pre = block_exclusive_scan(v, wsum, &total);
-    if (b < nblocks) orow[b] = carry + pre;
+    uint32_t run = carry + radix_block_scan(sum, wsum, &total);
+#pragma unroll
+    for (int i = 0; i < kRowItems; i++) {
+      if (i < q && b0 + i < p0 + len) orow[b0 + i] = run;
+      run += v[i];
+    }
     carry += total;
-    __syncthreads();  // wsum is reused by the next chunk
+    __syncthreads();  // wsum is reused by the next piece
   }
-  if (threadIdx.x == 0) totals[d] = carry;
+  if (t == 0) totals[d] = carry;
 }
 
-// Stable scatter of one 4096-key chunk.  Keys are ranked inside each wave
-// with ballot peer masks (rank = popcount of lower lanes holding the same
-// digit), waves are combined through per-wave digit counts, and the chunk is
-// first reordered by digit in LDS so that each digit's run leaves the block
-// as one contiguous, coalesced write.
-__global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, int64_t n, int shift, int nbits, const uint32_t* __restrict__ offs,
-    const uint32_t* __restrict__ totals, int64_t nblocks) {
-  __shared__ uint32_t wh[kThreads / kWave][kRadix];
-  __shared__ uint32_t goff[kRadix];    // global start of this block's run of digit d
-  __shared__ uint32_t lstart[kRadix];  // start of digit d's run inside the chunk
-  __shared__ uint32_t sk[kChunk];     // the chunk reordered by digit: keys, then values
-  __shared__ uint32_t wsum[kThreads / kWave];
-  const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
-  const uint32_t mask = (1u << nbits) - 1u;
-#pragma unroll
-  for (int k = 0; k < kThreads / kWave; k++) wh[k][t] = 0;
-  {  // digit bases: exclusive scan of the digit totals
-    uint32_t tot;
-    const uint32_t base = block_exclusive_scan(totals[t], wsum, &tot);
-    goff[t] = base + offs[(int64_t)t * nblocks + blockIdx.x];
-  }
-  __syncthreads();
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-  int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)w * (kChunk / 4);
-  uint32_t kk[kItems], vv[kItems], rk[kItems];
-#pragma unroll
-  for (int r = 0; r < kItems; r++) {  // all loads first
-    int64_t g = base + r * kWave + lane;
-    kk[r] = g < n ? kin[g] : 0u;
-    vv[r] = g < n ? vin[g] : 0u;
-  }
-#pragma unroll
-  for (int r = 0; r < kItems; r++) {
-    int64_t g = base + r * kWave + lane;
-    bool valid = g < n;
-    uint32_t k = kk[r];
-    uint32_t d = (k >> shift) & mask;
-    uint64_t peers = __ballot(valid);
-    for (int b = 0; b < nbits; b++) {
-      bool bit = (d >> b) & 1u;
-      uint64_t bal = __ballot(bit);
-      peers &= bit ? bal : ~bal;
-    }
-    uint32_t before = (uint32_t)__popcll(peers & lt);
-    uint32_t run = valid ? wh[w][d] : 0u;
-    if (valid && before == 0) wh[w][d] = run + (uint32_t)__popcll(peers);
-    rk[r] = valid ? run + before : 0xffffffffu;
-  }
-  __syncthreads();
-  {  // per digit t: exclusive prefix over the waves, and the chunk's digit total
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < kThreads / kWave; k++) {
-      uint32_t c = wh[k][t];
-      wh[k][t] = sum;
-      sum += c;
-    }
-    uint32_t tot;
-    lstart[t] = block_exclusive_scan(sum, wsum, &tot);
-  }
-  __syncthreads();
-  uint32_t lp[kItems];  // each key's place in the chunk's digit order
-#pragma unroll
-  for (int r = 0; r < kItems; r++) {
-    if (rk[r] == 0xffffffffu) { lp[r] = 0xffffffffu; continue; }
-    const uint32_t d = (kk[r] >> shift) & mask;
-    lp[r] = lstart[d] + wh[w][d] + rk[r];
-    sk[lp[r]] = kk[r];
-  }
-  __syncthreads();
-  const int cnt = (int)min((int64_t)kChunk, n - (int64_t)blockIdx.x * kChunk);
-  uint32_t pos[kItems];  // output position of the chunk's j-th key, j = t + 256 i
-#pragma unroll
-  for (int i = 0; i < kItems; i++) {
-    const int j = t + i * kThreads;
-    if (j >= cnt) continue;
-    const uint32_t k = sk[j];
-    const uint32_t d = (k >> shift) & mask;
-    pos[i] = goff[d] + (uint32_t)j - lstart[d];
-    kout[pos[i]] = k;
-  }
-  __syncthreads();  // the same LDS now stages the values
-#pragma unroll
-  for (int r = 0; r < kItems; r++)
-    if (lp[r] != 0xffffffffu) sk[lp[r]] = vv[r];
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < kItems; i++) {
-    const int j = t + i * kThreads;
-    if (j < cnt) vout[pos[i]] = sk[j];
-  }
+template <bool PAY>
+__global__ void __launch_bounds__(kRThreadsSort) radix_scatter_kernel(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, const uint32_t* __restrict__ pin,
+    int64_t n_max, const uint32_t* n_dev, KVSink sink, int shift, int nbits,
+    const uint32_t* __restrict__ offs, const uint32_t* __restrict__ totals, int64_t nblocks) {
+  __shared__ RadixRankSmem S;
+  __shared__ uint32_t sk[kRChunk];
+  const int64_t n = n_dev ? (int64_t)*n_dev : n_max;
+  if ((int64_t)blockIdx.x * kRChunk >= n) return;  // past the count: nothing to place
+  uint32_t kk[kRItems], vv[kRItems], pp[kRItems];
+  const uint32_t vmask = radix_load_kv(kin, vin, PAY ? pin : nullptr, n, kk, vv, pp);
+  radix_scatter_chunk<PAY>(kk, vv, pp, vmask, shift, nbits, offs, totals, nblocks, sink, S, sk);
 }
 
-int64_t radix_blocks(int64_t n) { return ceil_div(n > 0 ? n : 1, kChunk); }
+gut_status radix_hist(const uint32_t* keys, int64_t n_max, const uint32_t* n_dev, int shift,
+                      uint32_t mask, uint32_t* counts, int64_t nblocks, hipStream_t st) {
+  radix_hist_kernel<<<(unsigned)nblocks, kRThreadsSort, 0, st>>>(keys, n_max, n_dev, shift, mask, counts,
+                                                                 nblocks);
+  GUT_LAUNCH_CHECK();
+  return GUT_OK;
+}
+
+gut_status radix_rowscan(const uint32_t* counts, uint32_t* offs, uint32_t* totals, int64_t nblocks,
+                         hipStream_t st, const RowscanTail* tail) {
+  RowscanTail tl = {};
+  if (tail) tl = *tail;
+  radix_rowscan_kernel<<<kRadix + (tail ? 1 : 0), kRThreadsSort, 0, st>>>(counts, offs, totals, nblocks,
+                                                                          tl);
+  GUT_LAUNCH_CHECK();
+  return GUT_OK;
+}
+
+int64_t radix_blocks(int64_t n) { return ceil_div(n > 0 ? n : 1, kRChunk); }
 
 size_t radix_temp_bytes(int64_t n) {
   int64_t nb = radix_blocks(n);
@@ -278,35 +214,48 @@ size_t radix_temp_bytes(int64_t n) {
   return 2 * cnt + align256(kRadix * sizeof(uint32_t));
 }
 
-gut_status radix_sort_pairs_pp(uint32_t* kA, uint32_t* vA, uint32_t* kB, uint32_t* vB, int64_t n,
-                               int bits, void* temp, hipStream_t st, int* result_in_b) {
+RadixTemp radix_temp(void* temp, int64_t n_max) {
+  const size_t cnt_bytes = align256((size_t)kRadix * radix_blocks(n_max) * sizeof(uint32_t));
+  RadixTemp r;
+  r.counts = (uint32_t*)temp;
+  r.offs = (uint32_t*)((char*)temp + cnt_bytes);
+  r.totals = (uint32_t*)((char*)temp + 2 * cnt_bytes);
+  return r;
+}
+
+gut_status radix_sort_passes(uint32_t* kA, uint32_t* vA, uint32_t* kB, uint32_t* vB, int64_t n_max,
+                             const uint32_t* n_dev, int bits, int pass0, int pass_end, void* temp,
+                             hipStream_t st, int* result_in_b, uint2* ranges, uint32_t* pA,
+                             uint32_t* pB) {
   *result_in_b = 0;
-  if (n <= 0) return GUT_OK;
-  int passes = (bits + kRadixBits - 1) / kRadixBits;
-  if (passes < 1) passes = 1;
-  // spread the bits evenly over the passes (14 bits: 7 + 7, not 8 + 6), so
-  // no pass scatters into more digit runs than it must
-  const int per = (bits + passes - 1) / passes;
-  int64_t nb = radix_blocks(n);
-  size_t cnt_bytes = align256((size_t)kRadix * nb * sizeof(uint32_t));
-  uint32_t* counts = (uint32_t*)temp;
-  uint32_t* offs = (uint32_t*)((char*)temp + cnt_bytes);
-  uint32_t* totals = (uint32_t*)((char*)temp + 2 * cnt_bytes);
-  uint32_t *ks = kA, *vs = vA;
-  for (int p = 0; p < passes; p++) {
+  if (n_max <= 0) return GUT_OK;
+  const int passes = radix_passes(bits), per = radix_per_pass(bits);
+  if (pass_end > passes) pass_end = passes;
+  const int64_t nb = radix_blocks(n_max);
+  const RadixTemp rt = radix_temp(temp, n_max);
+  uint32_t *ks = kA, *vs = vA, *ps = pA;
+  for (int p = pass0; p < pass_end; p++) {
     uint32_t* kd = ks == kA ? kB : kA;
     uint32_t* vd = ks == kA ? vB : vA;
-    int shift = p * per;
-    int nbits = bits - shift < per ? bits - shift : per;
-    radix_hist_kernel<<<(unsigned)nb, kThreads, 0, st>>>(ks, n, shift, (1u << nbits) - 1u, counts, nb);
-    GUT_LAUNCH_CHECK();
-    radix_rowscan_kernel<<<kRadix, kThreads, 0, st>>>(counts, offs, totals, nb);
-    GUT_LAUNCH_CHECK();
-    radix_scatter_kernel<<<(unsigned)nb, kThreads, 0, st>>>(ks, vs, kd, vd, n, shift, nbits, offs,
-                                                            totals, nb);
+    uint32_t* pd = ks == kA ? pB : pA;
+    const int shift = p * per;
+    const int nbits = bits - shift < per ? bits - shift : per;
+    gut_status s = radix_hist(ks, n_max, n_dev, shift, (1u << nbits) - 1u, rt.counts, nb, st);
+    if (s != GUT_OK) return s;
+    if ((s = radix_rowscan(rt.counts, rt.offs, rt.totals, nb, st)) != GUT_OK) return s;
+    // with ranges, the last pass keeps no keys: the ranges imply them
+    const bool last_ranges = p == passes - 1 && ranges;
+    const KVSink sink = {last_ranges ? nullptr : kd, vd, last_ranges ? ranges : nullptr, pd};
+    if (pA)
+      radix_scatter_kernel<true><<<(unsigned)nb, kRThreadsSort, 0, st>>>(
+          ks, vs, ps, n_max, n_dev, sink, shift, nbits, rt.offs, rt.totals, nb);
+    else
+      radix_scatter_kernel<false><<<(unsigned)nb, kRThreadsSort, 0, st>>>(
+          ks, vs, nullptr, n_max, n_dev, sink, shift, nbits, rt.offs, rt.totals, nb);
     GUT_LAUNCH_CHECK();
     ks = kd;
     vs = vd;
+    ps = pd;
   }
   *result_in_b = ks == kB;
   return GUT_OK;

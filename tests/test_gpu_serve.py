@@ -69,11 +69,12 @@ def test_serve_mix_equals_alone():
 
 def test_serve_admission_and_growth():
     say("[serve admission]")
-    scene = G.clustered_scene(20000, seed=1003)
+    scene = G.clustered_scene(30000, seed=1003)
     gs = R.GaussianScene.from_host(scene)
     budget = 64 << 20
     with Server(gs, mem_budget_bytes=budget, max_slots=2, max_batch_cams=4) as srv:
-        # 64 cameras x 20k particles: ~90 MB of per-entry buffers, above the 64 MB budget
+        # 64 cameras x 30k particles: ~93 MB of per-entry buffers (48 B per entry),
+        # above the 64 MB budget
         many = [G.camera("pinhole", 64, 48, 60.0, R0=np.eye(3), t0=np.array([0, 0, 8.0]))] * 64
         with pytest.raises(L.GutError) as ei:
             srv.submit(many)
