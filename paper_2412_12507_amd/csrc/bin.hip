@@ -535,6 +535,10 @@ extern "C" gut_status gut_bin(const gut_projected* proj, int64_t n, const gut_ca
     set_error("projected rect, tiles and depth are required");
     return GUT_E_INVALID;
   }
+  if (((uintptr_t)proj->rect & 7) || ((uintptr_t)tile_ranges & 7)) {
+    set_error("rect and tile_ranges must be 8-byte aligned");
+    return GUT_E_INVALID;
+  }
   if (n < 0 || pair_capacity < 0 || !tile_ranges || (pair_capacity > 0 && !sorted_ids)) {
     set_error("bad sizes or NULL outputs");
     return GUT_E_INVALID;

@@ -89,6 +89,7 @@ __device__ __forceinline__ void render_tile(
         if (!wave_any(!(done0 && done1))) { wave_done = true; break; }
         const uint32_t q = 64u * h + (uint32_t)__builtin_ctzll(m);
         m &= m - 1ull;
+        const uint32_t idx1 = b + q + 1;  // the entry's 1-based place in the list
         const float4* P = &pd[q * S];
         PairRegs<RS> r;
         load_pair<RS>(P, r);
@@ -110,8 +111,8 @@ __device__ __forceinline__ void render_tile(
           const float ae = contrib[k] ? ev[k].a : 0.0f;
           wgt[k] = ae * T[k];
           T[k] = fmaf(-ae, T[k], T[k]);  // Tn, or T itself when not contributing
-          last[k] = contrib[k] ? b + q + 1 : last[k];
-          if (NE) nev[k] = stop ? b + q + 1 : nev[k];
+          last[k] = contrib[k] ? idx1 : last[k];
+          if (NE) nev[k] = stop ? idx1 : nev[k];
           if (k) done1 = done1 || stop; else done0 = done0 || stop;
         }
         // some lane passed the alpha_min test, so almost always some lane

@@ -348,8 +348,9 @@ __device__ __forceinline__ void eval_alpha(const PairRegs<RS>& r, float amax, Ev
   o->idd = idd;
   o->araw = araw;
   o->clamped = araw > amax;
-  // araw >= 0, so med3(araw, 0, amax) = min(araw, amax) in one instruction
-  o->a = o->ok ? __builtin_amdgcn_fmed3f(araw, 0.0f, amax) : 0.0f;
+  // araw >= 0, so med3(araw, 0, amax) = min(araw, amax) in one instruction;
+  // callers use a only where ok holds (their live / hit masks include it)
+  o->a = __builtin_amdgcn_fmed3f(araw, 0.0f, amax);
 }
 
 // Colour of a pair (FP64 slots).
