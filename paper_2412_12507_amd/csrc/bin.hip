@@ -91,9 +91,9 @@ __device__ inline uint32_t load_entry_chunk(const uint32_t* __restrict__ tiles,
                                             const float* __restrict__ depth, int64_t E,
                                             uint32_t (&kk)[kRItems], uint32_t (&vv)[kRItems],
                                             unsigned long long* pairs, const short4* __restrict__ rect,
-                                            uint32_t (&pp)[kRItems]) {
+                                            uint32_t (&pp)[kRItems], int64_t chunk) {
   const int lane = threadIdx.x & (kRWave - 1), w = threadIdx.x / kRWave;
-  const int64_t base = (int64_t)blockIdx.x * kRChunk + (int64_t)w * (kRChunk / kRWaves);
+  const int64_t base = chunk * kRChunk + (int64_t)w * (kRChunk / kRWaves);
   uint32_t vmask = 0;
   unsigned long long sum = 0;
 #pragma unroll
@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(kRThreadsSort) entry_hist_kernel(
     ranges[i] = make_uint2(~0u, 0u);
   uint32_t kk[kRItems], vv[kRItems], pp[kRItems];
   unsigned long long pairs;
-  const uint32_t vmask = load_entry_chunk(tiles, depth, E, kk, vv, &pairs, nullptr, pp);
+  const uint32_t vmask = load_entry_chunk(tiles, depth, E, kk, vv, &pairs, nullptr, pp, blockIdx.x);
   uint32_t nv = (uint32_t)__popc(vmask);
   for (int o = 32; o > 0; o >>= 1) {
     pairs += __shfl_xor(pairs, o, 64);
@@ -152,8 +152,10 @@ __global__ void __launch_bounds__(kRThreadsSort) entry_scatter_kernel(
   __shared__ RadixRankSmem S;
   __shared__ uint32_t sk[kRChunk];
   uint32_t kk[kRItems], vv[kRItems], pp[kRItems];
-  const uint32_t vmask = load_entry_chunk(tiles, depth, E, kk, vv, nullptr, PACKED ? rect : nullptr, pp);
-  radix_scatter_chunk<PACKED>(kk, vv, pp, vmask, 0, kRadixBits, offs, totals, nblocks, sink, S, sk);
+  const int64_t chunk = radix_xcd_chunk(nblocks);
+  const uint32_t vmask =
+      load_entry_chunk(tiles, depth, E, kk, vv, nullptr, PACKED ? rect : nullptr, pp, chunk);
+  radix_scatter_chunk<PACKED>(kk, vv, pp, vmask, 0, kRadixBits, offs, totals, nblocks, chunk, sink, S, sk);
 }
 
 // Output of the last depth pass when the rectangles travel packed: the
@@ -188,10 +190,11 @@ __global__ void __launch_bounds__(kRThreadsSort) entry_final_kernel(
   __shared__ RadixRankSmem S;
   __shared__ uint32_t sk[kRChunk];
   const int64_t n = *n_dev;
-  if ((int64_t)blockIdx.x * kRChunk >= n) return;
+  const int64_t chunk = radix_xcd_chunk((n + kRChunk - 1) / kRChunk);
+  if (chunk < 0) return;
   uint32_t kk[kRItems], vv[kRItems], pp[kRItems];
-  const uint32_t vmask = radix_load_kv(kin, vin, pin, n, kk, vv, pp);
-  radix_scatter_chunk<true>(kk, vv, pp, vmask, shift, nbits, offs, totals, nblocks, sink, S, sk);
+  const uint32_t vmask = radix_load_kv(kin, vin, pin, n, chunk, kk, vv, pp);
+  radix_scatter_chunk<true>(kk, vv, pp, vmask, shift, nbits, offs, totals, nblocks, chunk, sink, S, sk);
 }
 
 // The depth-sorted entries' tile counts and geometry, gathered once by a

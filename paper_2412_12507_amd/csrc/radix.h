@@ -63,6 +63,20 @@ __device__ inline void radix_hist_store(const uint32_t (&kk)[kRItems], uint32_t 
   counts[(int64_t)t * nblocks + blockIdx.x] = h[t];
 }
 
+// The chunk a scatter block takes.  Blocks are dealt to the 8 XCDs in turn
+// (block b to XCD b % 8), so chunk = b would give neighbouring chunks, whose
+// runs of a digit are neighbours in the output, to different L2s, and each
+// would write its runs back as partial lines.  Instead XCD x takes the
+// contiguous chunks [x q + min(x, r), ...) of the nact = 8 q + r chunks that
+// hold items, in order (a bijection on blocks 0 .. nact-1: XCD x receives
+// exactly q + (x < r) of them); blocks from nact on get -1 and stay idle.
+__device__ inline int64_t radix_xcd_chunk(int64_t nact) {
+  const int64_t b = blockIdx.x, x = b & 7, k = b >> 3;
+  if (b >= nact) return -1;
+  const int64_t q = nact >> 3, r = nact & 7;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // LDS of one scatter block's ranking; the chunk is reordered by digit through
 // a separate kRChunk-word staging array (keys, then values).
 struct RadixRankSmem {
@@ -112,7 +126,7 @@ __device__ inline void radix_scatter_chunk(const uint32_t (&kk)[kRItems], const 
                                            int nbits,
                                            const uint32_t* __restrict__ offs,
                                            const uint32_t* __restrict__ totals, int64_t nblocks,
-                                           const Sink& sink, RadixRankSmem& S,
+                                           int64_t chunk, const Sink& sink, RadixRankSmem& S,
                                            uint32_t* __restrict__ sk) {
   const int t = threadIdx.x, lane = t & (kRWave - 1), w = t / kRWave;
   const uint32_t mask = (1u << nbits) - 1u;
@@ -121,7 +135,7 @@ __device__ inline void radix_scatter_chunk(const uint32_t (&kk)[kRItems], const 
   {  // digit bases: exclusive scan of the digit totals
     uint32_t tot;
     const uint32_t base = radix_block_scan(totals[t], S.wsum, &tot);
-    S.goff[t] = base + offs[(int64_t)t * nblocks + blockIdx.x];
+    S.goff[t] = base + offs[(int64_t)t * nblocks + chunk];
   }
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kRWave - lane));
@@ -210,11 +224,11 @@ __device__ inline void radix_scatter_chunk(const uint32_t (&kk)[kRItems], const 
 // Items of this block's chunk: (key, value[, payload]) below the count n
 // (vin / pin may be null when not wanted).
 __device__ inline uint32_t radix_load_kv(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                         const uint32_t* __restrict__ pin, int64_t n,
+                                         const uint32_t* __restrict__ pin, int64_t n, int64_t chunk,
                                          uint32_t (&kk)[kRItems], uint32_t (&vv)[kRItems],
                                          uint32_t (&pp)[kRItems]) {
   const int lane = threadIdx.x & (kRWave - 1), w = threadIdx.x / kRWave;
-  const int64_t base = (int64_t)blockIdx.x * kRChunk + (int64_t)w * (kRChunk / kRWaves);
+  const int64_t base = chunk * kRChunk + (int64_t)w * (kRChunk / kRWaves);
   uint32_t vmask = 0;
 #pragma unroll
   for (int r = 0; r < kRItems; r++) {

@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(kRThreadsSort) radix_hist_kernel(const uint32_
   __shared__ uint32_t h[kRadix];
   const int64_t n = n_dev ? (int64_t)*n_dev : n_max;
   uint32_t kk[kRItems], vv[kRItems], pp[kRItems];
-  const uint32_t vmask = radix_load_kv(keys, nullptr, nullptr, n, kk, vv, pp);
+  const uint32_t vmask = radix_load_kv(keys, nullptr, nullptr, n, blockIdx.x, kk, vv, pp);
   radix_hist_store(kk, vmask, shift, mask, h, counts, nblocks);
 }
 
@@ -182,10 +182,11 @@ __global__ void __launch_bounds__(kRThreadsSort) radix_scatter_kernel(
   __shared__ RadixRankSmem S;
   __shared__ uint32_t sk[kRChunk];
   const int64_t n = n_dev ? (int64_t)*n_dev : n_max;
-  if ((int64_t)blockIdx.x * kRChunk >= n) return;  // past the count: nothing to place
+  const int64_t chunk = radix_xcd_chunk((n + kRChunk - 1) / kRChunk);
+  if (chunk < 0) return;  // past the count: nothing to place
   uint32_t kk[kRItems], vv[kRItems], pp[kRItems];
-  const uint32_t vmask = radix_load_kv(kin, vin, PAY ? pin : nullptr, n, kk, vv, pp);
-  radix_scatter_chunk<PAY>(kk, vv, pp, vmask, shift, nbits, offs, totals, nblocks, sink, S, sk);
+  const uint32_t vmask = radix_load_kv(kin, vin, PAY ? pin : nullptr, n, chunk, kk, vv, pp);
+  radix_scatter_chunk<PAY>(kk, vv, pp, vmask, shift, nbits, offs, totals, nblocks, chunk, sink, S, sk);
 }
 
 gut_status radix_hist(const uint32_t* keys, int64_t n_max, const uint32_t* n_dev, int shift,
