@@ -20,8 +20,9 @@
  *    only inside a gut_server (within its budget) and inside gut_bin for its
  *    tiny pinned read-back slot.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
- *    Every call is asynchronous on it, except gut_bin, which synchronises the
- *    stream once to read back the visible-entry and pair counts.
+ *    Every call is asynchronous on it, except gut_bin, which waits once, for
+ *    an event it records on the stream as soon as the visible-entry and pair
+ *    counts exist (its later kernels are already queued behind that event).
  *  - Arrays are row-major, float32, contiguous.  Particle arrays are
  *    structure-of-arrays: means[n,3], scales[n,3], quats[n,4] (w,x,y,z; any
  *    non-zero quaternion, normalised inside), opacities[n], sh[n,K,3] with
@@ -149,8 +150,11 @@ size_t gut_bin_workspace_bytes(int64_t n, int32_t n_cams, int64_t pair_capacity)
  *                             tiles in this order to shorten the tail.
  *   sorted_ids  [pair_capacity] uint32 out: entry ids e = cam*n + i
  *   n_pairs     host int64*   out (nullable): number of pairs P
- * If P > pair_capacity nothing is written past the buffer, *n_pairs holds the
- * required size and GUT_E_CAPACITY is returned. */
+ * proj's rect (8-byte aligned), tiles and depth are read as gut_project
+ * writes them (tiles[e] = the area of rect[e], 0 when culled); tile_ranges
+ * must be 8-byte aligned.  If P > pair_capacity nothing is written past the
+ * buffer, every tile's range is empty, *n_pairs holds the required size and
+ * GUT_E_CAPACITY is returned. */
 gut_status gut_bin(const gut_projected* proj, int64_t n, const gut_camera* cams, int32_t n_cams,
                    const gut_params* p, void* ws, size_t ws_bytes, int64_t pair_capacity,
                    uint32_t* tile_ranges, uint32_t* sorted_ids, int64_t* n_pairs, void* stream);
