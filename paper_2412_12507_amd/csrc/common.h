@@ -142,6 +142,10 @@ __device__ inline float dot3f(float3 a, float3 b) { return a.x * b.x + a.y * b.y
 __device__ inline float3 cross3f(float3 a, float3 b) {
   return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
+// The same with one rounding less per component (two instructions, not three).
+__device__ inline float3 cross3f_fma(float3 a, float3 b) {
+  return f3(fmaf(a.y, b.z, -a.z * b.y), fmaf(a.z, b.x, -a.x * b.z), fmaf(a.x, b.y, -a.y * b.x));
+}
 
 // FP64 3-vectors.  Products are summed with explicit fma: the code is built
 // with contraction off (so that kernels sharing code round identically), and

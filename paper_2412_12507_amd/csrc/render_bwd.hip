@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
           const float c = -ev[k].a * gA;  // 2 dL/domega^2
           float3 dg, cr;
           pair_vectors<RS>(P, ev[k], u[k], v[k], &dg, &cr);
-          float3 p = cross3f(dg, cr);
+          float3 p = cross3f_fma(dg, cr);
           p = f3(p.x * ev[k].idd, p.y * ev[k].idd, p.z * ev[k].idd);
           const float3 cp = f3(c * p.x, c * p.y, c * p.z);
           // G terms are cp p^T: kept as factors so the two pixels combine in fmas
