@@ -62,34 +62,52 @@ __device__ inline float3 cam_at(const DevCam& c, float3 y0, float t) {
   if (c.shutter != GUT_ROLLING_TOP_TO_BOTTOM) return y0;
   float3 y = f3(y0.x - t * c.deltaf[0], y0.y - t * c.deltaf[1], y0.z - t * c.deltaf[2]);
   if (c.anglef == 0.0f) return y;
-  float s, co;
-  sincosf(t * c.anglef, &s, &co);
+  float s, oc;  // sin x and 1 - cos x, x = t angle
+  const float x = t * c.anglef;
+  if (fabsf(c.anglef) <= 0.5f) {
+    // |x| <= 0.5 (t in [0, 1]): Taylor series of sin x to x^9 and of
+    // 1 - cos x to x^10, truncation below 2e-11; 1 - cos x from its own
+    // series also avoids the cancellation of 1 - cos x in FP32
+    const float x2 = x * x;
+    s = x * fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, 1.0f / 362880.0f, -1.0f / 5040.0f), 1.0f / 120.0f),
+                          -1.0f / 6.0f), 1.0f);
+    oc = x2 * fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, 1.0f / 3628800.0f, -1.0f / 40320.0f), 1.0f / 720.0f),
+                            -1.0f / 24.0f), 0.5f);
+  } else {
+    float co;
+    sincosf(x, &s, &co);
+    oc = 1.0f - co;
+  }
   float3 k = f3(c.axisf[0], c.axisf[1], c.axisf[2]);
   float3 kxy = cross3f(k, y);
   float3 kkxy = cross3f(k, kxy);
-  float oc = 1.0f - co;
   return f3(y.x - s * kxy.x + oc * kkxy.x, y.y - s * kxy.y + oc * kkxy.y,
             y.z - s * kxy.z + oc * kkxy.z);
 }
 
 // g: camera-frame point -> pixel coordinates; returns validity.
 __device__ inline bool project_cam(const DevCam& c, float3 p, float near_plane, float2* v) {
+  // hardware reciprocal and reciprocal square root (about 1 ulp): the pixel
+  // coordinates they feed carry far larger errors from the FP32 inputs
   if (c.model == GUT_PINHOLE) {
-    float iz = 1.0f / p.z;
+    float iz = __builtin_amdgcn_rcpf(p.z);
     v->x = c.fxf * p.x * iz + c.cxf;
     v->y = c.fyf * p.y * iz + c.cyf;
     return p.z > near_plane;
   }
   float r2 = p.x * p.x + p.y * p.y;
-  float r = sqrtf(r2);
+  // on the axis (r2 far below any pixel offset, and clear of denormals) the
+  // projection is the principal point
+  float ir = r2 > 1e-30f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+  float r = r2 * ir;
   float th = atan2f(r, p.z);
-  float rho = sqrtf(r2 + p.z * p.z);
   float t2 = th * th;
   float td = th * (1.0f + t2 * (c.kf[0] + t2 * (c.kf[1] + t2 * (c.kf[2] + t2 * c.kf[3]))));
-  float sc = r > 0.0f ? td / r : 0.0f;
+  float sc = td * ir;
   v->x = c.fxf * sc * p.x + c.cxf;
   v->y = c.fyf * sc * p.y + c.cyf;
-  return th <= c.theta_limf && rho > near_plane;
+  // |p| > near, compared squared
+  return th <= c.theta_limf && fmaf(p.z, p.z, r2) > near_plane * near_plane;
 }
 
 // Exposure time of a point and its final projection (rolling shutter: the
