@@ -76,8 +76,6 @@ static PairLayout pair_layout(int64_t cap) {
 size_t bin_entry_bytes(int64_t E) { return entry_layout(E).total; }
 size_t bin_pair_bytes(int64_t cap) { return pair_layout(cap).total; }
 
-// The entries of this block's chunk as depth-sort items: key = depth bits,
-// value = entry id, valid = the entry touches a tile.
 // Packed tile rectangle: x0 | y0 << 8 | (x1 - x0) << 16 | (y1 - y0) << 24,
 // exact when every camera has at most 256 tiles per axis.
 __device__ inline uint32_t pack_rect(short4 r) {
@@ -85,8 +83,10 @@ __device__ inline uint32_t pack_rect(short4 r) {
          (((uint32_t)(r.w - r.y) & 255u) << 24);
 }
 
-// *pairs (if given) receives the sum of the items' tile counts; rect (if
-// given) fills pp with the packed rectangles.
+// The entries of chunk `chunk` as depth-sort items: key = depth bits, value =
+// entry id, valid = the entry touches a tile.  *pairs (if given) receives the
+// sum of the items' tile counts; rect (if given) fills pp with the packed
+// rectangles.
 __device__ inline uint32_t load_entry_chunk(const uint32_t* __restrict__ tiles,
                                             const float* __restrict__ depth, int64_t E,
                                             uint32_t (&kk)[kRItems], uint32_t (&vv)[kRItems],
