@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(kRThreads, 4) render_kernel(
 // others, and leaves once every counter is past its share.  Images go to
 // outs[camera] ([H, W, 3]).
 template <bool RS>
-__global__ void __launch_bounds__(kRThreads, 3) render_batch_kernel(
+__global__ void __launch_bounds__(kRThreads, 4) render_batch_kernel(
     const DevCam* __restrict__ cams, const int* __restrict__ cam_list,
     const int* __restrict__ item_start, int n_list, int n_items, unsigned* __restrict__ counters,
     Thresholds th, int n, const uint2* __restrict__ ranges, const uint32_t* __restrict__ order,
@@ -181,7 +181,6 @@ __global__ void __launch_bounds__(kRThreads, 3) render_batch_kernel(
   __shared__ WaveBoxes wb;
   __shared__ float red[6];
   __shared__ int item_s;
-  __shared__ DevCam cam_s;  // the current item's camera, staged in LDS
   const int nx = 8;
   const int my = blockIdx.x % nx;
   const int q = n_items / nx, r = n_items % nx;
@@ -204,15 +203,12 @@ __global__ void __launch_bounds__(kRThreads, 3) render_batch_kernel(
     if (item < 0) break;
     int j = 0;
     while (j + 1 < n_list && item_start[j + 1] <= item) j++;
-    const int c = cam_list[j];
-    {
-      const int* src = reinterpret_cast<const int*>(&cams[c]);
-      int* dst = reinterpret_cast<int*>(&cam_s);
-      for (int w = threadIdx.x; w < (int)(sizeof(DevCam) / sizeof(int)); w += blockDim.x) dst[w] = src[w];
-    }
-    __syncthreads();
-    const int tile = (int)order[cam_s.tile_base + (item - item_start[j])];
-    render_tile<RS, false>(cam_s, th, n, c, tile, ranges, ids, record, rgb, outs[c], nullptr, nullptr,
+    // the camera is read where it lies, at a wave-uniform index, so its
+    // fields load into scalar registers
+    const int c = __builtin_amdgcn_readfirstlane(cam_list[j]);
+    const DevCam& cam = cams[c];
+    const int tile = (int)order[cam.tile_base + (item - item_start[j])];
+    render_tile<RS, false>(cam, th, n, c, tile, ranges, ids, record, rgb, outs[c], nullptr, nullptr,
                     nullptr, 0, pd, pf, F, wb, red);
   }
 }
