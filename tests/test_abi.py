@@ -113,6 +113,15 @@ def test_bin_and_render_validation_without_launch():
     st = lib.gut_bin(L.ref(pj), 10, arr, 1, L.ref(p), C.c_void_p(4097), need, 100, C.c_void_p(4096),
                      C.c_void_p(4096), None, None)
     assert st == L.GUT_E_INVALID
+    # rect and tile_ranges are read as 8-byte vectors
+    pj.rect = 4100
+    st = lib.gut_bin(L.ref(pj), 10, arr, 1, L.ref(p), C.c_void_p(4096), need, 100, C.c_void_p(4096),
+                     C.c_void_p(4096), None, None)
+    assert st == L.GUT_E_INVALID and b"8-byte" in lib.gut_last_error()
+    pj.rect = 4096
+    st = lib.gut_bin(L.ref(pj), 10, arr, 1, L.ref(p), C.c_void_p(4096), need, 100, C.c_void_p(4100),
+                     C.c_void_p(4096), None, None)
+    assert st == L.GUT_E_INVALID and b"8-byte" in lib.gut_last_error()
     # render: NULL outputs
     st = lib.gut_render(L.ref(pj), 10, C.c_void_p(4096), C.c_void_p(4096), arr, 1, L.ref(p), None,
                         None, None, None, None)
