@@ -8,10 +8,11 @@ with the scene and all buffers resident in HBM; the step includes gut_bin's
 one host read-back of the pair count.
 
 Also reported on the same line:
-  roofline      the compositing kernel (the dominant one): algorithmic FP32
-                FLOPs (E_eval x 55, E_eval = list entries evaluated per pixel
-                up to its stop, counted by the kernel itself) per launch over
-                its average duration from HIP events on its stream, against
+  roofline      the compositing kernel (the dominant one; one launch renders
+                both views): algorithmic FP32 FLOPs (E_eval x 55, E_eval =
+                list entries evaluated per pixel up to its stop, counted by
+                the kernel itself) per launch over its average duration from
+                HIP events on its stream, against
                 the chip's FP32 vector peak; plus its HBM bytes per launch
                 from rocprofv3 FETCH_SIZE / WRITE_SIZE counters calibrated on
                 kernels of known traffic (profiles/render_traffic.json, made
@@ -63,10 +64,25 @@ def render_source_hash():
     return h.hexdigest()
 
 
+def render_launches(cams):
+    """Render launches gut_render makes for these cameras: consecutive cameras
+    of one shutter type and one tile count share a launch, up to 4 (the
+    benchmark's two 1920x1080 global-shutter views take one)."""
+    launches, prev, run = 0, None, 0
+    for c in cams:
+        key = (c.get("shutter", "global"), -(-int(c["width"]) // 16) * -(-int(c["height"]) // 16))
+        if key == prev and run < 4:
+            run += 1
+        else:
+            launches, prev, run = launches + 1, key, 1
+    return launches
+
+
 def pmc_summary(fetch_dir, write_dir, out_path, command):
-    """Per-launch HBM bytes of the timed render kernel (render_kernel<false,
-    false>: global shutter, no n_eval) from two rocprofv3 --pmc runs of
-    `bench.py --calib-copy` (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).
+    """Per-launch HBM bytes of the timed render kernel (render_multi_kernel<false,
+    false>: global shutter, no n_eval, both views in one launch) from two
+    rocprofv3 --pmc runs of `bench.py --calib-copy` (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch).
     Each counter is scaled by what it reads for a kernel of known traffic in
     the same run: the 1 GiB add (reads 1 GiB) for FETCH_SIZE and the 1 GiB
     fill (writes 1 GiB) for WRITE_SIZE."""
@@ -88,8 +104,8 @@ def pmc_summary(fetch_dir, write_dir, out_path, command):
     fr, wr = read(fetch_dir, "FETCH_SIZE"), read(write_dir, "WRITE_SIZE")
     f_add = pick(fr, "CUDAFunctor_add", "CUDAFunctorOnSelf_add")
     w_fill = pick(wr, "FillFunctor")
-    f_r = pick(fr, "gut::render_kernel<false, false>")
-    w_r = pick(wr, "gut::render_kernel<false, false>")
+    f_r = pick(fr, "gut::render_multi_kernel<false, false>")
+    w_r = pick(wr, "gut::render_multi_kernel<false, false>")
     if not (f_add and w_fill and f_r and w_r):
         raise SystemExit("pmc summary: calibration or render dispatches missing")
     ff = CALIB_BYTES / (f_add[0] * 1024.0)
@@ -339,8 +355,9 @@ def main():
     fw = bench_forward(gs, cams, args.steps, args.warmup, R, torch)
     npx = sum(c["width"] * c["height"] for c in cams)
     value = npx / (fw["ms_per_step"] * 1e-3) / 1e6
-    render_ms_per_launch = fw["stage_ms"][2] / len(cams)
-    flops_per_launch = fw["e_eval"] * F_EVAL / len(cams)
+    launches = render_launches(cams)
+    render_ms_per_launch = fw["stage_ms"][2] / launches
+    flops_per_launch = fw["e_eval"] * F_EVAL / launches
     achieved = flops_per_launch / (render_ms_per_launch * 1e-3) / 1e12
     traffic = None
     if args.traffic_json and os.path.exists(args.traffic_json):
@@ -351,8 +368,10 @@ def main():
                     frac=achieved / PEAK_FP32_TFLOPS, traffic=traffic,
                     peak_nonpacked=PEAK_FP32_NONPACKED_TFLOPS,
                     frac_nonpacked=achieved / PEAK_FP32_NONPACKED_TFLOPS,
-                    kernel="render_kernel (gut_render)",
-                    e_eval_per_launch=fw["e_eval"] / len(cams), flops_per_eval=F_EVAL,
+                    kernel="render_multi_kernel (gut_render, both views in one launch)"
+                    if launches == 1 and len(cams) > 1 else "render_kernel (gut_render)",
+                    launches_per_step=launches,
+                    e_eval_per_launch=fw["e_eval"] / launches, flops_per_eval=F_EVAL,
                     ms_per_launch=render_ms_per_launch)
     del fw["img"]
     # HBM rooflines of the other stages, on their algorithmic bytes per step:

@@ -161,6 +161,36 @@ __global__ void __launch_bounds__(kRThreads, 4) render_kernel(
                   out_ne, cam.pixel_base, pd, pf, F, wb, red);
 }
 
+// Several cameras of one shutter type and one tile count in one launch
+// (kMultiCams at most, passed by value): block b takes tile b / n of camera
+// b % n in that camera's render order, so the cameras' longest tiles start
+// together and one camera's tail overlaps the others' work instead of ending
+// a launch of its own.
+constexpr int kMultiCams = 4;
+struct MultiCams {
+  DevCam cam[kMultiCams];
+  int idx[kMultiCams];  // the cameras' indices in the call
+  int n;
+};
+
+template <bool RS, bool NE>
+__global__ void __launch_bounds__(kRThreads, 4) render_multi_kernel(
+    MultiCams mc, Thresholds th, int n, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
+    const float4* __restrict__ record, const float* __restrict__ rgb, float* __restrict__ out_rgb,
+    float* __restrict__ out_T, uint32_t* __restrict__ out_nc, uint32_t* __restrict__ out_ne) {
+  __shared__ float4 pd[kRBatch * Slots<RS, false>::N];
+  __shared__ uint32_t pf[kRBatch];
+  __shared__ TileFrameD F;
+  __shared__ WaveBoxes wb;
+  __shared__ float red[6];
+  const int c = (int)(blockIdx.x % (unsigned)mc.n), k = (int)(blockIdx.x / (unsigned)mc.n);
+  const DevCam& cam = mc.cam[c];
+  const int tile = (int)order[cam.tile_base + k];
+  render_tile<RS, NE>(cam, th, n, mc.idx[c], tile, ranges, ids, record, rgb, out_rgb, out_T, out_nc,
+                      out_ne, cam.pixel_base, pd, pf, F, wb, red);
+}
+
 // Persistent render of the cameras of one shutter type in a multi-camera
 // batch.  Items are (camera, k-th tile of its render order) over the listed
 // cameras, in order.  Item i belongs to XCD i % 8 (blocks are dealt to XCDs
@@ -269,6 +299,35 @@ gut_status launch_render(const DevCam& cam, const Thresholds& th, int n, int cam
   return GUT_OK;
 }
 
+// Consecutive cameras of one shutter type and one tile count share a launch
+// (up to kMultiCams); a camera alone takes render_kernel.
+static gut_status launch_render_group(const DevCam* dc, int c0, int c1, const Thresholds& th, int n,
+                                      const uint32_t* ranges, const uint32_t* order,
+                                      const uint32_t* ids, const float* record, const float* rgb,
+                                      float* out_rgb, float* out_T, uint32_t* out_nc, uint32_t* out_ne,
+                                      hipStream_t s) {
+  if (c1 - c0 == 1)
+    return launch_render(dc[c0], th, n, c0, ranges, order, ids, record, rgb, out_rgb, out_T, out_nc,
+                         out_ne, s);
+  MultiCams mc = {};
+  mc.n = c1 - c0;
+  for (int k = 0; k < mc.n; k++) {
+    mc.cam[k] = dc[c0 + k];
+    mc.idx[k] = c0 + k;
+  }
+  dim3 grid(mc.n * dc[c0].tiles_x * dc[c0].tiles_y), block(kRThreads);
+#define GUT_RM(RS, NE)                                                                              \
+  render_multi_kernel<RS, NE><<<grid, block, 0, s>>>(mc, th, n, (const uint2*)ranges, order, ids,     \
+                                                     (const float4*)record, rgb, out_rgb, out_T, out_nc, \
+                                                     out_ne)
+  const bool rs = dc[c0].shutter == GUT_ROLLING_TOP_TO_BOTTOM;
+  if (rs) { if (out_ne) GUT_RM(true, true); else GUT_RM(true, false); }
+  else { if (out_ne) GUT_RM(false, true); else GUT_RM(false, false); }
+#undef GUT_RM
+  GUT_LAUNCH_CHECK();
+  return GUT_OK;
+}
+
 }  // namespace gut
 
 using namespace gut;
@@ -296,11 +355,16 @@ extern "C" gut_status gut_render(const gut_projected* proj, int64_t n, const uin
   int64_t T = 0;
   if ((st = prepare_cams(cams, n_cams, *p, dc, &T, nullptr)) != GUT_OK) return st;
   Thresholds th = make_thresholds(*p);
-  for (int c = 0; c < n_cams; c++) {
-    st = launch_render(dc[c], th, (int)n, c, tile_ranges, tile_ranges + 2 * T, sorted_ids,
-                       proj->record, proj->rgb, rgb, T_final, n_contrib, n_eval,
-                       (hipStream_t)stream);
+  for (int c0 = 0; c0 < n_cams;) {
+    int c1 = c0 + 1;
+    while (c1 < n_cams && c1 - c0 < kMultiCams && dc[c1].shutter == dc[c0].shutter &&
+           dc[c1].tiles_x * dc[c1].tiles_y == dc[c0].tiles_x * dc[c0].tiles_y)
+      c1++;
+    st = launch_render_group(dc, c0, c1, th, (int)n, tile_ranges, tile_ranges + 2 * T, sorted_ids,
+                             proj->record, proj->rgb, rgb, T_final, n_contrib, n_eval,
+                             (hipStream_t)stream);
     if (st != GUT_OK) return st;
+    c0 = c1;
   }
   return GUT_OK;
 }
