@@ -289,64 +289,60 @@ __global__ void particle_grad_kernel(int n, const float* __restrict__ scales,
 }
 
 // K7b: SH colour of one camera -> dL/dbeta and dL/dmu through the view
-// direction.  One thread per particle; its 3K coefficients are read and its
-// 3K gradients written as float4 runs when 3K is a multiple of 4 (degrees 1
-// and 3), all issued back to back, so a wave keeps many requests in flight
-// and every line it touches is used whole across its 64 particles.  The
-// first camera writes g_sh (zeros for particles without colour gradient),
-// later cameras add to it.
+// direction.  One thread per particle, 256 per block.  The block's
+// coefficients (3K floats per particle, one contiguous slab) come in and its
+// gradients go out as contiguous runs through LDS, at a padded stride so each
+// thread's own row hits distinct banks; every global access is coalesced and
+// all of a thread's loads are issued before any is used.  The first camera
+// writes g_sh (zeros for particles without colour gradient), later cameras
+// add to it.
 constexpr int kShThreads = 256;
 
-template <int C, bool VEC>
-__device__ __forceinline__ void load_run(const float* __restrict__ p, float (&v)[C]) {
-  if constexpr (VEC && C % 4 == 0) {
-    const float4* q = reinterpret_cast<const float4*>(p);
-#pragma unroll
-    for (int k = 0; k < C / 4; k++) {
-      const float4 f = q[k];
-      v[4 * k] = f.x; v[4 * k + 1] = f.y; v[4 * k + 2] = f.z; v[4 * k + 3] = f.w;
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < C; k++) v[k] = p[k];
-  }
-}
-
-template <int C, bool VEC>
-__device__ __forceinline__ void store_run(float* __restrict__ p, const float (&v)[C]) {
-  if constexpr (VEC && C % 4 == 0) {
-    float4* q = reinterpret_cast<float4*>(p);
-#pragma unroll
-    for (int k = 0; k < C / 4; k++) q[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
-  } else {
-#pragma unroll
-    for (int k = 0; k < C; k++) p[k] = v[k];
-  }
-}
-
-// VEC: sh and g_sh are 16-byte aligned.
-template <int DEG, bool VEC>
+template <int DEG>
 __global__ void __launch_bounds__(kShThreads) sh_grad_kernel(
     int n, int cam_idx, int first, DevCam cam, Thresholds th, const float* __restrict__ means,
     const float* __restrict__ sh, const float* __restrict__ rgb, const double* __restrict__ acc_rgb,
     float* __restrict__ g_means, float* __restrict__ g_sh) {
-  constexpr int K = (DEG + 1) * (DEG + 1), C = 3 * K;
-  const long long i = (long long)blockIdx.x * kShThreads + threadIdx.x;
-  if (i >= n) return;
-  const long long e = (long long)cam_idx * n + i;
-  float gr[3];
-  bool live[3];
-  for (int c = 0; c < 3; c++) {
-    gr[c] = (float)acc_rgb[3 * e + c];
-    live[c] = gr[c] != 0.0f && rgb[3 * e + c] > 0.0f;  // max(0, .) clamps the rest
+  constexpr int K = (DEG + 1) * (DEG + 1), C = 3 * K, LD = C + 1;
+  constexpr int kPer = C;  // slab floats per thread (C * 256 / 256)
+  __shared__ float lb[kShThreads * LD];
+  const int t = threadIdx.x;
+  const long long i0 = (long long)blockIdx.x * kShThreads;
+  const int cnt = (int)min((long long)kShThreads, (long long)n - i0);
+  const long long i = i0 + t;
+  float gr[3] = {0.f, 0.f, 0.f};
+  bool live[3] = {false, false, false};
+  if (t < cnt) {
+    const long long e = (long long)cam_idx * n + i;
+    for (int c = 0; c < 3; c++) {
+      gr[c] = (float)acc_rgb[3 * e + c];
+      live[c] = gr[c] != 0.0f && rgb[3 * e + c] > 0.0f;  // max(0, .) clamps the rest
+    }
   }
   const bool any = live[0] || live[1] || live[2];
+  const bool block_any = __syncthreads_or(any);
+  if (!block_any && !first) return;  // nothing to add for these particles
+  const float* src = sh + i0 * C;
+  float* dst = g_sh + i0 * C;
+  const int m = cnt * C;  // slab length
+  if (block_any) {
+    float v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; q++) {
+      const int j = t + q * kShThreads;
+      v[q] = j < m ? src[j] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; q++) {
+      const int j = t + q * kShThreads;
+      lb[(j / C) * LD + j % C] = v[q];
+    }
+  }
+  __syncthreads();
   float gs[C];
 #pragma unroll
   for (int k = 0; k < C; k++) gs[k] = 0.0f;
   if (any) {
-    float b[C];
-    load_run<C, VEC>(sh + i * C, b);
     float3 mu = f3(means[3 * i], means[3 * i + 1], means[3 * i + 2]);
     float t0 = 0.0f;
     if (cam.shutter == GUT_ROLLING_TOP_TO_BOTTOM) {  // exposure time of the mean, as in K1
@@ -362,6 +358,7 @@ __global__ void __launch_bounds__(kShThreads) sh_grad_kernel(
     float3 dY[K];
     sh_basis<DEG>(d.x, d.y, d.z, Y);
     sh_basis_grad<DEG>(d.x, d.y, d.z, dY);
+    const float* b = lb + t * LD;
     float3 gd = f3(0.f, 0.f, 0.f);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -378,15 +375,16 @@ __global__ void __launch_bounds__(kShThreads) sh_grad_kernel(
     g_means[3 * i + 1] += (gd.y - d.y * pdd) * id;
     g_means[3 * i + 2] += (gd.z - d.z * pdd) * id;
   }
-  float* dst = g_sh + i * C;
-  if (first) {
-    store_run<C, VEC>(dst, gs);
-  } else if (any) {
-    float cur[C];
-    load_run<C, VEC>(dst, cur);
+  __syncthreads();  // the coefficients are read; the same LDS takes the gradients
 #pragma unroll
-    for (int k = 0; k < C; k++) cur[k] += gs[k];
-    store_run<C, VEC>(dst, cur);
+  for (int k = 0; k < C; k++) lb[t * LD + k] = gs[k];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPer; q++) {
+    const int j = t + q * kShThreads;
+    if (j >= m) continue;
+    const float g = lb[(j / C) * LD + j % C];
+    dst[j] = first ? g : dst[j] + g;
   }
 }
 
@@ -467,16 +465,15 @@ extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected
                                          g_scales, g_quats, g_opacities);
   GUT_LAUNCH_CHECK();
   const dim3 gs_grid((unsigned)((n + kShThreads - 1) / kShThreads));
-  const bool vec = !(((uintptr_t)scene->sh | (uintptr_t)g_sh) & 15);
   for (int c = 0; c < n_cams; c++) {
-#define GUT_SHG(D, V)                                                                          \
-  sh_grad_kernel<D, V><<<gs_grid, kShThreads, 0, s>>>((int)n, c, c == 0, dc[c], th, scene->means, \
-                                                      scene->sh, proj->rgb, acc_rgb, g_means, g_sh)
+#define GUT_SHG(D)                                                                          \
+  sh_grad_kernel<D><<<gs_grid, kShThreads, 0, s>>>((int)n, c, c == 0, dc[c], th, scene->means, \
+                                                   scene->sh, proj->rgb, acc_rgb, g_means, g_sh)
     switch (scene->sh_degree) {
-      case 0: GUT_SHG(0, false); break;
-      case 1: if (vec) GUT_SHG(1, true); else GUT_SHG(1, false); break;
-      case 2: GUT_SHG(2, false); break;
-      default: if (vec) GUT_SHG(3, true); else GUT_SHG(3, false); break;
+      case 0: GUT_SHG(0); break;
+      case 1: GUT_SHG(1); break;
+      case 2: GUT_SHG(2); break;
+      default: GUT_SHG(3); break;
     }
 #undef GUT_SHG
     GUT_LAUNCH_CHECK();
