@@ -328,9 +328,9 @@ def main():
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.traffic_json, args.pmc_command)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build renders on a single MI355X "
-              "(multi-GPU sharding is a design note, not implemented); run with --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: libgut renders on a single MI355X "
+              "(how the path would shard over GPUs is described, not implemented); "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
