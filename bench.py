@@ -47,7 +47,7 @@ if ROOT not in sys.path:
 F_EVAL = 55            # FP32 FLOPs per (pixel, particle) evaluation (mul and add counted apart)
 PEAK_FP32_TFLOPS = 157.3
 # the FP32 ceiling without packed-math instructions (256 CUs x 64 lanes x 2 FLOPs x 2.4 GHz),
-# which this build does not emit
+# which libgut is compiled not to emit
 PEAK_FP32_NONPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "render_traffic.json")

@@ -60,7 +60,7 @@ typedef enum {
   GUT_E_CAPACITY = 2,    /* pair buffer too small; required size reported */
   GUT_E_HIP = 3,         /* a HIP runtime call failed */
   GUT_E_ADMISSION = 4,   /* serving: request can never fit the memory budget */
-  GUT_E_UNSUPPORTED = 5, /* valid request outside what this build supports */
+  GUT_E_UNSUPPORTED = 5, /* valid request outside what libgut supports */
   GUT_E_NOT_FOUND = 6    /* serving: unknown request id */
 } gut_status;
 

@@ -194,7 +194,7 @@ gut_status check_params(const gut_params* p) {
     return GUT_E_INVALID;
   }
   if (p->tile != kTile) {
-    set_error("tile size %d unsupported (this build renders 16x16 tiles)", p->tile);
+    set_error("tile size %d unsupported (libgut renders 16x16 tiles)", p->tile);
     return GUT_E_UNSUPPORTED;
   }
   if (p->rs_iters < 0 || p->rs_iters > 64) {
