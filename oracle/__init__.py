@@ -60,7 +60,8 @@ class Params(C.Structure):
     _fields_ = [("ut_alpha", C.c_double), ("ut_beta", C.c_double), ("ut_kappa", C.c_double),
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double), ("t_min", C.c_double),
                 ("near_plane", C.c_double), ("k_sigma_max", C.c_double),
-                ("tile", C.c_int32), ("rs_iters", C.c_int32), ("bg", C.c_double * 3)]
+                ("tile", C.c_int32), ("rs_iters", C.c_int32), ("bg", C.c_double * 3),
+                ("kernel_degree", C.c_int32)]
 
 
 class SceneS(C.Structure):
@@ -100,7 +101,7 @@ def _declare(L):
     L.ora_pixel_ray.restype = C.c_int
     L.ora_sh_basis.argtypes = [C.c_int, vp, vp]
     L.ora_sh_basis_grad.argtypes = [C.c_int, vp, vp]
-    L.ora_particle_alpha.argtypes = [vp, vp, vp, d, vp, vp, vp, vp, vp]
+    L.ora_particle_alpha.argtypes = [vp, vp, vp, d, vp, vp, i32, vp, vp, vp]
     L.ora_particle_alpha.restype = C.c_int
     L.ora_project.argtypes = [vp, vp, vp, vp]
     L.ora_bin.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
@@ -132,7 +133,7 @@ def default_params(**kw) -> dict:
     f = lambda v: float(np.float32(v))
     p = dict(ut_alpha=1.0, ut_beta=2.0, ut_kappa=0.0, alpha_min=f(1.0 / 255.0),
              alpha_max=f(0.99), t_min=f(1e-4), near_plane=f(0.2), k_sigma_max=3.0,
-             tile=16, rs_iters=3, bg=(0.0, 0.0, 0.0))
+             tile=16, rs_iters=3, bg=(0.0, 0.0, 0.0), kernel_degree=2)
     p.update(kw)
     return p
 
@@ -151,6 +152,7 @@ def _params(p: dict) -> Params:
         setattr(s, k, float(p[k]))
     s.tile = int(p["tile"])
     s.rs_iters = int(p["rs_iters"])
+    s.kernel_degree = int(p.get("kernel_degree", 2))
     for i in range(3):
         s.bg[i] = float(p["bg"][i])
     return s
@@ -293,11 +295,11 @@ def sh_basis_grad(degree, d):
     return dY
 
 
-def particle_alpha(mu, quat, scale, opacity, o, d):
+def particle_alpha(mu, quat, scale, opacity, o, d, kernel_degree=2):
     mu, quat, scale, o, d = (np.ascontiguousarray(x, np.float64) for x in (mu, quat, scale, o, d))
     tau, om2, a = C.c_double(), C.c_double(), C.c_double()
     ok = lib().ora_particle_alpha(_p(mu), _p(quat), _p(scale), float(opacity), _p(o), _p(d),
-                                  C.byref(tau), C.byref(om2), C.byref(a))
+                                  int(kernel_degree), C.byref(tau), C.byref(om2), C.byref(a))
     return bool(ok), tau.value, om2.value, a.value
 
 

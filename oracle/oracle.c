@@ -418,6 +418,34 @@ static void sh_color(int degree, const double* beta /* [K,3] */, const double di
 static int tiles_x(const ora_camera* c, const ora_params* p) { return (c->width + p->tile - 1) / p->tile; }
 static int tiles_y(const ora_camera* c, const ora_params* p) { return (c->height + p->tile - 1) / p->tile; }
 
+/* Particle response at squared canonical distance w2 = omega^2 (Supp. A):
+ * rho = exp(-lambda (w2)^(n/2)), the generalized Gaussian of degree n.  The
+ * scale lambda is chosen so that rho at distance r = 3 equals the reference
+ * Gaussian's exp(-r^2 / 2); that reading gives lambda = r^(2-n) / 2, so that
+ * degree 2 is exactly the Gaussian exp(-omega^2 / 2) of Eq. 11. */
+static double kernel_lambda(int n) { return 0.5 * pow(3.0, 2.0 - n); }
+
+static double response(const ora_params* p, double w2) {
+  const int n = p->kernel_degree;
+  if (n == 2) return exp(-0.5 * w2);
+  return exp(-kernel_lambda(n) * pow(w2, 0.5 * n));
+}
+
+/* d rho / d omega^2 = -lambda (n/2) (omega^2)^(n/2 - 1) rho */
+static double response_dw2(const ora_params* p, double w2) {
+  const int n = p->kernel_degree;
+  if (n == 2) return -0.5 * exp(-0.5 * w2);
+  return -kernel_lambda(n) * 0.5 * n * pow(w2, 0.5 * n - 1.0) * response(p, w2);
+}
+
+/* The canonical distance at which sigma rho falls to alpha_min:
+ * lambda k^n = ln(sigma / alpha_min). */
+static double cutoff_distance(const ora_params* p, double sig) {
+  const int n = p->kernel_degree;
+  if (n == 2) return sqrt(2.0 * log(sig / p->alpha_min));
+  return pow(log(sig / p->alpha_min) / kernel_lambda(n), 1.0 / n);
+}
+
 int ora_project(const ora_scene* s, const ora_camera* c, const ora_params* p, ora_proj* out) {
   const int K = (s->sh_degree + 1) * (s->sh_degree + 1);
   const int tx = tiles_x(c, p), ty = tiles_y(c, p);
@@ -460,8 +488,8 @@ int ora_project(const ora_scene* s, const ora_camera* c, const ora_params* p, or
     if (!all_ok) cull = 2;
 
     /* Extent(Sigma', sigma) (reading R10): the k-sigma box with k the
-     * distance at which sigma * exp(-k^2/2) reaches alpha_min, capped at 3. */
-    double ks = sqrt(2.0 * log(sig / p->alpha_min));
+     * distance at which sigma * rho(k^2) reaches alpha_min, capped at 3. */
+    double ks = cutoff_distance(p, sig);
     if (ks > p->k_sigma_max) ks = p->k_sigma_max;
     double hx = ks * sqrt(cov[0] > 0 ? cov[0] : 0), hy = ks * sqrt(cov[2] > 0 ? cov[2] : 0);
     double* e = &out->edge[4 * i];
@@ -626,8 +654,10 @@ static void eval_geo(const particle_geo* g, const double o[3], const double d[3]
 }
 
 int ora_particle_alpha(const double mu[3], const double quat[4], const double scale[3],
-                       double opacity, const double o[3], const double d[3], double* tau_max,
-                       double* omega2, double* alpha_raw) {
+                       double opacity, const double o[3], const double d[3], int32_t kernel_degree,
+                       double* tau_max, double* omega2, double* alpha_raw) {
+  ora_params kp;
+  kp.kernel_degree = kernel_degree;
   double R[9];
   particle_geo g;
   ora_quat_to_rot(quat, R);
@@ -640,7 +670,7 @@ int ora_particle_alpha(const double mu[3], const double quat[4], const double sc
   eval_geo(&g, o, d, og, dg, &odot, &om2);
   *tau_max = -odot / dot3(dg, dg);
   *omega2 = om2;
-  *alpha_raw = opacity * exp(-0.5 * om2);
+  *alpha_raw = opacity * response(&kp, om2);
   return odot < 0;
 }
 
@@ -690,7 +720,7 @@ static void render_pixel(const render_ctx* X, const int32_t* ids, const int32_t*
     int skip = odot >= 0; /* tau_max <= 0: the maximum lies behind the origin (reading R15) */
     if (pt.type == PT_TAU && pt.pos == q) skip = !skip;
     if (skip) continue;
-    double a = g->sigma * exp(-0.5 * om2);
+    double a = g->sigma * response(p, om2);
     if (a > p->alpha_max) a = p->alpha_max;
     if (cand && *ncand < MAXCAND && fabs(a - p->alpha_min) < X->amb->alpha)
       cand[(*ncand)++] = (perturb){PT_ALPHA, q};
@@ -912,7 +942,7 @@ int ora_backward(const ora_scene* s, const ora_proj* pr, const ora_camera* c, co
             double og[3], dg[3], odot, om2;
             eval_geo(g, o, d, og, dg, &odot, &om2);
             if (odot >= 0) continue;
-            double a = g->sigma * exp(-0.5 * om2);
+            double a = g->sigma * response(p, om2);
             int clamped = a > p->alpha_max;
             if (clamped) a = p->alpha_max;
             if (a < p->alpha_min) continue;
@@ -940,11 +970,12 @@ int ora_backward(const ora_scene* s, const ora_proj* pr, const ora_camera* c, co
             for (int ch = 0; ch < 3; ch++) Sa[ch] += col[ch] * r->a * r->Tb;
             if (r->clamped) continue; /* alpha = alpha_max: no dependence (reading R14) */
             const particle_geo* g = &geo[r->id];
-            double e = exp(-0.5 * r->om2);
+            double e = response(p, r->om2);
 #pragma omp atomic
             g_opac[r->id] += gA * e;
-            /* d alpha / d omega^2 = -1/2 sigma e^{-omega^2/2} */
-            double gom2 = gA * (-0.5 * g->sigma * e);
+            /* d alpha / d omega^2 = sigma d rho / d omega^2 (-1/2 sigma e^{-omega^2/2}
+             * for the Gaussian, Supp. B) */
+            double gom2 = gA * g->sigma * response_dw2(p, r->om2);
             /* d omega^2 / d o_g = 2 o_g + 2 tau_g d_g/|d_g| ; d omega^2 / d d_g = 2 tau (o_g + tau d_g) */
             double dd = dot3(r->dg, r->dg);
             double tau = -dot3(r->og, r->dg) / dd;
@@ -1006,7 +1037,7 @@ int64_t ora_record(const ora_scene* s, const ora_proj* pr, const ora_camera* c, 
       double og[3], dg[3], odot, om2;
       eval_geo(g, o, d, og, dg, &odot, &om2);
       if (odot >= 0) continue;
-      double a = g->sigma * exp(-0.5 * om2);
+      double a = g->sigma * response(p, om2);
       int cl = a > p->alpha_max;
       if (cl) a = p->alpha_max;
       if (a < p->alpha_min) continue;
@@ -1051,7 +1082,7 @@ double ora_loss_frozen(const ora_scene* s, const ora_proj* pr, const ora_camera*
         const particle_geo* g = &geo[contrib[k]];
         double og[3], dg[3], odot, om2;
         eval_geo(g, o, d, og, dg, &odot, &om2);
-        double a = clamped[k] ? p->alpha_max : g->sigma * exp(-0.5 * om2);
+        double a = clamped[k] ? p->alpha_max : g->sigma * response(p, om2);
         for (int ch = 0; ch < 3; ch++) C[ch] += a * T * rgb[3 * contrib[k] + ch];
         T *= (1.0 - a);
       }

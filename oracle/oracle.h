@@ -48,6 +48,7 @@ typedef struct {
   double alpha_min, alpha_max, t_min, near_plane, k_sigma_max;
   int32_t tile, rs_iters;
   double bg[3];
+  int32_t kernel_degree; /* n of the generalized Gaussian response (Supp. A); 2 = Gaussian */
 } ora_params;
 
 typedef struct {
@@ -122,9 +123,10 @@ int ora_pixel_ray(const ora_camera* c, double u, double v, double o[3], double d
                   double* margin);
 void ora_sh_basis(int degree, const double dir[3], double* Y /* [(deg+1)^2] */);
 void ora_sh_basis_grad(int degree, const double dir[3], double* dY /* [(deg+1)^2,3] */);
-/* alpha of one particle on one ray (Eq. 11 + Eq. 5's alpha); returns 0 if tau <= 0. */
+/* alpha of one particle on one ray (Eq. 11 + Eq. 5's alpha) with the response of
+ * degree kernel_degree (Supp. A; 2 = Gaussian); returns 0 if tau <= 0. */
 int ora_particle_alpha(const double mu[3], const double quat[4], const double scale[3],
-                       double opacity, const double o[3], const double d[3],
+                       double opacity, const double o[3], const double d[3], int32_t kernel_degree,
                        double* tau_max, double* omega2, double* alpha_raw);
 
 /* ---- pipeline ---- */

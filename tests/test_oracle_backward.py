@@ -5,7 +5,8 @@
 2. Central finite differences (h = 1e-6) of a linear image loss with every
    discrete decision frozen (tile lists, skip masks, stop index, clamps)
    against the oracle's analytic gradient, for all 59 parameters of 64
-   particles, under pinhole, fisheye and rolling-shutter cameras.
+   particles, under pinhole, fisheye and rolling-shutter cameras, with the
+   Gaussian response and with generalized responses of degree 3, 4 and 8.
 """
 import math
 
@@ -53,8 +54,8 @@ def test_dalpha_dmu_closed_form():
     assert checked >= 10
 
 
-def _fd_check(scene, cam, seed, h=1e-6, bg=(0.0, 0.0, 0.0), use_dT=True):
-    p = O.default_params(bg=bg)
+def _fd_check(scene, cam, seed, h=1e-6, bg=(0.0, 0.0, 0.0), use_dT=True, kernel_degree=2):
+    p = O.default_params(bg=bg, kernel_degree=kernel_degree)
     sc = O.as_oscene(scene)
     pr = O.project(sc, cam, p)
     bins = O.bin_tiles(pr, cam, p)
@@ -108,3 +109,13 @@ def test_backward_central_differences_dense_overlap(kind):
     worst = _fd_check(scene, cam, seed=3014, bg=(0.2, 0.5, 0.9))
     for k, v in worst.items():
         assert v < 1e-6, (kind, k, v)
+
+
+@pytest.mark.parametrize("kind,n", [("pinhole", 4), ("fisheye", 3), ("rolling", 8)])
+def test_backward_central_differences_generalized_kernel(kind, n):
+    """The degree-n response of Supp. A: its chain d rho / d omega^2 against
+    central differences, with dense overlap so clamps and stops occur."""
+    scene, cam = G.config4_gradcheck(kind, log_scale_mean=-2.2)
+    worst = _fd_check(scene, cam, seed=3024 + n, bg=(0.1, 0.3, 0.6), kernel_degree=n)
+    for k, v in worst.items():
+        assert v < 1e-6, (kind, n, k, v)

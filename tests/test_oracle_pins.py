@@ -345,6 +345,89 @@ def test_single_isotropic_particle_closed_form():
 
 
 # ---------------------------------------------------------------------------
+# Generalized Gaussian response of degree n (Supp. A)
+# ---------------------------------------------------------------------------
+
+def _lambda_from_definition(n):
+    """The scale that gives the degree-n kernel the reference Gaussian's
+    response at canonical distance r = 3: lambda 3^n = 3^2 / 2."""
+    return 4.5 / 3.0 ** n
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 8])
+@pytest.mark.parametrize("seed", range(3))
+def test_generalized_response_equals_gaussian_at_r3(n, seed):
+    """Supp. A defines lambda so that every degree has the Gaussian's
+    response at distance r = 3: a ray passing 3 s from an isotropic
+    particle's centre sees sigma exp(-9/2) whatever n."""
+    rng = np.random.default_rng(seed)
+    mu, s, sig = rng.normal(size=3), math.exp(rng.normal(-1, 0.3)), 0.7
+    q = rng.normal(size=4)
+    d = rng.normal(size=3)
+    d /= np.linalg.norm(d)
+    perp = np.cross(d, rng.normal(size=3))
+    perp /= np.linalg.norm(perp)
+    o = mu + 3.0 * s * perp - 5.0 * d  # closest approach 3 s, in front of the origin
+    ok, tau, om2, a = O.particle_alpha(mu, q, np.full(3, s), sig, o, d, n)
+    assert ok and abs(om2 - 9.0) < 1e-9
+    assert abs(a - sig * math.exp(-4.5)) < 1e-12
+
+
+@pytest.mark.parametrize("w", [0.0, 0.5, 1.7, 2.9, 3.1, 4.0])
+def test_generalized_response_denser_inside_steeper_outside(w):
+    """Higher degrees are denser inside r = 3 and fall off faster outside
+    (Supp. A, Fig. of the generalized particle); degree 2 is exp(-w^2/2)."""
+    mu, q, s = np.zeros(3), np.array([1.0, 0, 0, 0]), np.ones(3)
+    o, d = np.array([w, 0.0, -6.0]), np.array([0.0, 0.0, 1.0])
+    vals = [O.particle_alpha(mu, q, s, 1.0, o, d, n)[3] for n in (2, 3, 4, 5, 8)]
+    assert abs(vals[0] - math.exp(-0.5 * w * w)) < 1e-15
+    steps = np.diff(vals)
+    if w == 0.0:
+        assert np.all(np.abs(np.array(vals) - 1.0) < 1e-15)
+    elif w < 3.0:
+        assert np.all(steps > 0)
+    else:
+        assert np.all(steps < 0)
+
+
+@pytest.mark.parametrize("n", [3, 4, 8])
+def test_generalized_single_particle_closed_form_and_extent(n):
+    """One isotropic particle of low opacity rendered with the degree-n
+    response: every pixel equals c sigma exp(-lambda (d_perp / s)^n) with
+    lambda from Supp. A's definition and d_perp from vector geometry.  The
+    particle sits so that its degree-n alpha_min circle crosses into a tile
+    column that the Gaussian's (smaller, for this opacity) circle does not
+    reach: an extent computed for the Gaussian would leave those pixels black."""
+    cam = G.camera("pinhole", 128, 128, 80.0, R0=np.eye(3), t0=np.array([0.0, 0.0, 4.0]))
+    s, sig, col = 0.5, 0.1, np.array([0.9, 0.4, 0.1])
+    mu = np.array([9.2 * 4.2 / 80.0, 0.0, 0.2])  # centre 9.2 px right of the principal point
+    sh = ((col - 0.5) / G.SH_C0)[None, None, :]
+    sc = O.OScene(mu[None], np.full((1, 3), s), np.array([[0.3, 0.1, 0.7, -0.2]]),
+                  np.array([sig]), sh, 0)
+    p = O.default_params(kernel_degree=n)
+    pr, b, res = O.render_full(sc, cam, p)
+    img = O.to_image(res, cam, p)
+    lam = _lambda_from_definition(n)
+    k_gauss = math.sqrt(2 * math.log(sig * 255))
+    o = np.array([0.0, 0.0, -4.0])
+    worst, n_checked, ring = 0.0, 0, 0
+    for py in range(128):
+        for px in range(128):
+            d = np.array([(px + 0.5 - 64) / 80.0, (py + 0.5 - 64) / 80.0, 1.0])
+            w = np.linalg.norm(np.cross(mu - o, d / np.linalg.norm(d))) / s
+            a = sig * math.exp(-lam * w ** n)
+            if abs(a - 1 / 255) < 1e-6:
+                continue
+            expect = col * a if a >= 1 / 255 else np.zeros(3)
+            worst = max(worst, np.abs(img[py, px] - expect).max())
+            n_checked += 1
+            if a >= 1 / 255 and w > k_gauss and px < 48:
+                ring += 1
+    assert n_checked > 16000 and ring > 0
+    assert worst < 1e-12
+
+
+# ---------------------------------------------------------------------------
 # Compositing (Eq. 5)
 # ---------------------------------------------------------------------------
 
