@@ -26,6 +26,8 @@ Also reported on the same line:
                 mean, max and HIP-event median are in fwd_bwd_detail
   rolling_shutter_3m   stage times of the same forward step on the 3M-particle
                 rolling-shutter fisheye 1600x1200 view (context, not the metric)
+  generalized_degrees  the same forward step with the generalized Gaussian
+                responses of degree 3, 4 and 8 (Supp. A), beside degree 2
   cpu_baseline  the FP64 oracle on this host's cores, timed on whole steps of
                 the same two-view batch (projection, binning, every tile)
                 until its time budget is spent
@@ -33,6 +35,7 @@ Also reported on the same line:
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -80,7 +83,8 @@ def render_launches(cams):
 
 def pmc_summary(fetch_dir, write_dir, out_path, command):
     """Per-launch HBM bytes of the timed render kernel (render_multi_kernel<false,
-    false>: global shutter, no n_eval, both views in one launch) from two
+    false, false>: global shutter, no n_eval, Gaussian response, both views in
+    one launch) from two
     rocprofv3 --pmc runs of `bench.py --calib-copy` (FETCH_SIZE, then
     WRITE_SIZE, KiB per dispatch).
     Each counter is scaled by what it reads for a kernel of known traffic in
@@ -104,8 +108,8 @@ def pmc_summary(fetch_dir, write_dir, out_path, command):
     fr, wr = read(fetch_dir, "FETCH_SIZE"), read(write_dir, "WRITE_SIZE")
     f_add = pick(fr, "CUDAFunctor_add", "CUDAFunctorOnSelf_add")
     w_fill = pick(wr, "FillFunctor")
-    f_r = pick(fr, "gut::render_multi_kernel<false, false>")
-    w_r = pick(wr, "gut::render_multi_kernel<false, false>")
+    f_r = pick(fr, "gut::render_multi_kernel<false, false, false>")
+    w_r = pick(wr, "gut::render_multi_kernel<false, false, false>")
     if not (f_add and w_fill and f_r and w_r):
         raise SystemExit("pmc summary: calibration or render dispatches missing")
     ff = CALIB_BYTES / (f_add[0] * 1024.0)
@@ -125,34 +129,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bench_forward(gs, cams, steps, warmup, R, torch):
+def bench_forward(gs, cams, steps, warmup, R, torch, params=None):
     proj = R.alloc_projection(gs.n, len(cams), gs.means.device)
-    R.project(gs, cams, out=proj)
-    bins = R.bin_tiles(proj, cams)
+    R.project(gs, cams, params, out=proj)
+    bins = R.bin_tiles(proj, cams, params)
     img = R.alloc_image(cams, gs.means.device)
     n_ev = 4
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(n_ev)] for _ in range(steps)]
 
     def step(e=None):
         if e: e[0].record()
-        R.project(gs, cams, out=proj)
+        R.project(gs, cams, params, out=proj)
         if e: e[1].record()
-        R.bin_tiles(proj, cams, bins=bins)
+        R.bin_tiles(proj, cams, params, bins=bins)
         if e: e[2].record()
-        R.render(proj, bins, cams, out=img)
+        R.render(proj, bins, cams, params, out=img)
         if e: e[3].record()
 
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    # no Python garbage collection inside the timed region (a full collection
+    # stalls the host, and with it the launches, for tens of milliseconds)
+    gc.collect()
+    gc.disable()
     t0 = time.perf_counter()
     for k in range(steps):
         step(ev[k])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    gc.enable()
     st = np.array([[ev[k][i].elapsed_time(ev[k][i + 1]) for i in range(n_ev - 1)] for k in range(steps)])
     # one extra, untimed render that counts evaluations per pixel
-    img_eval = R.render(proj, bins, cams, with_eval=True)
+    img_eval = R.render(proj, bins, cams, params, with_eval=True)
     torch.cuda.synchronize()
     e_eval = int(img_eval.n_eval.to(torch.int64).sum().item())
     return dict(ms_per_step=(t1 - t0) * 1e3 / steps, stage_ms=st.mean(0), stage_p10=np.percentile(st, 10, 0),
@@ -195,6 +204,8 @@ def bench_fwd_bwd(scene, cam, steps, warmup, R, G, torch):
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
     walls = []
+    gc.collect()
+    gc.disable()
     for k in range(steps):  # each step bracketed by synchronisations
         t0 = time.perf_counter()
         ev[k][0].record()
@@ -202,6 +213,7 @@ def bench_fwd_bwd(scene, cam, steps, warmup, R, G, torch):
         ev[k][1].record()
         torch.cuda.synchronize()
         walls.append((time.perf_counter() - t0) * 1e3)
+    gc.enable()
     per = sorted(a.elapsed_time(b) for a, b in ev)
     return dict(ms_per_view=float(np.median(walls)), ms_mean=float(np.mean(walls)),
                 ms_max=float(np.max(walls)), gpu_ms_median=per[len(per) // 2])
@@ -318,6 +330,9 @@ def main():
                          "(reads 1 GiB, writes 1 GiB)")
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--degrees", default="3,4,8",
+                    help="generalized-Gaussian degrees (Supp. A) timed on the same forward step")
+    ap.add_argument("--no-degrees", action="store_true")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the 3M-particle rolling-shutter fisheye stage timings")
     ap.add_argument("--serve-requests", type=int, default=120)
@@ -388,6 +403,24 @@ def main():
                 frac=b / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS)
         for k, b, ms in (("project", proj_bytes, fw["stage_ms"][0]), ("bin", bin_bytes, fw["stage_ms"][1]))}
 
+    # the generalized Gaussian responses of Supp. A on the same forward step
+    # (its table trades quality for speed across degrees 2..8)
+    degrees = None
+    if args.degrees and not args.no_degrees:
+        degrees = {"2": dict(mpix_per_s=value, stages_ms={"project": fw["stage_ms"][0],
+                                                          "bin": fw["stage_ms"][1],
+                                                          "render": fw["stage_ms"][2]},
+                             n_pairs=fw["n_pairs"])}
+        for d in [int(x) for x in args.degrees.split(",")]:
+            log(f"[bench] forward steps, response of degree {d}")
+            fd = bench_forward(gs, cams, max(3, args.steps // 2), 2, R, torch, dict(kernel_degree=d))
+            degrees[str(d)] = dict(mpix_per_s=npx / (fd["ms_per_step"] * 1e-3) / 1e6,
+                                   stages_ms={"project": fd["stage_ms"][0], "bin": fd["stage_ms"][1],
+                                              "render": fd["stage_ms"][2]},
+                                   n_pairs=fd["n_pairs"], e_eval=fd["e_eval"])
+            del fd
+        degrees["2"]["e_eval"] = fw["e_eval"]
+
     fwd_bwd = None
     if not args.no_fwd_bwd:
         log("[bench] fwd+bwd on the fisheye view")
@@ -451,6 +484,7 @@ def main():
         "fwd_bwd_ms_per_view": fwd_bwd["ms_per_view"] if fwd_bwd else None,
         "fwd_bwd_detail": fwd_bwd,
         "rolling_shutter_3m": c3,
+        "generalized_degrees": degrees,
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -95,12 +95,19 @@ typedef struct {
 /* Method parameters.  gut_default_params fills: UT alpha=1, beta=2, kappa=0
  * (Sec. 4.4); alpha_min=1/255, alpha_max=0.99, t_min=1e-4, near_plane=0.2
  * (the 3DGS values the paper adopts); k_sigma_max=3 (extent cap); tile=16;
- * rs_iters=3 (rolling-shutter time iterations); bg = 0. */
+ * rs_iters=3 (rolling-shutter time iterations); bg = 0; kernel_degree=2.
+ * kernel_degree n in [2, 8] selects the particle response
+ * rho = exp(-lambda (omega^2)^(n/2)), the generalized Gaussian of degree n of
+ * Supp. A, with lambda = 3^(2-n) / 2 so that every degree has the Gaussian's
+ * response at canonical distance 3; n = 2 is the Gaussian exp(-omega^2 / 2)
+ * of Eq. 11.  It applies to projection (the extent's cutoff distance),
+ * rendering and the backward pass alike. */
 typedef struct {
   float ut_alpha, ut_beta, ut_kappa;
   float alpha_min, alpha_max, t_min, near_plane, k_sigma_max;
   int32_t tile, rs_iters;
   float bg[3];
+  int32_t kernel_degree;
 } gut_params;
 
 /* Outputs of gut_project (caller-allocated device arrays).

@@ -51,7 +51,8 @@ class Params(C.Structure):
     _fields_ = [("ut_alpha", C.c_float), ("ut_beta", C.c_float), ("ut_kappa", C.c_float),
                 ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
                 ("near_plane", C.c_float), ("k_sigma_max", C.c_float),
-                ("tile", C.c_int32), ("rs_iters", C.c_int32), ("bg", C.c_float * 3)]
+                ("tile", C.c_int32), ("rs_iters", C.c_int32), ("bg", C.c_float * 3),
+                ("kernel_degree", C.c_int32)]
 
 
 class Projected(C.Structure):
@@ -167,7 +168,7 @@ def params_struct(params: dict | None = None) -> Params:
         if k == "bg":
             for i in range(3):
                 p.bg[i] = float(v[i])
-        elif k in ("tile", "rs_iters"):
+        elif k in ("tile", "rs_iters", "kernel_degree"):
             setattr(p, k, int(v))
         else:
             setattr(p, k, float(v))

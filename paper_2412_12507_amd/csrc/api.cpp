@@ -201,6 +201,10 @@ gut_status check_params(const gut_params* p) {
     set_error("rs_iters must be in [0, 64]");
     return GUT_E_INVALID;
   }
+  if (p->kernel_degree < 2 || p->kernel_degree > 8) {
+    set_error("kernel_degree must be in [2, 8]");
+    return GUT_E_INVALID;
+  }
   return GUT_OK;
 }
 
@@ -225,6 +229,18 @@ Thresholds make_thresholds(const gut_params& p) {
   t.k_sigma_max = p.k_sigma_max;
   for (int i = 0; i < 3; i++) t.bg[i] = p.bg[i];
   t.rs_iters = p.rs_iters;
+  // generalized Gaussian of degree n (Supp. A): rho = exp(-lambda (omega^2)^(n/2))
+  // with lambda = 3^(2-n) / 2, the response of the Gaussian at distance 3
+  const int n = p.kernel_degree;
+  const double h = 0.5 * n, lam = 0.5 * std::pow(3.0, 2.0 - n);
+  const double log2e = 1.4426950408889634, l2ln2 = std::log2(2.0 * 0.6931471805599453);
+  t.kdeg = n;
+  t.k_h = (float)h;
+  t.k_inv_h = (float)(1.0 / h);
+  t.k_l = (float)(std::log2(lam * log2e) + h * l2ln2);
+  t.k_f = (float)(std::log2(2.0 * lam * h) + (h - 1.0) * l2ln2);
+  t.k_lam = (float)lam;
+  t.k_inv_n = (float)(1.0 / n);
   return t;
 }
 
@@ -277,6 +293,7 @@ void gut_default_params(gut_params* p) {
   p->tile = kTile;
   p->rs_iters = 3;
   p->bg[0] = p->bg[1] = p->bg[2] = 0.0f;
+  p->kernel_degree = 2;
 }
 
 int64_t gut_num_tiles(const gut_camera* cams, int32_t n_cams, const gut_params* p) {

@@ -52,6 +52,13 @@ struct Thresholds {
   float alpha_min, alpha_max, t_min, near_plane, k_sigma_max;
   float bg[3];
   int rs_iters;
+  // Response of degree kdeg (2: the Gaussian).  With q = omega^2 log2(e) / 2
+  // (the log2-unit exponent of the Gaussian), the degree-n exponent is
+  // x = 2^(k_h log2 q + k_l) and sigma rho = 2^(lsig - x); the chain factor
+  // of d alpha / d omega^2 relative to the Gaussian's is 2^((k_h - 1) log2 q + k_f).
+  // k_lam and k_inv_n give the extent's cutoff (ln(sigma / alpha_min) / lambda)^(1/n).
+  int kdeg;
+  float k_h, k_inv_h, k_l, k_f, k_lam, k_inv_n;
 };
 
 // ---------------------------------------------------------------- errors

@@ -93,8 +93,11 @@ __global__ void __launch_bounds__(256) project_kernel(
     }
     vmean = make_float2(mx, my);
     if (ok_all) {
-      // Extent: the box of the k-sigma ellipse, k where sigma e^{-k^2/2} = alpha_min (<= 3)
-      float ks = fminf(th.k_sigma_max, sqrtf(2.0f * logf(sig / th.alpha_min)));
+      // Extent: the box of the k-sigma ellipse, k where sigma rho(k^2) = alpha_min (<= 3):
+      // sqrt(2 ln(sigma / alpha_min)) for the Gaussian, else (ln(sigma / alpha_min) / lambda)^(1/n)
+      const float lnr = logf(sig / th.alpha_min);
+      float ks = th.kdeg == 2 ? sqrtf(2.0f * lnr) : powf(lnr / th.k_lam, th.k_inv_n);
+      ks = fminf(th.k_sigma_max, ks);
       float hx = ks * sqrtf(fmaxf(cxx, 0.0f)), hy = ks * sqrtf(fmaxf(cyy, 0.0f));
       const float inv_t = 1.0f / kTile;
       int x0 = max((int)floorf((mx - hx) * inv_t), 0);

@@ -24,8 +24,8 @@ constexpr int kRThreads = 128;
 constexpr int kRBatch = kRThreads;
 
 // One tile of one camera.  pd, pf, F, wb and red are the block's LDS; out_*
-// are indexed by pix_base + y * W + x.
-template <bool RS, bool NE>
+// are indexed by pix_base + y * W + x.  GEN: response of degree th.kdeg > 2.
+template <bool RS, bool NE, bool GEN>
 __device__ __forceinline__ void render_tile(
     const DevCam& cam, const Thresholds& th, int n, int cam_idx, int tile,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
@@ -74,8 +74,8 @@ __device__ __forceinline__ void render_tile(
     uint32_t fl = 0u;
     if (b + t < len) {
       uint32_t e = ids[rg.x + b + t];
-      fl = pair_setup<RS, false>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n), F, cam,
-                          umax, vmax, dtmax, th.alpha_min, l2amin, wb, kRThreads / 64, &pd[t * S]);
+      fl = pair_setup<RS, false, GEN>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n), F,
+                                      cam, umax, vmax, dtmax, th, l2amin, wb, kRThreads / 64, &pd[t * S]);
     }
     pf[t] = fl;
     __syncthreads();
@@ -102,7 +102,7 @@ __device__ __forceinline__ void render_tile(
         float wgt[2];
 #pragma unroll
         for (int k = 0; k < 2; k++) {
-          eval_alpha<RS>(r, th.alpha_max, &ev[k]);
+          eval_alpha<RS, GEN>(r, th, &ev[k]);
           const bool live = k ? live1 : live0;
           const float Tn = fmaf(-ev[k].a, T[k], T[k]);  // T (1 - alpha)
           const bool below = Tn < th.t_min;
@@ -145,7 +145,7 @@ __device__ __forceinline__ void render_tile(
 
 // One block per tile, taken in the render order (longest lists first).  NE:
 // also count each pixel's evaluated entries (out_ne non-null).
-template <bool RS, bool NE>
+template <bool RS, bool NE, bool GEN>
 __global__ void __launch_bounds__(kRThreads, 4) render_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
@@ -157,8 +157,8 @@ __global__ void __launch_bounds__(kRThreads, 4) render_kernel(
   __shared__ WaveBoxes wb;
   __shared__ float red[6];
   const int tile = (int)order[cam.tile_base + blockIdx.x];
-  render_tile<RS, NE>(cam, th, n, cam_idx, tile, ranges, ids, record, rgb, out_rgb, out_T, out_nc,
-                  out_ne, cam.pixel_base, pd, pf, F, wb, red);
+  render_tile<RS, NE, GEN>(cam, th, n, cam_idx, tile, ranges, ids, record, rgb, out_rgb, out_T, out_nc,
+                           out_ne, cam.pixel_base, pd, pf, F, wb, red);
 }
 
 // Several cameras of one shutter type and one tile count in one launch
@@ -173,7 +173,7 @@ struct MultiCams {
   int n;
 };
 
-template <bool RS, bool NE>
+template <bool RS, bool NE, bool GEN>
 __global__ void __launch_bounds__(kRThreads, 4) render_multi_kernel(
     MultiCams mc, Thresholds th, int n, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
@@ -187,8 +187,8 @@ __global__ void __launch_bounds__(kRThreads, 4) render_multi_kernel(
   const int c = (int)(blockIdx.x % (unsigned)mc.n), k = (int)(blockIdx.x / (unsigned)mc.n);
   const DevCam& cam = mc.cam[c];
   const int tile = (int)order[cam.tile_base + k];
-  render_tile<RS, NE>(cam, th, n, mc.idx[c], tile, ranges, ids, record, rgb, out_rgb, out_T, out_nc,
-                      out_ne, cam.pixel_base, pd, pf, F, wb, red);
+  render_tile<RS, NE, GEN>(cam, th, n, mc.idx[c], tile, ranges, ids, record, rgb, out_rgb, out_T,
+                           out_nc, out_ne, cam.pixel_base, pd, pf, F, wb, red);
 }
 
 // Persistent render of the cameras of one shutter type in a multi-camera
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(kRThreads, 4) render_multi_kernel(
 // share longest-first; a block that drains its XCD's share steals from the
 // others, and leaves once every counter is past its share.  Images go to
 // outs[camera] ([H, W, 3]).
-template <bool RS>
+template <bool RS, bool GEN>
 __global__ void __launch_bounds__(kRThreads, 4) render_batch_kernel(
     const DevCam* __restrict__ cams, const int* __restrict__ cam_list,
     const int* __restrict__ item_start, int n_list, int n_items, unsigned* __restrict__ counters,
@@ -238,8 +238,8 @@ __global__ void __launch_bounds__(kRThreads, 4) render_batch_kernel(
     const int c = __builtin_amdgcn_readfirstlane(cam_list[j]);
     const DevCam& cam = cams[c];
     const int tile = (int)order[cam.tile_base + (item - item_start[j])];
-    render_tile<RS, false>(cam, th, n, c, tile, ranges, ids, record, rgb, outs[c], nullptr, nullptr,
-                    nullptr, 0, pd, pf, F, wb, red);
+    render_tile<RS, false, GEN>(cam, th, n, c, tile, ranges, ids, record, rgb, outs[c], nullptr,
+                                nullptr, nullptr, 0, pd, pf, F, wb, red);
   }
 }
 
@@ -269,14 +269,14 @@ gut_status render_batch_launch(const DevCam* d_cams, const DevCam* h_cams, int n
     if (m == 0) continue;
     int* dl = d_lists + type * (2 * kMaxCams + 1);
     GUT_HIP(hipMemcpyAsync(dl, hl, (2 * kMaxCams + 1) * sizeof(int), hipMemcpyHostToDevice, s));
-    if (type == 1)
-      render_batch_kernel<true><<<n_blocks, kRThreads, 0, s>>>(
-          d_cams, dl, dl + kMaxCams, m, items, d_counters + 8 * type, th, n, (const uint2*)ranges,
-          order, ids, (const float4*)record, rgb, d_outs);
-    else
-      render_batch_kernel<false><<<n_blocks, kRThreads, 0, s>>>(
-          d_cams, dl, dl + kMaxCams, m, items, d_counters + 8 * type, th, n, (const uint2*)ranges,
-          order, ids, (const float4*)record, rgb, d_outs);
+#define GUT_RB(RS, GEN)                                                                          \
+  render_batch_kernel<RS, GEN><<<n_blocks, kRThreads, 0, s>>>(                                    \
+      d_cams, dl, dl + kMaxCams, m, items, d_counters + 8 * type, th, n, (const uint2*)ranges, order, \
+      ids, (const float4*)record, rgb, d_outs)
+    const bool gen = th.kdeg != 2;
+    if (type == 1) { if (gen) GUT_RB(true, true); else GUT_RB(true, false); }
+    else { if (gen) GUT_RB(false, true); else GUT_RB(false, false); }
+#undef GUT_RB
     GUT_LAUNCH_CHECK();
   }
   return GUT_OK;
@@ -287,13 +287,16 @@ gut_status launch_render(const DevCam& cam, const Thresholds& th, int n, int cam
                          const float* record, const float* rgb, float* out_rgb, float* out_T,
                          uint32_t* out_nc, uint32_t* out_ne, hipStream_t s) {
   dim3 grid(cam.tiles_x * cam.tiles_y), block(kRThreads);
-#define GUT_RK(RS, NE)                                                                        \
-  render_kernel<RS, NE><<<grid, block, 0, s>>>(cam, th, n, cam_idx, (const uint2*)ranges, order, \
-                                               ids, (const float4*)record, rgb, out_rgb, out_T,   \
-                                               out_nc, out_ne)
+#define GUT_RK(RS, NE, GEN)                                                                     \
+  render_kernel<RS, NE, GEN><<<grid, block, 0, s>>>(cam, th, n, cam_idx, (const uint2*)ranges,    \
+                                                    order, ids, (const float4*)record, rgb, out_rgb, \
+                                                    out_T, out_nc, out_ne)
+#define GUT_RK2(RS, NE) \
+  if (th.kdeg != 2) GUT_RK(RS, NE, true); else GUT_RK(RS, NE, false)
   const bool rs = cam.shutter == GUT_ROLLING_TOP_TO_BOTTOM;
-  if (rs) { if (out_ne) GUT_RK(true, true); else GUT_RK(true, false); }
-  else { if (out_ne) GUT_RK(false, true); else GUT_RK(false, false); }
+  if (rs) { if (out_ne) GUT_RK2(true, true); else GUT_RK2(true, false); }
+  else { if (out_ne) GUT_RK2(false, true); else GUT_RK2(false, false); }
+#undef GUT_RK2
 #undef GUT_RK
   GUT_LAUNCH_CHECK();
   return GUT_OK;
@@ -316,13 +319,16 @@ static gut_status launch_render_group(const DevCam* dc, int c0, int c1, const Th
     mc.idx[k] = c0 + k;
   }
   dim3 grid(mc.n * dc[c0].tiles_x * dc[c0].tiles_y), block(kRThreads);
-#define GUT_RM(RS, NE)                                                                              \
-  render_multi_kernel<RS, NE><<<grid, block, 0, s>>>(mc, th, n, (const uint2*)ranges, order, ids,     \
-                                                     (const float4*)record, rgb, out_rgb, out_T, out_nc, \
-                                                     out_ne)
+#define GUT_RM(RS, NE, GEN)                                                                          \
+  render_multi_kernel<RS, NE, GEN><<<grid, block, 0, s>>>(mc, th, n, (const uint2*)ranges, order, ids, \
+                                                          (const float4*)record, rgb, out_rgb, out_T,   \
+                                                          out_nc, out_ne)
+#define GUT_RM2(RS, NE) \
+  if (th.kdeg != 2) GUT_RM(RS, NE, true); else GUT_RM(RS, NE, false)
   const bool rs = dc[c0].shutter == GUT_ROLLING_TOP_TO_BOTTOM;
-  if (rs) { if (out_ne) GUT_RM(true, true); else GUT_RM(true, false); }
-  else { if (out_ne) GUT_RM(false, true); else GUT_RM(false, false); }
+  if (rs) { if (out_ne) GUT_RM2(true, true); else GUT_RM2(true, false); }
+  else { if (out_ne) GUT_RM2(false, true); else GUT_RM2(false, false); }
+#undef GUT_RM2
 #undef GUT_RM
   GUT_LAUNCH_CHECK();
   return GUT_OK;

@@ -75,7 +75,7 @@ __device__ inline float wave_reduce16(const float* g) {
 constexpr int kBwThreads = 128;
 constexpr int kBwBatch = kBwThreads;
 
-template <bool RS>
+template <bool RS, bool GEN>
 __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
@@ -147,8 +147,8 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
     if (b + t < maxlast) {
       uint32_t e = ids[rg.x + b + t];
       pe[t] = e;
-      fl = pair_setup<RS, true>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n), F, cam,
-                          umax, vmax, dtmax, th.alpha_min, l2amin, wb, kBwThreads / 64, &pd[t * S]);
+      fl = pair_setup<RS, true, GEN>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n), F,
+                                     cam, umax, vmax, dtmax, th, l2amin, wb, kBwThreads / 64, &pd[t * S]);
     }
     pf[t] = fl;
     __syncthreads();
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
         float gk[2][9], wfk[2], gAk[2], rhok[2];
 #pragma unroll
         for (int k = 0; k < 2; k++) {
-          eval_alpha<RS>(r, th.alpha_max, &ev[k]);
+          eval_alpha<RS, GEN>(r, th, &ev[k]);
           const float Tb = T[k];
           const float ae = hit[k] ? ev[k].a : 0.0f;
           const float wgt = ae * Tb;
@@ -196,7 +196,10 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
           // rho = exp(-omega^2 / 2) = (sigma rho) / sigma
           gAk[k] = gA;
           rhok[k] = ev[k].araw * isig;
-          const float c = -ev[k].a * gA;  // 2 dL/domega^2
+          // 2 dL/domega^2; a degree-n response scales d alpha / d omega^2 by
+          // 2 lambda (n/2) (omega^2)^(n/2 - 1) relative to the Gaussian's
+          float c = -ev[k].a * gA;
+          if (GEN) c *= __builtin_amdgcn_exp2f(fmaf(th.k_h - 1.0f, ev[k].lq, th.k_f));
           float3 dg, cr;
           pair_vectors<RS>(P, ev[k], u[k], v[k], &dg, &cr);
           float3 p = cross3f_fma(dg, cr);
@@ -450,14 +453,14 @@ extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected
   Thresholds th = make_thresholds(*p);
   for (int c = 0; c < n_cams; c++) {
     dim3 grid(dc[c].tiles_x * dc[c].tiles_y), block(kBwThreads);
-    if (dc[c].shutter == GUT_ROLLING_TOP_TO_BOTTOM)
-      render_bwd_kernel<true><<<grid, block, 0, s>>>(
-          dc[c], th, (int)n, c, (const uint2*)tile_ranges, order, sorted_ids,
-          (const float4*)proj->record, proj->rgb, rgb, T_final, n_contrib, d_rgb, d_T, acc, acc_rgb);
-    else
-      render_bwd_kernel<false><<<grid, block, 0, s>>>(
-          dc[c], th, (int)n, c, (const uint2*)tile_ranges, order, sorted_ids,
-          (const float4*)proj->record, proj->rgb, rgb, T_final, n_contrib, d_rgb, d_T, acc, acc_rgb);
+#define GUT_RBW(RS, GEN)                                                                          \
+  render_bwd_kernel<RS, GEN><<<grid, block, 0, s>>>(                                               \
+      dc[c], th, (int)n, c, (const uint2*)tile_ranges, order, sorted_ids, (const float4*)proj->record, \
+      proj->rgb, rgb, T_final, n_contrib, d_rgb, d_T, acc, acc_rgb)
+    const bool gen = th.kdeg != 2;
+    if (dc[c].shutter == GUT_ROLLING_TOP_TO_BOTTOM) { if (gen) GUT_RBW(true, true); else GUT_RBW(true, false); }
+    else { if (gen) GUT_RBW(false, true); else GUT_RBW(false, false); }
+#undef GUT_RBW
     GUT_LAUNCH_CHECK();
   }
   dim3 g1((unsigned)((n + 255) / 256)), b1(256);

@@ -159,13 +159,16 @@ __device__ inline bool ellipse_meets_box(double qmin, double N11, double N12, do
 }
 
 // Forms a pair's slots (FP64 -> FP32) and returns one bit per wave of the
-// block: bit k set when wave k's pixel box may see alpha >= alpha_min.
-template <bool RS, bool BWD>
+// block: bit k set when wave k's pixel box may see alpha >= alpha_min.  GEN:
+// the response has degree th.kdeg > 2, and the threshold kept in Kp is the
+// one on omega'^2 where the degree-n exponent reaches log2(sigma / alpha_min).
+template <bool RS, bool BWD, bool GEN>
 __device__ inline unsigned pair_setup(const float4* __restrict__ record,
                                       const float* __restrict__ rgb, long long e, int i,
                                       const TileFrameD& F, const DevCam& cam, float umax,
-                                      float vmax, float dtmax, float amin, float log2_amin,
-                                      const WaveBoxes& wb, int nwaves, float4* out) {
+                                      float vmax, float dtmax, const Thresholds& th,
+                                      float log2_amin, const WaveBoxes& wb, int nwaves, float4* out) {
+  const float amin = th.alpha_min;
   float4 r0 = record[4 * (long long)i], r1 = record[4 * (long long)i + 1];
   float4 r2 = record[4 * (long long)i + 2], r3 = record[4 * (long long)i + 3];
   const double M[9] = {r1.x, r1.y, r1.z, r2.x, r2.y, r2.z, r3.x, r3.y, r3.z};
@@ -196,7 +199,9 @@ __device__ inline unsigned pair_setup(const float4* __restrict__ record,
     mixed = true;  // decide per pixel
   }
   const float lsig = log2f(sigma);
-  const float Kp = (!never && sigma >= amin) ? lsig - log2_amin : -1.0f;
+  float Kp = (!never && sigma >= amin) ? lsig - log2_amin : -1.0f;
+  // degree n: 2^(k_h log2 q + k_l) <= Kp  <=>  q <= 2^((log2 Kp - k_l) / k_h)
+  if (GEN && Kp > 0.0f) Kp = exp2f((log2f(Kp) - th.k_l) * th.k_inv_h);
   unsigned flags = 0;
   if (Kp >= 0.0f) {
     // the per-pixel test uses this FP32 Kp; cull with it in natural units
@@ -268,6 +273,7 @@ __device__ inline unsigned pair_setup(const float4* __restrict__ record,
 
 struct Eval {
   float a;       // alpha after the alpha_max clamp (0 when the pair is skipped)
+  float lq;      // degree-n responses: log2 of omega'^2
   bool ok;       // tau_max > 0 and omega^2 <= K (alpha >= alpha_min)
   bool clamped;  // sigma rho > alpha_max
   float cc;      // omega'^2 |d_g|^2 (omega'^2 = omega^2 log2(e) / 2)
@@ -340,11 +346,19 @@ __device__ __forceinline__ void eval_test(const PairRegs<RS>& r, const float4* P
 }
 
 // Stage 2 (only for waves where some pixel passed): alpha = min(sigma rho, alpha_max)
-// with sigma rho = 2^(lsig - omega'^2).
-template <bool RS>
-__device__ __forceinline__ void eval_alpha(const PairRegs<RS>& r, float amax, Eval* o) {
+// with sigma rho = 2^(lsig - omega'^2), or for a degree-n response (GEN)
+// 2^(lsig - x), x = 2^(k_h log2 omega'^2 + k_l).
+template <bool RS, bool GEN>
+__device__ __forceinline__ void eval_alpha(const PairRegs<RS>& r, const Thresholds& th, Eval* o) {
+  const float amax = th.alpha_max;
   const float idd = __builtin_amdgcn_rcpf(o->dd);
-  const float araw = __builtin_amdgcn_exp2f(fmaf(-o->cc, idd, r.lsig));
+  float araw;
+  if (GEN) {
+    o->lq = __builtin_amdgcn_logf(o->cc * idd);  // log2; -inf at the centre line
+    araw = __builtin_amdgcn_exp2f(r.lsig - __builtin_amdgcn_exp2f(fmaf(th.k_h, o->lq, th.k_l)));
+  } else {
+    araw = __builtin_amdgcn_exp2f(fmaf(-o->cc, idd, r.lsig));
+  }
   o->idd = idd;
   o->araw = araw;
   o->clamped = araw > amax;

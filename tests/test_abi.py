@@ -34,6 +34,7 @@ def test_default_params_and_helpers():
     assert p.ut_alpha == 1.0 and p.ut_beta == 2.0 and p.ut_kappa == 0.0
     assert p.alpha_min == np.float32(1 / 255) and p.alpha_max == np.float32(0.99)
     assert p.t_min == np.float32(1e-4) and p.tile == 16 and p.rs_iters == 3
+    assert p.kernel_degree == 2
     cams = G.config2_cameras()
     arr = L.camera_array(cams)
     assert lib.gut_num_tiles(arr, 2, L.ref(p)) == 2 * 120 * 68
@@ -83,6 +84,10 @@ def test_argument_validation_without_launch():
     assert lib.gut_project(L.ref(sc), arr, 1, L.ref(p3), L.ref(out), None) == L.GUT_E_INVALID
     p4 = L.params_struct(dict(ut_alpha=0.0))
     assert lib.gut_project(L.ref(sc), arr, 1, L.ref(p4), L.ref(out), None) == L.GUT_E_INVALID
+    for deg in (0, 1, 9):
+        p5 = L.params_struct(dict(kernel_degree=deg))
+        assert lib.gut_project(L.ref(sc), arr, 1, L.ref(p5), L.ref(out), None) == L.GUT_E_INVALID
+        assert "kernel_degree" in lib.gut_last_error().decode()
     # too many cameras, bad scene
     assert lib.gut_project(L.ref(sc), arr, 0, L.ref(p), L.ref(out), None) == L.GUT_E_INVALID
     sc.sh_degree = 4

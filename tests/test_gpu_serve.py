@@ -90,3 +90,20 @@ def test_serve_admission_and_growth():
         assert torch.equal(out[0], alone[0])
         st = srv.stats()
         assert st["rejected"] == 0 and st["completed"] == 1
+
+
+def test_serve_generalized_degree_equals_alone():
+    """The server's batched kernels with a degree-4 response (Supp. A): each
+    request bitwise equal to rendering it alone with the same parameters."""
+    say("[serve degree 4 vs alone]")
+    scene = G.clustered_scene(30000, seed=1003)
+    gs = R.GaussianScene.from_host(scene)
+    reqs = small_requests(6, seed=3006)
+    params = dict(kernel_degree=4)
+    with Server(gs, params, mem_budget_bytes=1 << 30, max_slots=2, max_batch_cams=8) as srv:
+        ids = [srv.submit(cams)[0] for cams in reqs]
+        outs = {rid: srv.wait(rid) for rid in ids}
+        for rid, cams in zip(ids, reqs):
+            alone = render_sequential(gs, cams, params)
+            for a, b in zip(outs[rid], alone):
+                assert torch.equal(a, b)
