@@ -103,6 +103,9 @@ def _declare(L):
     L.ora_sh_basis_grad.argtypes = [C.c_int, vp, vp]
     L.ora_particle_alpha.argtypes = [vp, vp, vp, d, vp, vp, i32, vp, vp, vp]
     L.ora_particle_alpha.restype = C.c_int
+    L.ora_project_samples.argtypes = [vp, vp, C.c_int, i64, vp, vp, vp]
+    L.ora_ewa.argtypes = [vp, vp, d, vp, vp, vp, d, vp, vp]
+    L.ora_ewa.restype = C.c_int
     L.ora_project.argtypes = [vp, vp, vp, vp]
     L.ora_bin.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
     L.ora_bin.restype = i64
@@ -301,6 +304,29 @@ def particle_alpha(mu, quat, scale, opacity, o, d, kernel_degree=2):
     ok = lib().ora_particle_alpha(_p(mu), _p(quat), _p(scale), float(opacity), _p(o), _p(d),
                                   int(kernel_degree), C.byref(tau), C.byref(om2), C.byref(a))
     return bool(ok), tau.value, om2.value, a.value
+
+
+def project_samples(cam, x, iters=20, params=None):
+    """World points x[m,3] through the camera as sigma points (Supp. C's
+    Monte-Carlo reference); returns (v[m,2], ok[m])."""
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+    v = np.zeros((x.shape[0], 2))
+    ok = np.zeros(x.shape[0], np.int32)
+    cs = camera_struct(cam)
+    ps = _params(params or default_params())
+    lib().ora_project_samples(C.byref(cs), C.byref(ps), int(iters), x.shape[0], _p(x), _p(v), _p(ok))
+    return v, ok.astype(bool)
+
+
+def ewa(cam, mu, quat, scale, t=0.0, h=1e-6, params=None):
+    """EWA projection (Eq. 3) at exposure time t: (ok, mean[2], cov[2,2])."""
+    mu, quat, scale = (np.ascontiguousarray(a, np.float64) for a in (mu, quat, scale))
+    m, c = np.zeros(2), np.zeros(3)
+    cs = camera_struct(cam)
+    ps = _params(params or default_params())
+    ok = lib().ora_ewa(C.byref(cs), C.byref(ps), float(t), _p(mu), _p(quat), _p(scale), float(h),
+                       _p(m), _p(c))
+    return bool(ok), m, np.array([[c[0], c[1]], [c[1], c[2]]])
 
 
 # ----------------------------------------------------------------------------

@@ -231,6 +231,69 @@ int ora_solve_time(const ora_camera* c, const ora_params* p, int iters, const do
   return solve_time_ctx(&X, p, iters, x, t_out, v, margin);
 }
 
+/* Monte-Carlo reference projection (Supp. C, Gaussian projection quality):
+ * each world point goes through the camera as a sigma point does, with its
+ * rolling-shutter exposure time solved by `iters` fixed-point iterations. */
+void ora_project_samples(const ora_camera* c, const ora_params* p, int iters, int64_t m,
+                         const double* x, double* v, int32_t* ok) {
+  camctx X;
+  camctx_init(&X, c);
+  for (int64_t j = 0; j < m; j++) {
+    double t, margin;
+    ok[j] = solve_time_ctx(&X, p, iters, &x[3 * j], &t, &v[2 * j], &margin);
+  }
+}
+
+/* EWA projection (Eq. 3): the mean projected at exposure time t, and the
+ * covariance J Sigma J^T with J the Jacobian of the camera's projection of a
+ * world point at that fixed time (the first-order Taylor term, here taken by
+ * central differences of step h in each world axis, so it includes the lens
+ * distortion but not the rolling shutter).  Returns 0 if any projection is
+ * invalid. */
+int ora_ewa(const ora_camera* c, const ora_params* p, double t, const double mu[3],
+            const double quat[4], const double scale[3], double h, double mean2d[2],
+            double cov2d[3]) {
+  camctx X;
+  camctx_init(&X, c);
+  double margin, J[2][3];
+  if (!project_ctx(&X, p, t, mu, mean2d, &margin)) return 0;
+  for (int k = 0; k < 3; k++) {
+    double xp[3] = {mu[0], mu[1], mu[2]}, xm[3] = {mu[0], mu[1], mu[2]}, vp[2], vm[2];
+    xp[k] += h;
+    xm[k] -= h;
+    if (!project_ctx(&X, p, t, xp, vp, &margin) || !project_ctx(&X, p, t, xm, vm, &margin)) return 0;
+    J[0][k] = (vp[0] - vm[0]) / (2 * h);
+    J[1][k] = (vp[1] - vm[1]) / (2 * h);
+  }
+  /* Sigma = R diag(s^2) R^T (Eq. 2) */
+  double R[9], S[9];
+  ora_quat_to_rot(quat, R);
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) {
+      double acc = 0;
+      for (int k = 0; k < 3; k++) acc += R[3 * a + k] * scale[k] * scale[k] * R[3 * b + k];
+      S[3 * a + b] = acc;
+    }
+  double JS[2][3];
+  for (int r = 0; r < 2; r++)
+    for (int b = 0; b < 3; b++) {
+      double acc = 0;
+      for (int k = 0; k < 3; k++) acc += J[r][k] * S[3 * k + b];
+      JS[r][b] = acc;
+    }
+  double C[2][2];
+  for (int r = 0; r < 2; r++)
+    for (int q = 0; q < 2; q++) {
+      double acc = 0;
+      for (int k = 0; k < 3; k++) acc += JS[r][k] * J[q][k];
+      C[r][q] = acc;
+    }
+  cov2d[0] = C[0][0];
+  cov2d[1] = C[0][1];
+  cov2d[2] = C[1][1];
+  return 1;
+}
+
 /* Ray through pixel-centre coordinates (u, v): origin and direction in world
  * space.  Rolling shutter: the pose of row floor(v) at t = row/(H-1).
  * Fisheye: theta from theta_d by bisection on [0, theta_lim]; pixels outside

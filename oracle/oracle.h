@@ -118,6 +118,17 @@ int ora_project_point(const ora_camera* c, const ora_params* p, double t, const 
 /* Solve the rolling-shutter exposure time of a point (Sec. 4.1, reading R7). */
 int ora_solve_time(const ora_camera* c, const ora_params* p, int iters, const double x[3],
                    double* t, double v[2], double* margin);
+/* Monte-Carlo reference projection (Supp. C): m world points x[m,3] through
+ * the camera, each with its rolling-shutter time solved by `iters`
+ * iterations; v[m,2] pixel positions, ok[m] validity. */
+void ora_project_samples(const ora_camera* c, const ora_params* p, int iters, int64_t m,
+                         const double* x, double* v, int32_t* ok);
+/* EWA projection (Eq. 3) at exposure time t: mean and covariance J Sigma J^T
+ * with J the camera's Jacobian at mu by central differences of step h.
+ * Returns 0 if a projection is invalid. */
+int ora_ewa(const ora_camera* c, const ora_params* p, double t, const double mu[3],
+            const double quat[4], const double scale[3], double h, double mean2d[2],
+            double cov2d[3]);
 /* Ray of pixel centre (u, v) (row from v): returns 1 if valid. */
 int ora_pixel_ray(const ora_camera* c, double u, double v, double o[3], double d[3],
                   double* margin);
