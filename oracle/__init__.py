@@ -77,7 +77,7 @@ class ProjS(C.Structure):
 
 class Amb(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("alpha", "trans", "tau", "depth", "edge", "valid",
-                                          "pixel", "diff")]
+                                          "pixel", "diff", "clip")]
 
 
 class ImageS(C.Structure):
@@ -109,9 +109,9 @@ def _declare(L):
     L.ora_project.argtypes = [vp, vp, vp, vp]
     L.ora_bin.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
     L.ora_bin.restype = i64
-    L.ora_render.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, vp]
-    L.ora_backward.argtypes = [vp] * 9 + [vp] * 5
-    L.ora_record.argtypes = [vp] * 10
+    L.ora_render.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp]
+    L.ora_backward.argtypes = [vp] * 10 + [vp] * 5
+    L.ora_record.argtypes = [vp] * 11
     L.ora_record.restype = i64
     L.ora_loss_frozen.argtypes = [vp] * 9
     L.ora_loss_frozen.restype = d
@@ -143,7 +143,7 @@ def default_params(**kw) -> dict:
 
 def default_amb(**kw) -> dict:
     a = dict(alpha=1e-6, trans=1e-4, tau=1e-5, depth=1e-6, edge=2e-3, valid=1e-5, pixel=1e-9,
-             diff=1e-6)
+             diff=1e-6, clip=1e-5)
     a.update(kw)
     return a
 
@@ -372,11 +372,20 @@ def bin_tiles(proj: Projection, cam, params=None, amb=None):
     return ts, ids[:total], fl[:total]
 
 
+def _clip(clip, cam):
+    if clip is None:
+        return None
+    c = np.ascontiguousarray(clip, np.float64).reshape(-1)
+    assert c.size == cam["width"] * cam["height"]
+    return c
+
+
 def render(scene, proj, cam, bins, params=None, amb=None, tiles=None, brute_force=False,
-           alternatives=True):
+           alternatives=True, clip=None):
     """Render the listed tiles (default: all).  Returns a dict of per-pixel
     arrays laid out [n_tiles, tile, tile, ...]; ``to_image`` reassembles a
-    full render."""
+    full render.  clip: [H, W] hybrid-rendering clip distances (Sec. 6.2)."""
+    clip = _clip(clip, cam)
     sc = as_oscene(scene)
     p = params or default_params()
     a = _amb(amb or default_amb())
@@ -399,7 +408,7 @@ def render(scene, proj, cam, bins, params=None, amb=None, tiles=None, brute_forc
                                                      np.zeros(1, np.int32))
     ss, cs, ps, prs = sc.struct(), camera_struct(cam), _params(p), proj.struct()
     lib().ora_render(_ref(ss), _ref(prs), _ref(cs), _ref(ps), _ref(a), _p(tstart), _p(ids),
-                     _p(fl), _p(tiles), len(tiles), int(bool(brute_force)), _ref(img))
+                     _p(fl), _p(tiles), len(tiles), int(bool(brute_force)), _p(clip), _ref(img))
     out["tiles"] = tiles
     return out
 
@@ -416,7 +425,8 @@ def to_image(res, cam, params=None, key="rgb"):
     return a[: cam["height"], : cam["width"]]
 
 
-def backward(scene, proj, cam, bins, dL_drgb, dL_dT=None, params=None):
+def backward(scene, proj, cam, bins, dL_drgb, dL_dT=None, params=None, clip=None):
+    clip = _clip(clip, cam)
     sc = as_oscene(scene)
     p = params or default_params()
     n, K = sc.n, (sc.sh_degree + 1) ** 2
@@ -427,12 +437,13 @@ def backward(scene, proj, cam, bins, dL_drgb, dL_dT=None, params=None):
     tstart, ids, fl = bins
     ss, cs, ps, prs = sc.struct(), camera_struct(cam), _params(p), proj.struct()
     lib().ora_backward(_ref(ss), _ref(prs), _ref(cs), _ref(ps), _p(tstart), _p(ids), _p(fl),
-                       _p(dC), _p(dT), _p(g["means"]), _p(g["scales"]), _p(g["quats"]),
+                       _p(clip), _p(dC), _p(dT), _p(g["means"]), _p(g["scales"]), _p(g["quats"]),
                        _p(g["opacities"]), _p(g["sh"]))
     return g
 
 
-def record(scene, proj, cam, bins, params=None):
+def record(scene, proj, cam, bins, params=None, clip=None):
+    clip = _clip(clip, cam)
     sc = as_oscene(scene)
     p = params or default_params()
     tstart, ids, fl = bins
@@ -440,11 +451,11 @@ def record(scene, proj, cam, bins, params=None):
     npx = cam["width"] * cam["height"]
     pix_start = np.zeros(npx + 1, np.int64)
     total = lib().ora_record(_ref(ss), _ref(prs), _ref(cs), _ref(ps), _p(tstart), _p(ids), _p(fl),
-                             _p(pix_start), None, None)
+                             _p(clip), _p(pix_start), None, None)
     contrib = np.zeros(max(total, 1), np.int32)
     clamped = np.zeros(max(total, 1), np.int32)
     lib().ora_record(_ref(ss), _ref(prs), _ref(cs), _ref(ps), _p(tstart), _p(ids), _p(fl),
-                     _p(pix_start), _p(contrib), _p(clamped))
+                     _p(clip), _p(pix_start), _p(contrib), _p(clamped))
     return pix_start, contrib, clamped
 
 

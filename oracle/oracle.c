@@ -741,7 +741,7 @@ int ora_particle_alpha(const double mu[3], const double quat[4], const double sc
 /* Render: front-to-back Eq. 5 over the tile list, response at tau_max        */
 /* ------------------------------------------------------------------------- */
 
-enum { PT_NONE = 0, PT_TOGGLE, PT_ALPHA, PT_STOP, PT_TAU, PT_SWAP };
+enum { PT_NONE = 0, PT_TOGGLE, PT_ALPHA, PT_STOP, PT_TAU, PT_SWAP, PT_CLIP };
 typedef struct { int type; int64_t pos; } perturb;
 typedef struct { double rgb[3], T; int nc, ne; } pix_result;
 
@@ -755,9 +755,17 @@ typedef struct {
 
 #define MAXCAND 64
 
+/* Hybrid rendering (Sec. 6.2): the rasterizer discards a hit whose
+ * maximum-response point tau_max lies beyond the ray's closest surface
+ * intersection, clipv (distance along the ray from its origin; INFINITY:
+ * none). */
+static double hit_distance(double odot, const double dg[3], const double d[3]) {
+  return -odot / dot3(dg, dg) * sqrt(dot3(d, d));
+}
+
 static void render_pixel(const render_ctx* X, const int32_t* ids, const int32_t* flags, int64_t L,
-                         const double o[3], const double d[3], perturb pt, pix_result* res,
-                         perturb* cand, int* ncand) {
+                         const double o[3], const double d[3], double clipv, perturb pt,
+                         pix_result* res, perturb* cand, int* ncand) {
   const ora_params* p = X->p;
   double T = 1.0, C[3] = {0, 0, 0};
   int member_pos = 0, nc = 0, ne = -1;
@@ -783,6 +791,14 @@ static void render_pixel(const render_ctx* X, const int32_t* ids, const int32_t*
     int skip = odot >= 0; /* tau_max <= 0: the maximum lies behind the origin (reading R15) */
     if (pt.type == PT_TAU && pt.pos == q) skip = !skip;
     if (skip) continue;
+    if (isfinite(clipv)) {
+      const double dist = hit_distance(odot, dg, d);
+      if (cand && *ncand < MAXCAND && fabs(dist - clipv) <= X->amb->clip * clipv)
+        cand[(*ncand)++] = (perturb){PT_CLIP, q};
+      int behind = dist > clipv;
+      if (pt.type == PT_CLIP && pt.pos == q) behind = !behind;
+      if (behind) continue;
+    }
     double a = g->sigma * response(p, om2);
     if (a > p->alpha_max) a = p->alpha_max;
     if (cand && *ncand < MAXCAND && fabs(a - p->alpha_min) < X->amb->alpha)
@@ -821,7 +837,7 @@ static int cmp_depth_id(const void* a, const void* b) { return cmp_entry(a, b); 
 int ora_render(const ora_scene* s, const ora_proj* pr, const ora_camera* c, const ora_params* p,
                const ora_amb* amb, const int64_t* tile_start, const int32_t* ids,
                const int32_t* flags, const int32_t* tile_list, int32_t n_tiles,
-               int32_t brute_force, ora_image* out) {
+               int32_t brute_force, const double* clip, ora_image* out) {
   const int tx = tiles_x(c, p), ts = p->tile;
   particle_geo* geo = build_geo(s, pr);
   render_ctx X = {s, pr, p, geo, amb};
@@ -855,9 +871,12 @@ int ora_render(const ora_scene* s, const ora_proj* pr, const ora_camera* c, cons
         int ncand = 0, nalt = 0;
         int inside = px < c->width && py < c->height;
         double o[3], d[3], pm = INFINITY;
+        const double clipv = clip && px < c->width && py < c->height ? clip[(int64_t)py * c->width + px]
+                                                                     : INFINITY;
         if (inside) {
           inside = pixel_ray_ctx(&CX, px + 0.5, py + 0.5, o, d, &pm);
-          if (inside) render_pixel(&X, lid, lfl, L, o, d, (perturb){PT_NONE, 0}, &r, cand, &ncand);
+          if (inside)
+            render_pixel(&X, lid, lfl, L, o, d, clipv, (perturb){PT_NONE, 0}, &r, cand, &ncand);
         }
         out->inside[pix] = inside;
         for (int ch = 0; ch < 3; ch++) out->rgb[3 * pix + ch] = r.rgb[ch];
@@ -870,7 +889,7 @@ int ora_render(const ora_scene* s, const ora_proj* pr, const ora_camera* c, cons
         if (px < c->width && py < c->height && fabs(pm) < amb->pixel) {
           namb++;
           pix_result a = {{p->bg[0], p->bg[1], p->bg[2]}, 1.0, 0, 0};
-          if (!inside) render_pixel(&X, lid, lfl, L, o, d, (perturb){PT_NONE, 0}, &a, NULL, NULL);
+          if (!inside) render_pixel(&X, lid, lfl, L, o, d, clipv, (perturb){PT_NONE, 0}, &a, NULL, NULL);
           int64_t k = pix * ORA_MAXALT + nalt;
           for (int ch = 0; ch < 3; ch++) out->alt_rgb[3 * k + ch] = a.rgb[ch];
           out->alt_T[k] = a.T; out->alt_nc[k] = a.nc; out->alt_ne[k] = a.ne;
@@ -878,7 +897,7 @@ int ora_render(const ora_scene* s, const ora_proj* pr, const ora_camera* c, cons
         }
         for (int q = 0; q < ncand && inside; q++) {
           pix_result a;
-          render_pixel(&X, lid, lfl, L, o, d, cand[q], &a, NULL, NULL);
+          render_pixel(&X, lid, lfl, L, o, d, clipv, cand[q], &a, NULL, NULL);
           double diff = fabs(a.T - r.T);
           for (int ch = 0; ch < 3; ch++) diff = fmax(diff, fabs(a.rgb[ch] - r.rgb[ch]));
           int same_int = a.nc == r.nc && a.ne == r.ne;
@@ -959,8 +978,8 @@ static void finish_particle(const ora_scene* s, const ora_proj* pr, const camctx
 
 int ora_backward(const ora_scene* s, const ora_proj* pr, const ora_camera* c, const ora_params* p,
                  const int64_t* tile_start, const int32_t* ids, const int32_t* flags,
-                 const double* dL_drgb, const double* dL_dT, double* g_means, double* g_scales,
-                 double* g_quats, double* g_opac, double* g_sh) {
+                 const double* clip, const double* dL_drgb, const double* dL_dT, double* g_means,
+                 double* g_scales, double* g_quats, double* g_opac, double* g_sh) {
   const int tx = tiles_x(c, p), ty = tiles_y(c, p), ts = p->tile;
   const int K = (s->sh_degree + 1) * (s->sh_degree + 1);
   const int64_t n = s->n;
@@ -1005,6 +1024,7 @@ int ora_backward(const ora_scene* s, const ora_proj* pr, const ora_camera* c, co
             double og[3], dg[3], odot, om2;
             eval_geo(g, o, d, og, dg, &odot, &om2);
             if (odot >= 0) continue;
+            if (clip && hit_distance(odot, dg, d) > clip[pix]) continue;
             double a = g->sigma * response(p, om2);
             int clamped = a > p->alpha_max;
             if (clamped) a = p->alpha_max;
@@ -1080,7 +1100,7 @@ int ora_backward(const ora_scene* s, const ora_proj* pr, const ora_camera* c, co
 
 int64_t ora_record(const ora_scene* s, const ora_proj* pr, const ora_camera* c, const ora_params* p,
                    const int64_t* tile_start, const int32_t* ids, const int32_t* flags,
-                   int64_t* pix_start, int32_t* contrib, int32_t* clamped) {
+                   const double* clip, int64_t* pix_start, int32_t* contrib, int32_t* clamped) {
   const int tx = tiles_x(c, p), ts = p->tile;
   particle_geo* geo = build_geo(s, pr);
   camctx CX;
@@ -1100,6 +1120,7 @@ int64_t ora_record(const ora_scene* s, const ora_proj* pr, const ora_camera* c, 
       double og[3], dg[3], odot, om2;
       eval_geo(g, o, d, og, dg, &odot, &om2);
       if (odot >= 0) continue;
+      if (clip && hit_distance(odot, dg, d) > clip[pix]) continue;
       double a = g->sigma * response(p, om2);
       int cl = a > p->alpha_max;
       if (cl) a = p->alpha_max;

@@ -83,6 +83,7 @@ typedef struct {
   double valid;  /* validity margin of a sigma point          */
   double pixel;  /* fisheye image-circle margin (radians)     */
   double diff;   /* an alternative is kept only if it differs by more than this */
+  double clip;   /* |hit distance - clip distance| (relative) */
 } ora_amb;
 
 #define ORA_MAXALT 8
@@ -151,18 +152,22 @@ int64_t ora_bin(int64_t n, const ora_proj* pr, const ora_camera* c, const ora_pa
 int ora_render(const ora_scene* s, const ora_proj* pr, const ora_camera* c,
                const ora_params* p, const ora_amb* amb, const int64_t* tile_start,
                const int32_t* ids, const int32_t* flags, const int32_t* tile_list,
-               int32_t n_tiles, int32_t brute_force, ora_image* out);
+               int32_t n_tiles, int32_t brute_force,
+               const double* clip /* [H*W] nullable: hybrid-rendering clip distances, Sec. 6.2 */,
+               ora_image* out);
 /* Backward (Supp. B): gradients w.r.t. the activated parameters. */
 int ora_backward(const ora_scene* s, const ora_proj* pr, const ora_camera* c,
                  const ora_params* p, const int64_t* tile_start, const int32_t* ids,
-                 const int32_t* flags, const double* dL_drgb /* [H,W,3] */,
+                 const int32_t* flags, const double* clip /* [H*W] nullable */,
+                 const double* dL_drgb /* [H,W,3] */,
                  const double* dL_dT /* [H,W] nullable */, double* g_means, double* g_scales,
                  double* g_quats, double* g_opac, double* g_sh);
 /* Frozen-decision loss for finite differences: record contributors once,
  * then evaluate L = sum wC*C + wT*T with every discrete decision held. */
 int64_t ora_record(const ora_scene* s, const ora_proj* pr, const ora_camera* c,
                    const ora_params* p, const int64_t* tile_start, const int32_t* ids,
-                   const int32_t* flags, int64_t* pix_start /* [H*W+1] */,
+                   const int32_t* flags, const double* clip /* [H*W] nullable */,
+                   int64_t* pix_start /* [H*W+1] */,
                    int32_t* contrib /* nullable for count */, int32_t* clamped);
 double ora_loss_frozen(const ora_scene* s, const ora_proj* pr, const ora_camera* c,
                        const ora_params* p, const int64_t* pix_start, const int32_t* contrib,

@@ -54,21 +54,21 @@ def test_dalpha_dmu_closed_form():
     assert checked >= 10
 
 
-def _fd_check(scene, cam, seed, h=1e-6, bg=(0.0, 0.0, 0.0), use_dT=True, kernel_degree=2):
+def _fd_check(scene, cam, seed, h=1e-6, bg=(0.0, 0.0, 0.0), use_dT=True, kernel_degree=2, clip=None):
     p = O.default_params(bg=bg, kernel_degree=kernel_degree)
     sc = O.as_oscene(scene)
     pr = O.project(sc, cam, p)
     bins = O.bin_tiles(pr, cam, p)
-    rec = O.record(sc, pr, cam, bins, p)
+    rec = O.record(sc, pr, cam, bins, p, clip=clip)
     rng = np.random.default_rng(seed)
     H, W = cam["height"], cam["width"]
     wC = rng.normal(size=(H, W, 3))
     wT = rng.normal(size=(H, W)) if use_dT else None
-    g = O.backward(sc, pr, cam, bins, wC, wT, p)
+    g = O.backward(sc, pr, cam, bins, wC, wT, p, clip=clip)
     assert len(rec[1]) > 50  # the check must exercise compositing
     L0 = O.loss_frozen(sc, pr, cam, rec, wC, wT, p)
     # the analytic render must agree with the frozen loss at theta_0
-    res = O.render(sc, pr, cam, bins, p, alternatives=False)
+    res = O.render(sc, pr, cam, bins, p, alternatives=False, clip=clip)
     img, T = O.to_image(res, cam), O.to_image(res, cam, key="T")
     L_render = (wC * img).sum() + ((wT * T).sum() if use_dT else 0.0)
     assert abs(L_render - L0) < 1e-10 * max(1, abs(L0))
@@ -119,3 +119,16 @@ def test_backward_central_differences_generalized_kernel(kind, n):
     worst = _fd_check(scene, cam, seed=3024 + n, bg=(0.1, 0.3, 0.6), kernel_degree=n)
     for k, v in worst.items():
         assert v < 1e-6, (kind, n, k, v)
+
+
+@pytest.mark.parametrize("kind", ["pinhole", "rolling"])
+def test_backward_central_differences_with_depth_clip(kind):
+    """A per-pixel clip distance (Sec. 6.2's hybrid rendering) inside the
+    particles' depth range: the clipped contributors get their gradients, the
+    clipped-away ones none, consistently with the frozen clipped loss."""
+    scene, cam = G.config4_gradcheck(kind, log_scale_mean=-2.2)
+    rng = np.random.default_rng(3030)
+    clip = rng.uniform(2.6, 3.4, size=(cam["height"], cam["width"]))
+    worst = _fd_check(scene, cam, seed=3031, bg=(0.1, 0.3, 0.6), clip=clip)
+    for k, v in worst.items():
+        assert v < 1e-6, (kind, k, v)

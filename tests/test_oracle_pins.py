@@ -428,6 +428,65 @@ def test_generalized_single_particle_closed_form_and_extent(n):
 
 
 # ---------------------------------------------------------------------------
+# Hybrid-rendering depth clip (Sec. 6.2)
+# ---------------------------------------------------------------------------
+
+def test_clip_at_infinity_changes_nothing():
+    sc, cams = G.config1()
+    cam = cams[0]
+    pr, b, res = O.render_full(sc, cam)
+    clip = np.full((cam["height"], cam["width"]), np.inf)
+    res2 = O.render(sc, pr, cam, b, clip=clip)
+    for k in ("rgb", "T", "n_contrib", "n_eval"):
+        np.testing.assert_array_equal(res[k], res2[k])
+
+
+@pytest.mark.parametrize("clipd,which", [(3.0, "none"), (4.6, "front"), (20.0, "both")])
+def test_clip_two_particles_closed_form(clipd, which):
+    """Two isotropic particles in front of each other: a clip distance before
+    both, between them, or past both keeps no hit, the front one, or both.
+    Each hit's distance is the centre's projection on the ray and its alpha
+    sigma exp(-d_perp^2 / 2 s^2) (vector geometry)."""
+    cam = G.camera("pinhole", 32, 32, 40.0, R0=np.eye(3), t0=np.array([0.0, 0.0, 4.0]))
+    mus = np.array([[0.02, -0.01, 0.0], [-0.03, 0.02, 1.2]])
+    s = np.array([0.15, 0.2])
+    sig = np.array([0.6, 0.8])
+    cols = np.array([[0.9, 0.2, 0.1], [0.1, 0.3, 0.95]])
+    sh = ((cols - 0.5) / G.SH_C0)[:, None, :]
+    sc = O.OScene(mus, np.repeat(s[:, None], 3, 1), np.array([[1.0, 0, 0, 0], [0.6, 0.2, -0.3, 0.7]]),
+                  sig, sh, 0)
+    p = O.default_params()
+    pr = O.project(sc, cam, p)
+    b = O.bin_tiles(pr, cam, p)
+    clip = np.full((32, 32), clipd)
+    img = O.to_image(O.render(sc, pr, cam, b, p, clip=clip), cam, p)
+    o = np.array([0.0, 0.0, -4.0])
+    n_checked = 0
+    for py in range(8, 24, 2):
+        for px in range(8, 24, 2):
+            d = np.array([(px + 0.5 - 16) / 40.0, (py + 0.5 - 16) / 40.0, 1.0])
+            dh = d / np.linalg.norm(d)
+            expect, T = np.zeros(3), 1.0
+            for k in range(2):  # front to back (sorted depth order is 0, 1)
+                dist = (mus[k] - o) @ dh
+                a = sig[k] * math.exp(-np.linalg.norm(np.cross(mus[k] - o, dh)) ** 2 / (2 * s[k] ** 2))
+                if a < 1 / 255 or dist > clipd:
+                    continue
+                expect += T * a * cols[k]
+                T *= 1 - a
+            np.testing.assert_allclose(img[py, px], expect, atol=1e-12)
+            n_checked += 1
+    assert n_checked == 64
+    centre = img[16, 16]
+    if which == "none":
+        assert np.all(centre == 0)
+    elif which == "front":
+        assert centre[0] > centre[2]   # the red front particle alone
+    else:
+        assert centre[2] > 0.2          # the blue one behind shows through
+
+
+# ---------------------------------------------------------------------------
 # Compositing (Eq. 5)
 # ---------------------------------------------------------------------------
 
