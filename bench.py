@@ -28,6 +28,8 @@ Also reported on the same line:
                 rolling-shutter fisheye 1600x1200 view (context, not the metric)
   generalized_degrees  the same forward step with the generalized Gaussian
                 responses of degree 3, 4 and 8 (Supp. A), beside degree 2
+  depth_clip    the same forward step with a per-pixel clip distance
+                (hybrid rendering, Sec. 6.2)
   cpu_baseline  the FP64 oracle on this host's cores, timed on whole steps of
                 the same two-view batch (projection, binning, every tile)
                 until its time budget is spent
@@ -129,7 +131,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bench_forward(gs, cams, steps, warmup, R, torch, params=None):
+def bench_forward(gs, cams, steps, warmup, R, torch, params=None, clip=None):
     proj = R.alloc_projection(gs.n, len(cams), gs.means.device)
     R.project(gs, cams, params, out=proj)
     bins = R.bin_tiles(proj, cams, params)
@@ -143,7 +145,7 @@ def bench_forward(gs, cams, steps, warmup, R, torch, params=None):
         if e: e[1].record()
         R.bin_tiles(proj, cams, params, bins=bins)
         if e: e[2].record()
-        R.render(proj, bins, cams, params, out=img)
+        R.render(proj, bins, cams, params, out=img, clip=clip)
         if e: e[3].record()
 
     for _ in range(warmup):
@@ -161,7 +163,7 @@ def bench_forward(gs, cams, steps, warmup, R, torch, params=None):
     gc.enable()
     st = np.array([[ev[k][i].elapsed_time(ev[k][i + 1]) for i in range(n_ev - 1)] for k in range(steps)])
     # one extra, untimed render that counts evaluations per pixel
-    img_eval = R.render(proj, bins, cams, params, with_eval=True)
+    img_eval = R.render(proj, bins, cams, params, with_eval=True, clip=clip)
     torch.cuda.synchronize()
     e_eval = int(img_eval.n_eval.to(torch.int64).sum().item())
     return dict(ms_per_step=(t1 - t0) * 1e3 / steps, stage_ms=st.mean(0), stage_p10=np.percentile(st, 10, 0),
@@ -333,6 +335,8 @@ def main():
     ap.add_argument("--degrees", default="3,4,8",
                     help="generalized-Gaussian degrees (Supp. A) timed on the same forward step")
     ap.add_argument("--no-degrees", action="store_true")
+    ap.add_argument("--no-clip", action="store_true",
+                    help="skip the hybrid-rendering depth-clip timing (Sec. 6.2)")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the 3M-particle rolling-shutter fisheye stage timings")
     ap.add_argument("--serve-requests", type=int, default=120)
@@ -421,6 +425,20 @@ def main():
             del fd
         degrees["2"]["e_eval"] = fw["e_eval"]
 
+    # hybrid rendering (Sec. 6.2): the same step with a per-pixel clip
+    # distance, U[6, 10] (the clusters span distances 3..13 from the cameras)
+    depth_clip = None
+    if not args.no_clip:
+        log("[bench] forward steps with a per-pixel depth clip")
+        g = torch.Generator(device="cuda").manual_seed(4003)
+        clip = 6.0 + 4.0 * torch.rand(npx, device="cuda", generator=g)
+        fc = bench_forward(gs, cams, max(3, args.steps // 2), 2, R, torch, None, clip)
+        depth_clip = dict(mpix_per_s=npx / (fc["ms_per_step"] * 1e-3) / 1e6,
+                          stages_ms={"project": fc["stage_ms"][0], "bin": fc["stage_ms"][1],
+                                     "render": fc["stage_ms"][2]},
+                          e_eval=fc["e_eval"], clip="U[6, 10] per pixel")
+        del fc, clip
+
     fwd_bwd = None
     if not args.no_fwd_bwd:
         log("[bench] fwd+bwd on the fisheye view")
@@ -485,6 +503,7 @@ def main():
         "fwd_bwd_detail": fwd_bwd,
         "rolling_shutter_3m": c3,
         "generalized_degrees": degrees,
+        "depth_clip": depth_clip,
         "serving": serving,
         "cpu_baseline": cpu,
     }

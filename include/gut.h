@@ -168,6 +168,12 @@ gut_status gut_bin(const gut_projected* proj, int64_t n, const gut_camera* cams,
 
 /* Eq. 5 front to back over each tile list with alpha = sigma * rho at tau_max
  * (Eq. 11); stops before a particle that would take T below t_min.
+ *   clip_depth [P_px]  float   in, nullable: hybrid rendering (Sec. 6.2) --
+ *                             each pixel's distance along its ray (from the
+ *                             ray origin, world units) to the closest surface
+ *                             intersection; a particle whose maximum-response
+ *                             point lies farther is discarded for that pixel
+ *                             (+inf: no clip).  NULL: no clipping.
  *   rgb       [P_px,3] float   out: C + T * bg
  *   T_final   [P_px]   float   out: final transmittance
  *   n_contrib [P_px]   uint32  out: list position + 1 of the last contributor
@@ -175,15 +181,16 @@ gut_status gut_bin(const gut_projected* proj, int64_t n, const gut_camera* cams,
  * where P_px = gut_num_pixels(cams, n_cams). */
 gut_status gut_render(const gut_projected* proj, int64_t n, const uint32_t* tile_ranges,
                       const uint32_t* sorted_ids, const gut_camera* cams, int32_t n_cams,
-                      const gut_params* p, float* rgb, float* T_final, uint32_t* n_contrib,
-                      uint32_t* n_eval, void* stream);
+                      const gut_params* p, const float* clip_depth, float* rgb, float* T_final,
+                      uint32_t* n_contrib, uint32_t* n_eval, void* stream);
 
 /* Workspace for gut_render_bwd (bytes). */
 size_t gut_render_bwd_workspace_bytes(int64_t n, int32_t n_cams);
 
 /* Supp. B: gradients of a loss given dL/d(rgb) [P_px,3] and optionally
  * dL/d(T_final) [P_px] (nullable), recomputing the compositing front to back
- * from T_final and n_contrib.  Gradients are w.r.t. the activated parameters
+ * from T_final and n_contrib.  clip_depth must be the array (or NULL) the
+ * forward gut_render call used; the clip decision carries no gradient.  Gradients are w.r.t. the activated parameters
  * passed in `scene` and are OVERWRITTEN (summed over cameras):
  * g_means[n,3], g_scales[n,3], g_quats[n,4], g_opacities[n], g_sh[n,K,3].
  * No gradient flows through the sigma-point projection, the rectangles, the
@@ -191,7 +198,8 @@ size_t gut_render_bwd_workspace_bytes(int64_t n, int32_t n_cams);
 gut_status gut_render_bwd(const gut_scene* scene, const gut_projected* proj,
                           const uint32_t* tile_ranges, const uint32_t* sorted_ids,
                           const gut_camera* cams, int32_t n_cams, const gut_params* p,
-                          const float* rgb, const float* T_final, const uint32_t* n_contrib,
+                          const float* clip_depth, const float* rgb, const float* T_final,
+                          const uint32_t* n_contrib,
                           const float* d_rgb, const float* d_T, float* g_means, float* g_scales,
                           float* g_quats, float* g_opacities, float* g_sh, void* ws,
                           size_t ws_bytes, void* stream);

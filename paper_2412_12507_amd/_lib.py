@@ -97,11 +97,11 @@ def load():
     L.gut_bin_workspace_bytes.restype = sz
     L.gut_bin.argtypes = [vp, i64, vp, i32, vp, vp, sz, i64, vp, vp, vp, vp]
     L.gut_bin.restype = st
-    L.gut_render.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
+    L.gut_render.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.gut_render.restype = st
     L.gut_render_bwd_workspace_bytes.argtypes = [i64, i32]
     L.gut_render_bwd_workspace_bytes.restype = sz
-    L.gut_render_bwd.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+    L.gut_render_bwd.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                  vp, vp, vp, sz, vp]
     L.gut_render_bwd.restype = st
     serve_sigs = {

@@ -25,11 +25,14 @@ constexpr int kRBatch = kRThreads;
 
 // One tile of one camera.  pd, pf, F, wb and red are the block's LDS; out_*
 // are indexed by pix_base + y * W + x.  GEN: response of degree th.kdeg > 2.
-template <bool RS, bool NE, bool GEN>
+// CLIP: per-pixel clip distances (hybrid rendering, Sec. 6.2), indexed as
+// the outputs; hits beyond them are discarded.
+template <bool RS, bool NE, bool GEN, bool CLIP>
 __device__ __forceinline__ void render_tile(
     const DevCam& cam, const Thresholds& th, int n, int cam_idx, int tile,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
-    const float4* __restrict__ record, const float* __restrict__ rgb, float* __restrict__ out_rgb,
+    const float4* __restrict__ record, const float* __restrict__ rgb, const float* __restrict__ clip,
+    float* __restrict__ out_rgb,
     float* __restrict__ out_T, uint32_t* __restrict__ out_nc, uint32_t* __restrict__ out_ne,
     long long pix_base, float4* pd, uint32_t* pf, TileFrameD& F, WaveBoxes& wb, float* red) {
   constexpr int S = Slots<RS, false>::N;
@@ -54,6 +57,15 @@ __device__ __forceinline__ void render_tile(
   tile_bounds<2>(u, v, dt, active, red, &umax, &vmax, &dtmax);
   const float l2amin = log2f(th.alpha_min);
   wave_box<2>(u, v, active, &wb);
+  float clipv[2] = {0.f, 0.f}, dlen[2] = {1.f, 1.f};
+  if (CLIP) {
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      if (!active[k]) continue;
+      clipv[k] = clip[pix_base + (long long)(py0 + 4 * k) * cam.W + px];
+      dlen[k] = sqrtf(fmaf(u[k], u[k], fmaf(v[k], v[k], 1.0f)));
+    }
+  }
 
   const uint2 rg = ranges[cam.tile_base + tile];
   const uint32_t len = __builtin_amdgcn_readfirstlane(rg.y - rg.x);
@@ -95,7 +107,10 @@ __device__ __forceinline__ void render_tile(
         load_pair<RS>(P, r);
         Eval ev[2];
 #pragma unroll
-        for (int k = 0; k < 2; k++) eval_test<RS>(r, P, u[k], v[k], dt[k], &ev[k]);
+        for (int k = 0; k < 2; k++) {
+          eval_test<RS>(r, P, u[k], v[k], dt[k], &ev[k]);
+          if (CLIP) ev[k].ok = ev[k].ok && !behind_clip<RS>(r, P, u[k], v[k], dt[k], dlen[k], clipv[k], ev[k].dd);
+        }
         const bool live0 = ev[0].ok && !done0, live1 = ev[1].ok && !done1;
         if (!wave_any(live0 || live1)) continue;  // nothing reaches alpha_min here
         bool contrib[2];
@@ -145,11 +160,12 @@ __device__ __forceinline__ void render_tile(
 
 // One block per tile, taken in the render order (longest lists first).  NE:
 // also count each pixel's evaluated entries (out_ne non-null).
-template <bool RS, bool NE, bool GEN>
+template <bool RS, bool NE, bool GEN, bool CLIP>
 __global__ void __launch_bounds__(kRThreads, 4) render_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
-    const float4* __restrict__ record, const float* __restrict__ rgb, float* __restrict__ out_rgb,
+    const float4* __restrict__ record, const float* __restrict__ rgb, const float* __restrict__ clip,
+    float* __restrict__ out_rgb,
     float* __restrict__ out_T, uint32_t* __restrict__ out_nc, uint32_t* __restrict__ out_ne) {
   __shared__ float4 pd[kRBatch * Slots<RS, false>::N];
   __shared__ uint32_t pf[kRBatch];
@@ -157,8 +173,8 @@ __global__ void __launch_bounds__(kRThreads, 4) render_kernel(
   __shared__ WaveBoxes wb;
   __shared__ float red[6];
   const int tile = (int)order[cam.tile_base + blockIdx.x];
-  render_tile<RS, NE, GEN>(cam, th, n, cam_idx, tile, ranges, ids, record, rgb, out_rgb, out_T, out_nc,
-                           out_ne, cam.pixel_base, pd, pf, F, wb, red);
+  render_tile<RS, NE, GEN, CLIP>(cam, th, n, cam_idx, tile, ranges, ids, record, rgb, clip, out_rgb,
+                                 out_T, out_nc, out_ne, cam.pixel_base, pd, pf, F, wb, red);
 }
 
 // Several cameras of one shutter type and one tile count in one launch
@@ -173,11 +189,12 @@ struct MultiCams {
   int n;
 };
 
-template <bool RS, bool NE, bool GEN>
+template <bool RS, bool NE, bool GEN, bool CLIP>
 __global__ void __launch_bounds__(kRThreads, 4) render_multi_kernel(
     MultiCams mc, Thresholds th, int n, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
-    const float4* __restrict__ record, const float* __restrict__ rgb, float* __restrict__ out_rgb,
+    const float4* __restrict__ record, const float* __restrict__ rgb, const float* __restrict__ clip,
+    float* __restrict__ out_rgb,
     float* __restrict__ out_T, uint32_t* __restrict__ out_nc, uint32_t* __restrict__ out_ne) {
   __shared__ float4 pd[kRBatch * Slots<RS, false>::N];
   __shared__ uint32_t pf[kRBatch];
@@ -187,8 +204,8 @@ __global__ void __launch_bounds__(kRThreads, 4) render_multi_kernel(
   const int c = (int)(blockIdx.x % (unsigned)mc.n), k = (int)(blockIdx.x / (unsigned)mc.n);
   const DevCam& cam = mc.cam[c];
   const int tile = (int)order[cam.tile_base + k];
-  render_tile<RS, NE, GEN>(cam, th, n, mc.idx[c], tile, ranges, ids, record, rgb, out_rgb, out_T,
-                           out_nc, out_ne, cam.pixel_base, pd, pf, F, wb, red);
+  render_tile<RS, NE, GEN, CLIP>(cam, th, n, mc.idx[c], tile, ranges, ids, record, rgb, clip, out_rgb,
+                                 out_T, out_nc, out_ne, cam.pixel_base, pd, pf, F, wb, red);
 }
 
 // Persistent render of the cameras of one shutter type in a multi-camera
@@ -238,8 +255,8 @@ __global__ void __launch_bounds__(kRThreads, 4) render_batch_kernel(
     const int c = __builtin_amdgcn_readfirstlane(cam_list[j]);
     const DevCam& cam = cams[c];
     const int tile = (int)order[cam.tile_base + (item - item_start[j])];
-    render_tile<RS, false, GEN>(cam, th, n, c, tile, ranges, ids, record, rgb, outs[c], nullptr,
-                                nullptr, nullptr, 0, pd, pf, F, wb, red);
+    render_tile<RS, false, GEN, false>(cam, th, n, c, tile, ranges, ids, record, rgb, nullptr, outs[c],
+                                       nullptr, nullptr, nullptr, 0, pd, pf, F, wb, red);
   }
 }
 
@@ -284,19 +301,22 @@ gut_status render_batch_launch(const DevCam* d_cams, const DevCam* h_cams, int n
 
 gut_status launch_render(const DevCam& cam, const Thresholds& th, int n, int cam_idx,
                          const uint32_t* ranges, const uint32_t* order, const uint32_t* ids,
-                         const float* record, const float* rgb, float* out_rgb, float* out_T,
-                         uint32_t* out_nc, uint32_t* out_ne, hipStream_t s) {
+                         const float* record, const float* rgb, const float* clip, float* out_rgb,
+                         float* out_T, uint32_t* out_nc, uint32_t* out_ne, hipStream_t s) {
   dim3 grid(cam.tiles_x * cam.tiles_y), block(kRThreads);
-#define GUT_RK(RS, NE, GEN)                                                                     \
-  render_kernel<RS, NE, GEN><<<grid, block, 0, s>>>(cam, th, n, cam_idx, (const uint2*)ranges,    \
-                                                    order, ids, (const float4*)record, rgb, out_rgb, \
-                                                    out_T, out_nc, out_ne)
+#define GUT_RK(RS, NE, GEN, CLIP)                                                                  \
+  render_kernel<RS, NE, GEN, CLIP><<<grid, block, 0, s>>>(cam, th, n, cam_idx, (const uint2*)ranges, \
+                                                          order, ids, (const float4*)record, rgb,     \
+                                                          clip, out_rgb, out_T, out_nc, out_ne)
+#define GUT_RK1(RS, NE, GEN) \
+  if (clip) GUT_RK(RS, NE, GEN, true); else GUT_RK(RS, NE, GEN, false)
 #define GUT_RK2(RS, NE) \
-  if (th.kdeg != 2) GUT_RK(RS, NE, true); else GUT_RK(RS, NE, false)
+  do { if (th.kdeg != 2) { GUT_RK1(RS, NE, true); } else { GUT_RK1(RS, NE, false); } } while (0)
   const bool rs = cam.shutter == GUT_ROLLING_TOP_TO_BOTTOM;
   if (rs) { if (out_ne) GUT_RK2(true, true); else GUT_RK2(true, false); }
   else { if (out_ne) GUT_RK2(false, true); else GUT_RK2(false, false); }
 #undef GUT_RK2
+#undef GUT_RK1
 #undef GUT_RK
   GUT_LAUNCH_CHECK();
   return GUT_OK;
@@ -307,11 +327,11 @@ gut_status launch_render(const DevCam& cam, const Thresholds& th, int n, int cam
 static gut_status launch_render_group(const DevCam* dc, int c0, int c1, const Thresholds& th, int n,
                                       const uint32_t* ranges, const uint32_t* order,
                                       const uint32_t* ids, const float* record, const float* rgb,
-                                      float* out_rgb, float* out_T, uint32_t* out_nc, uint32_t* out_ne,
-                                      hipStream_t s) {
+                                      const float* clip, float* out_rgb, float* out_T,
+                                      uint32_t* out_nc, uint32_t* out_ne, hipStream_t s) {
   if (c1 - c0 == 1)
-    return launch_render(dc[c0], th, n, c0, ranges, order, ids, record, rgb, out_rgb, out_T, out_nc,
-                         out_ne, s);
+    return launch_render(dc[c0], th, n, c0, ranges, order, ids, record, rgb, clip, out_rgb, out_T,
+                         out_nc, out_ne, s);
   MultiCams mc = {};
   mc.n = c1 - c0;
   for (int k = 0; k < mc.n; k++) {
@@ -319,16 +339,19 @@ static gut_status launch_render_group(const DevCam* dc, int c0, int c1, const Th
     mc.idx[k] = c0 + k;
   }
   dim3 grid(mc.n * dc[c0].tiles_x * dc[c0].tiles_y), block(kRThreads);
-#define GUT_RM(RS, NE, GEN)                                                                          \
-  render_multi_kernel<RS, NE, GEN><<<grid, block, 0, s>>>(mc, th, n, (const uint2*)ranges, order, ids, \
-                                                          (const float4*)record, rgb, out_rgb, out_T,   \
-                                                          out_nc, out_ne)
+#define GUT_RM(RS, NE, GEN, CLIP)                                                                    \
+  render_multi_kernel<RS, NE, GEN, CLIP><<<grid, block, 0, s>>>(mc, th, n, (const uint2*)ranges, order, \
+                                                                ids, (const float4*)record, rgb, clip,  \
+                                                                out_rgb, out_T, out_nc, out_ne)
+#define GUT_RM1(RS, NE, GEN) \
+  if (clip) GUT_RM(RS, NE, GEN, true); else GUT_RM(RS, NE, GEN, false)
 #define GUT_RM2(RS, NE) \
-  if (th.kdeg != 2) GUT_RM(RS, NE, true); else GUT_RM(RS, NE, false)
+  do { if (th.kdeg != 2) { GUT_RM1(RS, NE, true); } else { GUT_RM1(RS, NE, false); } } while (0)
   const bool rs = dc[c0].shutter == GUT_ROLLING_TOP_TO_BOTTOM;
   if (rs) { if (out_ne) GUT_RM2(true, true); else GUT_RM2(true, false); }
   else { if (out_ne) GUT_RM2(false, true); else GUT_RM2(false, false); }
 #undef GUT_RM2
+#undef GUT_RM1
 #undef GUT_RM
   GUT_LAUNCH_CHECK();
   return GUT_OK;
@@ -340,8 +363,8 @@ using namespace gut;
 
 extern "C" gut_status gut_render(const gut_projected* proj, int64_t n, const uint32_t* tile_ranges,
                                  const uint32_t* sorted_ids, const gut_camera* cams, int32_t n_cams,
-                                 const gut_params* p, float* rgb, float* T_final,
-                                 uint32_t* n_contrib, uint32_t* n_eval, void* stream) {
+                                 const gut_params* p, const float* clip_depth, float* rgb,
+                                 float* T_final, uint32_t* n_contrib, uint32_t* n_eval, void* stream) {
   gut_status st = check_params(p);
   if (st != GUT_OK) return st;
   if (!proj || (n > 0 && (!proj->record || !proj->rgb)) || !tile_ranges || !rgb || !T_final ||
@@ -367,7 +390,7 @@ extern "C" gut_status gut_render(const gut_projected* proj, int64_t n, const uin
            dc[c1].tiles_x * dc[c1].tiles_y == dc[c0].tiles_x * dc[c0].tiles_y)
       c1++;
     st = launch_render_group(dc, c0, c1, th, (int)n, tile_ranges, tile_ranges + 2 * T, sorted_ids,
-                             proj->record, proj->rgb, rgb, T_final, n_contrib, n_eval,
+                             proj->record, proj->rgb, clip_depth, rgb, T_final, n_contrib, n_eval,
                              (hipStream_t)stream);
     if (st != GUT_OK) return st;
     c0 = c1;

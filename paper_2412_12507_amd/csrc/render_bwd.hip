@@ -75,11 +75,11 @@ __device__ inline float wave_reduce16(const float* g) {
 constexpr int kBwThreads = 128;
 constexpr int kBwBatch = kBwThreads;
 
-template <bool RS, bool GEN>
+template <bool RS, bool GEN, bool CLIP>
 __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
-    const float4* __restrict__ record,
+    const float4* __restrict__ record, const float* __restrict__ clip,
     const float* __restrict__ rgb, const float* __restrict__ out_rgb,
     const float* __restrict__ out_T, const uint32_t* __restrict__ out_nc,
     const float* __restrict__ d_rgb, const float* __restrict__ d_T, double* __restrict__ acc,
@@ -113,6 +113,15 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
   tile_bounds<2>(u, v, dt, active, red, &umax, &vmax, &dtmax);
   const float l2amin = log2f(th.alpha_min);
   wave_box<2>(u, v, active, &wb);
+  float clipv[2] = {0.f, 0.f}, dlen[2] = {1.f, 1.f};  // the forward's clip test operands
+  if (CLIP) {
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      if (!active[k]) continue;
+      clipv[k] = clip[cam.pixel_base + (long long)(py0 + 4 * k) * cam.W + px];
+      dlen[k] = sqrtf(fmaf(u[k], u[k], fmaf(v[k], v[k], 1.0f)));
+    }
+  }
 
   // Per pixel: the loss gradients, T_N gT, and Z = sum_c gC_c (C_c - C_<=j,c)
   // in FP64 (C the output colour, C_<=j the running colour including entry
@@ -168,7 +177,10 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
         load_pair<RS>(P, r);
         Eval ev[2];
 #pragma unroll
-        for (int k = 0; k < 2; k++) eval_test<RS>(r, P, u[k], v[k], dt[k], &ev[k]);
+        for (int k = 0; k < 2; k++) {
+          eval_test<RS>(r, P, u[k], v[k], dt[k], &ev[k]);
+          if (CLIP) ev[k].ok = ev[k].ok && !behind_clip<RS>(r, P, u[k], v[k], dt[k], dlen[k], clipv[k], ev[k].dd);
+        }
         bool hit[2];
         hit[0] = ev[0].ok && idx < last[0];
         hit[1] = ev[1].ok && idx < last[1];
@@ -409,7 +421,7 @@ extern "C" size_t gut_render_bwd_workspace_bytes(int64_t n, int32_t n_cams) {
 extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected* proj,
                                      const uint32_t* tile_ranges, const uint32_t* sorted_ids,
                                      const gut_camera* cams, int32_t n_cams, const gut_params* p,
-                                     const float* rgb, const float* T_final,
+                                     const float* clip_depth, const float* rgb, const float* T_final,
                                      const uint32_t* n_contrib, const float* d_rgb,
                                      const float* d_T, float* g_means, float* g_scales,
                                      float* g_quats, float* g_opacities, float* g_sh, void* ws,
@@ -453,13 +465,16 @@ extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected
   Thresholds th = make_thresholds(*p);
   for (int c = 0; c < n_cams; c++) {
     dim3 grid(dc[c].tiles_x * dc[c].tiles_y), block(kBwThreads);
-#define GUT_RBW(RS, GEN)                                                                          \
-  render_bwd_kernel<RS, GEN><<<grid, block, 0, s>>>(                                               \
+#define GUT_RBW(RS, GEN, CLIP)                                                                      \
+  render_bwd_kernel<RS, GEN, CLIP><<<grid, block, 0, s>>>(                                           \
       dc[c], th, (int)n, c, (const uint2*)tile_ranges, order, sorted_ids, (const float4*)proj->record, \
-      proj->rgb, rgb, T_final, n_contrib, d_rgb, d_T, acc, acc_rgb)
+      clip_depth, proj->rgb, rgb, T_final, n_contrib, d_rgb, d_T, acc, acc_rgb)
+#define GUT_RBW1(RS, GEN) \
+  if (clip_depth) GUT_RBW(RS, GEN, true); else GUT_RBW(RS, GEN, false)
     const bool gen = th.kdeg != 2;
-    if (dc[c].shutter == GUT_ROLLING_TOP_TO_BOTTOM) { if (gen) GUT_RBW(true, true); else GUT_RBW(true, false); }
-    else { if (gen) GUT_RBW(false, true); else GUT_RBW(false, false); }
+    if (dc[c].shutter == GUT_ROLLING_TOP_TO_BOTTOM) { if (gen) { GUT_RBW1(true, true); } else { GUT_RBW1(true, false); } }
+    else { if (gen) { GUT_RBW1(false, true); } else { GUT_RBW1(false, false); } }
+#undef GUT_RBW1
 #undef GUT_RBW
     GUT_LAUNCH_CHECK();
   }

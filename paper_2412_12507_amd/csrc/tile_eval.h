@@ -367,6 +367,27 @@ __device__ __forceinline__ void eval_alpha(const PairRegs<RS>& r, const Threshol
   o->a = __builtin_amdgcn_fmed3f(araw, 0.0f, amax);
 }
 
+// Hybrid rendering (Sec. 6.2): does the pair's maximum-response point lie
+// beyond the pixel's clip distance (its closest surface intersection)?  With
+// d = n + u e1 + v e2 (|d| = dlen = sqrt(1 + u^2 + v^2)) the hit is at
+// tau' = -(o_g . d_g) / |d_g|^2 along d, i.e. at distance tau' dlen, so it is
+// behind when -(o_g . d_g) dlen > clip |d_g|^2.  o_g . d_g is the same affine
+// (bilinear under a rolling shutter) form as the tau_max sign test.  Forward
+// and backward call this with the same operands.
+template <bool RS>
+__device__ __forceinline__ bool behind_clip(const PairRegs<RS>& r, const float4* P, float u, float v,
+                                            float dt, float dlen, float clip, float dd) {
+  float odg;
+  if (!RS) {
+    const float4 p5 = P[5];
+    odg = fmaf(v, p5.z, fmaf(u, p5.y, p5.x));
+  } else {
+    odg = fmaf(v, r.p4.w, fmaf(u, r.p3.w, r.p5.w));
+    odg = fmaf(dt, fmaf(v, r.p9.w, fmaf(u, r.p8.w, r.p7.w)), odg);
+  }
+  return -odg * dlen > clip * dd;
+}
+
 // Colour of a pair (FP64 slots).
 template <bool RS>
 __device__ __forceinline__ void pair_colour(const float4* P, double c[3]) {

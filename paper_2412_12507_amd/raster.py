@@ -184,22 +184,35 @@ def alloc_image(cams, device="cuda", with_eval=False) -> Image:
                  shapes=[(int(c["height"]), int(c["width"])) for c in cams])
 
 
+def _clip_arg(clip, cams):
+    """Per-pixel clip distances (hybrid rendering, Sec. 6.2): a float32 device
+    tensor with one value per pixel of the call, or None."""
+    if clip is None:
+        return None
+    clip = clip.contiguous()
+    if clip.dtype != torch.float32 or clip.numel() != num_pixels(cams) or not clip.is_cuda:
+        raise ValueError("clip must be a float32 CUDA tensor with one value per pixel")
+    return clip
+
+
 def render(proj: Projection, bins: Bins, cams, params=None, out: Image | None = None,
-           with_eval=False) -> Image:
+           with_eval=False, clip: torch.Tensor | None = None) -> Image:
     if out is None:
         out = alloc_image(cams, proj.depth.device, with_eval)
     arr = L.camera_array(cams)
     p = L.params_struct(params)
     ps = proj.struct()
+    clip = _clip_arg(clip, cams)
     L.check(L.load().gut_render(L.ref(ps), proj.n, _ptr(bins.ranges), _ptr(bins.ids), arr,
-                                len(cams), L.ref(p), _ptr(out.rgb), _ptr(out.T),
+                                len(cams), L.ref(p), _ptr(clip), _ptr(out.rgb), _ptr(out.T),
                                 _ptr(out.n_contrib), _ptr(out.n_eval), _stream()), "gut_render")
     return out
 
 
 def render_backward(scene: GaussianScene, proj: Projection, bins: Bins, cams, image: Image,
                     d_rgb: torch.Tensor, d_T: torch.Tensor | None = None, params=None,
-                    grads: dict | None = None, workspace: torch.Tensor | None = None) -> dict:
+                    grads: dict | None = None, workspace: torch.Tensor | None = None,
+                    clip: torch.Tensor | None = None) -> dict:
     lib = L.load()
     n, nc = scene.n, len(cams)
     dev = scene.means.device
@@ -215,8 +228,9 @@ def render_backward(scene: GaussianScene, proj: Projection, bins: Bins, cams, im
     ss, ps = scene.struct(), proj.struct()
     d_rgb = d_rgb.contiguous()
     d_T = None if d_T is None else d_T.contiguous()
+    clip = _clip_arg(clip, cams)
     L.check(lib.gut_render_bwd(L.ref(ss), L.ref(ps), _ptr(bins.ranges), _ptr(bins.ids), arr, nc,
-                               L.ref(p), _ptr(image.rgb), _ptr(image.T), _ptr(image.n_contrib),
+                               L.ref(p), _ptr(clip), _ptr(image.rgb), _ptr(image.T), _ptr(image.n_contrib),
                                _ptr(d_rgb), _ptr(d_T), _ptr(grads["means"]),
                                _ptr(grads["scales"]), _ptr(grads["quats"]),
                                _ptr(grads["opacities"]), _ptr(grads["sh"]), _ptr(workspace),

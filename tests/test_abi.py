@@ -129,13 +129,13 @@ def test_bin_and_render_validation_without_launch():
     assert st == L.GUT_E_INVALID and b"8-byte" in lib.gut_last_error()
     # render: NULL outputs
     st = lib.gut_render(L.ref(pj), 10, C.c_void_p(4096), C.c_void_p(4096), arr, 1, L.ref(p), None,
-                        None, None, None, None)
+                        None, None, None, None, None)
     assert st == L.GUT_E_INVALID
     # bwd: workspace too small
     sc = _scene_struct()
     z = C.c_void_p(4096)
-    st = lib.gut_render_bwd(L.ref(sc), L.ref(pj), z, z, arr, 1, L.ref(p), z, z, z, z, None, z, z, z,
-                            z, z, z, 16, None)
+    st = lib.gut_render_bwd(L.ref(sc), L.ref(pj), z, z, arr, 1, L.ref(p), None, z, z, z, z, None, z,
+                            z, z, z, z, z, 16, None)
     assert st == L.GUT_E_INVALID
 
 

@@ -1,0 +1,103 @@
+"""Hybrid-rendering depth clip (Sec. 6.2) on the HIP path against the FP64
+oracle: hits whose maximum-response point lies beyond a pixel's clip
+distance are discarded, in the forward (every pixel, 1e-4) and the backward
+(gradients 1e-3), under pinhole, fisheye and rolling-shutter cameras."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import gut_synth as G
+import oracle as O
+from paper_2412_12507_amd import raster as R
+from parity import compare_pixels, gpu_forward, grad_compare, image_np
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def clip_map(cam, lo, hi, seed, inf_frac=0.1):
+    """Per-pixel clip distances U[lo, hi], a fraction of them +inf."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(lo, hi, size=(cam["height"], cam["width"]))
+    c[rng.random(c.shape) < inf_frac] = np.inf
+    return c
+
+
+CASES = {
+    "c1": lambda: (G.config1()[0], G.config1()[1][0], 2.6, 3.4),
+    "c2-fisheye": lambda: (G.clustered_scene(20000, seed=1002), G.config2_cameras(320, 180)[1], 5.0, 11.0),
+    "c3-rolling": lambda: (G.clustered_scene(30000, seed=1003), G.config3_camera(400, 300), 5.0, 11.0),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_forward_parity_with_clip(case):
+    say(f"[depth clip forward] {case}")
+    scene, cam, lo, hi = CASES[case]()
+    clip = clip_map(cam, lo, hi, seed=4001)
+    p = O.default_params()
+    gs = R.GaussianScene.from_host(scene)
+    proj = R.project(gs, [cam], p)
+    bins = R.bin_tiles(proj, [cam], p)
+    ct = torch.as_tensor(clip.reshape(-1), dtype=torch.float32, device="cuda")
+    img = R.render(proj, bins, [cam], p, with_eval=True, clip=ct)
+    full = R.render(proj, bins, [cam], p)
+    torch.cuda.synchronize()
+    pr = O.project(scene, cam, p)
+    ob = O.bin_tiles(pr, cam, p)
+    # the oracle clips at the FP32 values the GPU reads
+    res = O.render(scene, pr, cam, ob, p, clip=clip.astype(np.float32).astype(np.float64))
+    rep = compare_pixels(image_np(img), res, cam, p)
+    say("  pixels", {k: v for k, v in rep.items() if k != "fails"}, rep["fails"][:3])
+    assert rep["n_fail"] == 0
+    changed = (img.rgb - full.rgb).abs().amax(1).gt(1e-3).float().mean().item()
+    say("  fraction of pixels the clip changes:", changed)
+    assert changed > 0.05
+
+
+def test_clip_at_infinity_is_bitwise_no_clip():
+    scene, cam, _, _ = CASES["c2-fisheye"]()
+    gs, proj, bins, a = gpu_forward(scene, [cam], None, with_eval=False)
+    ct = torch.full((cam["height"] * cam["width"],), float("inf"), device="cuda")
+    b = R.render(proj, bins, [cam], None, clip=ct)
+    torch.cuda.synchronize()
+    assert torch.equal(a.rgb, b.rgb) and torch.equal(a.T, b.T) and torch.equal(a.n_contrib, b.n_contrib)
+
+
+@pytest.mark.parametrize("kind", ["pinhole", "fisheye", "rolling"])
+def test_backward_parity_with_clip(kind):
+    say(f"[depth clip backward] {kind}")
+    p = O.default_params(bg=(0.1, 0.3, 0.6))
+    scene, cam = G.config4_gradcheck(kind, log_scale_mean=-2.2)
+    clip = clip_map(cam, 2.6, 3.4, seed=4002).astype(np.float32).astype(np.float64)
+    pr = O.project(scene, cam, p)
+    ob = O.bin_tiles(pr, cam, p)
+    res = O.render(scene, pr, cam, ob, p, clip=clip)
+    rng = np.random.default_rng(13)
+    H, W = cam["height"], cam["width"]
+    amb = O.to_image(res, cam, p, key="n_alt") > 0
+    wC, wT = rng.normal(size=(H, W, 3)), rng.normal(size=(H, W))
+    wC[amb] = 0
+    wT[amb] = 0
+    say("  ambiguous pixels zeroed:", int(amb.sum()))
+    g_ora = O.backward(scene, pr, cam, ob, wC, wT, p, clip=clip)
+    gs = R.GaussianScene.from_host(scene)
+    proj = R.project(gs, [cam], p)
+    bins = R.bin_tiles(proj, [cam], p)
+    ct = torch.as_tensor(clip.reshape(-1), dtype=torch.float32, device="cuda")
+    img = R.render(proj, bins, [cam], p, clip=ct)
+    d_rgb = torch.as_tensor(wC.reshape(-1, 3), dtype=torch.float32, device="cuda")
+    d_T = torch.as_tensor(wT.reshape(-1), dtype=torch.float32, device="cuda")
+    g = R.render_backward(gs, proj, bins, [cam], img, d_rgb, d_T, p, clip=ct)
+    torch.cuda.synchronize()
+    rep = grad_compare(g, g_ora)
+    say("  grads", rep)
+    for k, v in rep.items():
+        assert v["rel"] <= 1e-3, (k, v)
+        assert v["elem_fail"] == 0, (k, v)
