@@ -85,8 +85,8 @@ def render_launches(cams):
 
 def pmc_summary(fetch_dir, write_dir, out_path, command):
     """Per-launch HBM bytes of the timed render kernel (render_multi_kernel<false,
-    false, false>: global shutter, no n_eval, Gaussian response, both views in
-    one launch) from two
+    false, false, false>: global shutter, no n_eval, Gaussian response, no
+    clip, both views in one launch) from two
     rocprofv3 --pmc runs of `bench.py --calib-copy` (FETCH_SIZE, then
     WRITE_SIZE, KiB per dispatch).
     Each counter is scaled by what it reads for a kernel of known traffic in
@@ -110,8 +110,8 @@ def pmc_summary(fetch_dir, write_dir, out_path, command):
     fr, wr = read(fetch_dir, "FETCH_SIZE"), read(write_dir, "WRITE_SIZE")
     f_add = pick(fr, "CUDAFunctor_add", "CUDAFunctorOnSelf_add")
     w_fill = pick(wr, "FillFunctor")
-    f_r = pick(fr, "gut::render_multi_kernel<false, false, false>")
-    w_r = pick(wr, "gut::render_multi_kernel<false, false, false>")
+    f_r = pick(fr, "gut::render_multi_kernel<false, false, false, false>")
+    w_r = pick(wr, "gut::render_multi_kernel<false, false, false, false>")
     if not (f_add and w_fill and f_r and w_r):
         raise SystemExit("pmc summary: calibration or render dispatches missing")
     ff = CALIB_BYTES / (f_add[0] * 1024.0)

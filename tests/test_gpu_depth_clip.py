@@ -101,3 +101,30 @@ def test_backward_parity_with_clip(kind):
     for k, v in rep.items():
         assert v["rel"] <= 1e-3, (k, v)
         assert v["elem_fail"] == 0, (k, v)
+
+
+def test_multi_camera_clip_equals_single_calls():
+    """A two-camera call (one merged launch) reads each camera's clip values
+    at its own pixel offset: equal to clipping each camera alone."""
+    scene = G.clustered_scene(20000, seed=1002)
+    pin = G.config2_cameras(320, 180)[0]
+    R2, t2 = G.look_at((1.5, 0.8, -7.5))
+    cams = [pin, dict(pin, R0=R2, t0=t2, R1=R2, t1=t2)]  # two pinholes of one size: one launch
+    clips = [clip_map(c, 5.0, 11.0, seed=4010 + i) for i, c in enumerate(cams)]
+    gs = R.GaussianScene.from_host(scene)
+    proj = R.project(gs, cams)
+    bins = R.bin_tiles(proj, cams)
+    ct = torch.as_tensor(np.concatenate([c.reshape(-1) for c in clips]), dtype=torch.float32,
+                         device="cuda")
+    both = R.render(proj, bins, cams, clip=ct)
+    torch.cuda.synchronize()
+    off = 0
+    for cam, c in zip(cams, clips):
+        _, pj1, b1, _ = gpu_forward(scene, [cam], None, with_eval=False)
+        one = R.render(pj1, b1, [cam], clip=torch.as_tensor(c.reshape(-1), dtype=torch.float32,
+                                                            device="cuda"))
+        torch.cuda.synchronize()
+        npx = cam["width"] * cam["height"]
+        assert torch.equal(both.rgb[off:off + npx], one.rgb)
+        assert torch.equal(both.T[off:off + npx], one.T)
+        off += npx
