@@ -238,11 +238,11 @@ def render_backward(scene: GaussianScene, proj: Projection, bins: Bins, cams, im
     return grads
 
 
-def forward(scene: GaussianScene, cams, params=None, with_eval=False):
+def forward(scene: GaussianScene, cams, params=None, with_eval=False, clip=None):
     """project -> bin -> render; returns (proj, bins, image)."""
     proj = project(scene, cams, params)
     bins = bin_tiles(proj, cams, params)
-    img = render(proj, bins, cams, params, with_eval=with_eval)
+    img = render(proj, bins, cams, params, with_eval=with_eval, clip=clip)
     return proj, bins, img
 
 
@@ -252,15 +252,16 @@ class GutRender(torch.autograd.Function):
     forward keeps only the compositing state the backward recomputes from
     (T_final, n_contrib, the tile lists and the projected records); with
     ``recompute_projection`` it drops the projection too and re-runs it in
-    backward (saves C*n*28 B + n*64 B)."""
+    backward (saves C*n*28 B + n*64 B).  ``clip``: per-pixel clip distances
+    of hybrid rendering (Sec. 6.2), used by forward and backward alike."""
 
     @staticmethod
     def forward(ctx, means, scales, quats, opacities, sh, sh_degree, cams, params,
-                recompute_projection):
+                recompute_projection, clip=None):
         scene = GaussianScene(means.contiguous(), scales.contiguous(), quats.contiguous(),
                               opacities.contiguous(), sh.contiguous(), int(sh_degree))
-        proj, bins, img = forward(scene, cams, params)
-        ctx.cams, ctx.params, ctx.sh_degree = cams, params, int(sh_degree)
+        proj, bins, img = forward(scene, cams, params, clip=clip)
+        ctx.cams, ctx.params, ctx.sh_degree, ctx.clip = cams, params, int(sh_degree), clip
         ctx.recompute = bool(recompute_projection)
         ctx.bins = bins
         ctx.img = img
@@ -275,15 +276,18 @@ class GutRender(torch.autograd.Function):
         proj = ctx.proj if ctx.proj is not None else project(scene, ctx.cams, ctx.params)
         if d_rgb is None:
             d_rgb = torch.zeros_like(ctx.img.rgb)
-        g = render_backward(scene, proj, ctx.bins, ctx.cams, ctx.img, d_rgb, d_T, ctx.params)
-        return g["means"], g["scales"], g["quats"], g["opacities"], g["sh"], None, None, None, None
+        g = render_backward(scene, proj, ctx.bins, ctx.cams, ctx.img, d_rgb, d_T, ctx.params,
+                            clip=ctx.clip)
+        return g["means"], g["scales"], g["quats"], g["opacities"], g["sh"], None, None, None, None, None
 
 
 def render_gaussians(means, scales, quats, opacities, sh, sh_degree, cams, params=None,
-                     recompute_projection=False):
-    """Differentiable render; returns (list of [H,W,3] images, list of [H,W] T_final)."""
+                     recompute_projection=False, clip=None):
+    """Differentiable render; returns (list of [H,W,3] images, list of [H,W] T_final).
+    params may select the generalized response (kernel_degree); clip gives
+    per-pixel clip distances (hybrid rendering)."""
     rgb, T = GutRender.apply(means, scales, quats, opacities, sh, sh_degree, cams, params,
-                             recompute_projection)
+                             recompute_projection, clip)
     out_rgb, out_T, o = [], [], 0
     for c in cams:
         h, w = int(c["height"]), int(c["width"])

@@ -102,3 +102,28 @@ def test_backward_parity_degree(kind, n):
     for k, v in rep.items():
         assert v["rel"] <= 1e-3, (k, v)
         assert v["elem_fail"] == 0, (k, v)
+
+
+def test_full_size_two_view_batch_degree4_sampled():
+    """The benchmark's degree-4 step at full size: 1M particles, pinhole +
+    fisheye 1920x1080 in one call (one merged render launch); every
+    particle's projection and sampled tiles of both views (the longest lists
+    plus random ones) against the oracle."""
+    say("[degree 4 full size] two-view batch")
+    scene, cams = G.config2_scene(), G.config2_cameras()
+    p = O.default_params(kernel_degree=4)
+    gs, proj, bins, img = gpu_forward(scene, cams, p)
+    for c, cam in enumerate(cams):
+        pr = O.project(scene, cam, p)
+        rep = compare_projection(proj, pr, c, scene.n, params=p)
+        say("  projection", c, rep)
+        assert rep["cull_mismatch_unexplained"] == 0 and rep["rect_mismatch_unexplained"] == 0
+        ob = O.bin_tiles(pr, cam, p)
+        tx, ty = O.tiles_xy(cam, p)
+        lens = np.diff(ob[0])
+        rng = np.random.default_rng(70 + c)
+        tiles = np.unique(np.concatenate([np.argsort(lens)[-5:], rng.choice(tx * ty, 12, replace=False)]))
+        res = O.render(scene, pr, cam, ob, p, tiles=tiles.astype(np.int32))
+        rep = compare_pixels(image_np(img, c), res, cam, p)
+        say("  pixels", c, {k: v for k, v in rep.items() if k != "fails"}, rep["fails"][:3])
+        assert rep["n_fail"] == 0
