@@ -65,6 +65,7 @@ __device__ __forceinline__ void render_tile(
       clipv[k] = clip[pix_base + (long long)(py0 + 4 * k) * cam.W + px];
       dlen[k] = sqrtf(fmaf(u[k], u[k], fmaf(v[k], v[k], 1.0f)));
     }
+    wave_clip_max<2>(clipv, active, &wb);
   }
 
   const uint2 rg = ranges[cam.tile_base + tile];
@@ -86,7 +87,7 @@ __device__ __forceinline__ void render_tile(
     uint32_t fl = 0u;
     if (b + t < len) {
       uint32_t e = ids[rg.x + b + t];
-      fl = pair_setup<RS, false, GEN>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n), F,
+      fl = pair_setup<RS, false, GEN, CLIP>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n), F,
                                       cam, umax, vmax, dtmax, th, l2amin, wb, kRThreads / 64, &pd[t * S]);
     }
     pf[t] = fl;

@@ -121,6 +121,7 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
       clipv[k] = clip[cam.pixel_base + (long long)(py0 + 4 * k) * cam.W + px];
       dlen[k] = sqrtf(fmaf(u[k], u[k], fmaf(v[k], v[k], 1.0f)));
     }
+    wave_clip_max<2>(clipv, active, &wb);
   }
 
   // Per pixel: the loss gradients, T_N gT, and Z = sum_c gC_c (C_c - C_<=j,c)
@@ -156,7 +157,7 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
     if (b + t < maxlast) {
       uint32_t e = ids[rg.x + b + t];
       pe[t] = e;
-      fl = pair_setup<RS, true, GEN>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n), F,
+      fl = pair_setup<RS, true, GEN, CLIP>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n), F,
                                      cam, umax, vmax, dtmax, th, l2amin, wb, kBwThreads / 64, &pd[t * S]);
     }
     pf[t] = fl;

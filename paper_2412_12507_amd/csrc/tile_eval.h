@@ -137,6 +137,7 @@ __device__ inline void affine_qr(d3 c0, d3 c1, d3 c2, double q[6]) {
 // Forward and backward cull identically.
 struct WaveBoxes {
   float u0[4], u1[4], v0[4], v1[4];
+  float cmax[4];  // largest clip distance of the wave's pixels (hybrid rendering)
 };
 
 // Does the ellipse qmin + [du dv] [[N11 N12] [N12 N22]] [du dv]^T <= 0
@@ -162,7 +163,10 @@ __device__ inline bool ellipse_meets_box(double qmin, double N11, double N12, do
 // block: bit k set when wave k's pixel box may see alpha >= alpha_min.  GEN:
 // the response has degree th.kdeg > 2, and the threshold kept in Kp is the
 // one on omega'^2 where the degree-n exponent reaches log2(sigma / alpha_min).
-template <bool RS, bool BWD, bool GEN>
+// CLIP (hybrid rendering): a wave whose largest clip distance (wb.cmax) lies
+// before the particle's alpha_min ellipsoid loses its bit too -- every hit it
+// could see would be clipped.
+template <bool RS, bool BWD, bool GEN, bool CLIP>
 __device__ inline unsigned pair_setup(const float4* __restrict__ record,
                                       const float* __restrict__ rgb, long long e, int i,
                                       const TileFrameD& F, const DevCam& cam, float umax,
@@ -233,6 +237,22 @@ __device__ inline unsigned pair_setup(const float4* __restrict__ record,
         }
       }
     }
+  }
+  if (CLIP && flags) {
+    // Any accepted hit is a point of the ellipsoid |M (x - mu)|^2 <= Kc, whose
+    // world radius is at most sqrt(Kc) s_max (s_k = 1 / |row k of M|), so it
+    // lies at least |o - mu| - sqrt(Kc) s_max from the ray origin o, which
+    // under a rolling shutter moves up to dtmax |c1 - c0| from o_T.  The
+    // per-pixel test carries ~1e-6 relative error: a 1e-4 margin keeps every
+    // culled pair clipped there too.
+    const double Kc = (double)Kp / kHalfLog2e * (1.0 + 1e-3) + 1e-5;
+    double rmin = 3e300;
+    for (int k = 0; k < 3; k++) rmin = fmin(rmin, M[3 * k] * M[3 * k] + M[3 * k + 1] * M[3 * k + 1] +
+                                                      M[3 * k + 2] * M[3 * k + 2]);
+    double lb = sqrt(dot(rel, rel)) - sqrt(Kc / rmin);
+    if (RS) lb -= (double)dtmax * sqrt(cam.dc[0] * cam.dc[0] + cam.dc[1] * cam.dc[1] + cam.dc[2] * cam.dc[2]);
+    for (int k = 0; k < nwaves; k++)
+      if (lb > (double)wb.cmax[k] * (1.0 + 1e-4)) flags &= ~(1u << k);
   }
   const float* c = rgb + 3 * e;
   const float mflag = mixed ? -1.0f : 1.0f;
@@ -472,6 +492,19 @@ __device__ inline void wave_box(const float* u, const float* v, const bool* vali
     const int w = threadIdx.x >> 6;
     wb->u0[w] = a0; wb->u1[w] = a1; wb->v0[w] = b0; wb->v1[w] = b1;
   }
+}
+
+// Largest clip distance over each wave's valid pixels (+inf if any is
+// unclipped; -inf if the wave has no valid pixel).
+template <int NP>
+__device__ inline void wave_clip_max(const float* clip, const bool* valid, WaveBoxes* wb) {
+  float c = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < NP; k++)
+    if (valid[k]) c = fmaxf(c, clip[k]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c = fmaxf(c, __shfl_xor(c, o, 64));
+  if ((threadIdx.x & 63) == 0) wb->cmax[threadIdx.x >> 6] = c;
 }
 
 // True when pred holds on some active lane (the wave's lane mask, without a
