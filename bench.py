@@ -50,6 +50,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 F_EVAL = 55            # FP32 FLOPs per (pixel, particle) evaluation (mul and add counted apart)
+F_EVAL_GEN = F_EVAL + 4   # degree-n response: (omega^2)^(n/2) as exp2(h log2 w), 2 transcendentals + fma + mul
+F_EVAL_CLIP = F_EVAL + 5  # depth clip: o_g.d_g (2 fma), two products and the compare
 PEAK_FP32_TFLOPS = 157.3
 # the FP32 ceiling without packed-math instructions (256 CUs x 64 lanes x 2 FLOPs x 2.4 GHz),
 # which libgut is compiled not to emit
@@ -418,10 +420,14 @@ def main():
         for d in [int(x) for x in args.degrees.split(",")]:
             log(f"[bench] forward steps, response of degree {d}")
             fd = bench_forward(gs, cams, max(3, args.steps // 2), 2, R, torch, dict(kernel_degree=d))
+            ach = fd["e_eval"] * F_EVAL_GEN / launches / (fd["stage_ms"][2] / launches * 1e-3) / 1e12
             degrees[str(d)] = dict(mpix_per_s=npx / (fd["ms_per_step"] * 1e-3) / 1e6,
                                    stages_ms={"project": fd["stage_ms"][0], "bin": fd["stage_ms"][1],
                                               "render": fd["stage_ms"][2]},
-                                   n_pairs=fd["n_pairs"], e_eval=fd["e_eval"])
+                                   n_pairs=fd["n_pairs"], e_eval=fd["e_eval"],
+                                   roofline=dict(bound="alu", achieved=ach, peak=PEAK_FP32_TFLOPS,
+                                                 unit="TFLOP/s", frac=ach / PEAK_FP32_TFLOPS,
+                                                 flops_per_eval=F_EVAL_GEN))
             del fd
         degrees["2"]["e_eval"] = fw["e_eval"]
 
@@ -433,10 +439,13 @@ def main():
         g = torch.Generator(device="cuda").manual_seed(4003)
         clip = 6.0 + 4.0 * torch.rand(npx, device="cuda", generator=g)
         fc = bench_forward(gs, cams, max(3, args.steps // 2), 2, R, torch, None, clip)
+        ach = fc["e_eval"] * F_EVAL_CLIP / (fc["stage_ms"][2] * 1e-3) / 1e12
         depth_clip = dict(mpix_per_s=npx / (fc["ms_per_step"] * 1e-3) / 1e6,
                           stages_ms={"project": fc["stage_ms"][0], "bin": fc["stage_ms"][1],
                                      "render": fc["stage_ms"][2]},
-                          e_eval=fc["e_eval"], clip="U[6, 10] per pixel")
+                          e_eval=fc["e_eval"], clip="U[6, 10] per pixel",
+                          roofline=dict(bound="alu", achieved=ach, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                                        frac=ach / PEAK_FP32_TFLOPS, flops_per_eval=F_EVAL_CLIP))
         del fc, clip
 
     fwd_bwd = None
