@@ -179,3 +179,40 @@ def grad_compare(g_gpu, g_ora):
                  if not elem.reshape(-1)[i]]
         out[k] = dict(rel=float(rel), elem_fail=int((~elem).sum()), max=float(m), worst=worst)
     return out
+
+
+def sampled_backward_check(scene, cam, p, clip=None, seed=17, n_long=4, n_rand=12):
+    """Backward parity at full size on sampled tiles: loss weights random on
+    the longest-list tiles plus random ones (ambiguous pixels zeroed), zero
+    elsewhere; every particle's gradient against the oracle.  clip: [H, W]
+    clip distances (hybrid rendering) or None.  Returns grad_compare's report."""
+    gs = to_torch_scene(scene)
+    proj = R.project(gs, [cam], p)
+    bins = R.bin_tiles(proj, [cam], p)
+    ct = None if clip is None else torch.as_tensor(clip.reshape(-1), dtype=torch.float32, device="cuda")
+    img = R.render(proj, bins, [cam], p, clip=ct)
+    torch.cuda.synchronize()
+    clip64 = None if clip is None else clip.astype(np.float32).astype(np.float64)
+    pr = O.project(scene, cam, p)
+    ob = O.bin_tiles(pr, cam, p)
+    tx, ty = O.tiles_xy(cam, p)
+    ts = p["tile"]
+    lens = np.diff(ob[0])
+    rng = np.random.default_rng(seed)
+    tiles = np.unique(np.concatenate([np.argsort(lens)[-n_long:], rng.choice(tx * ty, n_rand, replace=False)]))
+    res = O.render(scene, pr, cam, ob, p, tiles=tiles.astype(np.int32), clip=clip64)
+    H, W = cam["height"], cam["width"]
+    wC = np.zeros((H, W, 3))
+    for slot, t in enumerate(tiles):
+        y0, x0 = (int(t) // tx) * ts, (int(t) % tx) * ts
+        for ly in range(ts):
+            for lx in range(ts):
+                py, px = y0 + ly, x0 + lx
+                if py >= H or px >= W or res["n_alt"][slot * ts * ts + ly * ts + lx] > 0:
+                    continue
+                wC[py, px] = rng.normal(size=3)
+    g_ora = O.backward(scene, pr, cam, ob, wC, None, p, clip=clip64)
+    d_rgb = torch.as_tensor(wC.reshape(-1, 3), dtype=torch.float32, device="cuda")
+    g = R.render_backward(gs, proj, bins, [cam], img, d_rgb, None, p, clip=ct)
+    torch.cuda.synchronize()
+    return grad_compare(g, g_ora)

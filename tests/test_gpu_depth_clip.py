@@ -183,3 +183,16 @@ def test_autograd_with_clip_and_degree_matches_direct_calls():
     torch.cuda.synchronize()
     for leaf, k in zip(leaves, ("means", "scales", "quats", "opacities", "sh")):
         assert torch.allclose(leaf.grad, g[k], rtol=1e-6, atol=1e-9 * float(g[k].abs().max()) + 1e-12), k
+
+
+def test_full_size_backward_clip_sampled():
+    """Clipped backward at full size (1M particles, fisheye 1920x1080, clip
+    U[6, 10]) on sampled tiles: every particle's gradient against the oracle."""
+    from parity import sampled_backward_check
+    say("[depth clip full size backward] fisheye")
+    cam = G.config2_cameras()[1]
+    rep = sampled_backward_check(G.config2_scene(), cam, O.default_params(),
+                                 clip=clip_map(cam, 6.0, 10.0, seed=4030, inf_frac=0.0), seed=37)
+    say("  grads", {k: (v["rel"], v["elem_fail"]) for k, v in rep.items()})
+    for k, v in rep.items():
+        assert v["rel"] <= 1e-3 and v["elem_fail"] == 0, (k, v)

@@ -127,3 +127,15 @@ def test_full_size_two_view_batch_degree4_sampled():
         rep = compare_pixels(image_np(img, c), res, cam, p)
         say("  pixels", c, {k: v for k, v in rep.items() if k != "fails"}, rep["fails"][:3])
         assert rep["n_fail"] == 0
+
+
+def test_full_size_backward_degree4_sampled():
+    """Degree-4 backward at full size (1M particles, fisheye 1920x1080) on
+    sampled tiles: every particle's gradient against the oracle."""
+    from parity import sampled_backward_check
+    say("[degree 4 full size backward] fisheye")
+    rep = sampled_backward_check(G.config2_scene(), G.config2_cameras()[1],
+                                 O.default_params(kernel_degree=4), seed=27)
+    say("  grads", {k: (v["rel"], v["elem_fail"]) for k, v in rep.items()})
+    for k, v in rep.items():
+        assert v["rel"] <= 1e-3 and v["elem_fail"] == 0, (k, v)
