@@ -61,7 +61,7 @@ class Params(C.Structure):
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double), ("t_min", C.c_double),
                 ("near_plane", C.c_double), ("k_sigma_max", C.c_double),
                 ("tile", C.c_int32), ("rs_iters", C.c_int32), ("bg", C.c_double * 3),
-                ("kernel_degree", C.c_int32)]
+                ("kernel_degree", C.c_int32), ("kbuffer", C.c_int32)]
 
 
 class SceneS(C.Structure):
@@ -77,7 +77,7 @@ class ProjS(C.Structure):
 
 class Amb(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("alpha", "trans", "tau", "depth", "edge", "valid",
-                                          "pixel", "diff", "clip")]
+                                          "pixel", "diff", "clip", "order")]
 
 
 class ImageS(C.Structure):
@@ -136,14 +136,14 @@ def default_params(**kw) -> dict:
     f = lambda v: float(np.float32(v))
     p = dict(ut_alpha=1.0, ut_beta=2.0, ut_kappa=0.0, alpha_min=f(1.0 / 255.0),
              alpha_max=f(0.99), t_min=f(1e-4), near_plane=f(0.2), k_sigma_max=3.0,
-             tile=16, rs_iters=3, bg=(0.0, 0.0, 0.0), kernel_degree=2)
+             tile=16, rs_iters=3, bg=(0.0, 0.0, 0.0), kernel_degree=2, kbuffer=0)
     p.update(kw)
     return p
 
 
 def default_amb(**kw) -> dict:
     a = dict(alpha=1e-6, trans=1e-4, tau=1e-5, depth=1e-6, edge=2e-3, valid=1e-5, pixel=1e-9,
-             diff=1e-6, clip=1e-5)
+             diff=1e-6, clip=1e-5, order=1e-5)
     a.update(kw)
     return a
 
@@ -156,6 +156,7 @@ def _params(p: dict) -> Params:
     s.tile = int(p["tile"])
     s.rs_iters = int(p["rs_iters"])
     s.kernel_degree = int(p.get("kernel_degree", 2))
+    s.kbuffer = int(p.get("kbuffer", 0))
     for i in range(3):
         s.bg[i] = float(p["bg"][i])
     return s
@@ -426,6 +427,8 @@ def to_image(res, cam, params=None, key="rgb"):
 
 
 def backward(scene, proj, cam, bins, dL_drgb, dL_dT=None, params=None, clip=None):
+    if (params or {}).get("kbuffer", 0):
+        raise NotImplementedError("the oracle has no backward for the k-buffer")
     clip = _clip(clip, cam)
     sc = as_oscene(scene)
     p = params or default_params()

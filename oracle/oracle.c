@@ -741,8 +741,8 @@ int ora_particle_alpha(const double mu[3], const double quat[4], const double sc
 /* Render: front-to-back Eq. 5 over the tile list, response at tau_max        */
 /* ------------------------------------------------------------------------- */
 
-enum { PT_NONE = 0, PT_TOGGLE, PT_ALPHA, PT_STOP, PT_TAU, PT_SWAP, PT_CLIP };
-typedef struct { int type; int64_t pos; } perturb;
+enum { PT_NONE = 0, PT_TOGGLE, PT_ALPHA, PT_STOP, PT_TAU, PT_SWAP, PT_CLIP, PT_ORDER };
+typedef struct { int type; int64_t pos, pos2; } perturb;
 typedef struct { double rgb[3], T; int nc, ne; } pix_result;
 
 typedef struct {
@@ -763,10 +763,131 @@ static double hit_distance(double odot, const double dg[3], const double d[3]) {
   return -odot / dot3(dg, dg) * sqrt(dot3(d, d));
 }
 
+static void add_cand(perturb* cand, int* ncand, perturb c) {
+  if (!cand || *ncand >= MAXCAND) return;
+  for (int i = 0; i < *ncand; i++)
+    if (cand[i].type == c.type && cand[i].pos == c.pos && cand[i].pos2 == c.pos2) return;
+  cand[(*ncand)++] = c;
+}
+
+/* "Ours (sorted)" (Sec. 4.3): multi-layer alpha blending with a per-ray
+ * buffer of the k farthest hits seen so far.  A hit is a list entry with
+ * tau_max > 0, not clipped and alpha >= alpha_min, placed at its
+ * maximum-response distance along the ray.  While the buffer has room, a hit
+ * is inserted in distance order (after nearer ones, before equal or farther
+ * ones).  Once it is full, the nearer of the new hit and the buffer's nearest
+ * is blended into the pixel front to back; if that was the buffered one, the
+ * new hit takes a place in the buffer.  Blending stops before a hit that
+ * would take T below t_min (the blended part's transmittance has vanished);
+ * at the end of the list the buffer is blended nearest first under the same
+ * rule.  n_contrib counts blended hits. */
+typedef struct { double dist, a; int64_t q; int32_t id; } hit_rec;
+#define ORA_MAXK 256
+
+/* x strictly nearer than y; PT_ORDER flips the order of one pair. */
+static int nearer(const render_ctx* X, const hit_rec* x, const hit_rec* y, perturb pt, perturb* cand,
+                  int* ncand) {
+  int r = x->dist < y->dist;
+  if (fabs(x->dist - y->dist) <= X->amb->order * fmax(x->dist, y->dist))
+    add_cand(cand, ncand, (perturb){PT_ORDER, x->q < y->q ? x->q : y->q, x->q < y->q ? y->q : x->q});
+  if (pt.type == PT_ORDER && ((pt.pos == x->q && pt.pos2 == y->q) || (pt.pos == y->q && pt.pos2 == x->q)))
+    r = !r;
+  return r;
+}
+
+/* Eq. 5 for one hit; returns 1 (and adds nothing) if it would take T below t_min. */
+static int blend_hit(const render_ctx* X, const hit_rec* h, double* T, double C[3], int* nc, perturb pt,
+                     perturb* cand, int* ncand) {
+  const ora_params* p = X->p;
+  const double Tn = *T * (1.0 - h->a);
+  if (fabs(Tn / p->t_min - 1.0) < X->amb->trans) add_cand(cand, ncand, (perturb){PT_STOP, h->q, 0});
+  int stop = Tn < p->t_min;
+  if (pt.type == PT_STOP && pt.pos == h->q) stop = !stop;
+  if (stop) return 1;
+  const double* c = &X->pr->rgb[3 * h->id];
+  for (int ch = 0; ch < 3; ch++) C[ch] += h->a * *T * c[ch];
+  *T = Tn;
+  (*nc)++;
+  return 0;
+}
+
+static void render_pixel_kbuffer(const render_ctx* X, const int32_t* ids, const int32_t* flags,
+                                 int64_t L, const double o[3], const double d[3], double clipv,
+                                 perturb pt, pix_result* res, perturb* cand, int* ncand) {
+  const ora_params* p = X->p;
+  const int k = p->kbuffer < ORA_MAXK ? p->kbuffer : ORA_MAXK;
+  hit_rec buf[ORA_MAXK];
+  int n = 0, nc = 0, member_pos = 0, ne = -1, stopped = 0;
+  double T = 1.0, C[3] = {0, 0, 0};
+  for (int64_t pos = 0; pos < L && !stopped; pos++) {
+    int64_t q = pos;
+    if (pt.type == PT_SWAP && pos == pt.pos) q = pos + 1;
+    else if (pt.type == PT_SWAP && pos == pt.pos + 1) q = pos - 1;
+    int member = flags[q] & 1;
+    if (pt.type == PT_TOGGLE && pt.pos == q) member = !member;
+    if (flags[q] & 2) add_cand(cand, ncand, (perturb){PT_TOGGLE, q, 0});
+    if (pos + 1 < L && (flags[q] & 1) && (flags[q + 1] & 1)) {
+      double d0 = X->pr->depth[ids[q]], d1 = X->pr->depth[ids[q + 1]];
+      if (fabs(d1 - d0) <= X->amb->depth * d0) add_cand(cand, ncand, (perturb){PT_SWAP, pos, 0});
+    }
+    if (!member) continue;
+    member_pos++;
+    const particle_geo* g = &X->geo[ids[q]];
+    double og[3], dg[3], odot, om2;
+    eval_geo(g, o, d, og, dg, &odot, &om2);
+    if (fabs(odot) < X->amb->tau * sqrt(dot3(og, og) * dot3(dg, dg)))
+      add_cand(cand, ncand, (perturb){PT_TAU, q, 0});
+    int skip = odot >= 0;
+    if (pt.type == PT_TAU && pt.pos == q) skip = !skip;
+    if (skip) continue;
+    const double dist = hit_distance(odot, dg, d);
+    if (isfinite(clipv)) {
+      if (fabs(dist - clipv) <= X->amb->clip * clipv) add_cand(cand, ncand, (perturb){PT_CLIP, q, 0});
+      int behind = dist > clipv;
+      if (pt.type == PT_CLIP && pt.pos == q) behind = !behind;
+      if (behind) continue;
+    }
+    double a = g->sigma * response(p, om2);
+    if (a > p->alpha_max) a = p->alpha_max;
+    if (fabs(a - p->alpha_min) < X->amb->alpha) add_cand(cand, ncand, (perturb){PT_ALPHA, q, 0});
+    int below = a < p->alpha_min;
+    if (pt.type == PT_ALPHA && pt.pos == q) below = !below;
+    if (below) continue;
+    hit_rec h = {dist, a, q, ids[q]};
+    if (n == k) {
+      /* full: blend the nearer of the new hit and the buffer's nearest */
+      if (!nearer(X, &buf[0], &h, pt, cand, ncand)) {
+        if (blend_hit(X, &h, &T, C, &nc, pt, cand, ncand)) { stopped = 1; ne = member_pos; }
+        continue;
+      }
+      if (blend_hit(X, &buf[0], &T, C, &nc, pt, cand, ncand)) { stopped = 1; ne = member_pos; continue; }
+      for (int j = 1; j < n; j++) buf[j - 1] = buf[j];
+      n--;
+    }
+    /* insert after the hits nearer than h */
+    int at = 0;
+    while (at < n && nearer(X, &buf[at], &h, pt, cand, ncand)) at++;
+    for (int j = n; j > at; j--) buf[j] = buf[j - 1];
+    buf[at] = h;
+    n++;
+  }
+  if (ne < 0) ne = member_pos;
+  for (int j = 0; j < n && !stopped; j++)
+    if (blend_hit(X, &buf[j], &T, C, &nc, pt, cand, ncand)) stopped = 1;
+  for (int ch = 0; ch < 3; ch++) res->rgb[ch] = C[ch] + T * p->bg[ch];
+  res->T = T;
+  res->nc = nc;
+  res->ne = ne;
+}
+
 static void render_pixel(const render_ctx* X, const int32_t* ids, const int32_t* flags, int64_t L,
                          const double o[3], const double d[3], double clipv, perturb pt,
                          pix_result* res, perturb* cand, int* ncand) {
   const ora_params* p = X->p;
+  if (X->p->kbuffer > 0) {
+    render_pixel_kbuffer(X, ids, flags, L, o, d, clipv, pt, res, cand, ncand);
+    return;
+  }
   double T = 1.0, C[3] = {0, 0, 0};
   int member_pos = 0, nc = 0, ne = -1;
   for (int64_t pos = 0; pos < L; pos++) {
@@ -980,6 +1101,7 @@ int ora_backward(const ora_scene* s, const ora_proj* pr, const ora_camera* c, co
                  const int64_t* tile_start, const int32_t* ids, const int32_t* flags,
                  const double* clip, const double* dL_drgb, const double* dL_dT, double* g_means,
                  double* g_scales, double* g_quats, double* g_opac, double* g_sh) {
+  if (p->kbuffer > 0) return -1; /* the k-buffer's backward is not part of the oracle */
   const int tx = tiles_x(c, p), ty = tiles_y(c, p), ts = p->tile;
   const int K = (s->sh_degree + 1) * (s->sh_degree + 1);
   const int64_t n = s->n;
@@ -1101,6 +1223,7 @@ int ora_backward(const ora_scene* s, const ora_proj* pr, const ora_camera* c, co
 int64_t ora_record(const ora_scene* s, const ora_proj* pr, const ora_camera* c, const ora_params* p,
                    const int64_t* tile_start, const int32_t* ids, const int32_t* flags,
                    const double* clip, int64_t* pix_start, int32_t* contrib, int32_t* clamped) {
+  if (p->kbuffer > 0) return -1;
   const int tx = tiles_x(c, p), ts = p->tile;
   particle_geo* geo = build_geo(s, pr);
   camctx CX;

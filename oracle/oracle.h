@@ -49,6 +49,7 @@ typedef struct {
   int32_t tile, rs_iters;
   double bg[3];
   int32_t kernel_degree; /* n of the generalized Gaussian response (Supp. A); 2 = Gaussian */
+  int32_t kbuffer;       /* 0: tile-order compositing; k > 0: per-ray k-buffer (MLAB, Sec. 4.3) */
 } ora_params;
 
 typedef struct {
@@ -84,6 +85,7 @@ typedef struct {
   double pixel;  /* fisheye image-circle margin (radians)     */
   double diff;   /* an alternative is kept only if it differs by more than this */
   double clip;   /* |hit distance - clip distance| (relative) */
+  double order;  /* |distance difference| of two hits in a k-buffer (relative) */
 } ora_amb;
 
 #define ORA_MAXALT 8
