@@ -30,6 +30,8 @@ Also reported on the same line:
                 responses of degree 3, 4 and 8 (Supp. A), beside degree 2
   depth_clip    the same forward step with a per-pixel clip distance
                 (hybrid rendering, Sec. 6.2)
+  kbuffer_sorted  the same forward step rendered with the per-ray k = 16
+                buffer ("Ours (sorted)", Sec. 4.3)
   cpu_baseline  the FP64 oracle on this host's cores, timed on whole steps of
                 the same two-view batch (projection, binning, every tile)
                 until its time budget is spent
@@ -337,6 +339,8 @@ def main():
     ap.add_argument("--degrees", default="3,4,8",
                     help="generalized-Gaussian degrees (Supp. A) timed on the same forward step")
     ap.add_argument("--no-degrees", action="store_true")
+    ap.add_argument("--no-kbuffer", action="store_true",
+                    help="skip the k-buffer (\"Ours (sorted)\", Sec. 4.3) timing")
     ap.add_argument("--no-clip", action="store_true",
                     help="skip the hybrid-rendering depth-clip timing (Sec. 6.2)")
     ap.add_argument("--no-c3", action="store_true",
@@ -448,6 +452,17 @@ def main():
                                         frac=ach / PEAK_FP32_TFLOPS, flops_per_eval=F_EVAL_CLIP))
         del fc, clip
 
+    # "Ours (sorted)" (Sec. 4.3): the same step with the per-ray k-buffer, k = 16
+    kbuffer = None
+    if not args.no_kbuffer:
+        log("[bench] forward steps with the k = 16 per-ray buffer")
+        fk = bench_forward(gs, cams, max(3, args.steps // 2), 2, R, torch, dict(kbuffer=16))
+        kbuffer = dict(k=16, mpix_per_s=npx / (fk["ms_per_step"] * 1e-3) / 1e6,
+                       stages_ms={"project": fk["stage_ms"][0], "bin": fk["stage_ms"][1],
+                                  "render": fk["stage_ms"][2]},
+                       e_eval=fk["e_eval"])
+        del fk
+
     fwd_bwd = None
     if not args.no_fwd_bwd:
         log("[bench] fwd+bwd on the fisheye view")
@@ -513,6 +528,7 @@ def main():
         "rolling_shutter_3m": c3,
         "generalized_degrees": degrees,
         "depth_clip": depth_clip,
+        "kbuffer_sorted": kbuffer,
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -101,13 +101,21 @@ typedef struct {
  * Supp. A, with lambda = 3^(2-n) / 2 so that every degree has the Gaussian's
  * response at canonical distance 3; n = 2 is the Gaussian exp(-omega^2 / 2)
  * of Eq. 11.  It applies to projection (the extent's cutoff distance),
- * rendering and the backward pass alike. */
+ * rendering and the backward pass alike.
+ * kbuffer k in [0, 16] (default 0): k > 0 selects "Ours (sorted)" of Sec. 4.3
+ * in gut_render -- each pixel keeps its k farthest hits (distance along the
+ * ray of tau_max) in a buffer and blends the nearest as the buffer overflows,
+ * then the buffer nearest first (multi-layer alpha blending); n_contrib then
+ * counts blended hits.  Forward only: gut_render_bwd and gut_serve_create
+ * return GUT_E_UNSUPPORTED for k > 0, as does gut_render with clip_depth or
+ * kernel_degree != 2. */
 typedef struct {
   float ut_alpha, ut_beta, ut_kappa;
   float alpha_min, alpha_max, t_min, near_plane, k_sigma_max;
   int32_t tile, rs_iters;
   float bg[3];
   int32_t kernel_degree;
+  int32_t kbuffer;
 } gut_params;
 
 /* Outputs of gut_project (caller-allocated device arrays).

@@ -52,7 +52,7 @@ class Params(C.Structure):
                 ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
                 ("near_plane", C.c_float), ("k_sigma_max", C.c_float),
                 ("tile", C.c_int32), ("rs_iters", C.c_int32), ("bg", C.c_float * 3),
-                ("kernel_degree", C.c_int32)]
+                ("kernel_degree", C.c_int32), ("kbuffer", C.c_int32)]
 
 
 class Projected(C.Structure):
@@ -168,7 +168,7 @@ def params_struct(params: dict | None = None) -> Params:
         if k == "bg":
             for i in range(3):
                 p.bg[i] = float(v[i])
-        elif k in ("tile", "rs_iters", "kernel_degree"):
+        elif k in ("tile", "rs_iters", "kernel_degree", "kbuffer"):
             setattr(p, k, int(v))
         else:
             setattr(p, k, float(v))

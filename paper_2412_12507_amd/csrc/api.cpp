@@ -205,6 +205,10 @@ gut_status check_params(const gut_params* p) {
     set_error("kernel_degree must be in [2, 8]");
     return GUT_E_INVALID;
   }
+  if (p->kbuffer < 0 || p->kbuffer > 16) {
+    set_error("kbuffer must be in [0, 16]");
+    return GUT_E_INVALID;
+  }
   return GUT_OK;
 }
 
@@ -294,6 +298,7 @@ void gut_default_params(gut_params* p) {
   p->rs_iters = 3;
   p->bg[0] = p->bg[1] = p->bg[2] = 0.0f;
   p->kernel_degree = 2;
+  p->kbuffer = 0;
 }
 
 int64_t gut_num_tiles(const gut_camera* cams, int32_t n_cams, const gut_params* p) {

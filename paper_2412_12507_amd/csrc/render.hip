@@ -300,6 +300,173 @@ gut_status render_batch_launch(const DevCam* d_cams, const DevCam* h_cams, int n
   return GUT_OK;
 }
 
+// "Ours (sorted)" (Sec. 4.3): multi-layer alpha blending with a per-ray
+// buffer of the kKBuf farthest hits.  One 256-thread block per tile, one pixel
+// per thread (wave w owns rows 4w .. 4w + 3), the tile's list consumed in
+// batches of 256 pairs set up as in render_tile.  A hit is a list entry that
+// passes the alpha_min test; its distance along the ray is tau_max |d|.  Each
+// thread keeps its buffer sorted nearest first in registers: slot 0 holds the
+// nearest hit, or a -inf sentinel (alpha 0) while the buffer is not full;
+// capacity k < kKBuf leaves kKBuf - k +inf walls at the far end.  A hit no
+// nearer than slot 0 evicts it -- slot 0 is blended (a sentinel blends to
+// nothing) and the hit is merged into the remaining sorted slots by a fixed
+// compare-select chain; a hit at or before slot 0 is blended at once.  Blending
+// is Eq. 5 with the t_min stop; at the end of the list the buffer is blended
+// nearest first.  Colours are read by entry id when a hit is blended.
+constexpr int kKBuf = 16;
+constexpr int kKThreads = 256;
+
+__device__ __forceinline__ void kbuf_blend(float a, uint32_t e, const float* __restrict__ rgb,
+                                           float t_min, float& T, double (&C)[3], uint32_t& nc,
+                                           bool& done) {
+  if (a <= 0.0f || done) return;  // a sentinel or a wall, or the pixel has stopped
+  const float Tn = fmaf(-a, T, T);
+  if (Tn < t_min) { done = true; return; }
+  const double w = (double)(a * T);
+  C[0] = fma(w, (double)rgb[3 * (size_t)e], C[0]);
+  C[1] = fma(w, (double)rgb[3 * (size_t)e + 1], C[1]);
+  C[2] = fma(w, (double)rgb[3 * (size_t)e + 2], C[2]);
+  T = Tn;
+  nc++;
+}
+
+template <bool RS, bool NE>
+__global__ void __launch_bounds__(kKThreads, 2) render_kbuffer_kernel(
+    DevCam cam, Thresholds th, int n, int cam_idx, int kcap, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
+    const float4* __restrict__ record, const float* __restrict__ rgb, float* __restrict__ out_rgb,
+    float* __restrict__ out_T, uint32_t* __restrict__ out_nc, uint32_t* __restrict__ out_ne) {
+  constexpr int S = Slots<RS, false>::N;
+  __shared__ float4 pd[kKThreads * S];
+  __shared__ uint32_t pf[kKThreads];
+  __shared__ uint32_t pe[kKThreads];
+  __shared__ TileFrameD F;
+  __shared__ WaveBoxes wb;
+  __shared__ float red[12];
+  const int tile = (int)order[cam.tile_base + blockIdx.x];
+  const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  const int px = tx * kTile + (lane & (kTile - 1));
+  const int py = ty * kTile + 4 * wv + (lane >> 4);
+  if (t == 0) tile_frame(cam, tx, ty, &F);
+  __syncthreads();
+  const bool inside = px < cam.W && py < cam.H;
+  float u = 0.f, v = 0.f, dt = 0.f;
+  bool active = inside && pixel_ray(cam, F, px, py, &u, &v, &dt);
+  float umax, vmax, dtmax;
+  tile_bounds<1>(&u, &v, &dt, &active, red, &umax, &vmax, &dtmax);
+  const float l2amin = log2f(th.alpha_min);
+  wave_box<1>(&u, &v, &active, &wb);
+  const float dlen = sqrtf(fmaf(u, u, fmaf(v, v, 1.0f)));
+
+  const uint2 rg = ranges[cam.tile_base + tile];
+  const uint32_t len = __builtin_amdgcn_readfirstlane(rg.y - rg.x);
+  float bd[kKBuf], ba[kKBuf];
+  uint32_t bi[kKBuf];
+#pragma unroll
+  for (int j = 0; j < kKBuf; j++) {
+    bd[j] = j < kcap ? -INFINITY : INFINITY;
+    ba[j] = 0.0f;
+    bi[j] = 0u;
+  }
+  float T = 1.0f;
+  double C[3] = {0.0, 0.0, 0.0};
+  uint32_t nc = 0u, nev = active ? len : 0u;
+  bool done = !active;
+  for (uint32_t b = 0; b < len; b += kKThreads) {
+    if (__syncthreads_count(!done) == 0) break;  // (also publishes wb before the first setup)
+    uint32_t fl = 0u;
+    if (b + t < len) {
+      const uint32_t e = ids[rg.x + b + t];
+      pe[t] = e;
+      fl = pair_setup<RS, false, false, false>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n),
+                                               F, cam, umax, vmax, dtmax, th, l2amin, wb, kKThreads / 64,
+                                               &pd[t * S]);
+    }
+    pf[t] = fl;
+    __syncthreads();
+    bool wave_done = false;
+    for (int h = 0; h < kKThreads / 64 && !wave_done; h++) {
+      unsigned long long m = __builtin_amdgcn_ballot_w64((pf[lane + 64 * h] >> wv) & 1u);
+      while (m) {
+        if (!wave_any(!done)) { wave_done = true; break; }
+        const uint32_t q = 64u * h + (uint32_t)__builtin_ctzll(m);
+        m &= m - 1ull;
+        const float4* P = &pd[q * S];
+        PairRegs<RS> r;
+        load_pair<RS>(P, r);
+        Eval ev;
+        eval_test<RS>(r, P, u, v, dt, &ev);
+        const bool live = ev.ok && !done;
+        if (!wave_any(live)) continue;
+        eval_alpha<RS, false>(r, th, &ev);
+        if (live) {
+          // the hit's distance tau' |d|, tau' = -(o_g . d_g) / |d_g|^2 (the clip test's form)
+          float odg;
+          if (!RS) {
+            const float4 p5 = P[5];
+            odg = fmaf(v, p5.z, fmaf(u, p5.y, p5.x));
+          } else {
+            odg = fmaf(v, r.p4.w, fmaf(u, r.p3.w, r.p5.w));
+            odg = fmaf(dt, fmaf(v, r.p9.w, fmaf(u, r.p8.w, r.p7.w)), odg);
+          }
+          const float dist = -odg * dlen * ev.idd;
+          const uint32_t e = pe[q];
+          const uint32_t idx1 = b + q + 1;
+          if (dist <= bd[0]) {
+            kbuf_blend(ev.a, e, rgb, th.t_min, T, C, nc, done);
+          } else {
+            kbuf_blend(ba[0], bi[0], rgb, th.t_min, T, C, nc, done);
+            // merge the hit into slots 1 .. kKBuf-1 (sorted), dropping slot 0
+#pragma unroll
+            for (int j = 0; j < kKBuf - 1; j++) {
+              const bool nx = bd[j + 1] < dist, here = j == 0 || bd[j] < dist;
+              const float od = nx ? bd[j + 1] : (here ? dist : bd[j]);
+              const float oa = nx ? ba[j + 1] : (here ? ev.a : ba[j]);
+              const uint32_t oi = nx ? bi[j + 1] : (here ? e : bi[j]);
+              bd[j] = od; ba[j] = oa; bi[j] = oi;
+            }
+            const bool last = bd[kKBuf - 1] < dist;
+            ba[kKBuf - 1] = last ? ev.a : ba[kKBuf - 1];
+            bi[kKBuf - 1] = last ? e : bi[kKBuf - 1];
+            bd[kKBuf - 1] = last ? dist : bd[kKBuf - 1];
+          }
+          if (NE && done) nev = idx1;
+        }
+      }
+    }
+  }
+  // the buffer, nearest first
+#pragma unroll
+  for (int j = 0; j < kKBuf; j++) kbuf_blend(ba[j], bi[j], rgb, th.t_min, T, C, nc, done);
+  if (!inside) return;
+  const long long pix = cam.pixel_base + (long long)py * cam.W + px;
+  out_rgb[3 * pix] = (float)fma((double)T, (double)th.bg[0], C[0]);
+  out_rgb[3 * pix + 1] = (float)fma((double)T, (double)th.bg[1], C[1]);
+  out_rgb[3 * pix + 2] = (float)fma((double)T, (double)th.bg[2], C[2]);
+  if (out_T) out_T[pix] = T;
+  if (out_nc) out_nc[pix] = nc;
+  if (NE) out_ne[pix] = nev;
+}
+
+static gut_status launch_render_kbuffer(const DevCam& cam, const Thresholds& th, int n, int cam_idx,
+                                        int kcap, const uint32_t* ranges, const uint32_t* order,
+                                        const uint32_t* ids, const float* record, const float* rgb,
+                                        float* out_rgb, float* out_T, uint32_t* out_nc,
+                                        uint32_t* out_ne, hipStream_t s) {
+  dim3 grid(cam.tiles_x * cam.tiles_y), block(kKThreads);
+#define GUT_RKB(RS, NE)                                                                          \
+  render_kbuffer_kernel<RS, NE><<<grid, block, 0, s>>>(cam, th, n, cam_idx, kcap, (const uint2*)ranges, \
+                                                       order, ids, (const float4*)record, rgb, out_rgb,  \
+                                                       out_T, out_nc, out_ne)
+  const bool rs = cam.shutter == GUT_ROLLING_TOP_TO_BOTTOM;
+  if (rs) { if (out_ne) GUT_RKB(true, true); else GUT_RKB(true, false); }
+  else { if (out_ne) GUT_RKB(false, true); else GUT_RKB(false, false); }
+#undef GUT_RKB
+  GUT_LAUNCH_CHECK();
+  return GUT_OK;
+}
+
 gut_status launch_render(const DevCam& cam, const Thresholds& th, int n, int cam_idx,
                          const uint32_t* ranges, const uint32_t* order, const uint32_t* ids,
                          const float* record, const float* rgb, const float* clip, float* out_rgb,
@@ -385,6 +552,18 @@ extern "C" gut_status gut_render(const gut_projected* proj, int64_t n, const uin
   int64_t T = 0;
   if ((st = prepare_cams(cams, n_cams, *p, dc, &T, nullptr)) != GUT_OK) return st;
   Thresholds th = make_thresholds(*p);
+  if (p->kbuffer > 0) {  // "Ours (sorted)": one launch per camera
+    if (clip_depth || p->kernel_degree != 2) {
+      set_error("the k-buffer render supports neither clip_depth nor kernel_degree != 2");
+      return GUT_E_UNSUPPORTED;
+    }
+    for (int c = 0; c < n_cams; c++)
+      if ((st = launch_render_kbuffer(dc[c], th, (int)n, c, p->kbuffer, tile_ranges, tile_ranges + 2 * T,
+                                      sorted_ids, proj->record, proj->rgb, rgb, T_final, n_contrib,
+                                      n_eval, (hipStream_t)stream)) != GUT_OK)
+        return st;
+    return GUT_OK;
+  }
   for (int c0 = 0; c0 < n_cams;) {
     int c1 = c0 + 1;
     while (c1 < n_cams && c1 - c0 < kMultiCams && dc[c1].shutter == dc[c0].shutter &&

@@ -429,6 +429,10 @@ extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected
                                      size_t ws_bytes, void* stream) {
   gut_status st = check_params(p);
   if (st != GUT_OK) return st;
+  if (p->kbuffer > 0) {
+    set_error("gut_render_bwd: the k-buffer render has no backward");
+    return GUT_E_UNSUPPORTED;
+  }
   if ((st = check_scene(scene, true)) != GUT_OK) return st;
   if (!proj || !proj->record || !proj->rgb || !tile_ranges || !rgb || !T_final || !n_contrib ||
       !d_rgb || !g_means || !g_scales || !g_quats || !g_opacities || !g_sh) {

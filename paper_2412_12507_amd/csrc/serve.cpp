@@ -366,6 +366,10 @@ extern "C" gut_status gut_serve_create(const gut_scene* scene, const gut_params*
                                        int32_t max_batch_cams, gut_server** out) {
   gut_status st = check_params(p);
   if (st != GUT_OK) return st;
+  if (p->kbuffer > 0) {
+    set_error("gut_serve_create: the server renders in tile order (kbuffer must be 0)");
+    return GUT_E_UNSUPPORTED;
+  }
   if ((st = check_scene(scene, true)) != GUT_OK) return st;
   if (!out || max_slots < 1 || max_slots > 16 || max_batch_cams < 1 || max_batch_cams > kMaxCams) {
     set_error("max_slots must be in [1, 16] and max_batch_cams in [1, %d]", kMaxCams);

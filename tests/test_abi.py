@@ -88,6 +88,10 @@ def test_argument_validation_without_launch():
         p5 = L.params_struct(dict(kernel_degree=deg))
         assert lib.gut_project(L.ref(sc), arr, 1, L.ref(p5), L.ref(out), None) == L.GUT_E_INVALID
         assert "kernel_degree" in lib.gut_last_error().decode()
+    for kb in (-1, 17):
+        p6 = L.params_struct(dict(kbuffer=kb))
+        assert lib.gut_project(L.ref(sc), arr, 1, L.ref(p6), L.ref(out), None) == L.GUT_E_INVALID
+        assert "kbuffer" in lib.gut_last_error().decode()
     # too many cameras, bad scene
     assert lib.gut_project(L.ref(sc), arr, 0, L.ref(p), L.ref(out), None) == L.GUT_E_INVALID
     sc.sh_degree = 4
@@ -137,6 +141,15 @@ def test_bin_and_render_validation_without_launch():
     st = lib.gut_render_bwd(L.ref(sc), L.ref(pj), z, z, arr, 1, L.ref(p), None, z, z, z, z, None, z,
                             z, z, z, z, z, 16, None)
     assert st == L.GUT_E_INVALID
+    # the k-buffer render is forward only, without clip or generalized responses
+    pk = L.params_struct(dict(kbuffer=16))
+    st = lib.gut_render_bwd(L.ref(sc), L.ref(pj), z, z, arr, 1, L.ref(pk), None, z, z, z, z, None, z,
+                            z, z, z, z, z, 1 << 30, None)
+    assert st == L.GUT_E_UNSUPPORTED
+    pkd = L.params_struct(dict(kbuffer=16, kernel_degree=4))
+    st = lib.gut_render(L.ref(pj), 10, C.c_void_p(4096), C.c_void_p(4096), arr, 1, L.ref(pkd), None,
+                        z, z, z, None, None)
+    assert st == L.GUT_E_UNSUPPORTED
 
 
 def test_serve_validation_without_launch():
@@ -146,6 +159,8 @@ def test_serve_validation_without_launch():
     h = C.c_void_p()
     # bad slot counts / batch sizes
     assert lib.gut_serve_create(L.ref(sc), L.ref(p), 1 << 30, 0, 8, C.byref(h)) == L.GUT_E_INVALID
+    pk = L.params_struct(dict(kbuffer=16))
+    assert lib.gut_serve_create(L.ref(sc), L.ref(pk), 1 << 30, 2, 8, C.byref(h)) == L.GUT_E_UNSUPPORTED
     assert lib.gut_serve_create(L.ref(sc), L.ref(p), 1 << 30, 2, 0, C.byref(h)) == L.GUT_E_INVALID
     assert lib.gut_serve_create(L.ref(sc), L.ref(p), 1 << 30, 2, 65, C.byref(h)) == L.GUT_E_INVALID
     # budget below the resident records of the scene
