@@ -427,8 +427,6 @@ def to_image(res, cam, params=None, key="rgb"):
 
 
 def backward(scene, proj, cam, bins, dL_drgb, dL_dT=None, params=None, clip=None):
-    if (params or {}).get("kbuffer", 0):
-        raise NotImplementedError("the oracle has no backward for the k-buffer")
     clip = _clip(clip, cam)
     sc = as_oscene(scene)
     p = params or default_params()

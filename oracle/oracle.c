@@ -1097,11 +1097,67 @@ static void finish_particle(const ora_scene* s, const ora_proj* pr, const camctx
   for (int j = 0; j < 3; j++) g_means[3 * i + j] += (gd[j] - dv[j] * pdd) / dist;
 }
 
+/* The k-buffer's blend sequence of one pixel (Sec. 4.3, as in
+ * render_pixel_kbuffer): the contributors in the order they are blended, each
+ * with the transmittance before it.  Returns their number (at most L). */
+typedef struct { contrib_rec r; double dist; } kbuf_item;
+static int64_t kbuffer_sequence(const ora_params* p, const particle_geo* geo, const int32_t* lid,
+                                const int32_t* lfl, int64_t L, const double o[3], const double d[3],
+                                double clipv, contrib_rec* rec) {
+  const int k = p->kbuffer < ORA_MAXK ? p->kbuffer : ORA_MAXK;
+  kbuf_item buf[ORA_MAXK];
+  int n = 0;
+  int64_t m = 0;
+  double T = 1.0;
+  int stopped = 0;
+  /* Eq. 5 for one hit: appended with T before it, unless it would take T below t_min */
+#define KB_BLEND(it)                                              \
+  do {                                                            \
+    const double Tn_ = T * (1.0 - (it).r.a);                      \
+    if (Tn_ < p->t_min) { stopped = 1; break; }                   \
+    rec[m] = (it).r;                                              \
+    rec[m].Tb = T;                                                \
+    m++;                                                          \
+    T = Tn_;                                                      \
+  } while (0)
+  for (int64_t pos = 0; pos < L && !stopped; pos++) {
+    if (!(lfl[pos] & 1)) continue;
+    const particle_geo* g = &geo[lid[pos]];
+    kbuf_item h;
+    double odot, om2;
+    eval_geo(g, o, d, h.r.og, h.r.dg, &odot, &om2);
+    if (odot >= 0) continue;
+    h.dist = hit_distance(odot, h.r.dg, d);
+    if (h.dist > clipv) continue;
+    double a = g->sigma * response(p, om2);
+    h.r.clamped = a > p->alpha_max;
+    if (h.r.clamped) a = p->alpha_max;
+    if (a < p->alpha_min) continue;
+    h.r.id = lid[pos];
+    h.r.a = a;
+    h.r.om2 = om2;
+    if (n == k) {
+      if (!(buf[0].dist < h.dist)) { KB_BLEND(h); continue; }
+      KB_BLEND(buf[0]);
+      if (stopped) continue;
+      for (int j = 1; j < n; j++) buf[j - 1] = buf[j];
+      n--;
+    }
+    int at = 0;
+    while (at < n && buf[at].dist < h.dist) at++;
+    for (int j = n; j > at; j--) buf[j] = buf[j - 1];
+    buf[at] = h;
+    n++;
+  }
+  for (int j = 0; j < n && !stopped; j++) KB_BLEND(buf[j]);
+#undef KB_BLEND
+  return m;
+}
+
 int ora_backward(const ora_scene* s, const ora_proj* pr, const ora_camera* c, const ora_params* p,
                  const int64_t* tile_start, const int32_t* ids, const int32_t* flags,
                  const double* clip, const double* dL_drgb, const double* dL_dT, double* g_means,
                  double* g_scales, double* g_quats, double* g_opac, double* g_sh) {
-  if (p->kbuffer > 0) return -1; /* the k-buffer's backward is not part of the oracle */
   const int tx = tiles_x(c, p), ty = tiles_y(c, p), ts = p->tile;
   const int K = (s->sh_degree + 1) * (s->sh_degree + 1);
   const int64_t n = s->n;
@@ -1137,10 +1193,14 @@ int ora_backward(const ora_scene* s, const ora_proj* pr, const ora_camera* c, co
           if (gC[0] == 0.0 && gC[1] == 0.0 && gC[2] == 0.0 && gT == 0.0) continue;
           double o[3], d[3], pm;
           if (!pixel_ray_ctx(&CX, px + 0.5, py + 0.5, o, d, &pm)) continue;
-          /* forward pass, keeping each contributor (Eq. 5) */
+          /* forward pass, keeping each contributor (Eq. 5) in blend order */
           double T = 1.0;
           int m = 0;
-          for (int64_t pos = 0; pos < L; pos++) {
+          if (p->kbuffer > 0) {
+            m = (int)kbuffer_sequence(p, geo, lid, lfl, L, o, d, clip ? clip[pix] : INFINITY, rec);
+            if (m > 0) T = rec[m - 1].Tb * (1.0 - rec[m - 1].a);
+          }
+          for (int64_t pos = 0; pos < L && p->kbuffer <= 0; pos++) {
             if (!(lfl[pos] & 1)) continue;
             const particle_geo* g = &geo[lid[pos]];
             double og[3], dg[3], odot, om2;
@@ -1223,19 +1283,28 @@ int ora_backward(const ora_scene* s, const ora_proj* pr, const ora_camera* c, co
 int64_t ora_record(const ora_scene* s, const ora_proj* pr, const ora_camera* c, const ora_params* p,
                    const int64_t* tile_start, const int32_t* ids, const int32_t* flags,
                    const double* clip, int64_t* pix_start, int32_t* contrib, int32_t* clamped) {
-  if (p->kbuffer > 0) return -1;
   const int tx = tiles_x(c, p), ts = p->tile;
   particle_geo* geo = build_geo(s, pr);
   camctx CX;
   camctx_init(&CX, c);
   const int64_t npx = (int64_t)c->width * c->height;
-  int64_t total = 0;
+  int64_t total = 0, cap = 0;
+  contrib_rec* rec = NULL;
   for (int64_t pix = 0; pix < npx; pix++) {
     int px = (int)(pix % c->width), py = (int)(pix / c->width);
     int64_t t = (int64_t)(py / ts) * tx + px / ts;
     double o[3], d[3], pm;
     if (contrib) pix_start[pix] = total;
     if (!pixel_ray_ctx(&CX, px + 0.5, py + 0.5, o, d, &pm)) continue;
+    if (p->kbuffer > 0) {  /* the contributors in blend order */
+      const int64_t L = tile_start[t + 1] - tile_start[t];
+      if (L > cap) { cap = L; rec = (contrib_rec*)realloc(rec, (size_t)cap * sizeof(contrib_rec)); }
+      const int64_t m = kbuffer_sequence(p, geo, &ids[tile_start[t]], &flags[tile_start[t]], L, o, d,
+                                         clip ? clip[pix] : INFINITY, rec);
+      for (int64_t j = 0; j < m; j++, total++)
+        if (contrib) { contrib[total] = rec[j].id; clamped[total] = rec[j].clamped; }
+      continue;
+    }
     double T = 1.0;
     for (int64_t pos = tile_start[t]; pos < tile_start[t + 1]; pos++) {
       if (!(flags[pos] & 1)) continue;
@@ -1256,6 +1325,7 @@ int64_t ora_record(const ora_scene* s, const ora_proj* pr, const ora_camera* c, 
     }
   }
   if (contrib) pix_start[npx] = total;
+  free(rec);
   free(geo);
   return total;
 }

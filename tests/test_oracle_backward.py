@@ -54,8 +54,9 @@ def test_dalpha_dmu_closed_form():
     assert checked >= 10
 
 
-def _fd_check(scene, cam, seed, h=1e-6, bg=(0.0, 0.0, 0.0), use_dT=True, kernel_degree=2, clip=None):
-    p = O.default_params(bg=bg, kernel_degree=kernel_degree)
+def _fd_check(scene, cam, seed, h=1e-6, bg=(0.0, 0.0, 0.0), use_dT=True, kernel_degree=2, clip=None,
+              kbuffer=0):
+    p = O.default_params(bg=bg, kernel_degree=kernel_degree, kbuffer=kbuffer)
     sc = O.as_oscene(scene)
     pr = O.project(sc, cam, p)
     bins = O.bin_tiles(pr, cam, p)
@@ -132,3 +133,14 @@ def test_backward_central_differences_with_depth_clip(kind):
     worst = _fd_check(scene, cam, seed=3031, bg=(0.1, 0.3, 0.6), clip=clip)
     for k, v in worst.items():
         assert v < 1e-6, (kind, k, v)
+
+
+@pytest.mark.parametrize("kind,k", [("pinhole", 16), ("fisheye", 2), ("rolling", 4)])
+def test_backward_central_differences_kbuffer(kind, k):
+    """The k-buffer ("Ours (sorted)", Sec. 4.3): the contributors in blend
+    order (a second implementation of the buffer, which must reproduce the
+    render), their gradients against central differences of the frozen loss."""
+    scene, cam = G.config4_gradcheck(kind, log_scale_mean=-2.2)
+    worst = _fd_check(scene, cam, seed=3040 + k, bg=(0.1, 0.3, 0.6), kbuffer=k)
+    for key, v in worst.items():
+        assert v < 1e-6, (kind, k, key, v)
