@@ -175,16 +175,16 @@ def bench_forward(gs, cams, steps, warmup, R, torch, params=None, clip=None):
                 n_visible=int((proj.tiles > 0).sum().item()), img=img)
 
 
-def bench_fwd_bwd(scene, cam, steps, warmup, R, G, torch):
+def bench_fwd_bwd(scene, cam, steps, warmup, R, G, torch, params=None):
     """Forward + L1 loss + backward on one view, the differentiation workload."""
     gs = R.GaussianScene.from_host(scene)
     tgt_scene = R.GaussianScene.from_host(G.perturb_raw(scene, seed=3004))
-    _, _, timg = R.forward(tgt_scene, [cam])
+    _, _, timg = R.forward(tgt_scene, [cam], params)
     target = timg.rgb.clone()
     del tgt_scene, timg
     proj = R.alloc_projection(gs.n, 1, gs.means.device)
-    R.project(gs, [cam], out=proj)
-    bins = R.bin_tiles(proj, [cam])
+    R.project(gs, [cam], params, out=proj)
+    bins = R.bin_tiles(proj, [cam], params)
     img = R.alloc_image([cam], gs.means.device)
     grads = dict(means=torch.empty_like(gs.means), scales=torch.empty_like(gs.scales),
                  quats=torch.empty_like(gs.quats), opacities=torch.empty_like(gs.opacities),
@@ -194,15 +194,15 @@ def bench_fwd_bwd(scene, cam, steps, warmup, R, G, torch):
 
     def step():
         nonlocal ws
-        R.project(gs, [cam], out=proj)
-        R.bin_tiles(proj, [cam], bins=bins)
-        R.render(proj, bins, [cam], out=img)
+        R.project(gs, [cam], params, out=proj)
+        R.bin_tiles(proj, [cam], params, bins=bins)
+        R.render(proj, bins, [cam], params, out=img)
         d_rgb = torch.sign(img.rgb - target) / npx          # dL/dC of mean |C - C_target|
         if ws is None:
             from paper_2412_12507_amd import _lib as L
             need = L.load().gut_render_bwd_workspace_bytes(gs.n, 1)
             ws = torch.empty(need, dtype=torch.uint8, device=gs.means.device)
-        R.render_backward(gs, proj, bins, [cam], img, d_rgb, None, grads=grads, workspace=ws)
+        R.render_backward(gs, proj, bins, [cam], img, d_rgb, None, params, grads=grads, workspace=ws)
 
     for _ in range(warmup):
         step()
@@ -467,6 +467,10 @@ def main():
     if not args.no_fwd_bwd:
         log("[bench] fwd+bwd on the fisheye view")
         fwd_bwd = bench_fwd_bwd(scene, cams[1], max(3, args.steps // 2), 2, R, G, torch)
+        if kbuffer is not None:
+            log("[bench] fwd+bwd on the fisheye view, k = 16 per-ray buffer")
+            kb = bench_fwd_bwd(scene, cams[1], max(3, args.steps // 4), 1, R, G, torch, dict(kbuffer=16))
+            kbuffer["fwd_bwd_ms_per_view"] = kb["ms_per_view"]
 
     c3 = None
     if not args.no_c3:

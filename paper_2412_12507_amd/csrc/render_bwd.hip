@@ -252,6 +252,193 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
   }
 }
 
+// Backward of the k-buffer render ("Ours (sorted)", Sec. 4.3).  It replays
+// render_kbuffer_kernel bit for bit (same blocks, pixels, pair setup, tests,
+// distances and buffer chain) and differentiates each hit when it is blended,
+// in blend order: the Supp. B recursion of render_bwd_kernel (T and
+// Z = gC . (C - C_<=j) carried forward from the forward's outputs) gives
+// dL/dalpha there.  The geometric factors a blend needs -- the closest-point
+// vector p and rho = alpha_raw / sigma -- are formed when the hit enters the
+// buffer (its pair is then in LDS) and travel with it; rho carries the sign
+// of the alpha_max clamp.  Blended hits of one wave belong to different
+// particles, so each lane adds its 13 values with its own FP64 atomics.
+constexpr int kKBufB = 16;
+constexpr int kKThreadsB = 256;
+
+struct KBufGrad {
+  double* acc;
+  double* acc_rgb;
+  const float* rgb;
+  int n, cam_idx;
+  float t_min;
+};
+
+__device__ __forceinline__ void kbuf_blend_bwd(float a, uint32_t e, float px_, float py_, float pz_,
+                                               float rho, const KBufGrad& K, const float (&gC)[3],
+                                               const double (&gCd)[3], float gTT, float& T, double& Z,
+                                               bool& done) {
+  if (a <= 0.0f || done) return;
+  const float Tb = T;
+  const float Tn = fmaf(-a, Tb, Tb);
+  if (Tn < K.t_min) { done = true; return; }
+  T = Tn;
+  const float wgt = a * Tb;
+  const double c0 = K.rgb[3 * (size_t)e], c1 = K.rgb[3 * (size_t)e + 1], c2 = K.rgb[3 * (size_t)e + 2];
+  const double D = fma(gCd[0], c0, fma(gCd[1], c1, gCd[2] * c2));
+  Z = fma(-(double)wgt, D, Z);
+  const float inv1m = __builtin_amdgcn_rcpf(1.0f - a);
+  float gA = fmaf(Tb, (float)D, -inv1m * ((float)Z + gTT));
+  if (rho < 0.0f) gA = 0.0f;  // alpha = alpha_max carries no gradient
+  const float c = -a * gA;    // 2 dL/domega^2
+  const int i = (int)(e - (uint32_t)K.cam_idx * (uint32_t)K.n);
+  double* g = K.acc + (long long)i * kAcc;
+  const float v[kAcc] = {c * px_ * px_, c * px_ * py_, c * px_ * pz_, c * py_ * py_, c * py_ * pz_,
+                         c * pz_ * pz_, c * px_, c * py_, c * pz_, gA * fabsf(rho)};
+#pragma unroll
+  for (int k = 0; k < kAcc; k++)
+    if (v[k] != 0.0f) atomicAdd(&g[k], (double)v[k]);
+#pragma unroll
+  for (int ch = 0; ch < 3; ch++) {
+    const float w = wgt * gC[ch];
+    if (w != 0.0f) atomicAdd(&K.acc_rgb[3 * (long long)e + ch], (double)w);
+  }
+}
+
+template <bool RS>
+__global__ void __launch_bounds__(kKThreadsB, 1) render_kbuffer_bwd_kernel(
+    DevCam cam, Thresholds th, int n, int cam_idx, int kcap, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
+    const float4* __restrict__ record, const float* __restrict__ rgb, const float* __restrict__ out_rgb,
+    const float* __restrict__ out_T, const float* __restrict__ d_rgb, const float* __restrict__ d_T,
+    double* __restrict__ acc, double* __restrict__ acc_rgb) {
+  constexpr int S = Slots<RS, true>::N;
+  __shared__ float4 pd[kKThreadsB * S];
+  __shared__ uint32_t pf[kKThreadsB];
+  __shared__ uint32_t pe[kKThreadsB];
+  __shared__ TileFrameD F;
+  __shared__ WaveBoxes wb;
+  __shared__ float red[12];
+  const int tile = (int)order[cam.tile_base + blockIdx.x];
+  const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  const int px = tx * kTile + (lane & (kTile - 1));
+  const int py = ty * kTile + 4 * wv + (lane >> 4);
+  if (t == 0) tile_frame(cam, tx, ty, &F);
+  __syncthreads();
+  const bool inside = px < cam.W && py < cam.H;
+  float u = 0.f, v = 0.f, dt = 0.f;
+  bool active = inside && pixel_ray(cam, F, px, py, &u, &v, &dt);
+  float umax, vmax, dtmax;
+  tile_bounds<1>(&u, &v, &dt, &active, red, &umax, &vmax, &dtmax);
+  const float l2amin = log2f(th.alpha_min);
+  wave_box<1>(&u, &v, &active, &wb);
+  const float dlen = sqrtf(fmaf(u, u, fmaf(v, v, 1.0f)));
+
+  // the loss gradients and Z = gC . C_out (FP64), as in render_bwd_kernel
+  float gC[3] = {0.f, 0.f, 0.f}, gTT = 0.f;
+  double gCd[3] = {0.0, 0.0, 0.0}, Z = 0.0;
+  if (active) {
+    const long long pix = cam.pixel_base + (long long)py * cam.W + px;
+    gTT = (d_T ? d_T[pix] : 0.0f) * out_T[pix];
+    for (int c = 0; c < 3; c++) {
+      gC[c] = d_rgb[3 * pix + c];
+      gCd[c] = gC[c];
+      Z = fma(gCd[c], (double)out_rgb[3 * pix + c], Z);
+    }
+  }
+  const KBufGrad K = {acc, acc_rgb, rgb, n, cam_idx, th.t_min};
+
+  const uint2 rg = ranges[cam.tile_base + tile];
+  const uint32_t len = __builtin_amdgcn_readfirstlane(rg.y - rg.x);
+  float bd[kKBufB], ba[kKBufB], bx[kKBufB], by[kKBufB], bz[kKBufB], br[kKBufB];
+  uint32_t bi[kKBufB];
+#pragma unroll
+  for (int j = 0; j < kKBufB; j++) {
+    bd[j] = j < kcap ? -INFINITY : INFINITY;
+    ba[j] = 0.0f; bx[j] = 0.0f; by[j] = 0.0f; bz[j] = 0.0f; br[j] = 0.0f;
+    bi[j] = 0u;
+  }
+  float T = 1.0f;
+  bool done = !active;
+  for (uint32_t b = 0; b < len; b += kKThreadsB) {
+    if (__syncthreads_count(!done) == 0) break;
+    uint32_t fl = 0u;
+    if (b + t < len) {
+      const uint32_t e = ids[rg.x + b + t];
+      pe[t] = e;
+      fl = pair_setup<RS, true, false, false>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n),
+                                              F, cam, umax, vmax, dtmax, th, l2amin, wb, kKThreadsB / 64,
+                                              &pd[t * S]);
+    }
+    pf[t] = fl;
+    __syncthreads();
+    bool wave_done = false;
+    for (int h = 0; h < kKThreadsB / 64 && !wave_done; h++) {
+      unsigned long long m = __builtin_amdgcn_ballot_w64((pf[lane + 64 * h] >> wv) & 1u);
+      while (m) {
+        if (!wave_any(!done)) { wave_done = true; break; }
+        const uint32_t q = 64u * h + (uint32_t)__builtin_ctzll(m);
+        m &= m - 1ull;
+        const float4* P = &pd[q * S];
+        PairRegs<RS> r;
+        load_pair<RS>(P, r);
+        Eval ev;
+        eval_test<RS>(r, P, u, v, dt, &ev);
+        const bool live = ev.ok && !done;
+        if (!wave_any(live)) continue;
+        eval_alpha<RS, false>(r, th, &ev);
+        if (live) {
+          float odg;
+          if (!RS) {
+            const float4 p5 = P[5];
+            odg = fmaf(v, p5.z, fmaf(u, p5.y, p5.x));
+          } else {
+            odg = fmaf(v, r.p4.w, fmaf(u, r.p3.w, r.p5.w));
+            odg = fmaf(dt, fmaf(v, r.p9.w, fmaf(u, r.p8.w, r.p7.w)), odg);
+          }
+          const float dist = -odg * dlen * ev.idd;
+          const uint32_t e = pe[q];
+          // the closest point p = d_g x (o_g x d_g) / |d_g|^2 and rho, as in render_bwd_kernel
+          float3 dg, cr;
+          pair_vectors<RS>(P, ev, u, v, &dg, &cr);
+          float3 pv = cross3f_fma(dg, cr);
+          pv = f3(pv.x * ev.idd, pv.y * ev.idd, pv.z * ev.idd);
+          const float rho0 = ev.araw * __builtin_amdgcn_exp2f(-r.lsig);
+          const float rho = ev.clamped ? -rho0 - 1e-30f : rho0;
+          if (dist <= bd[0]) {
+            kbuf_blend_bwd(ev.a, e, pv.x, pv.y, pv.z, rho, K, gC, gCd, gTT, T, Z, done);
+          } else {
+            kbuf_blend_bwd(ba[0], bi[0], bx[0], by[0], bz[0], br[0], K, gC, gCd, gTT, T, Z, done);
+#pragma unroll
+            for (int j = 0; j < kKBufB - 1; j++) {
+              const bool nx = bd[j + 1] < dist, here = j == 0 || bd[j] < dist;
+              bd[j] = nx ? bd[j + 1] : (here ? dist : bd[j]);
+              ba[j] = nx ? ba[j + 1] : (here ? ev.a : ba[j]);
+              bi[j] = nx ? bi[j + 1] : (here ? e : bi[j]);
+              bx[j] = nx ? bx[j + 1] : (here ? pv.x : bx[j]);
+              by[j] = nx ? by[j + 1] : (here ? pv.y : by[j]);
+              bz[j] = nx ? bz[j + 1] : (here ? pv.z : bz[j]);
+              br[j] = nx ? br[j + 1] : (here ? rho : br[j]);
+            }
+            const int L = kKBufB - 1;
+            const bool last = bd[L] < dist;
+            ba[L] = last ? ev.a : ba[L];
+            bi[L] = last ? e : bi[L];
+            bx[L] = last ? pv.x : bx[L];
+            by[L] = last ? pv.y : by[L];
+            bz[L] = last ? pv.z : bz[L];
+            br[L] = last ? rho : br[L];
+            bd[L] = last ? dist : bd[L];
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kKBufB; j++)
+    kbuf_blend_bwd(ba[j], bi[j], bx[j], by[j], bz[j], br[j], K, gC, gCd, gTT, T, Z, done);
+}
+
 // K7a: camera-independent part of the per-particle chain (FP64: the
 // quaternion gradient is a difference of terms of the size of dL/dR).
 __global__ void particle_grad_kernel(int n, const float* __restrict__ scales,
@@ -429,8 +616,8 @@ extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected
                                      size_t ws_bytes, void* stream) {
   gut_status st = check_params(p);
   if (st != GUT_OK) return st;
-  if (p->kbuffer > 0) {
-    set_error("gut_render_bwd: the k-buffer render has no backward");
+  if (p->kbuffer > 0 && (clip_depth || p->kernel_degree != 2)) {
+    set_error("the k-buffer render supports neither clip_depth nor kernel_degree != 2");
     return GUT_E_UNSUPPORTED;
   }
   if ((st = check_scene(scene, true)) != GUT_OK) return st;
@@ -468,7 +655,19 @@ extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected
   zero_f64_kernel<<<(unsigned)((m2 + 255) / 256), 256, 0, s>>>(acc_rgb, m2);
   GUT_LAUNCH_CHECK();
   Thresholds th = make_thresholds(*p);
-  for (int c = 0; c < n_cams; c++) {
+  for (int c = 0; c < n_cams && p->kbuffer > 0; c++) {  // "Ours (sorted)"
+    dim3 grid(dc[c].tiles_x * dc[c].tiles_y), block(kKThreadsB);
+    if (dc[c].shutter == GUT_ROLLING_TOP_TO_BOTTOM)
+      render_kbuffer_bwd_kernel<true><<<grid, block, 0, s>>>(
+          dc[c], th, (int)n, c, p->kbuffer, (const uint2*)tile_ranges, order, sorted_ids,
+          (const float4*)proj->record, proj->rgb, rgb, T_final, d_rgb, d_T, acc, acc_rgb);
+    else
+      render_kbuffer_bwd_kernel<false><<<grid, block, 0, s>>>(
+          dc[c], th, (int)n, c, p->kbuffer, (const uint2*)tile_ranges, order, sorted_ids,
+          (const float4*)proj->record, proj->rgb, rgb, T_final, d_rgb, d_T, acc, acc_rgb);
+    GUT_LAUNCH_CHECK();
+  }
+  for (int c = 0; c < n_cams && p->kbuffer == 0; c++) {
     dim3 grid(dc[c].tiles_x * dc[c].tiles_y), block(kBwThreads);
 #define GUT_RBW(RS, GEN, CLIP)                                                                      \
   render_bwd_kernel<RS, GEN, CLIP><<<grid, block, 0, s>>>(                                           \
