@@ -273,14 +273,20 @@ struct KBufGrad {
   float t_min;
 };
 
-__device__ __forceinline__ void kbuf_blend_bwd(float a, uint32_t e, float px_, float py_, float pz_,
+// One blend of the replay (Eq. 5 with the t_min stop, as kbuf_blend) and the
+// hit's 13 gradient values: G (6), h (3), dL/dsigma, then dL/dc (3).
+// Returns false (values zero) for a sentinel, a wall, a stopped pixel or a
+// hit that would cross t_min.
+__device__ __forceinline__ bool kbuf_blend_bwd(float a, uint32_t e, float px_, float py_, float pz_,
                                                float rho, const KBufGrad& K, const float (&gC)[3],
                                                const double (&gCd)[3], float gTT, float& T, double& Z,
-                                               bool& done) {
-  if (a <= 0.0f || done) return;
+                                               bool& done, float (&v)[16]) {
+#pragma unroll
+  for (int k = 0; k < 16; k++) v[k] = 0.0f;
+  if (a <= 0.0f || done) return false;
   const float Tb = T;
   const float Tn = fmaf(-a, Tb, Tb);
-  if (Tn < K.t_min) { done = true; return; }
+  if (Tn < K.t_min) { done = true; return false; }
   T = Tn;
   const float wgt = a * Tb;
   const double c0 = K.rgb[3 * (size_t)e], c1 = K.rgb[3 * (size_t)e + 1], c2 = K.rgb[3 * (size_t)e + 2];
@@ -290,17 +296,42 @@ __device__ __forceinline__ void kbuf_blend_bwd(float a, uint32_t e, float px_, f
   float gA = fmaf(Tb, (float)D, -inv1m * ((float)Z + gTT));
   if (rho < 0.0f) gA = 0.0f;  // alpha = alpha_max carries no gradient
   const float c = -a * gA;    // 2 dL/domega^2
-  const int i = (int)(e - (uint32_t)K.cam_idx * (uint32_t)K.n);
-  double* g = K.acc + (long long)i * kAcc;
-  const float v[kAcc] = {c * px_ * px_, c * px_ * py_, c * px_ * pz_, c * py_ * py_, c * py_ * pz_,
-                         c * pz_ * pz_, c * px_, c * py_, c * pz_, gA * fabsf(rho)};
+  v[0] = c * px_ * px_; v[1] = c * px_ * py_; v[2] = c * px_ * pz_;
+  v[3] = c * py_ * py_; v[4] = c * py_ * pz_; v[5] = c * pz_ * pz_;
+  v[6] = c * px_; v[7] = c * py_; v[8] = c * pz_;
+  v[9] = gA * fabsf(rho);
+  v[10] = wgt * gC[0]; v[11] = wgt * gC[1]; v[12] = wgt * gC[2];
+  return true;
+}
+
+// Adds the wave's blended values to the per-particle sums.  Lanes that
+// blended the same entry in this step (neighbouring pixels usually blend the
+// same particle together) are summed across the wave first, one entry at a
+// time, so each distinct entry costs 13 atomics instead of 13 per lane.
+// Called by the whole wave.
+__device__ __forceinline__ void kbuf_add_wave(bool valid, uint32_t e, const float (&v)[16],
+                                              const KBufGrad& K) {
+  const int lane = threadIdx.x & 63;
+  uint32_t key = valid ? e : 0xffffffffu;
+  while (true) {
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(key != 0xffffffffu);
+    if (!m) break;
+    const uint32_t e0 = (uint32_t)__builtin_amdgcn_readlane((int)key, (int)__builtin_ctzll(m));
+    const bool mine = key == e0;
+    float g[16];
 #pragma unroll
-  for (int k = 0; k < kAcc; k++)
-    if (v[k] != 0.0f) atomicAdd(&g[k], (double)v[k]);
-#pragma unroll
-  for (int ch = 0; ch < 3; ch++) {
-    const float w = wgt * gC[ch];
-    if (w != 0.0f) atomicAdd(&K.acc_rgb[3 * (long long)e + ch], (double)w);
+    for (int k = 0; k < 16; k++) g[k] = mine ? v[k] : 0.0f;
+    const float tot = wave_reduce16(g);  // lane 4k holds value k
+    const int k = lane >> 2;
+    if ((lane & 3) == 0 && k < kAcc + 3 && tot != 0.0f) {
+      if (k < kAcc) {
+        const int i = (int)(e0 - (uint32_t)K.cam_idx * (uint32_t)K.n);
+        atomicAdd(&K.acc[(long long)i * kAcc + k], (double)tot);
+      } else {
+        atomicAdd(&K.acc_rgb[3 * (long long)e0 + (k - kAcc)], (double)tot);
+      }
+    }
+    if (mine) key = 0xffffffffu;
   }
 }
 
@@ -387,6 +418,11 @@ __global__ void __launch_bounds__(kKThreadsB, 1) render_kbuffer_bwd_kernel(
         const bool live = ev.ok && !done;
         if (!wave_any(live)) continue;
         eval_alpha<RS, false>(r, th, &ev);
+        bool valid = false;
+        uint32_t be = 0u;
+        float vals[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++) vals[k] = 0.0f;
         if (live) {
           float odg;
           if (!RS) {
@@ -406,9 +442,12 @@ __global__ void __launch_bounds__(kKThreadsB, 1) render_kbuffer_bwd_kernel(
           const float rho0 = ev.araw * __builtin_amdgcn_exp2f(-r.lsig);
           const float rho = ev.clamped ? -rho0 - 1e-30f : rho0;
           if (dist <= bd[0]) {
-            kbuf_blend_bwd(ev.a, e, pv.x, pv.y, pv.z, rho, K, gC, gCd, gTT, T, Z, done);
+            valid = kbuf_blend_bwd(ev.a, e, pv.x, pv.y, pv.z, rho, K, gC, gCd, gTT, T, Z, done, vals);
+            be = e;
           } else {
-            kbuf_blend_bwd(ba[0], bi[0], bx[0], by[0], bz[0], br[0], K, gC, gCd, gTT, T, Z, done);
+            valid = kbuf_blend_bwd(ba[0], bi[0], bx[0], by[0], bz[0], br[0], K, gC, gCd, gTT, T, Z, done,
+                                   vals);
+            be = bi[0];
 #pragma unroll
             for (int j = 0; j < kKBufB - 1; j++) {
               const bool nx = bd[j + 1] < dist, here = j == 0 || bd[j] < dist;
@@ -431,12 +470,17 @@ __global__ void __launch_bounds__(kKThreadsB, 1) render_kbuffer_bwd_kernel(
             bd[L] = last ? dist : bd[L];
           }
         }
+        kbuf_add_wave(valid, be, vals, K);  // the whole wave, after the divergent part
       }
     }
   }
 #pragma unroll
-  for (int j = 0; j < kKBufB; j++)
-    kbuf_blend_bwd(ba[j], bi[j], bx[j], by[j], bz[j], br[j], K, gC, gCd, gTT, T, Z, done);
+  for (int j = 0; j < kKBufB; j++) {
+    float vals[16];
+    const bool valid = kbuf_blend_bwd(ba[j], bi[j], bx[j], by[j], bz[j], br[j], K, gC, gCd, gTT, T, Z,
+                                      done, vals);
+    kbuf_add_wave(valid, bi[j], vals, K);
+  }
 }
 
 // K7a: camera-independent part of the per-particle chain (FP64: the
