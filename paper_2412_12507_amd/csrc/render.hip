@@ -330,11 +330,12 @@ __device__ __forceinline__ void kbuf_blend(float a, uint32_t e, const float* __r
   nc++;
 }
 
-template <bool RS, bool NE>
+template <bool RS, bool NE, bool CLIP>
 __global__ void __launch_bounds__(kKThreads, 2) render_kbuffer_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, int kcap, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
-    const float4* __restrict__ record, const float* __restrict__ rgb, float* __restrict__ out_rgb,
+    const float4* __restrict__ record, const float* __restrict__ rgb, const float* __restrict__ clip,
+    float* __restrict__ out_rgb,
     float* __restrict__ out_T, uint32_t* __restrict__ out_nc, uint32_t* __restrict__ out_ne) {
   constexpr int S = Slots<RS, false>::N;
   __shared__ float4 pd[kKThreads * S];
@@ -358,6 +359,11 @@ __global__ void __launch_bounds__(kKThreads, 2) render_kbuffer_kernel(
   const float l2amin = log2f(th.alpha_min);
   wave_box<1>(&u, &v, &active, &wb);
   const float dlen = sqrtf(fmaf(u, u, fmaf(v, v, 1.0f)));
+  float clipv = 0.0f;  // hybrid rendering (Sec. 6.2), as in render_tile
+  if (CLIP) {
+    if (active) clipv = clip[cam.pixel_base + (long long)py * cam.W + px];
+    wave_clip_max<1>(&clipv, &active, &wb);
+  }
 
   const uint2 rg = ranges[cam.tile_base + tile];
   const uint32_t len = __builtin_amdgcn_readfirstlane(rg.y - rg.x);
@@ -379,9 +385,9 @@ __global__ void __launch_bounds__(kKThreads, 2) render_kbuffer_kernel(
     if (b + t < len) {
       const uint32_t e = ids[rg.x + b + t];
       pe[t] = e;
-      fl = pair_setup<RS, false, false, false>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n),
-                                               F, cam, umax, vmax, dtmax, th, l2amin, wb, kKThreads / 64,
-                                               &pd[t * S]);
+      fl = pair_setup<RS, false, false, CLIP>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n),
+                                              F, cam, umax, vmax, dtmax, th, l2amin, wb, kKThreads / 64,
+                                              &pd[t * S]);
     }
     pf[t] = fl;
     __syncthreads();
@@ -397,6 +403,7 @@ __global__ void __launch_bounds__(kKThreads, 2) render_kbuffer_kernel(
         load_pair<RS>(P, r);
         Eval ev;
         eval_test<RS>(r, P, u, v, dt, &ev);
+        if (CLIP) ev.ok = ev.ok && !behind_clip<RS>(r, P, u, v, dt, dlen, clipv, ev.dd);
         const bool live = ev.ok && !done;
         if (!wave_any(live)) continue;
         eval_alpha<RS, false>(r, th, &ev);
@@ -452,16 +459,20 @@ __global__ void __launch_bounds__(kKThreads, 2) render_kbuffer_kernel(
 static gut_status launch_render_kbuffer(const DevCam& cam, const Thresholds& th, int n, int cam_idx,
                                         int kcap, const uint32_t* ranges, const uint32_t* order,
                                         const uint32_t* ids, const float* record, const float* rgb,
-                                        float* out_rgb, float* out_T, uint32_t* out_nc,
-                                        uint32_t* out_ne, hipStream_t s) {
+                                        const float* clip, float* out_rgb, float* out_T,
+                                        uint32_t* out_nc, uint32_t* out_ne, hipStream_t s) {
   dim3 grid(cam.tiles_x * cam.tiles_y), block(kKThreads);
-#define GUT_RKB(RS, NE)                                                                          \
-  render_kbuffer_kernel<RS, NE><<<grid, block, 0, s>>>(cam, th, n, cam_idx, kcap, (const uint2*)ranges, \
-                                                       order, ids, (const float4*)record, rgb, out_rgb,  \
-                                                       out_T, out_nc, out_ne)
+#define GUT_RKB(RS, NE, CLIP)                                                                     \
+  render_kbuffer_kernel<RS, NE, CLIP><<<grid, block, 0, s>>>(cam, th, n, cam_idx, kcap,              \
+                                                             (const uint2*)ranges, order, ids,          \
+                                                             (const float4*)record, rgb, clip, out_rgb, \
+                                                             out_T, out_nc, out_ne)
+#define GUT_RKB1(RS, NE) \
+  do { if (clip) GUT_RKB(RS, NE, true); else GUT_RKB(RS, NE, false); } while (0)
   const bool rs = cam.shutter == GUT_ROLLING_TOP_TO_BOTTOM;
-  if (rs) { if (out_ne) GUT_RKB(true, true); else GUT_RKB(true, false); }
-  else { if (out_ne) GUT_RKB(false, true); else GUT_RKB(false, false); }
+  if (rs) { if (out_ne) GUT_RKB1(true, true); else GUT_RKB1(true, false); }
+  else { if (out_ne) GUT_RKB1(false, true); else GUT_RKB1(false, false); }
+#undef GUT_RKB1
 #undef GUT_RKB
   GUT_LAUNCH_CHECK();
   return GUT_OK;
@@ -553,14 +564,15 @@ extern "C" gut_status gut_render(const gut_projected* proj, int64_t n, const uin
   if ((st = prepare_cams(cams, n_cams, *p, dc, &T, nullptr)) != GUT_OK) return st;
   Thresholds th = make_thresholds(*p);
   if (p->kbuffer > 0) {  // "Ours (sorted)": one launch per camera
-    if (clip_depth || p->kernel_degree != 2) {
-      set_error("the k-buffer render supports neither clip_depth nor kernel_degree != 2");
+    if (p->kernel_degree != 2) {
+      set_error("the k-buffer render does not support kernel_degree != 2");
       return GUT_E_UNSUPPORTED;
     }
     for (int c = 0; c < n_cams; c++)
       if ((st = launch_render_kbuffer(dc[c], th, (int)n, c, p->kbuffer, tile_ranges, tile_ranges + 2 * T,
-                                      sorted_ids, proj->record, proj->rgb, rgb, T_final, n_contrib,
-                                      n_eval, (hipStream_t)stream)) != GUT_OK)
+                                      sorted_ids, proj->record, proj->rgb,
+                                      clip_depth, rgb,
+                                      T_final, n_contrib, n_eval, (hipStream_t)stream)) != GUT_OK)
         return st;
     return GUT_OK;
   }

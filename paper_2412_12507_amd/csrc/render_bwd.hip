@@ -335,11 +335,12 @@ __device__ __forceinline__ void kbuf_add_wave(bool valid, uint32_t e, const floa
   }
 }
 
-template <bool RS>
+template <bool RS, bool CLIP>
 __global__ void __launch_bounds__(kKThreadsB, 1) render_kbuffer_bwd_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, int kcap, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
-    const float4* __restrict__ record, const float* __restrict__ rgb, const float* __restrict__ out_rgb,
+    const float4* __restrict__ record, const float* __restrict__ rgb, const float* __restrict__ clip,
+    const float* __restrict__ out_rgb,
     const float* __restrict__ out_T, const float* __restrict__ d_rgb, const float* __restrict__ d_T,
     double* __restrict__ acc, double* __restrict__ acc_rgb) {
   constexpr int S = Slots<RS, true>::N;
@@ -364,6 +365,11 @@ __global__ void __launch_bounds__(kKThreadsB, 1) render_kbuffer_bwd_kernel(
   const float l2amin = log2f(th.alpha_min);
   wave_box<1>(&u, &v, &active, &wb);
   const float dlen = sqrtf(fmaf(u, u, fmaf(v, v, 1.0f)));
+  float clipv = 0.0f;  // the forward's clip operands
+  if (CLIP) {
+    if (active) clipv = clip[cam.pixel_base + (long long)py * cam.W + px];
+    wave_clip_max<1>(&clipv, &active, &wb);
+  }
 
   // the loss gradients and Z = gC . C_out (FP64), as in render_bwd_kernel
   float gC[3] = {0.f, 0.f, 0.f}, gTT = 0.f;
@@ -397,9 +403,9 @@ __global__ void __launch_bounds__(kKThreadsB, 1) render_kbuffer_bwd_kernel(
     if (b + t < len) {
       const uint32_t e = ids[rg.x + b + t];
       pe[t] = e;
-      fl = pair_setup<RS, true, false, false>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n),
-                                              F, cam, umax, vmax, dtmax, th, l2amin, wb, kKThreadsB / 64,
-                                              &pd[t * S]);
+      fl = pair_setup<RS, true, false, CLIP>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n),
+                                             F, cam, umax, vmax, dtmax, th, l2amin, wb, kKThreadsB / 64,
+                                             &pd[t * S]);
     }
     pf[t] = fl;
     __syncthreads();
@@ -415,6 +421,7 @@ __global__ void __launch_bounds__(kKThreadsB, 1) render_kbuffer_bwd_kernel(
         load_pair<RS>(P, r);
         Eval ev;
         eval_test<RS>(r, P, u, v, dt, &ev);
+        if (CLIP) ev.ok = ev.ok && !behind_clip<RS>(r, P, u, v, dt, dlen, clipv, ev.dd);
         const bool live = ev.ok && !done;
         if (!wave_any(live)) continue;
         eval_alpha<RS, false>(r, th, &ev);
@@ -660,8 +667,8 @@ extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected
                                      size_t ws_bytes, void* stream) {
   gut_status st = check_params(p);
   if (st != GUT_OK) return st;
-  if (p->kbuffer > 0 && (clip_depth || p->kernel_degree != 2)) {
-    set_error("the k-buffer render supports neither clip_depth nor kernel_degree != 2");
+  if (p->kbuffer > 0 && p->kernel_degree != 2) {
+    set_error("the k-buffer render does not support kernel_degree != 2");
     return GUT_E_UNSUPPORTED;
   }
   if ((st = check_scene(scene, true)) != GUT_OK) return st;
@@ -701,14 +708,13 @@ extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected
   Thresholds th = make_thresholds(*p);
   for (int c = 0; c < n_cams && p->kbuffer > 0; c++) {  // "Ours (sorted)"
     dim3 grid(dc[c].tiles_x * dc[c].tiles_y), block(kKThreadsB);
-    if (dc[c].shutter == GUT_ROLLING_TOP_TO_BOTTOM)
-      render_kbuffer_bwd_kernel<true><<<grid, block, 0, s>>>(
-          dc[c], th, (int)n, c, p->kbuffer, (const uint2*)tile_ranges, order, sorted_ids,
-          (const float4*)proj->record, proj->rgb, rgb, T_final, d_rgb, d_T, acc, acc_rgb);
-    else
-      render_kbuffer_bwd_kernel<false><<<grid, block, 0, s>>>(
-          dc[c], th, (int)n, c, p->kbuffer, (const uint2*)tile_ranges, order, sorted_ids,
-          (const float4*)proj->record, proj->rgb, rgb, T_final, d_rgb, d_T, acc, acc_rgb);
+#define GUT_KBW(RS, CLIP)                                                                           \
+  render_kbuffer_bwd_kernel<RS, CLIP><<<grid, block, 0, s>>>(                                        \
+      dc[c], th, (int)n, c, p->kbuffer, (const uint2*)tile_ranges, order, sorted_ids,                 \
+      (const float4*)proj->record, proj->rgb, clip_depth, rgb, T_final, d_rgb, d_T, acc, acc_rgb)
+    if (dc[c].shutter == GUT_ROLLING_TOP_TO_BOTTOM) { if (clip_depth) GUT_KBW(true, true); else GUT_KBW(true, false); }
+    else { if (clip_depth) GUT_KBW(false, true); else GUT_KBW(false, false); }
+#undef GUT_KBW
     GUT_LAUNCH_CHECK();
   }
   for (int c = 0; c < n_cams && p->kbuffer == 0; c++) {

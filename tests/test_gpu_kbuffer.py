@@ -100,3 +100,62 @@ def test_kbuffer_backward_parity(kind, k):
     for key, v in rep.items():
         assert v["rel"] <= 1e-3, (key, v)
         assert v["elem_fail"] == 0, (key, v)
+
+
+def _clip_map(cam, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(lo, hi, size=(cam["height"], cam["width"]))
+    c[rng.random(c.shape) < 0.1] = np.inf
+    return c.astype(np.float32).astype(np.float64)
+
+
+def test_kbuffer_forward_with_clip():
+    """Hybrid rendering with the sorted variant (Sec. 6.2 with Sec. 4.3):
+    k = 16 and a per-pixel clip map, every pixel against the oracle."""
+    say("[k-buffer + clip forward] c2-fisheye")
+    scene, cam = CASES["c2-fisheye"]()
+    p = O.default_params(kbuffer=16)
+    clip = _clip_map(cam, 5.0, 11.0, 4100)
+    gs = R.GaussianScene.from_host(scene)
+    proj = R.project(gs, [cam], p)
+    bins = R.bin_tiles(proj, [cam], p)
+    ct = torch.as_tensor(clip.reshape(-1), dtype=torch.float32, device="cuda")
+    img = R.render(proj, bins, [cam], p, with_eval=True, clip=ct)
+    torch.cuda.synchronize()
+    pr = O.project(scene, cam, p)
+    ob = O.bin_tiles(pr, cam, p)
+    res = O.render(scene, pr, cam, ob, p, clip=clip)
+    rep = compare_pixels(image_np(img), res, cam, p)
+    say("  pixels", {kk: v for kk, v in rep.items() if kk != "fails"}, rep["fails"][:3])
+    assert rep["n_fail"] == 0
+
+
+def test_kbuffer_backward_with_clip():
+    say("[k-buffer + clip backward] rolling k=4")
+    from parity import grad_compare
+    p = O.default_params(bg=(0.1, 0.3, 0.6), kbuffer=4)
+    scene, cam = G.config4_gradcheck("rolling", log_scale_mean=-2.2)
+    clip = _clip_map(cam, 2.6, 3.4, 4101)
+    pr = O.project(scene, cam, p)
+    ob = O.bin_tiles(pr, cam, p)
+    res = O.render(scene, pr, cam, ob, p, clip=clip)
+    rng = np.random.default_rng(15)
+    H, W = cam["height"], cam["width"]
+    amb = O.to_image(res, cam, p, key="n_alt") > 0
+    wC, wT = rng.normal(size=(H, W, 3)), rng.normal(size=(H, W))
+    wC[amb] = 0
+    wT[amb] = 0
+    g_ora = O.backward(scene, pr, cam, ob, wC, wT, p, clip=clip)
+    gs = R.GaussianScene.from_host(scene)
+    proj = R.project(gs, [cam], p)
+    bins = R.bin_tiles(proj, [cam], p)
+    ct = torch.as_tensor(clip.reshape(-1), dtype=torch.float32, device="cuda")
+    img = R.render(proj, bins, [cam], p, clip=ct)
+    d_rgb = torch.as_tensor(wC.reshape(-1, 3), dtype=torch.float32, device="cuda")
+    d_T = torch.as_tensor(wT.reshape(-1), dtype=torch.float32, device="cuda")
+    g = R.render_backward(gs, proj, bins, [cam], img, d_rgb, d_T, p, clip=ct)
+    torch.cuda.synchronize()
+    rep = grad_compare(g, g_ora)
+    say("  grads", {k: (v["rel"], v["elem_fail"]) for k, v in rep.items()})
+    for key, v in rep.items():
+        assert v["rel"] <= 1e-3 and v["elem_fail"] == 0, (key, v)
