@@ -108,8 +108,8 @@ typedef struct {
  * then the buffer nearest first (multi-layer alpha blending); n_contrib then
  * counts blended hits.  gut_render_bwd differentiates it in blend order.
  * It honours clip_depth (hybrid rendering, Sec. 6.2, renders primary rays
- * this way).  gut_serve_create returns GUT_E_UNSUPPORTED for k > 0, as do
- * gut_render and gut_render_bwd with kernel_degree != 2. */
+ * this way) and kernel_degree.  gut_serve_create returns GUT_E_UNSUPPORTED
+ * for k > 0. */
 typedef struct {
   float ut_alpha, ut_beta, ut_kappa;
   float alpha_min, alpha_max, t_min, near_plane, k_sigma_max;

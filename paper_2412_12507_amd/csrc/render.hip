@@ -330,7 +330,7 @@ __device__ __forceinline__ void kbuf_blend(float a, uint32_t e, const float* __r
   nc++;
 }
 
-template <bool RS, bool NE, bool CLIP>
+template <bool RS, bool NE, bool GEN, bool CLIP>
 __global__ void __launch_bounds__(kKThreads, 2) render_kbuffer_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, int kcap, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
@@ -385,9 +385,9 @@ __global__ void __launch_bounds__(kKThreads, 2) render_kbuffer_kernel(
     if (b + t < len) {
       const uint32_t e = ids[rg.x + b + t];
       pe[t] = e;
-      fl = pair_setup<RS, false, false, CLIP>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n),
-                                              F, cam, umax, vmax, dtmax, th, l2amin, wb, kKThreads / 64,
-                                              &pd[t * S]);
+      fl = pair_setup<RS, false, GEN, CLIP>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n),
+                                            F, cam, umax, vmax, dtmax, th, l2amin, wb, kKThreads / 64,
+                                            &pd[t * S]);
     }
     pf[t] = fl;
     __syncthreads();
@@ -406,7 +406,7 @@ __global__ void __launch_bounds__(kKThreads, 2) render_kbuffer_kernel(
         if (CLIP) ev.ok = ev.ok && !behind_clip<RS>(r, P, u, v, dt, dlen, clipv, ev.dd);
         const bool live = ev.ok && !done;
         if (!wave_any(live)) continue;
-        eval_alpha<RS, false>(r, th, &ev);
+        eval_alpha<RS, GEN>(r, th, &ev);
         if (live) {
           // the hit's distance tau' |d|, tau' = -(o_g . d_g) / |d_g|^2 (the clip test's form)
           float odg;
@@ -462,17 +462,20 @@ static gut_status launch_render_kbuffer(const DevCam& cam, const Thresholds& th,
                                         const float* clip, float* out_rgb, float* out_T,
                                         uint32_t* out_nc, uint32_t* out_ne, hipStream_t s) {
   dim3 grid(cam.tiles_x * cam.tiles_y), block(kKThreads);
-#define GUT_RKB(RS, NE, CLIP)                                                                     \
-  render_kbuffer_kernel<RS, NE, CLIP><<<grid, block, 0, s>>>(cam, th, n, cam_idx, kcap,              \
-                                                             (const uint2*)ranges, order, ids,          \
-                                                             (const float4*)record, rgb, clip, out_rgb, \
-                                                             out_T, out_nc, out_ne)
+#define GUT_RKB(RS, NE, GEN, CLIP)                                                                  \
+  render_kbuffer_kernel<RS, NE, GEN, CLIP><<<grid, block, 0, s>>>(cam, th, n, cam_idx, kcap,           \
+                                                                  (const uint2*)ranges, order, ids,       \
+                                                                  (const float4*)record, rgb, clip,       \
+                                                                  out_rgb, out_T, out_nc, out_ne)
+#define GUT_RKB0(RS, NE, GEN) \
+  do { if (clip) GUT_RKB(RS, NE, GEN, true); else GUT_RKB(RS, NE, GEN, false); } while (0)
 #define GUT_RKB1(RS, NE) \
-  do { if (clip) GUT_RKB(RS, NE, true); else GUT_RKB(RS, NE, false); } while (0)
+  do { if (th.kdeg != 2) GUT_RKB0(RS, NE, true); else GUT_RKB0(RS, NE, false); } while (0)
   const bool rs = cam.shutter == GUT_ROLLING_TOP_TO_BOTTOM;
   if (rs) { if (out_ne) GUT_RKB1(true, true); else GUT_RKB1(true, false); }
   else { if (out_ne) GUT_RKB1(false, true); else GUT_RKB1(false, false); }
 #undef GUT_RKB1
+#undef GUT_RKB0
 #undef GUT_RKB
   GUT_LAUNCH_CHECK();
   return GUT_OK;
@@ -564,10 +567,6 @@ extern "C" gut_status gut_render(const gut_projected* proj, int64_t n, const uin
   if ((st = prepare_cams(cams, n_cams, *p, dc, &T, nullptr)) != GUT_OK) return st;
   Thresholds th = make_thresholds(*p);
   if (p->kbuffer > 0) {  // "Ours (sorted)": one launch per camera
-    if (p->kernel_degree != 2) {
-      set_error("the k-buffer render does not support kernel_degree != 2");
-      return GUT_E_UNSUPPORTED;
-    }
     for (int c = 0; c < n_cams; c++)
       if ((st = launch_render_kbuffer(dc[c], th, (int)n, c, p->kbuffer, tile_ranges, tile_ranges + 2 * T,
                                       sorted_ids, proj->record, proj->rgb,

@@ -278,7 +278,7 @@ struct KBufGrad {
 // Returns false (values zero) for a sentinel, a wall, a stopped pixel or a
 // hit that would cross t_min.
 __device__ __forceinline__ bool kbuf_blend_bwd(float a, uint32_t e, float px_, float py_, float pz_,
-                                               float rho, const KBufGrad& K, const float (&gC)[3],
+                                               float rho, float fg, const KBufGrad& K, const float (&gC)[3],
                                                const double (&gCd)[3], float gTT, float& T, double& Z,
                                                bool& done, float (&v)[16]) {
 #pragma unroll
@@ -295,7 +295,7 @@ __device__ __forceinline__ bool kbuf_blend_bwd(float a, uint32_t e, float px_, f
   const float inv1m = __builtin_amdgcn_rcpf(1.0f - a);
   float gA = fmaf(Tb, (float)D, -inv1m * ((float)Z + gTT));
   if (rho < 0.0f) gA = 0.0f;  // alpha = alpha_max carries no gradient
-  const float c = -a * gA;    // 2 dL/domega^2
+  const float c = -a * gA * fg;  // 2 dL/domega^2 (fg: a degree-n response's chain factor, else 1)
   v[0] = c * px_ * px_; v[1] = c * px_ * py_; v[2] = c * px_ * pz_;
   v[3] = c * py_ * py_; v[4] = c * py_ * pz_; v[5] = c * pz_ * pz_;
   v[6] = c * px_; v[7] = c * py_; v[8] = c * pz_;
@@ -335,7 +335,7 @@ __device__ __forceinline__ void kbuf_add_wave(bool valid, uint32_t e, const floa
   }
 }
 
-template <bool RS, bool CLIP>
+template <bool RS, bool GEN, bool CLIP>
 __global__ void __launch_bounds__(kKThreadsB, 1) render_kbuffer_bwd_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, int kcap, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
@@ -387,12 +387,12 @@ __global__ void __launch_bounds__(kKThreadsB, 1) render_kbuffer_bwd_kernel(
 
   const uint2 rg = ranges[cam.tile_base + tile];
   const uint32_t len = __builtin_amdgcn_readfirstlane(rg.y - rg.x);
-  float bd[kKBufB], ba[kKBufB], bx[kKBufB], by[kKBufB], bz[kKBufB], br[kKBufB];
+  float bd[kKBufB], ba[kKBufB], bx[kKBufB], by[kKBufB], bz[kKBufB], br[kKBufB], bf[kKBufB];
   uint32_t bi[kKBufB];
 #pragma unroll
   for (int j = 0; j < kKBufB; j++) {
     bd[j] = j < kcap ? -INFINITY : INFINITY;
-    ba[j] = 0.0f; bx[j] = 0.0f; by[j] = 0.0f; bz[j] = 0.0f; br[j] = 0.0f;
+    ba[j] = 0.0f; bx[j] = 0.0f; by[j] = 0.0f; bz[j] = 0.0f; br[j] = 0.0f; bf[j] = 1.0f;
     bi[j] = 0u;
   }
   float T = 1.0f;
@@ -403,9 +403,9 @@ __global__ void __launch_bounds__(kKThreadsB, 1) render_kbuffer_bwd_kernel(
     if (b + t < len) {
       const uint32_t e = ids[rg.x + b + t];
       pe[t] = e;
-      fl = pair_setup<RS, true, false, CLIP>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n),
-                                             F, cam, umax, vmax, dtmax, th, l2amin, wb, kKThreadsB / 64,
-                                             &pd[t * S]);
+      fl = pair_setup<RS, true, GEN, CLIP>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n),
+                                           F, cam, umax, vmax, dtmax, th, l2amin, wb, kKThreadsB / 64,
+                                           &pd[t * S]);
     }
     pf[t] = fl;
     __syncthreads();
@@ -424,7 +424,7 @@ __global__ void __launch_bounds__(kKThreadsB, 1) render_kbuffer_bwd_kernel(
         if (CLIP) ev.ok = ev.ok && !behind_clip<RS>(r, P, u, v, dt, dlen, clipv, ev.dd);
         const bool live = ev.ok && !done;
         if (!wave_any(live)) continue;
-        eval_alpha<RS, false>(r, th, &ev);
+        eval_alpha<RS, GEN>(r, th, &ev);
         bool valid = false;
         uint32_t be = 0u;
         float vals[16];
@@ -448,12 +448,14 @@ __global__ void __launch_bounds__(kKThreadsB, 1) render_kbuffer_bwd_kernel(
           pv = f3(pv.x * ev.idd, pv.y * ev.idd, pv.z * ev.idd);
           const float rho0 = ev.araw * __builtin_amdgcn_exp2f(-r.lsig);
           const float rho = ev.clamped ? -rho0 - 1e-30f : rho0;
+          // degree n: d alpha / d omega^2 relative to the Gaussian's (as in render_bwd_kernel)
+          const float fg = GEN ? __builtin_amdgcn_exp2f(fmaf(th.k_h - 1.0f, ev.lq, th.k_f)) : 1.0f;
           if (dist <= bd[0]) {
-            valid = kbuf_blend_bwd(ev.a, e, pv.x, pv.y, pv.z, rho, K, gC, gCd, gTT, T, Z, done, vals);
+            valid = kbuf_blend_bwd(ev.a, e, pv.x, pv.y, pv.z, rho, fg, K, gC, gCd, gTT, T, Z, done, vals);
             be = e;
           } else {
-            valid = kbuf_blend_bwd(ba[0], bi[0], bx[0], by[0], bz[0], br[0], K, gC, gCd, gTT, T, Z, done,
-                                   vals);
+            valid = kbuf_blend_bwd(ba[0], bi[0], bx[0], by[0], bz[0], br[0], bf[0], K, gC, gCd, gTT, T, Z,
+                                   done, vals);
             be = bi[0];
 #pragma unroll
             for (int j = 0; j < kKBufB - 1; j++) {
@@ -465,6 +467,7 @@ __global__ void __launch_bounds__(kKThreadsB, 1) render_kbuffer_bwd_kernel(
               by[j] = nx ? by[j + 1] : (here ? pv.y : by[j]);
               bz[j] = nx ? bz[j + 1] : (here ? pv.z : bz[j]);
               br[j] = nx ? br[j + 1] : (here ? rho : br[j]);
+              if (GEN) bf[j] = nx ? bf[j + 1] : (here ? fg : bf[j]);
             }
             const int L = kKBufB - 1;
             const bool last = bd[L] < dist;
@@ -474,6 +477,7 @@ __global__ void __launch_bounds__(kKThreadsB, 1) render_kbuffer_bwd_kernel(
             by[L] = last ? pv.y : by[L];
             bz[L] = last ? pv.z : bz[L];
             br[L] = last ? rho : br[L];
+            if (GEN) bf[L] = last ? fg : bf[L];
             bd[L] = last ? dist : bd[L];
           }
         }
@@ -484,8 +488,8 @@ __global__ void __launch_bounds__(kKThreadsB, 1) render_kbuffer_bwd_kernel(
 #pragma unroll
   for (int j = 0; j < kKBufB; j++) {
     float vals[16];
-    const bool valid = kbuf_blend_bwd(ba[j], bi[j], bx[j], by[j], bz[j], br[j], K, gC, gCd, gTT, T, Z,
-                                      done, vals);
+    const bool valid = kbuf_blend_bwd(ba[j], bi[j], bx[j], by[j], bz[j], br[j], bf[j], K, gC, gCd, gTT,
+                                      T, Z, done, vals);
     kbuf_add_wave(valid, bi[j], vals, K);
   }
 }
@@ -667,10 +671,6 @@ extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected
                                      size_t ws_bytes, void* stream) {
   gut_status st = check_params(p);
   if (st != GUT_OK) return st;
-  if (p->kbuffer > 0 && p->kernel_degree != 2) {
-    set_error("the k-buffer render does not support kernel_degree != 2");
-    return GUT_E_UNSUPPORTED;
-  }
   if ((st = check_scene(scene, true)) != GUT_OK) return st;
   if (!proj || !proj->record || !proj->rgb || !tile_ranges || !rgb || !T_final || !n_contrib ||
       !d_rgb || !g_means || !g_scales || !g_quats || !g_opacities || !g_sh) {
@@ -708,12 +708,16 @@ extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected
   Thresholds th = make_thresholds(*p);
   for (int c = 0; c < n_cams && p->kbuffer > 0; c++) {  // "Ours (sorted)"
     dim3 grid(dc[c].tiles_x * dc[c].tiles_y), block(kKThreadsB);
-#define GUT_KBW(RS, CLIP)                                                                           \
-  render_kbuffer_bwd_kernel<RS, CLIP><<<grid, block, 0, s>>>(                                        \
+#define GUT_KBW(RS, GEN, CLIP)                                                                      \
+  render_kbuffer_bwd_kernel<RS, GEN, CLIP><<<grid, block, 0, s>>>(                                   \
       dc[c], th, (int)n, c, p->kbuffer, (const uint2*)tile_ranges, order, sorted_ids,                 \
       (const float4*)proj->record, proj->rgb, clip_depth, rgb, T_final, d_rgb, d_T, acc, acc_rgb)
-    if (dc[c].shutter == GUT_ROLLING_TOP_TO_BOTTOM) { if (clip_depth) GUT_KBW(true, true); else GUT_KBW(true, false); }
-    else { if (clip_depth) GUT_KBW(false, true); else GUT_KBW(false, false); }
+#define GUT_KBW1(RS, GEN) \
+  do { if (clip_depth) GUT_KBW(RS, GEN, true); else GUT_KBW(RS, GEN, false); } while (0)
+    const bool rs = dc[c].shutter == GUT_ROLLING_TOP_TO_BOTTOM, gen = th.kdeg != 2;
+    if (rs) { if (gen) GUT_KBW1(true, true); else GUT_KBW1(true, false); }
+    else { if (gen) GUT_KBW1(false, true); else GUT_KBW1(false, false); }
+#undef GUT_KBW1
 #undef GUT_KBW
     GUT_LAUNCH_CHECK();
   }

@@ -141,15 +141,7 @@ def test_bin_and_render_validation_without_launch():
     st = lib.gut_render_bwd(L.ref(sc), L.ref(pj), z, z, arr, 1, L.ref(p), None, z, z, z, z, None, z,
                             z, z, z, z, z, 16, None)
     assert st == L.GUT_E_INVALID
-    # the k-buffer render takes no clip distances or generalized responses
-    pk = L.params_struct(dict(kbuffer=16, kernel_degree=3))
-    st = lib.gut_render_bwd(L.ref(sc), L.ref(pj), z, z, arr, 1, L.ref(pk), None, z, z, z, z, None, z,
-                            z, z, z, z, z, 1 << 30, None)
-    assert st == L.GUT_E_UNSUPPORTED
-    pkd = L.params_struct(dict(kbuffer=16, kernel_degree=4))
-    st = lib.gut_render(L.ref(pj), 10, C.c_void_p(4096), C.c_void_p(4096), arr, 1, L.ref(pkd), None,
-                        z, z, z, None, None)
-    assert st == L.GUT_E_UNSUPPORTED
+
 
 
 def test_serve_validation_without_launch():

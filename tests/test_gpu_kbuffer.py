@@ -159,3 +159,40 @@ def test_kbuffer_backward_with_clip():
     say("  grads", {k: (v["rel"], v["elem_fail"]) for k, v in rep.items()})
     for key, v in rep.items():
         assert v["rel"] <= 1e-3 and v["elem_fail"] == 0, (key, v)
+
+
+def test_kbuffer_with_degree4_forward_and_backward():
+    """The sorted variant with the degree-4 response (Supp. A's table is
+    measured with it): every pixel of a fisheye view, then the gradients of a
+    dense pinhole view, against the oracle."""
+    say("[k-buffer + degree 4] fisheye forward, pinhole backward")
+    from parity import grad_compare
+    scene, cam = CASES["c2-fisheye"]()
+    p = O.default_params(kbuffer=16, kernel_degree=4)
+    gs, proj, bins, img = gpu_forward(scene, [cam], p)
+    pr = O.project(scene, cam, p)
+    ob = O.bin_tiles(pr, cam, p)
+    rep = compare_pixels(image_np(img), O.render(scene, pr, cam, ob, p), cam, p)
+    say("  pixels", {kk: v for kk, v in rep.items() if kk != "fails"}, rep["fails"][:3])
+    assert rep["n_fail"] == 0
+    p = O.default_params(bg=(0.1, 0.3, 0.6), kbuffer=16, kernel_degree=4)
+    scene, cam = G.config4_gradcheck("pinhole", log_scale_mean=-2.2)
+    pr = O.project(scene, cam, p)
+    ob = O.bin_tiles(pr, cam, p)
+    res = O.render(scene, pr, cam, ob, p)
+    rng = np.random.default_rng(16)
+    H, W = cam["height"], cam["width"]
+    amb = O.to_image(res, cam, p, key="n_alt") > 0
+    wC, wT = rng.normal(size=(H, W, 3)), rng.normal(size=(H, W))
+    wC[amb] = 0
+    wT[amb] = 0
+    g_ora = O.backward(scene, pr, cam, ob, wC, wT, p)
+    gs, proj, bins, img = gpu_forward(scene, [cam], p)
+    g = R.render_backward(gs, proj, bins, [cam], img,
+                          torch.as_tensor(wC.reshape(-1, 3), dtype=torch.float32, device="cuda"),
+                          torch.as_tensor(wT.reshape(-1), dtype=torch.float32, device="cuda"), p)
+    torch.cuda.synchronize()
+    rep = grad_compare(g, g_ora)
+    say("  grads", {k: (v["rel"], v["elem_fail"]) for k, v in rep.items()})
+    for key, v in rep.items():
+        assert v["rel"] <= 1e-3 and v["elem_fail"] == 0, (key, v)
