@@ -462,6 +462,15 @@ def main():
                                   "render": fk["stage_ms"][2]},
                        e_eval=fk["e_eval"])
         del fk
+        # Supp. A's table times the generalized kernels with the sorted variant
+        if args.degrees and not args.no_degrees:
+            kbuffer["degrees"] = {}
+            for d in [int(x) for x in args.degrees.split(",")]:
+                log(f"[bench] forward steps, k = 16 per-ray buffer, response of degree {d}")
+                fk = bench_forward(gs, cams, max(3, args.steps // 4), 1, R, torch, dict(kbuffer=16, kernel_degree=d))
+                kbuffer["degrees"][str(d)] = dict(mpix_per_s=npx / (fk["ms_per_step"] * 1e-3) / 1e6,
+                                                  render_ms=fk["stage_ms"][2])
+                del fk
 
     fwd_bwd = None
     if not args.no_fwd_bwd:
