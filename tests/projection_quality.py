@@ -106,8 +106,12 @@ def evaluate(scene, cam, n_max=400, seed=0, gpu=False, ewa_t=0.0):
     good = ok_mc & ok_e & (np.linalg.det(mc) > 0) & (np.linalg.det(ec) > 0) & (np.linalg.det(uc[idx]) > 0)
     kl_ut = kl_gauss2(mm[good], mc[good], um[idx][good], uc[idx][good])
     kl_ewa = kl_gauss2(mm[good], mc[good], em[good], ec[good])
+    # the other direction, KL(Q || P_MC) (the paper does not say which it uses)
+    kl_ut_r = kl_gauss2(um[idx][good], uc[idx][good], mm[good], mc[good])
+    kl_ewa_r = kl_gauss2(em[good], ec[good], mm[good], mc[good])
     return dict(n=int(good.sum()), ut_median=float(np.median(kl_ut)), ut_p90=float(np.percentile(kl_ut, 90)),
-                ewa_median=float(np.median(kl_ewa)), ewa_p90=float(np.percentile(kl_ewa, 90)))
+                ewa_median=float(np.median(kl_ewa)), ewa_p90=float(np.percentile(kl_ewa, 90)),
+                ut_median_rev=float(np.median(kl_ut_r)), ewa_median_rev=float(np.median(kl_ewa_r)))
 
 
 def cone_scene(half_angle_deg, n=1500, seed=1007, dist=1.5, log_scale_mean=-2.7):
@@ -154,11 +158,12 @@ def main():
     gpu = "--gpu" in sys.argv
     print(f"UT from {'the HIP path (gut_project)' if gpu else 'the oracle'}; EWA at exposure time 0")
     print(f"MC noise floor (median KL of an exact projection): {noise_floor_median():.2e}")
-    print(f"{'camera':42s} {'n':>5s} {'UT median':>10s} {'UT p90':>9s} {'EWA median':>11s} {'EWA p90':>9s}")
+    print(f"{'camera':42s} {'n':>5s} {'UT median':>10s} {'UT p90':>9s} {'EWA median':>11s} {'EWA p90':>9s}"
+          f" {'UT med Q||P':>12s} {'EWA med Q||P':>13s}")
     for name, scene, cam in sweep():
         r = evaluate(scene, cam, gpu=gpu)
         print(f"{name:42s} {r['n']:5d} {r['ut_median']:10.2e} {r['ut_p90']:9.2e} {r['ewa_median']:11.2e} "
-              f"{r['ewa_p90']:9.2e}", flush=True)
+              f"{r['ewa_p90']:9.2e} {r['ut_median_rev']:12.2e} {r['ewa_median_rev']:13.2e}", flush=True)
 
 
 if __name__ == "__main__":
