@@ -57,6 +57,44 @@ __global__ void __launch_bounds__(kRThreadsSort) scan_down_kernel(const uint32_t
   }
 }
 
+// Downsweep for up to kRChunk chunks whose sums are not yet scanned: each
+// block first reduces the sums of the chunks before it (a few hundred words
+// at the sizes here), so the scan of the sums needs no launch of its own.
+__global__ void __launch_bounds__(kRThreadsSort) scan_down_sums_kernel(const uint32_t* __restrict__ in,
+                                                                       uint32_t* __restrict__ out, int64_t n,
+                                                                       const uint32_t* __restrict__ sums) {
+  __shared__ uint32_t sm[kRChunk + kRChunk / 32];
+  __shared__ uint32_t wsum[kRWaves];
+  const int t = threadIdx.x;
+  uint32_t pre = 0;
+  for (int k = t; k < (int)blockIdx.x; k += kRThreadsSort) pre += sums[k];
+  uint32_t offset;
+  radix_block_scan(pre, wsum, &offset);  // offset = the block total of pre
+  __syncthreads();                        // wsum is reused below
+  int64_t base = (int64_t)blockIdx.x * kRChunk;
+#pragma unroll
+  for (int j = 0; j < kRItems; j++) {
+    int idx = j * kRThreadsSort + t;
+    int64_t g = base + idx;
+    sm[lds_pad(idx)] = g < n ? in[g] : 0u;
+  }
+  __syncthreads();
+  uint32_t v[kRItems], s = 0;
+#pragma unroll
+  for (int j = 0; j < kRItems; j++) { v[j] = sm[lds_pad(t * kRItems + j)]; s += v[j]; }
+  uint32_t total;
+  uint32_t run = radix_block_scan(s, wsum, &total) + offset;
+#pragma unroll
+  for (int j = 0; j < kRItems; j++) { sm[lds_pad(t * kRItems + j)] = run; run += v[j]; }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kRItems; j++) {
+    int idx = j * kRThreadsSort + t;
+    int64_t g = base + idx;
+    if (g < n) out[g] = sm[lds_pad(idx)];
+  }
+}
+
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -86,6 +124,11 @@ gut_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void
   if (!have_sums) {
     scan_reduce_kernel<<<(unsigned)nb, kRThreadsSort, 0, st>>>(in, n, sums);
     GUT_LAUNCH_CHECK();
+  }
+  if (nb <= kRChunk) {  // one level: the downsweep reduces the sums before each chunk itself
+    scan_down_sums_kernel<<<(unsigned)nb, kRThreadsSort, 0, st>>>(in, out, n, sums);
+    GUT_LAUNCH_CHECK();
+    return GUT_OK;
   }
   gut_status s = exclusive_scan_u32(sums, scanned, nb, rest, st, false);
   if (s != GUT_OK) return s;
