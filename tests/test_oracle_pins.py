@@ -97,6 +97,46 @@ def test_ut_on_axis_pinhole_closed_form(z, s, f):
     np.testing.assert_allclose(pr["cov2d"][0], [e, 0.0, e], rtol=1e-9, atol=1e-9)
 
 
+@pytest.mark.parametrize("a,b,k", [(1.0, 2.0, 0.0), (0.8, 0.5, 1.0), (1.0, 0.0, 0.0)])
+def test_ut_off_axis_centre_weight_closed_form(a, b, k):
+    """Eq. 9-10 worked by hand for an axis-aligned isotropic particle at
+    (x0, 0, z0) in front of a pinhole at the origin.  With g^2 = 3 + lambda the
+    seven sigma points are the centre and x0 +/- g s along x, y and z.  Along
+    x and y they project symmetrically about the centre's u = c + f x0 / z0;
+    along z they land at c + f x0 / (z0 -/+ g s), which pulls the UT mean off
+    the centre point by D = a s^2 / (z0^2 - g^2 s^2), a = f x0 / z0.  The
+    centre point therefore carries covariance weight into Sigma'_xx through
+    its w0^Sigma = lambda/(3+lambda) + (1 - alpha^2 + beta) (Eq. 8): using the
+    mean weight there instead drops (1 - alpha^2 + beta) D^2, about 5% here.
+    v is symmetric about c_y, so Sigma'_yy = 2 w (f g s / z0)^2 and
+    Sigma'_xy = 0."""
+    f, cx, cy = 100.0, 200.0, 50.0
+    x0, z0, s = 2.0, 3.0, 0.6
+    cam = G.camera("pinhole", 400, 100, f, cx=cx, cy=cy)
+    p = O.default_params(ut_alpha=a, ut_beta=b, ut_kappa=k)
+    sc = O.OScene(np.array([[x0, 0.0, z0]]), np.full((1, 3), s), np.array([[1.0, 0, 0, 0]]),
+                  np.array([0.9]), np.zeros((1, 1, 3)), 0)
+    pr = O.project(sc, cam, p)
+    assert pr["cull"][0] == 0
+
+    lam = a * a * (3 + k) - 3
+    g = math.sqrt(3 + lam)
+    w = 1.0 / (2 * (3 + lam))                      # every non-centre point
+    w0s = lam / (3 + lam) + (1 - a * a + b)        # centre, covariance
+    aa = f * x0 / z0
+    D = aa * s * s / (z0 * z0 - g * g * s * s)     # UT mean minus the centre's u
+    e = f * g * s / z0                             # x- and y-pair offsets
+    dz_p = -aa * g * s / (z0 + g * s)              # u(z0 + g s) - u(centre)
+    dz_m = aa * g * s / (z0 - g * s)               # u(z0 - g s) - u(centre)
+    cov_xx = w0s * D * D + w * ((e - D) ** 2 + (e + D) ** 2 + 2 * D * D
+                                + (dz_p - D) ** 2 + (dz_m - D) ** 2)
+    cov_yy = 2 * w * e * e
+    np.testing.assert_allclose(pr["mean2d"][0], [cx + aa + D, cy], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(pr["cov2d"][0], [cov_xx, 0.0, cov_yy], rtol=1e-12, atol=1e-9)
+    # the centre term is large enough to matter at this size
+    assert (1 - a * a + b) * D * D > 1e-3 * cov_xx or b == a * a - 1
+
+
 def test_ut_vs_ewa_converges_quadratically():
     """Off axis, the UT covariance approaches the linearised (EWA, Eq. 3)
     covariance J Sigma J^T as the particle shrinks, with error O((s/z)^2)."""
