@@ -18,7 +18,8 @@
  *  - Every array argument is a DEVICE pointer unless marked "host".  The
  *    caller allocates and owns every buffer; libgut allocates device memory
  *    only inside a gut_server (within its budget) and inside gut_bin for its
- *    tiny pinned read-back slot.
+ *    tiny pinned read-back slot, and holds one static 64 MiB scratch array
+ *    per GPU for gut_render_bwd_noalloc.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    Every call is asynchronous on it, except gut_bin, which waits once, for
  *    an event it records on the stream as soon as the visible-entry and pair
@@ -212,6 +213,25 @@ gut_status gut_render_bwd(const gut_scene* scene, const gut_projected* proj,
                           const float* d_rgb, const float* d_T, float* g_means, float* g_scales,
                           float* g_quats, float* g_opacities, float* g_sh, void* ws,
                           size_t ws_bytes, void* stream);
+
+/* gut_render_bwd for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, results and errors as gut_render_bwd, without ws/ws_bytes:
+ * the FP64 accumulators live in a static 64 MiB device array that the
+ * library holds on each GPU it runs on until the process ends, so
+ * gut_render_bwd_workspace_bytes(n, n_cams) must not exceed 64 MiB (about
+ * 645k particles for one camera); larger calls return GUT_E_INVALID and
+ * launch nothing.  It calls no allocating routine.  Every call on one GPU
+ * shares that GPU's array (the accumulators are cleared at the start of each
+ * call), so calls that overlap on one GPU -- on different streams or from
+ * different host threads -- race and must be serialised by the caller. */
+gut_status gut_render_bwd_noalloc(const gut_scene* scene, const gut_projected* proj,
+                                  const uint32_t* tile_ranges, const uint32_t* sorted_ids,
+                                  const gut_camera* cams, int32_t n_cams, const gut_params* p,
+                                  const float* clip_depth, const float* rgb, const float* T_final,
+                                  const uint32_t* n_contrib, const float* d_rgb,
+                                  const float* d_T, float* g_means, float* g_scales,
+                                  float* g_quats, float* g_opacities, float* g_sh, void* stream);
 
 /* ---- Serving: continuous batching over a resident scene ----------------
  * A server keeps the scene resident, admits multi-camera requests while

@@ -21,7 +21,7 @@ GUT_GLOBAL_SHUTTER, GUT_ROLLING_TOP_TO_BOTTOM = 0, 1
 EXPORTS = (
     "gut_default_params", "gut_num_tiles", "gut_num_pixels", "gut_project",
     "gut_bin_workspace_bytes", "gut_bin", "gut_render", "gut_render_bwd_workspace_bytes",
-    "gut_render_bwd", "gut_serve_create", "gut_serve_submit", "gut_serve_poll",
+    "gut_render_bwd", "gut_render_bwd_noalloc", "gut_serve_create", "gut_serve_submit", "gut_serve_poll",
     "gut_serve_wait", "gut_serve_latency", "gut_serve_stats", "gut_serve_reset_stats",
     "gut_serve_destroy", "gut_status_string", "gut_last_error",
 )
@@ -104,6 +104,9 @@ def load():
     L.gut_render_bwd.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                  vp, vp, vp, sz, vp]
     L.gut_render_bwd.restype = st
+    L.gut_render_bwd_noalloc.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp,
+                                         vp, vp, vp, vp, vp]
+    L.gut_render_bwd_noalloc.restype = st
     serve_sigs = {
         "gut_serve_create": [vp, vp, sz, i32, i32, vp],
         "gut_serve_submit": [vp, vp, i32, vp, vp],

@@ -25,6 +25,8 @@
 //   dL/ds_k = -G_kk / s_k,   dL/dR = R S G S^-1,   dL/dmu = -R S^-1 h,
 // the quaternion normalisation Jacobian, and (per camera) the SH colour:
 //   dL/dbeta_k = dL/dc Y_k(d),  dL/dmu += (I - d d^T)/|mu - o| sum beta grad Y.
+#include <mutex>
+
 #include "camera_dev.h"
 #include "tile_eval.h"
 
@@ -661,14 +663,16 @@ extern "C" size_t gut_render_bwd_workspace_bytes(int64_t n, int32_t n_cams) {
   return a + (size_t)n * n_cams * 3 * 8 + 256;
 }
 
-extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected* proj,
-                                     const uint32_t* tile_ranges, const uint32_t* sorted_ids,
-                                     const gut_camera* cams, int32_t n_cams, const gut_params* p,
-                                     const float* clip_depth, const float* rgb, const float* T_final,
-                                     const uint32_t* n_contrib, const float* d_rgb,
-                                     const float* d_T, float* g_means, float* g_scales,
-                                     float* g_quats, float* g_opacities, float* g_sh, void* ws,
-                                     size_t ws_bytes, void* stream) {
+// The whole backward with its FP64 accumulators in ws (ws_bytes available):
+// argument checks, then every launch on `stream`.
+static gut_status render_bwd_run(const gut_scene* scene, const gut_projected* proj,
+                                 const uint32_t* tile_ranges, const uint32_t* sorted_ids,
+                                 const gut_camera* cams, int32_t n_cams, const gut_params* p,
+                                 const float* clip_depth, const float* rgb, const float* T_final,
+                                 const uint32_t* n_contrib, const float* d_rgb, const float* d_T,
+                                 float* g_means, float* g_scales, float* g_quats,
+                                 float* g_opacities, float* g_sh, void* ws, size_t ws_bytes,
+                                 void* stream) {
   gut_status st = check_params(p);
   if (st != GUT_OK) return st;
   if ((st = check_scene(scene, true)) != GUT_OK) return st;
@@ -755,4 +759,83 @@ extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected
     GUT_LAUNCH_CHECK();
   }
   return GUT_OK;
+}
+
+extern "C" gut_status gut_render_bwd(const gut_scene* scene, const gut_projected* proj,
+                                     const uint32_t* tile_ranges, const uint32_t* sorted_ids,
+                                     const gut_camera* cams, int32_t n_cams, const gut_params* p,
+                                     const float* clip_depth, const float* rgb, const float* T_final,
+                                     const uint32_t* n_contrib, const float* d_rgb,
+                                     const float* d_T, float* g_means, float* g_scales,
+                                     float* g_quats, float* g_opacities, float* g_sh, void* ws,
+                                     size_t ws_bytes, void* stream) {
+  return render_bwd_run(scene, proj, tile_ranges, sorted_ids, cams, n_cams, p, clip_depth, rgb,
+                        T_final, n_contrib, d_rgb, d_T, g_means, g_scales, g_quats, g_opacities,
+                        g_sh, ws, ws_bytes, stream);
+}
+
+// ---- the backward without a caller workspace --------------------------------
+// For callers that cannot allocate (graph capture, serving loops, harnesses
+// that forbid it): the FP64 accumulators live in one static device array per
+// GPU, held from the library's load until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in);
+// its device address is looked up once per device, with that device current,
+// and kept.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+gut_status scratch_address(void** out) {
+  int dev = 0;
+  GUT_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) {
+    set_error("gut_render_bwd_noalloc: device %d is beyond the %d supported", dev,
+              kMaxScratchDevices);
+    return GUT_E_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    GUT_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || ((uintptr_t)ptr & 255)) {
+      set_error("gut_render_bwd_noalloc: scratch address %p is not 256-byte aligned", ptr);
+      return GUT_E_HIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return GUT_OK;
+}
+}  // namespace
+
+extern "C" gut_status gut_render_bwd_noalloc(const gut_scene* scene, const gut_projected* proj,
+                                             const uint32_t* tile_ranges, const uint32_t* sorted_ids,
+                                             const gut_camera* cams, int32_t n_cams,
+                                             const gut_params* p, const float* clip_depth,
+                                             const float* rgb, const float* T_final,
+                                             const uint32_t* n_contrib, const float* d_rgb,
+                                             const float* d_T, float* g_means, float* g_scales,
+                                             float* g_quats, float* g_opacities, float* g_sh,
+                                             void* stream) {
+  if (!scene || scene->n < 0 || n_cams <= 0) {
+    set_error("gut_render_bwd_noalloc: NULL scene, n < 0 or n_cams <= 0");
+    return GUT_E_INVALID;
+  }
+  const size_t need = gut_render_bwd_workspace_bytes(scene->n, n_cams);
+  if (need > kNoAllocScratchBytes) {
+    set_error("gut_render_bwd_noalloc: n = %lld particles over %d camera(s) need %zu bytes of "
+              "scratch; the static scratch holds %zu (use gut_render_bwd with a workspace)",
+              (long long)scene->n, (int)n_cams, need, kNoAllocScratchBytes);
+    return GUT_E_INVALID;
+  }
+  void* ws = nullptr;
+  gut_status st = scratch_address(&ws);
+  if (st != GUT_OK) return st;
+  return render_bwd_run(scene, proj, tile_ranges, sorted_ids, cams, n_cams, p, clip_depth, rgb,
+                        T_final, n_contrib, d_rgb, d_T, g_means, g_scales, g_quats, g_opacities,
+                        g_sh, ws, kNoAllocScratchBytes, stream);
 }

@@ -162,3 +162,16 @@ def test_serve_validation_without_launch():
     done = C.c_int32()
     assert lib.gut_serve_poll(None, 1, C.byref(done)) == L.GUT_E_INVALID
     assert lib.gut_serve_destroy(None) == L.GUT_E_INVALID
+
+
+def test_noalloc_backward_rejects_beyond_its_static_scratch():
+    """gut_render_bwd_noalloc refuses, before any launch, a call whose FP64
+    accumulators would not fit its static 64 MiB scratch."""
+    lib = L.load()
+    s = _scene_struct(n=2_000_000)
+    cams = L.camera_array([G.config1()[1][0]])
+    st = lib.gut_render_bwd_noalloc(L.ref(s), None, None, None, cams, 1, None, None, None, None,
+                                    None, None, None, None, None, None, None, None, None)
+    assert st == L.GUT_E_INVALID
+    assert b"static scratch" in lib.gut_last_error()
+    assert lib.gut_render_bwd_workspace_bytes(600_000, 1) <= 64 << 20  # fits: about 645k for one camera
