@@ -61,7 +61,7 @@ class Params(C.Structure):
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double), ("t_min", C.c_double),
                 ("near_plane", C.c_double), ("k_sigma_max", C.c_double),
                 ("tile", C.c_int32), ("rs_iters", C.c_int32), ("bg", C.c_double * 3),
-                ("kernel_degree", C.c_int32), ("kbuffer", C.c_int32)]
+                ("kernel_degree", C.c_int32), ("kbuffer", C.c_int32), ("tile_cull", C.c_int32)]
 
 
 class SceneS(C.Structure):
@@ -72,12 +72,13 @@ class SceneS(C.Structure):
 
 class ProjS(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("cull", "mean2d", "cov2d", "rect", "tiles", "depth",
-                                          "rgb", "rgb_raw", "tstar", "edge", "valid_margin")]
+                                          "rgb", "rgb_raw", "tstar", "edge", "valid_margin",
+                                          "kext")]
 
 
 class Amb(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("alpha", "trans", "tau", "depth", "edge", "valid",
-                                          "pixel", "diff", "clip", "order")]
+                                          "pixel", "diff", "clip", "order", "conic")]
 
 
 class ImageS(C.Structure):
@@ -107,6 +108,8 @@ def _declare(L):
     L.ora_ewa.argtypes = [vp, vp, d, vp, vp, vp, d, vp, vp]
     L.ora_ewa.restype = C.c_int
     L.ora_project.argtypes = [vp, vp, vp, vp]
+    L.ora_ellipse_box_qmin.argtypes = [vp, vp, d, d, d, d]
+    L.ora_ellipse_box_qmin.restype = d
     L.ora_bin.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
     L.ora_bin.restype = i64
     L.ora_render.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp]
@@ -136,14 +139,14 @@ def default_params(**kw) -> dict:
     f = lambda v: float(np.float32(v))
     p = dict(ut_alpha=1.0, ut_beta=2.0, ut_kappa=0.0, alpha_min=f(1.0 / 255.0),
              alpha_max=f(0.99), t_min=f(1e-4), near_plane=f(0.2), k_sigma_max=3.0,
-             tile=16, rs_iters=3, bg=(0.0, 0.0, 0.0), kernel_degree=2, kbuffer=0)
+             tile=16, rs_iters=3, bg=(0.0, 0.0, 0.0), kernel_degree=2, kbuffer=0, tile_cull=1)
     p.update(kw)
     return p
 
 
 def default_amb(**kw) -> dict:
     a = dict(alpha=1e-6, trans=1e-4, tau=1e-5, depth=1e-6, edge=2e-3, valid=1e-5, pixel=1e-9,
-             diff=1e-6, clip=1e-5, order=1e-5)
+             diff=1e-6, clip=1e-5, order=1e-5, conic=1e-6)
     a.update(kw)
     return a
 
@@ -157,6 +160,7 @@ def _params(p: dict) -> Params:
     s.rs_iters = int(p["rs_iters"])
     s.kernel_degree = int(p.get("kernel_degree", 2))
     s.kbuffer = int(p.get("kbuffer", 0))
+    s.tile_cull = int(p.get("tile_cull", 1))
     for i in range(3):
         s.bg[i] = float(p["bg"][i])
     return s
@@ -299,6 +303,13 @@ def sh_basis_grad(degree, d):
     return dY
 
 
+def ellipse_box_qmin(m, A, box):
+    """min over the closed box (x0, y0, x1, y1) of (v-m)^T A^-1 (v-m), A = (xx, xy, yy)."""
+    m = np.ascontiguousarray(m, np.float64)
+    A = np.ascontiguousarray(A, np.float64)
+    return float(lib().ora_ellipse_box_qmin(_p(m), _p(A), *[float(b) for b in box]))
+
+
 def particle_alpha(mu, quat, scale, opacity, o, d, kernel_degree=2):
     mu, quat, scale, o, d = (np.ascontiguousarray(x, np.float64) for x in (mu, quat, scale, o, d))
     tau, om2, a = C.c_double(), C.c_double(), C.c_double()
@@ -351,7 +362,8 @@ def project(scene, cam, params=None) -> Projection:
     out = Projection(cull=np.zeros(n, np.int32), mean2d=np.zeros((n, 2)), cov2d=np.zeros((n, 3)),
                      rect=np.zeros((n, 4), np.int32), tiles=np.zeros(n, np.int32),
                      depth=np.zeros(n), rgb=np.zeros((n, 3)), rgb_raw=np.zeros((n, 3)),
-                     tstar=np.zeros(n), edge=np.zeros((n, 4)), valid_margin=np.zeros(n))
+                     tstar=np.zeros(n), edge=np.zeros((n, 4)), valid_margin=np.zeros(n),
+                     kext=np.zeros(n))
     ss, cs, ps, prs = sc.struct(), camera_struct(cam), _params(p), out.struct()
     lib().ora_project(_ref(ss), _ref(cs), _ref(ps), _ref(prs))
     return out

@@ -529,6 +529,7 @@ int ora_project(const ora_scene* s, const ora_camera* c, const ora_params* p, or
     out->depth[i] = 0;
     out->tstar[i] = 0;
     out->valid_margin[i] = INFINITY;
+    out->kext[i] = 0;
     for (int j = 0; j < 3; j++) out->rgb[3 * i + j] = out->rgb_raw[3 * i + j] = 0;
     if (sig < p->alpha_min) { out->cull[i] = 1; continue; } /* can never reach alpha_min */
 
@@ -554,6 +555,7 @@ int ora_project(const ora_scene* s, const ora_camera* c, const ora_params* p, or
      * distance at which sigma * rho(k^2) reaches alpha_min, capped at 3. */
     double ks = cutoff_distance(p, sig);
     if (ks > p->k_sigma_max) ks = p->k_sigma_max;
+    out->kext[i] = ks;
     double hx = ks * sqrt(cov[0] > 0 ? cov[0] : 0), hy = ks * sqrt(cov[2] > 0 ? cov[2] : 0);
     double* e = &out->edge[4 * i];
     e[0] = mean[0] - hx; e[1] = mean[1] - hy; e[2] = mean[0] + hx; e[3] = mean[1] + hy;
@@ -637,6 +639,75 @@ static int particle_rects(const ora_proj* pr, int64_t i, const ora_camera* c, co
   return mx[0] <= mx[2] && mx[1] <= mx[3];
 }
 
+double ora_ellipse_box_qmin(const double m[2], const double A[3], double x0, double y0,
+                            double x1, double y1) {
+  const double det = A[0] * A[2] - A[1] * A[1];
+  if (!(det > 0)) return 0.0; /* degenerate ellipse: no culling */
+  if (m[0] >= x0 && m[0] <= x1 && m[1] >= y0 && m[1] <= y1) return 0.0;
+  /* Q = A^-1; outside the box the minimum of the convex form lies on its
+   * boundary: the smallest of the four edges' clamped one-dimensional minima */
+  const double Qxx = A[2] / det, Qxy = -A[1] / det, Qyy = A[0] / det;
+  double best = INFINITY;
+  for (int e = 0; e < 2; e++) { /* vertical edges x = x0, x1 */
+    const double dx = (e ? x1 : x0) - m[0];
+    double y = m[1] - Qxy * dx / Qyy;
+    if (y < y0) y = y0;
+    if (y > y1) y = y1;
+    const double dy = y - m[1];
+    const double q = Qxx * dx * dx + 2.0 * Qxy * dx * dy + Qyy * dy * dy;
+    if (q < best) best = q;
+  }
+  for (int e = 0; e < 2; e++) { /* horizontal edges y = y0, y1 */
+    const double dy = (e ? y1 : y0) - m[1];
+    double x = m[0] - Qxy * dy / Qxx;
+    if (x < x0) x = x0;
+    if (x > x1) x = x1;
+    const double dx = x - m[0];
+    const double q = Qxx * dx * dx + 2.0 * Qxy * dx * dy + Qyy * dy * dy;
+    if (q < best) best = q;
+  }
+  return best;
+}
+
+/* Membership of tile (x, y) in particle i's list.  The rectangle part is
+ * decided (inp) or undecided (und_rect) from the extent's edges; with tile
+ * culling the tile must also meet the extent ellipse (Sec. 4.1: the 2D conic
+ * feeds the tiling and culling of 3DGS and StopThePop), i.e. the minimum over
+ * the tile's closed box of (v-m)^T (k^2 Sigma')^-1 (v-m) is at most 1.  That
+ * decision is undecided within the margin the FP32 ellipse can move: if its
+ * boundary moves by at most `edge` pixels (the same bound as the rectangle's
+ * edges; the error comes from the projected sigma points, in every direction
+ * alike) and its matrix entries carry a relative rounding `conic`, the
+ * decision can flip only for
+ *   |sqrt(q_min) - 1| <= edge / sqrt(lambda_min) + conic trace / (2 lambda_min),
+ * lambda_min being the smaller eigenvalue of k^2 Sigma' (the ellipse grown by
+ * `edge` pixels lies inside q <= (1 + edge / sqrt(lambda_min))^2, the one
+ * shrunk by it contains q <= (1 - edge / sqrt(lambda_min))^2).  Returns bit0
+ * primary member, bit1 undecided. */
+static int tile_membership(const ora_proj* pr, int64_t i, const ora_params* p, const ora_amb* amb,
+                           int x, int y, int inp, int und_rect) {
+  int ein = 1, eund = 0;
+  if (p->tile_cull) {
+    const double k2 = pr->kext[i] * pr->kext[i];
+    const double A[3] = {k2 * pr->cov2d[3 * i], k2 * pr->cov2d[3 * i + 1], k2 * pr->cov2d[3 * i + 2]};
+    const double tr = A[0] + A[2], det = A[0] * A[2] - A[1] * A[1];
+    const double disc = sqrt(0.25 * (A[0] - A[2]) * (A[0] - A[2]) + A[1] * A[1]);
+    const double lmax = 0.5 * tr + disc, lmin = lmax > 0 ? det / lmax : 0.0;
+    if (!(lmin > 0)) {
+      eund = 1; /* degenerate in FP64: kept here, the FP32 side may cull */
+    } else {
+      const double t = p->tile;
+      const double q = ora_ellipse_box_qmin(&pr->mean2d[2 * i], A, x * t, y * t, (x + 1) * t, (y + 1) * t);
+      const double margin = amb->edge / sqrt(lmin) + 0.5 * amb->conic * tr / lmin;
+      ein = q <= 1.0;
+      eund = fabs(sqrt(q) - 1.0) <= margin;
+    }
+  }
+  const int member = inp && ein;
+  const int undec = (und_rect || eund) && (inp || und_rect) && (ein || eund);
+  return (member ? 1 : 0) | (undec ? 2 : 0);
+}
+
 int64_t ora_bin(int64_t n, const ora_proj* pr, const ora_camera* c, const ora_params* p,
                 const ora_amb* amb, int64_t* tile_start, int32_t* ids, int32_t* flags) {
   const int tx = tiles_x(c, p), ty = tiles_y(c, p);
@@ -649,8 +720,7 @@ int64_t ora_bin(int64_t n, const ora_proj* pr, const ora_camera* c, const ora_pa
       for (int x = mx[0]; x <= mx[2]; x++) {
         int inp = x >= pm[0] && x <= pm[2] && y >= pm[1] && y <= pm[3];
         int inmin = x >= mn[0] && x <= mn[2] && y >= mn[1] && y <= mn[3];
-        int undec = und || !inmin;
-        if (inp || undec) cnt[(int64_t)y * tx + x]++;
+        if (tile_membership(pr, i, p, amb, x, y, inp, und || !inmin)) cnt[(int64_t)y * tx + x]++;
       }
   }
   int64_t total = 0;
@@ -667,13 +737,13 @@ int64_t ora_bin(int64_t n, const ora_proj* pr, const ora_camera* c, const ora_pa
       for (int x = mx[0]; x <= mx[2]; x++) {
         int inp = x >= pm[0] && x <= pm[2] && y >= pm[1] && y <= pm[3];
         int inmin = x >= mn[0] && x <= mn[2] && y >= mn[1] && y <= mn[3];
-        int undec = und || !inmin;
-        if (!(inp || undec)) continue;
+        const int fl = tile_membership(pr, i, p, amb, x, y, inp, und || !inmin);
+        if (!fl) continue;
         int64_t t = (int64_t)y * tx + x;
         bin_entry* b = &ent[tile_start[t] + cnt[t]++];
         b->depth = pr->depth[i];
         b->id = (int32_t)i;
-        b->flags = (inp ? 1 : 0) | (undec ? 2 : 0);
+        b->flags = fl;
       }
   }
 #pragma omp parallel for schedule(dynamic, 16)

@@ -50,6 +50,9 @@ typedef struct {
   double bg[3];
   int32_t kernel_degree; /* n of the generalized Gaussian response (Supp. A); 2 = Gaussian */
   int32_t kbuffer;       /* 0: tile-order compositing; k > 0: per-ray k-buffer (MLAB, Sec. 4.3) */
+  int32_t tile_cull;     /* 1: a rectangle tile joins a list only if the extent ellipse meets it
+                            (the 3DGS / StopThePop tile culling of Sec. 4.1 and 4.4); 0: every
+                            tile of the rectangle */
 } ora_params;
 
 typedef struct {
@@ -71,6 +74,7 @@ typedef struct {
   double* tstar;        /* [n] exposure time of the mean point (0 for a global shutter) */
   double* edge;         /* [n,4] v_x - h_x, v_y - h_y, v_x + h_x, v_y + h_y in pixels */
   double* valid_margin; /* [n] smallest validity margin over all sigma-point projections */
+  double* kext;         /* [n] the extent's cutoff k (the ellipse is (v-m)^T Sigma'^-1 (v-m) <= k^2) */
 } ora_proj;
 
 /* Ambiguity thresholds: decisions whose margin falls below these are treated
@@ -86,6 +90,7 @@ typedef struct {
   double diff;   /* an alternative is kept only if it differs by more than this */
   double clip;   /* |hit distance - clip distance| (relative) */
   double order;  /* |distance difference| of two hits in a k-buffer (relative) */
+  double conic;  /* relative rounding of the extent ellipse's matrix entries (tile culling) */
 } ora_amb;
 
 #define ORA_MAXALT 8
@@ -143,10 +148,17 @@ int ora_particle_alpha(const double mu[3], const double quat[4], const double sc
                        double opacity, const double o[3], const double d[3], int32_t kernel_degree,
                        double* tau_max, double* omega2, double* alpha_raw);
 
+/* Tile culling of one extent ellipse (mean m, matrix A = k^2 Sigma', xx xy yy):
+ * the minimum of (v-m)^T A^-1 (v-m) over the closed box [x0,x1] x [y0,y1]
+ * (0 when m lies inside); the box meets the ellipse iff it is <= 1. */
+double ora_ellipse_box_qmin(const double m[2], const double A[3], double x0, double y0,
+                            double x1, double y1);
+
 /* ---- pipeline ---- */
 int ora_project(const ora_scene* s, const ora_camera* c, const ora_params* p, ora_proj* out);
-/* Tile lists sorted by (depth, id).  flags bit0: member of the primary rect;
- * bit1: membership undecided (rect edge or validity within the margin).
+/* Tile lists sorted by (depth, id).  flags bit0: member of the primary list;
+ * bit1: membership undecided (rect edge, validity or, with tile culling, the
+ * ellipse test within the margin).
  * Call with ids == NULL to get the entry count. */
 int64_t ora_bin(int64_t n, const ora_proj* pr, const ora_camera* c, const ora_params* p,
                 const ora_amb* amb, int64_t* tile_start /* [T+1] */, int32_t* ids,

@@ -54,6 +54,7 @@ static void params(ora_params* p, int degree, int kbuf) {
   p->k_sigma_max = 3; p->tile = 16; p->rs_iters = 3;
   p->kernel_degree = degree;
   p->kbuffer = kbuf;
+  p->tile_cull = degree == 2;  /* both tile rules */
 }
 
 static void run(const ora_camera* c, const ora_params* p, int n, int deg, int use_clip) {
@@ -82,8 +83,9 @@ static void run(const ora_camera* c, const ora_params* p, int n, int deg, int us
   pr.tstar = malloc(sizeof(double) * n);
   pr.edge = malloc(sizeof(double) * 4 * n);
   pr.valid_margin = malloc(sizeof(double) * n);
+  pr.kext = malloc(sizeof(double) * n);
   if (ora_project(&s, c, p, &pr) != 0) FAIL("ora_project failed");
-  ora_amb amb = {1e-6, 1e-4, 1e-5, 1e-6, 2e-3, 1e-5, 1e-9, 1e-7, 1e-5, 1e-5};
+  ora_amb amb = {1e-6, 1e-4, 1e-5, 1e-6, 2e-3, 1e-5, 1e-9, 1e-7, 1e-5, 1e-5, 1e-6};
   const int tx = (c->width + 15) / 16, ty = (c->height + 15) / 16, T = tx * ty;
   int64_t* ts = malloc(sizeof(int64_t) * (T + 1));
   int64_t P = ora_bin(n, &pr, c, p, &amb, ts, NULL, NULL);
@@ -145,6 +147,8 @@ static void run(const ora_camera* c, const ora_params* p, int n, int deg, int us
   ora_sh_basis_grad(3, d, dY);
   (void)ora_particle_alpha(mu, q, sc, op[0], o, d, p->kernel_degree, &tau, &om2, &ar);
   (void)ora_ewa(c, p, 0.0, mu, q, sc, 1e-6, m2, c2);
+  const double em[2] = {3.0, -2.0}, eA[3] = {40.0, 25.0, 20.0};
+  (void)ora_ellipse_box_qmin(em, eA, 0, 0, 16, 16);
   double xs[30];
   double vs[20];
   int32_t ok[10];
@@ -154,6 +158,7 @@ static void run(const ora_camera* c, const ora_params* p, int n, int deg, int us
   free(mu); free(sc); free(q); free(op); free(sh);
   free(pr.cull); free(pr.mean2d); free(pr.cov2d); free(pr.rect); free(pr.tiles); free(pr.depth);
   free(pr.rgb); free(pr.rgb_raw); free(pr.tstar); free(pr.edge); free(pr.valid_margin);
+  free(pr.kext);
   free(ts); free(ids); free(fl); free(clip); free(tl);
   free(im.rgb); free(im.T); free(im.n_contrib); free(im.n_eval); free(im.inside); free(im.n_alt);
   free(im.alt_rgb); free(im.alt_T); free(im.alt_nc); free(im.alt_ne); free(im.n_amb);

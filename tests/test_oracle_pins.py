@@ -437,16 +437,27 @@ def test_generalized_single_particle_closed_form_and_extent(n):
     lambda from Supp. A's definition and d_perp from vector geometry.  The
     particle sits so that its degree-n alpha_min circle crosses into a tile
     column that the Gaussian's (smaller, for this opacity) circle does not
-    reach: an extent computed for the Gaussian would leave those pixels black."""
+    reach: an extent computed for the Gaussian would leave those pixels black.
+    Rendered with the whole rectangle (no tile culling); with tile culling the
+    pixels inside the UT extent ellipse keep these values and the others keep
+    them or lose the particle entirely (the UT ellipse of this near particle,
+    s/z = 0.12, undershoots its exact silhouette by O((s/z)^2), so tiles that
+    only the silhouette reaches are culled: the approximation the rectangle
+    itself makes at its edges)."""
     cam = G.camera("pinhole", 128, 128, 80.0, R0=np.eye(3), t0=np.array([0.0, 0.0, 4.0]))
     s, sig, col = 0.5, 0.1, np.array([0.9, 0.4, 0.1])
     mu = np.array([9.2 * 4.2 / 80.0, 0.0, 0.2])  # centre 9.2 px right of the principal point
     sh = ((col - 0.5) / G.SH_C0)[None, None, :]
     sc = O.OScene(mu[None], np.full((1, 3), s), np.array([[0.3, 0.1, 0.7, -0.2]]),
                   np.array([sig]), sh, 0)
-    p = O.default_params(kernel_degree=n)
+    p = O.default_params(kernel_degree=n, tile_cull=0)
     pr, b, res = O.render_full(sc, cam, p)
     img = O.to_image(res, cam, p)
+    pc = O.default_params(kernel_degree=n)
+    _, _, resc = O.render_full(sc, cam, pc)
+    imc = O.to_image(resc, cam, pc)
+    A = pr["kext"][0] ** 2 * pr["cov2d"][0]
+    Q = np.linalg.inv(np.array([[A[0], A[1]], [A[1], A[2]]]))
     lam = _lambda_from_definition(n)
     k_gauss = math.sqrt(2 * math.log(sig * 255))
     o = np.array([0.0, 0.0, -4.0])
@@ -460,6 +471,12 @@ def test_generalized_single_particle_closed_form_and_extent(n):
                 continue
             expect = col * a if a >= 1 / 255 else np.zeros(3)
             worst = max(worst, np.abs(img[py, px] - expect).max())
+            dv = np.array([px + 0.5, py + 0.5]) - pr["mean2d"][0]
+            if dv @ Q @ dv <= 1.0:
+                worst_c = np.abs(imc[py, px] - expect).max()
+            else:
+                worst_c = min(np.abs(imc[py, px] - expect).max(), np.abs(imc[py, px]).max())
+            worst = max(worst, worst_c)
             n_checked += 1
             if a >= 1 / 255 and w > k_gauss and px < 48:
                 ring += 1
@@ -724,7 +741,7 @@ def test_tiled_equals_bruteforce_when_rects_cover_everything():
     sc = O.OScene(rng.uniform(-0.3, 0.3, (n, 3)), np.exp(rng.normal(0.3, 0.1, (n, 3))),
                   rng.normal(size=(n, 4)), rng.uniform(0.05, 0.2, n),
                   rng.normal(0, 1, (n, 1, 3)), 0)
-    p = O.default_params()
+    p = O.default_params(tile_cull=0)
     pr = O.project(sc, cam, p)
     assert (pr["cull"] == 0).all() and (pr["tiles"] == 9).all()
     b = O.bin_tiles(pr, cam, p)
@@ -749,12 +766,12 @@ def test_tiled_close_to_bruteforce_config1():
 
 
 def test_tile_lists_bruteforce():
-    """Each tile's list holds exactly the visible particles whose rectangle
-    covers it, ordered by (depth, id)."""
+    """Without tile culling each tile's list holds exactly the visible
+    particles whose rectangle covers it, ordered by (depth, id)."""
     sc, cams = G.config1()
     cam = cams[0]
     pr = O.project(sc, cam)
-    ts, ids, fl = O.bin_tiles(pr, cam)
+    ts, ids, fl = O.bin_tiles(pr, cam, O.default_params(tile_cull=0))
     prim = fl & 1 == 1
     tx, ty = O.tiles_xy(cam, O.default_params())
     vis = np.nonzero(pr["cull"] == 0)[0]
