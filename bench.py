@@ -131,11 +131,37 @@ def pmc_summary(fetch_dir, write_dir, out_path, command):
     print(json.dumps(out))
 
 
+# Algorithmic bytes of the HBM-bound stages, per step.
+# project: each particle's 236 B (SH degree 3) read once per launch of up to
+# four cameras; per (camera, particle) 28 B written (rectangle, tiles, depth,
+# colour) plus 24 B for tile culling (mean, extent ellipse); the 64 B render
+# record per particle.
+# bin: per entry its 4 B tile count read by the count and the scatter
+# kernels; per visible entry 32 B (rectangle, mean, ellipse) read by each and
+# 4 B depth by the scatter; per pair 8 B of key written and read back, 4 B of
+# id written; per tile 24 B of counts, starts, ranges and order.
+PROJ_CAMS_PER_LAUNCH = 4
+BIN_KERNELS = 8  # init, count, column scan, list scan, scatter, sorts (lists < 1024, < 4096, longer)
+
+
+def project_bytes(n, n_cams):
+    launches = -(-n_cams // PROJ_CAMS_PER_LAUNCH)
+    return launches * 236 * n + n_cams * (28 + 24) * n + 64 * n
+
+
+def binning_bytes(E, nvis, P, T):
+    return 8 * E + (2 * 32 + 4) * nvis + (8 + 8 + 4) * P + 24 * T
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bench_forward(gs, cams, steps, warmup, R, torch, params=None, clip=None):
+def bench_forward(gs, cams, steps, warmup, R, torch, params=None, clip=None, flush=None):
+    """Forward steps back to back (warm).  With `flush` (a tensor larger than
+    the 256 MB Infinity Cache) each timed step is preceded by a write of the
+    whole tensor, outside the stage events, so every stage starts cold; the
+    step time is then the sum of the stage events."""
     proj = R.alloc_projection(gs.n, len(cams), gs.means.device)
     R.project(gs, cams, params, out=proj)
     bins = R.bin_tiles(proj, cams, params)
@@ -161,16 +187,19 @@ def bench_forward(gs, cams, steps, warmup, R, torch, params=None, clip=None):
     gc.disable()
     t0 = time.perf_counter()
     for k in range(steps):
+        if flush is not None:
+            flush.fill_(float(k))
         step(ev[k])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     gc.enable()
     st = np.array([[ev[k][i].elapsed_time(ev[k][i + 1]) for i in range(n_ev - 1)] for k in range(steps)])
+    ms_step = (t1 - t0) * 1e3 / steps if flush is None else float(st.sum(1).mean())
     # one extra, untimed render that counts evaluations per pixel
     img_eval = R.render(proj, bins, cams, params, with_eval=True, clip=clip)
     torch.cuda.synchronize()
     e_eval = int(img_eval.n_eval.to(torch.int64).sum().item())
-    return dict(ms_per_step=(t1 - t0) * 1e3 / steps, stage_ms=st.mean(0), stage_p10=np.percentile(st, 10, 0),
+    return dict(ms_per_step=ms_step, stage_ms=st.mean(0), stage_p10=np.percentile(st, 10, 0),
                 stage_p90=np.percentile(st, 90, 0), e_eval=e_eval, n_pairs=bins.n_pairs,
                 n_visible=int((proj.tiles > 0).sum().item()), img=img)
 
@@ -288,10 +317,25 @@ def bench_serving(n_requests, rates, R, G, torch, n_particles=3_000_000, warm=8)
     return out
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(scene, cams, budget_s, O):
-    """The FP64 oracle on this host, timed on the same step as the GPU (both
-    views: projection, binning and every tile rendered), repeated until the
-    time budget is spent; whole steps only."""
+    """The FP64 oracle on this host, built here with -O3 -march=native and
+    timed on the same step as the GPU (both views: projection, binning and
+    every tile rendered) on all the threads it gets, repeated until the time
+    budget is spent (whole steps only); then single-threaded on the pinhole
+    view: projection, binning and one tile in 16 rendered, extrapolated to
+    the whole step."""
+    flags = O.use_native()
+    threads = O.set_threads(0)
     p = O.default_params()
     osc = O.OScene.from_scene(scene)
     steps, t_proj, t_bin, t_render = 0, 0.0, 0.0, 0.0
@@ -310,11 +354,31 @@ def cpu_baseline(scene, cams, budget_s, O):
         steps += 1
     total = t_proj + t_bin + t_render
     npx = steps * sum(c["width"] * c["height"] for c in cams)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # one thread, one view, a sample of its tiles
+    O.set_threads(1)
+    cam = cams[0]
+    t0 = time.perf_counter()
+    pr = O.project(osc, cam, p)
+    t1 = time.perf_counter()
+    ob = O.bin_tiles(pr, cam, p)
+    t2 = time.perf_counter()
+    tx, ty = O.tiles_xy(cam, p)
+    sample = np.arange(0, tx * ty, 16, dtype=np.int32)
+    O.render(osc, pr, cam, ob, p, alternatives=False, tiles=sample)
+    t3 = time.perf_counter()
+    O.set_threads(threads)
+    t_one = (t1 - t0) + (t2 - t1) + (t3 - t2) * (tx * ty) / len(sample)
+    single = cam["width"] * cam["height"] / t_one / 1e6
     return dict(value=npx / total / 1e6, unit="Mpix/s", cores=threads, kind="oracle",
                 sample=f"{steps} whole step(s) of the 1M-Gaussian pinhole + fisheye 1920x1080 "
                        f"batch: FP64 projection {t_proj:.1f} s, binning {t_bin:.1f} s, "
-                       f"rendering every tile {t_render:.1f} s")
+                       f"rendering every tile {t_render:.1f} s",
+                cpu_model=cpu_model(), nproc=os.cpu_count(),
+                affinity=len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+                build=flags, single_thread_mpix_per_s=single,
+                single_thread_sample=f"pinhole 1920x1080 view on one thread: projection {t1 - t0:.2f} s, "
+                                     f"binning {t2 - t1:.2f} s, {len(sample)} of {tx * ty} tiles "
+                                     f"rendered in {t3 - t2:.2f} s (scaled to all tiles)")
 
 
 def main():
@@ -399,19 +463,36 @@ def main():
                     e_eval_per_launch=fw["e_eval"] / launches, flops_per_eval=F_EVAL,
                     ms_per_launch=render_ms_per_launch)
     del fw["img"]
-    # HBM rooflines of the other stages, on their algorithmic bytes per step:
-    # project reads each particle (236 B at SH degree 3) and writes 28 B per
-    # (camera, particle) plus the 64 B render record; binning moves 8 B per
-    # entry (compaction), 20 B per visible entry + 8 B per pair (expansion), 20 B
-    # per key per radix pass (histogram read 4, scatter read 8 + write 8) over
-    # 4 depth passes and 2 tile passes, and 8 B per pair for the ranges.
     n, nc, nvis, P = args.n, len(cams), fw["n_visible"], fw["n_pairs"]
-    proj_bytes = nc * (236 + 28) * n + 64 * n
-    bin_bytes = 8 * nc * n + 20 * nvis + 8 * P + 20 * 4 * nvis + 20 * 2 * P + 8 * P
+    T = sum(-(-int(c["width"]) // 16) * -(-int(c["height"]) // 16) for c in cams)
+    proj_bytes, bin_bytes = project_bytes(n, nc), binning_bytes(n * nc, nvis, P, T)
     stage_roofline = {
         k: dict(bound="hbm", bytes=b, achieved_gbs=b / (ms * 1e-3) / 1e9, peak_gbs=PEAK_HBM_GBS,
                 frac=b / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS)
         for k, b, ms in (("project", proj_bytes, fw["stage_ms"][0]), ("bin", bin_bytes, fw["stage_ms"][1]))}
+    stage_roofline["bin"]["kernels"] = BIN_KERNELS
+
+    # the same step with every stage cold: a 512 MB write before each step
+    # evicts the scene and the buffers from the 256 MB Infinity Cache
+    log("[bench] forward steps, cold (Infinity Cache flushed before each step)")
+    flush = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
+    fcold = bench_forward(gs, cams, max(3, args.steps // 2), 2, R, torch, flush=flush)
+    del flush
+    cold = dict(ms_per_step=fcold["ms_per_step"],
+                stages_ms={"project": fcold["stage_ms"][0], "bin": fcold["stage_ms"][1],
+                           "render": fcold["stage_ms"][2]},
+                project_frac=proj_bytes / (fcold["stage_ms"][0] * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                bin_frac=bin_bytes / (fcold["stage_ms"][1] * 1e-3) / 1e9 / PEAK_HBM_GBS)
+    del fcold
+
+    # the rectangle-only tile lists (tile culling off), for comparison
+    log("[bench] forward steps without tile culling")
+    frect = bench_forward(gs, cams, max(3, args.steps // 2), 2, R, torch, dict(tile_cull=0))
+    rect_only = dict(mpix_per_s=npx / (frect["ms_per_step"] * 1e-3) / 1e6, n_pairs=frect["n_pairs"],
+                     e_eval=frect["e_eval"],
+                     stages_ms={"project": frect["stage_ms"][0], "bin": frect["stage_ms"][1],
+                                "render": frect["stage_ms"][2]})
+    del frect
 
     # the generalized Gaussian responses of Supp. A on the same forward step
     # (its table trades quality for speed across degrees 2..8)
@@ -534,6 +615,8 @@ def main():
         "stages_ms": {"project": fw["stage_ms"][0], "bin": fw["stage_ms"][1],
                       "render": fw["stage_ms"][2]},
         "stage_roofline": stage_roofline,
+        "stages_cold": cold,
+        "tile_cull_off": rect_only,
         "n_pairs": fw["n_pairs"],
         "n_visible": fw["n_visible"],
         "fwd_bwd_ms_per_view": fwd_bwd["ms_per_view"] if fwd_bwd else None,

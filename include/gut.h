@@ -6,7 +6,8 @@
  *   gut_project     per (camera, particle): sigma points, 2D mean/covariance,
  *                   extent, tile rectangle, sort depth, SH colour
  *                   (Alg. 1 with Alg. 2, Eq. 6-10, Sec. 4.1)
- *   gut_bin         (tile, depth) binning by device radix sort (Sec. 4.3)
+ *   gut_bin         per-tile lists in depth order (Sec. 4.3), with the
+ *                   tile culling of 3DGS / StopThePop (Sec. 4.1, 4.4)
  *   gut_render      per-tile front-to-back compositing (Eq. 5) with each
  *                   particle evaluated at its maximum response along the
  *                   pixel ray (Eq. 11, Sec. 4.2)
@@ -110,7 +111,12 @@ typedef struct {
  * counts blended hits.  gut_render_bwd differentiates it in blend order.
  * It honours clip_depth (hybrid rendering, Sec. 6.2, renders primary rays
  * this way) and kernel_degree.  gut_serve_create returns GUT_E_UNSUPPORTED
- * for k > 0. */
+ * for k > 0.
+ * tile_cull (default 1): gut_bin keeps a tile of a particle's rectangle only
+ * if the particle's extent ellipse (v - m)^T (k^2 Sigma')^-1 (v - m) <= 1
+ * meets the tile's box -- the 2D conic drives the tiling and culling of 3DGS
+ * and StopThePop (Sec. 4.1), which the method employs (Sec. 4.4); 0 keeps
+ * every tile of the rectangle. */
 typedef struct {
   float ut_alpha, ut_beta, ut_kappa;
   float alpha_min, alpha_max, t_min, near_plane, k_sigma_max;
@@ -118,6 +124,7 @@ typedef struct {
   float bg[3];
   int32_t kernel_degree;
   int32_t kbuffer;
+  int32_t tile_cull;
 } gut_params;
 
 /* Outputs of gut_project (caller-allocated device arrays).
@@ -127,8 +134,12 @@ typedef struct {
  *   rgb    [C*n,3] float  view-dependent colour max(0, 1/2 + SH)
  *   record [n,16]  float  render record: mu(3), opacity, M = S^-1 R^T (3x3,
  *                         rows padded to 4); written once per call
- *   mean2d [C*n,2] float  nullable: UT mean (Eq. 9)
- *   cov2d  [C*n,3] float  nullable: UT covariance xx, xy, yy (Eq. 10) */
+ *   mean2d [C*n,2] float  nullable: UT mean (Eq. 9); gut_bin needs it with tile_cull
+ *   cov2d  [C*n,3] float  nullable: UT covariance xx, xy, yy (Eq. 10)
+ *   extent [C*n,4] float  nullable (16-byte aligned): the extent ellipse
+ *                         k^2 Sigma' (xx, xy, yy) and its cutoff k (Alg. 1
+ *                         Extent); zeros for culled entries; gut_bin needs it
+ *                         with tile_cull */
 typedef struct {
   int16_t* rect;
   uint32_t* tiles;
@@ -137,6 +148,7 @@ typedef struct {
   float* record;
   float* mean2d;
   float* cov2d;
+  float* extent;
 } gut_projected;
 
 void gut_default_params(gut_params* p);
@@ -152,13 +164,18 @@ int64_t gut_num_pixels(const gut_camera* cams, int32_t n_cams);
 gut_status gut_project(const gut_scene* scene, const gut_camera* cams, int32_t n_cams,
                        const gut_params* p, const gut_projected* out, void* stream);
 
-/* Workspace for gut_bin (bytes, 256-aligned base expected). */
-size_t gut_bin_workspace_bytes(int64_t n, int32_t n_cams, int64_t pair_capacity);
+/* Workspace for gut_bin (bytes, 256-aligned base expected) for n particles
+ * seen by the n_cams cameras (host array) and pair_capacity pairs: a count
+ * matrix of ceil(n / 8192) rows by the cameras' total tile count (u32), 4 KiB,
+ * and 16 bytes per pair.  0 on bad arguments. */
+size_t gut_bin_workspace_bytes(int64_t n, const gut_camera* cams, int32_t n_cams, int64_t pair_capacity);
 
-/* Global per-tile depth sort (Sec. 4.3): visible entries are sorted by
- * (depth, entry id), duplicated once per touched tile, and stably sorted by
- * global tile id with a hand-written LSD radix sort.
- *   tile_ranges [3T] uint32   out: [T,2] [start, end) of each tile in sorted_ids,
+/* Global per-tile depth sort (Sec. 4.3): each tile's list holds the visible
+ * entries whose rectangle covers it (and, with tile_cull, whose extent
+ * ellipse meets it), ordered by (depth, entry id).  The lists are built by a
+ * counting sort over tiles and a per-tile radix sort in LDS.
+ *   tile_ranges [3T] uint32   out: [T,2] [start, end) of each tile in sorted_ids
+ *                             (an empty list has start == end),
  *                             then [T] the render order: for each camera, its
  *                             camera-local tile indices with the longest lists
  *                             first (bucketed by floor(log2(length)); order
@@ -167,11 +184,12 @@ size_t gut_bin_workspace_bytes(int64_t n, int32_t n_cams, int64_t pair_capacity)
  *                             tiles in this order to shorten the tail.
  *   sorted_ids  [pair_capacity] uint32 out: entry ids e = cam*n + i
  *   n_pairs     host int64*   out (nullable): number of pairs P
- * proj's rect (8-byte aligned), tiles and depth are read as gut_project
- * writes them (tiles[e] = the area of rect[e], 0 when culled); tile_ranges
- * must be 8-byte aligned.  If P > pair_capacity nothing is written past the
- * buffer, every tile's range is empty, *n_pairs holds the required size and
- * GUT_E_CAPACITY is returned. */
+ * proj's rect (8-byte aligned), tiles and depth -- with tile_cull also
+ * mean2d and extent -- are read as gut_project writes them (tiles[e] = the
+ * area of rect[e], 0 when culled); tile_ranges must be 8-byte aligned.  The
+ * workspace is gut_bin_workspace_bytes(n, cams, n_cams, pair_capacity).  If P >
+ * pair_capacity nothing is written past the buffer, every tile's range is
+ * empty, *n_pairs holds the required size and GUT_E_CAPACITY is returned. */
 gut_status gut_bin(const gut_projected* proj, int64_t n, const gut_camera* cams, int32_t n_cams,
                    const gut_params* p, void* ws, size_t ws_bytes, int64_t pair_capacity,
                    uint32_t* tile_ranges, uint32_t* sorted_ids, int64_t* n_pairs, void* stream);

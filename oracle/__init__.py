@@ -24,14 +24,37 @@ _lib = None
 MAXALT = 8
 
 
+FLAGS = ["-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
+         "-ffp-contract=off"]
+
+
 def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (C11, FP64, OpenMP)."""
+    """Compile liboracle.so with gcc (C11, FP64, OpenMP, no FMA contraction),
+    for any x86-64 host (the library travels with the tree)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
-                               "-fno-fast-math", _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc"] + FLAGS + [_SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+def use_native() -> str:
+    """Rebuild the oracle for this host's CPU (-march=native) in a temporary
+    folder and load that copy instead (for timing it); returns the flags."""
+    global _lib
+    import tempfile
+    flags = FLAGS + ["-march=native"]
+    path = os.path.join(tempfile.mkdtemp(prefix="oracle_native_"), "liboracle_native.so")
+    subprocess.check_call(["gcc"] + flags + [_SRC, "-o", path, "-lm"])
+    L = C.CDLL(path)
+    _declare(L)
+    _lib = L
+    return " ".join(flags)
+
+
+def set_threads(n: int = 0) -> int:
+    """OpenMP threads of the oracle: n > 0 sets them; returns the count in use."""
+    return int(lib().ora_set_threads(int(n)))
 
 
 def lib():
@@ -108,6 +131,8 @@ def _declare(L):
     L.ora_ewa.argtypes = [vp, vp, d, vp, vp, vp, d, vp, vp]
     L.ora_ewa.restype = C.c_int
     L.ora_project.argtypes = [vp, vp, vp, vp]
+    L.ora_set_threads.argtypes = [C.c_int]
+    L.ora_set_threads.restype = C.c_int
     L.ora_ellipse_box_qmin.argtypes = [vp, vp, d, d, d, d]
     L.ora_ellipse_box_qmin.restype = d
     L.ora_bin.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]

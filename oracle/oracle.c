@@ -639,6 +639,11 @@ static int particle_rects(const ora_proj* pr, int64_t i, const ora_camera* c, co
   return mx[0] <= mx[2] && mx[1] <= mx[3];
 }
 
+int ora_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+}
+
 double ora_ellipse_box_qmin(const double m[2], const double A[3], double x0, double y0,
                             double x1, double y1) {
   const double det = A[0] * A[2] - A[1] * A[1];

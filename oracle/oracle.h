@@ -154,6 +154,9 @@ int ora_particle_alpha(const double mu[3], const double quat[4], const double sc
 double ora_ellipse_box_qmin(const double m[2], const double A[3], double x0, double y0,
                             double x1, double y1);
 
+/* OpenMP threads of the calls below: n > 0 sets them; returns the count in use. */
+int ora_set_threads(int n);
+
 /* ---- pipeline ---- */
 int ora_project(const ora_scene* s, const ora_camera* c, const ora_params* p, ora_proj* out);
 /* Tile lists sorted by (depth, id).  flags bit0: member of the primary list;

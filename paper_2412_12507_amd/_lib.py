@@ -52,13 +52,13 @@ class Params(C.Structure):
                 ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
                 ("near_plane", C.c_float), ("k_sigma_max", C.c_float),
                 ("tile", C.c_int32), ("rs_iters", C.c_int32), ("bg", C.c_float * 3),
-                ("kernel_degree", C.c_int32), ("kbuffer", C.c_int32)]
+                ("kernel_degree", C.c_int32), ("kbuffer", C.c_int32), ("tile_cull", C.c_int32)]
 
 
 class Projected(C.Structure):
     _fields_ = [("rect", C.c_void_p), ("tiles", C.c_void_p), ("depth", C.c_void_p),
                 ("rgb", C.c_void_p), ("record", C.c_void_p), ("mean2d", C.c_void_p),
-                ("cov2d", C.c_void_p)]
+                ("cov2d", C.c_void_p), ("extent", C.c_void_p)]
 
 
 class ServeMetrics(C.Structure):
@@ -93,7 +93,7 @@ def load():
     L.gut_num_pixels.restype = i64
     L.gut_project.argtypes = [vp, vp, i32, vp, vp, vp]
     L.gut_project.restype = st
-    L.gut_bin_workspace_bytes.argtypes = [i64, i32, i64]
+    L.gut_bin_workspace_bytes.argtypes = [i64, vp, i32, i64]
     L.gut_bin_workspace_bytes.restype = sz
     L.gut_bin.argtypes = [vp, i64, vp, i32, vp, vp, sz, i64, vp, vp, vp, vp]
     L.gut_bin.restype = st
@@ -171,7 +171,7 @@ def params_struct(params: dict | None = None) -> Params:
         if k == "bg":
             for i in range(3):
                 p.bg[i] = float(v[i])
-        elif k in ("tile", "rs_iters", "kernel_degree", "kbuffer"):
+        elif k in ("tile", "rs_iters", "kernel_degree", "kbuffer", "tile_cull"):
             setattr(p, k, int(v))
         else:
             setattr(p, k, float(v))

@@ -20,8 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libgut.so")
 OBJDIR = os.path.join(PKG, "_build")
 
-SOURCES = ["api.cpp", "project.hip", "sort.hip", "bin.hip", "render.hip", "render_bwd.hip",
-           "serve.cpp"]
+SOURCES = ["api.cpp", "project.hip", "bin.hip", "render.hip", "render_bwd.hip", "serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -209,6 +209,10 @@ gut_status check_params(const gut_params* p) {
     set_error("kbuffer must be in [0, 16]");
     return GUT_E_INVALID;
   }
+  if (p->tile_cull != 0 && p->tile_cull != 1) {
+    set_error("tile_cull must be 0 or 1");
+    return GUT_E_INVALID;
+  }
   return GUT_OK;
 }
 
@@ -299,6 +303,7 @@ void gut_default_params(gut_params* p) {
   p->bg[0] = p->bg[1] = p->bg[2] = 0.0f;
   p->kernel_degree = 2;
   p->kbuffer = 0;
+  p->tile_cull = 1;
 }
 
 int64_t gut_num_tiles(const gut_camera* cams, int32_t n_cams, const gut_params* p) {

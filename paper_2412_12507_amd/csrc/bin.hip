@@ -1,24 +1,37 @@
-// Tile binning: the global per-tile depth sort of Sec. 4.3.
+// Tile binning: the global per-tile depth sort of Sec. 4.3, with the tile
+// culling of 3DGS and StopThePop that Sec. 4.1 and 4.4 name.
 //
-// Order of work (E = n_cams * n entries, P = pairs):
-//   1. stable LSD radix sort of the visible entries by depth (32 bits); its
-//      first pass reads every entry and places only the visible ones, so the
-//      compaction costs no pass of its own; its histogram also leaves
-//      per-block totals of N_vis and P, which go to the host while the rest
-//      of the sort runs; its last pass writes, instead of the depth keys, what
-//      the duplication reads: each entry's tile count and tile geometry
-//   2. scan of the tile counts in depth order -> pair offsets
-//   3. duplicate: each entry writes (global tile id, entry id) for every tile
-//      of its rectangle at its offset
-//   4. stable LSD radix sort of the P pairs by tile id (ceil(log2 T) bits);
-//      its last pass also writes the per-tile [start, end) ranges
-// Sorting entries by depth first and then pairs by tile only gives exactly the
-// (tile, depth, id) order of a full-key sort while moving far fewer bytes:
-// the tile sort carries 4-byte keys over ceil(log2 T)/8 passes instead of
-// 8-byte keys over (32 + log2 T)/8 passes.
+// Every (tile, entry) pair whose tile lies in the entry's rectangle -- and,
+// with tile culling, meets the entry's extent ellipse -- goes into that
+// tile's list, and each list is ordered by (depth, entry id).  Instead of a
+// global sort of all pairs by a (tile, depth) key, the lists are built by a
+// counting sort over tiles followed by one small sort per list:
+//   K1 bin_count_kernel     each block of up to 8192 entries (128 units of 64
+//                           neighbouring ones, strided over the camera)
+//                           counts its pairs per tile in LDS and writes the
+//                           counts as one row of a (block x tile) matrix
+//   K2 bin_colscan_kernel   per tile, the exclusive prefix of its column (the
+//                           block's offset inside the tile's list) and the
+//                           tile's count
+//   K3 bin_scan_kernel      per camera: the list starts, the render order
+//                           (longest lists first), how many lists are long,
+//                           and the pair total P (to the host: the one wait)
+//   K4 bin_scatter_kernel   each block writes its pairs' 64-bit keys (depth
+//                           bits << 32 | entry id) at its offsets in the lists
+//   K5 tile_sort_*_kernel   per list, in LDS: a bucket sort on the highest
+//                           bits that vary within it with a direct rank
+//                           count inside each bucket, or, if a bucket is
+//                           large, a stable LSD radix sort; one wave per
+//                           list below 1024 entries, 256 threads up to 4095,
+//                           512 (radix, in chunks) beyond
+// Nothing needs a device-wide atomic per pair or per touched tile: blocks on
+// different XCDs meet only in the count matrix, whose columns K2 scans.
+// The (depth bits, id) key orders exactly as a full (tile, depth, id) sort
+// would: depths are non-negative, so their bits order as the floats do.
+#include <algorithm>
 #include <cstring>
 
-#include "radix.h"
+#include "common.h"
 
 namespace gut {
 
@@ -30,314 +43,919 @@ struct CamTiles {
 
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Workspace of the entry phase (sized by E = n_cams * n) and of the pair
-// phase (sized by the pair capacity).
-struct EntryLayout {
-  size_t scalars, part_n, part_p, dkA, dvA, dkB, dvB, pA, pB, geo, offs, offs_tmp, radix_tmp, total;
+constexpr int kBinThreads = 1024;
+constexpr int kBinItems = 8;
+constexpr int kBinChunk = kBinThreads * kBinItems;  // entries per block, at most
+constexpr int kLdsTiles = 16000;  // tiles counted in LDS at once (64 KB); larger cameras go in windows
+
+// Small per-call values after the count matrix: per-camera pair totals, the
+// total P, and per camera the number of lists of at least 4096 and of at
+// least 1024 entries (the front of its render order).
+struct SmallLayout {
+  static constexpr size_t cam_pairs = 0;                     // u64 [kMaxCams]
+  static constexpr size_t total = cam_pairs + 8 * kMaxCams;  // u64
+  static constexpr size_t nbig = total + 256;                // u32 [kMaxCams]
+  static constexpr size_t nmid = nbig + 4 * kMaxCams;        // u32 [kMaxCams]
+  static constexpr size_t bytes = nmid + 4 * kMaxCams + 256;
 };
-struct PairLayout {
-  size_t pkA, pkB, pvB, radix_tmp, total;
+constexpr size_t kSmallBytes = 4096;
+static_assert(SmallLayout::bytes <= kSmallBytes, "small workspace");
+
+static int64_t blocks_per_cam(int64_t n) { return n > 0 ? (n + kBinChunk - 1) / kBinChunk : 0; }
+
+// Count phase: the (block x tile) matrix (blocks_per_cam x tiles of every
+// camera, u32) and the small values.
+size_t bin_count_bytes(int64_t n, int64_t T) { return al((size_t)(blocks_per_cam(n) * T) * 4) + kSmallBytes; }
+// Pair phase: the pairs' keys and a ping-pong copy for lists longer than one
+// LDS chunk.
+size_t bin_pair_bytes(int64_t cap) { return 2 * al((size_t)(cap > 0 ? cap : 1) * 8); }
+
+// --------------------------------------------------------------- culling
+
+// The tiles of one entry, row by row.  Without culling a row takes every
+// column of the rectangle.  With culling it takes the columns whose tiles
+// meet the extent ellipse (v - m)^T A^-1 (v - m) <= 1, A = k^2 Sigma': within
+// the horizontal band of tile row ty the ellipse spans x from its left
+// boundary at height yl to its right boundary at height yr, where yr is the
+// height of the ellipse's rightmost point clamped into the band (the right
+// boundary is concave in y) and yl likewise for the leftmost point.  The
+// ellipse comes in FP32 from the projection; the geometry runs in FP64.
+struct RowCull {
+  double vx, vy, ylo, yhi, yR, yL, slope, wfac, inv_c;
+  bool on;
 };
 
-static EntryLayout entry_layout(int64_t E) {
-  EntryLayout L;
-  size_t o = 0;
-  auto take = [&](size_t bytes) { size_t r = o; o += al(bytes); return r; };
-  const int64_t nb = radix_blocks(E);
-  L.scalars = take(64);
-  L.part_n = take(nb * 4);
-  L.part_p = take(nb * 8);
-  L.dkA = take(E * 4);
-  L.dvA = take(E * 4);
-  L.dkB = take(E * 4);
-  L.dvB = take(E * 4);
-  L.pA = take(E * 4);
-  L.pB = take(E * 4);
-  L.geo = take(E * 8);
-  L.offs = take(E * 4);
-  L.offs_tmp = take(scan_temp_bytes(E));
-  L.radix_tmp = take(radix_temp_bytes(E));
-  L.total = o;
-  return L;
+__device__ inline RowCull row_cull_setup(bool cull, const float2* __restrict__ mean2d,
+                                         const float4* __restrict__ extent, int64_t e) {
+  RowCull rc;
+  rc.on = false;
+  if (!cull) return rc;
+  const float2 m = mean2d[e];
+  const float4 A = extent[e];
+  const double a = A.x, b = A.y, c = A.z;
+  const double det = a * c - b * b;
+  if (!(det > 0.0) || !(a > 0.0) || !(c > 0.0)) return rc;  // degenerate: the whole rectangle
+  const double sa = sqrt(a), sc = sqrt(c);
+  rc.vx = m.x;
+  rc.vy = m.y;
+  rc.ylo = rc.vy - sc;
+  rc.yhi = rc.vy + sc;
+  rc.yR = rc.vy + b / sa;
+  rc.yL = rc.vy - b / sa;
+  rc.slope = b / c;
+  rc.wfac = det / c;
+  rc.inv_c = 1.0 / c;
+  rc.on = true;
+  return rc;
 }
 
-static PairLayout pair_layout(int64_t cap) {
-  PairLayout L;
-  size_t o = 0;
-  auto take = [&](size_t bytes) { size_t r = o; o += al(bytes); return r; };
-  L.pkA = take(cap * 4);
-  L.pkB = take(cap * 4);
-  L.pvB = take(cap * 4);
-  L.radix_tmp = take(radix_temp_bytes(cap));
-  L.total = o;
-  return L;
+// Columns [*c0, *c1] of tile row ty kept for the entry (empty if *c0 > *c1),
+// inside the rectangle's columns [x0, x1].
+__device__ inline void row_cull_range(const RowCull& rc, int ty, int x0, int x1, int* c0, int* c1) {
+  if (!rc.on) {
+    *c0 = x0;
+    *c1 = x1;
+    return;
+  }
+  const double Y0 = (double)ty * kTile, Y1 = Y0 + kTile;
+  const double lo = fmax(Y0, rc.ylo), hi = fmin(Y1, rc.yhi);
+  if (lo > hi) {
+    *c0 = 1;
+    *c1 = 0;
+    return;
+  }
+  const double yr = fmin(fmax(rc.yR, lo), hi), dr = yr - rc.vy;
+  const double xr = rc.vx + rc.slope * dr + sqrt(fmax(0.0, rc.wfac * (1.0 - dr * dr * rc.inv_c)));
+  const double yl = fmin(fmax(rc.yL, lo), hi), dl = yl - rc.vy;
+  const double xl = rc.vx + rc.slope * dl - sqrt(fmax(0.0, rc.wfac * (1.0 - dl * dl * rc.inv_c)));
+  const double inv_t = 1.0 / kTile;
+  *c0 = max(x0, (int)fmax(floor(xl * inv_t), -1.0));
+  *c1 = min(x1, (int)fmin(floor(xr * inv_t), 1e9));
 }
 
-size_t bin_entry_bytes(int64_t E) { return entry_layout(E).total; }
-size_t bin_pair_bytes(int64_t cap) { return pair_layout(cap).total; }
-
-// Packed tile rectangle: x0 | y0 << 8 | (x1 - x0) << 16 | (y1 - y0) << 24,
-// exact when every camera has at most 256 tiles per axis.
-__device__ inline uint32_t pack_rect(short4 r) {
-  return ((uint32_t)r.x & 255u) | (((uint32_t)r.y & 255u) << 8) | (((uint32_t)(r.z - r.x) & 255u) << 16) |
-         (((uint32_t)(r.w - r.y) & 255u) << 24);
+// Calls f(ty, c0, c1) for each tile row ty of the entry inside the row window
+// [w0, w1) whose kept columns [c0, c1] are not empty.  The rows are visited
+// from the rot-th one on, cyclically: lanes of a wave walking similar
+// entries (neighbouring ids are often neighbours in space) then work on
+// different rows at each step instead of piling onto the same LDS words.
+template <class F>
+__device__ inline void for_each_row(int64_t e, const short4* __restrict__ rect, bool cull,
+                                    const float2* __restrict__ mean2d, const float4* __restrict__ extent,
+                                    int w0, int w1, int rot, F&& f) {
+  const short4 r = rect[e];
+  const int ty0 = max((int)r.y, w0), ty1 = min((int)r.w, w1 - 1);
+  if (ty0 > ty1) return;
+  const RowCull rc = row_cull_setup(cull, mean2d, extent, e);
+  const int nr = ty1 - ty0 + 1;
+  int k = rot % nr;
+  for (int j = 0; j < nr; j++) {
+    const int ty = ty0 + k;
+    k = k + 1 == nr ? 0 : k + 1;
+    int c0, c1;
+    row_cull_range(rc, ty, r.x, r.z, &c0, &c1);
+    if (c0 <= c1) f(ty, c0, c1);
+  }
 }
 
-// The entries of chunk `chunk` as depth-sort items: key = depth bits, value =
-// entry id, valid = the entry touches a tile.  *pairs (if given) receives the
-// sum of the items' tile counts; rect (if given) fills pp with the packed
-// rectangles.
-__device__ inline uint32_t load_entry_chunk(const uint32_t* __restrict__ tiles,
-                                            const float* __restrict__ depth, int64_t E,
-                                            uint32_t (&kk)[kRItems], uint32_t (&vv)[kRItems],
-                                            unsigned long long* pairs, const short4* __restrict__ rect,
-                                            uint32_t (&pp)[kRItems], int64_t chunk) {
-  const int lane = threadIdx.x & (kRWave - 1), w = threadIdx.x / kRWave;
-  const int64_t base = chunk * kRChunk + (int64_t)w * (kRChunk / kRWaves);
+// ------------------------------------------------------ count and scatter
+
+struct BinArgs {
+  const short4* rect;
+  const uint32_t* tiles;
+  const float* depth;
+  const float2* mean2d;
+  const float4* extent;
+  int n;     // particles (entries per camera)
+  int bpc;   // blocks per camera
+  int cull;  // tile culling on
+  int n_cams;
+  CamTiles ct;
+};
+
+// Entries go to blocks in units of 64 consecutive ones (one per wave
+// lane): block b of a camera owns its units b, b + bpc, b + 2 bpc, ...  so
+// that the dense clusters of a scene, which hold runs of neighbouring entry
+// ids, spread over all blocks.  Inside a block the waves claim the block's
+// units one at a time from an LDS counter until none is left, which evens out
+// their work.
+__device__ inline int units_of_block(int n, int bpc, int b) {
+  const int nu = (n + 63) / 64;
+  return nu > b ? (nu - 1 - b) / bpc + 1 : 0;
+}
+
+// Claims the wave's next unit; returns its index among the block's units.
+__device__ inline int claim_unit(int* next) {
+  int k = 0;
+  if ((threadIdx.x & 63) == 0) k = atomicAdd(next, 1);
+  return __shfl(k, 0, 64);
+}
+
+// Tile rows of a camera whose tiles fit the LDS at once (with one spare
+// column per row for the count kernel's difference arrays).
+// Camera widths stay below 4096 tiles, so a window holds at least 3 rows.
+__host__ __device__ inline int window_rows(int txc, int tyc) {
+  const int r = kLdsTiles / (txc + 1);
+  return tyc < r ? tyc : r;
+}
+
+// In-place inclusive prefix sums of rows of txc words (row stride `stride`)
+// in LDS, one wave per row.
+__device__ inline void lds_row_scan(uint32_t* h, int nrow, int txc, int stride) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int q = (txc + 63) / 64;  // consecutive columns per lane
+  for (int r = w; r < nrow; r += nw) {
+    uint32_t* row = h + r * stride;
+    const int c0 = lane * q;
+    uint32_t sum = 0;
+    for (int c = c0; c < min(c0 + q, txc); c++) sum += row[c];
+    uint32_t x = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    uint32_t run = x - sum;
+    for (int c = c0; c < min(c0 + q, txc); c++) {
+      run += row[c];
+      row[c] = run;
+    }
+  }
+}
+
+// K1: one row of the count matrix per block (camera c, the units of it that
+// the block owns).  Each visible entry adds, per
+// tile row, +1 at its first kept column and -1 after its last to an LDS
+// difference array of the camera's tiles (in windows of tile rows); prefix
+// sums along the rows then give the counts.
+__global__ void __launch_bounds__(kBinThreads) bin_count_kernel(BinArgs a, uint32_t* __restrict__ M) {
+  extern __shared__ uint32_t h[];
+  __shared__ int next;
+  const int c = blockIdx.x / a.bpc, b = blockIdx.x % a.bpc;
+  const int txc = a.ct.tx[c], Tc = a.ct.count[c], tyc = Tc / txc, S = txc + 1;
+  const int64_t e0 = (int64_t)c * a.n;
+  const int lane = threadIdx.x & 63, nub = units_of_block(a.n, a.bpc, b);
+  uint32_t* row = M + (int64_t)a.bpc * a.ct.base[c] + (int64_t)b * Tc;
+  const int RW = window_rows(txc, tyc);
+  for (int w0 = 0; w0 < tyc; w0 += RW) {
+    const int nrow = min(RW, tyc - w0);
+    for (int i = threadIdx.x; i < nrow * S; i += kBinThreads) h[i] = 0u;
+    if (threadIdx.x == 0) next = 0;
+    __syncthreads();
+    for (int k = claim_unit(&next); k < nub; k = claim_unit(&next)) {
+      const int i = (b + k * a.bpc) * 64 + lane;
+      if (i < a.n && a.tiles[e0 + i] != 0u)
+        for_each_row(e0 + i, a.rect, a.cull, a.mean2d, a.extent, w0, w0 + nrow, lane, [&](int ty, int c0, int c1) {
+          uint32_t* hr = h + (ty - w0) * S;
+          atomicAdd(&hr[c0], 1u);
+          atomicAdd(&hr[c1 + 1], ~0u);  // -1
+        });
+    }
+    __syncthreads();
+    lds_row_scan(h, nrow, txc, S);
+    __syncthreads();
+    for (int r = threadIdx.x >> 6; r < nrow; r += kBinThreads / 64)
+      for (int x = lane; x < txc; x += 64) row[(w0 + r) * txc + x] = h[r * S + x];
+    __syncthreads();
+  }
+}
+
+// K2: for each tile (one thread per tile of every camera), the exclusive
+// prefix of its column of the count matrix, in place, and its count into
+// ranges[t].y; each block adds its tiles' counts to their cameras' totals
+// (one atomic per camera a block touches; the totals start at zero from the
+// init kernel).
+constexpr int kColThreads = 256;
+constexpr int kColUnroll = 8;
+__global__ void __launch_bounds__(kColThreads) bin_colscan_kernel(uint32_t* __restrict__ M, CamTiles ct,
+                                                                  int n_cams, int bpc, int64_t T,
+                                                                  uint2* __restrict__ ranges,
+                                                                  unsigned long long* __restrict__ cam_pairs) {
+  __shared__ unsigned long long cs[kMaxCams];
+  const int64_t g = (int64_t)blockIdx.x * kColThreads + threadIdx.x;
+  if (threadIdx.x < kMaxCams) cs[threadIdx.x] = 0ull;
+  __syncthreads();
+  if (g < T) {
+    int c = 0;
+    while (c + 1 < n_cams && ct.base[c + 1] <= g) c++;
+    const int Tc = ct.count[c], t = (int)(g - ct.base[c]);
+    uint32_t* col = M + (int64_t)bpc * ct.base[c] + t;
+    uint32_t run = 0;
+    for (int b0 = 0; b0 < bpc; b0 += kColUnroll) {
+      uint32_t v[kColUnroll];
+#pragma unroll
+      for (int k = 0; k < kColUnroll; k++) v[k] = b0 + k < bpc ? col[(int64_t)(b0 + k) * Tc] : 0u;
+#pragma unroll
+      for (int k = 0; k < kColUnroll; k++) {
+        if (b0 + k < bpc) col[(int64_t)(b0 + k) * Tc] = run;
+        run += v[k];
+      }
+    }
+    ranges[g].y = run;
+    atomicAdd(&cs[c], (unsigned long long)run);
+  }
+  __syncthreads();
+  if (threadIdx.x < n_cams && cs[threadIdx.x]) atomicAdd(&cam_pairs[threadIdx.x], cs[threadIdx.x]);
+}
+
+// Clears the per-camera totals K2 adds into.
+__global__ void bin_init_kernel(unsigned long long* __restrict__ cam_pairs) {
+  if (threadIdx.x < kMaxCams) cam_pairs[threadIdx.x] = 0ull;
+}
+
+// K4: each pair's key at its place: the tile's list start plus the block's
+// offset in the tile (the column prefix) plus its rank among the block's
+// pairs of that tile (an LDS counter; the order inside a block is arbitrary
+// and fixed by K5).  Writes nothing when P exceeds the capacity.
+__global__ void __launch_bounds__(kBinThreads) bin_scatter_kernel(BinArgs a, const uint32_t* __restrict__ M,
+                                                                  const uint2* __restrict__ ranges,
+                                                                  const unsigned long long* __restrict__ P_dev,
+                                                                  unsigned long long cap,
+                                                                  unsigned long long* __restrict__ keys) {
+  extern __shared__ uint32_t h[];
+  __shared__ int next;
+  if (*P_dev > cap) return;
+  const int c = blockIdx.x / a.bpc, b = blockIdx.x % a.bpc;
+  const int base = a.ct.base[c], txc = a.ct.tx[c], Tc = a.ct.count[c], tyc = Tc / txc;
+  const int64_t e0 = (int64_t)c * a.n;
+  const int lane = threadIdx.x & 63, nub = units_of_block(a.n, a.bpc, b);
+  const uint32_t* row = M + (int64_t)a.bpc * base + (int64_t)b * Tc;
+  const int RW = window_rows(txc, tyc);
+  for (int w0 = 0; w0 < tyc; w0 += RW) {
+    const int nrow = min(RW, tyc - w0), t0 = w0 * txc;
+    for (int i = threadIdx.x; i < nrow * txc; i += kBinThreads) h[i] = ranges[base + t0 + i].x + row[t0 + i];
+    if (threadIdx.x == 0) next = 0;
+    __syncthreads();
+    for (int k = claim_unit(&next); k < nub; k = claim_unit(&next)) {
+      const int i = (b + k * a.bpc) * 64 + lane;
+      if (!(i < a.n && a.tiles[e0 + i] != 0u)) continue;
+      const int64_t e = e0 + i;
+      const unsigned long long key = ((unsigned long long)__float_as_uint(a.depth[e]) << 32) | (uint32_t)e;
+      for_each_row(e, a.rect, a.cull, a.mean2d, a.extent, w0, w0 + nrow, lane, [&](int ty, int c0, int c1) {
+        uint32_t* hr = h + (ty - w0) * txc;
+        // four reservations in flight at a time; K1 counted the same tiles,
+        // so every slot lies below P <= cap
+        for (int x = c0; x <= c1; x += 4) {
+          uint32_t sl[4];
+#pragma unroll
+          for (int j = 0; j < 4; j++) sl[j] = x + j <= c1 ? atomicAdd(&hr[x + j], 1u) : 0xffffffffu;
+#pragma unroll
+          for (int j = 0; j < 4; j++)
+            if (sl[j] < cap) keys[sl[j]] = key;
+        }
+      });
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ scan
+
+constexpr int kScanThreads = 1024;
+constexpr int kScanItems = 16;
+constexpr int kMidBucket = 21;  // __clz of lengths >= 1024 is at most 21
+constexpr int kBigBucket = 19;  // __clz of lengths >= 4096 is at most 19
+
+__device__ inline uint32_t block_scan_1024(uint32_t v, uint32_t* wsum, uint32_t* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kScanThreads / 64; k++) {
+    const uint32_t s = wsum[k];
+    if (k < w) pre += s;
+    tot += s;
+  }
+  *total = tot;
+  return pre + x - v;
+}
+
+// K3, one block per camera: the lists' [start, end) (global over the
+// cameras), the render order of the camera's tiles (a counting sort by the
+// bit length of the list length, longest first; within a bucket the order
+// may vary from call to call), the number of lists of at least 4096 and of
+// at least 1024 entries (the front of that order), and from the last
+// camera's block the total P for the device and the host.
+__global__ void __launch_bounds__(kScanThreads) bin_scan_kernel(uint2* __restrict__ ranges,
+                                                                uint32_t* __restrict__ order, CamTiles ct,
+                                                                int n_cams, unsigned long long* __restrict__ sw,
+                                                                void* host) {
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  __shared__ unsigned bcnt[33], bcur[33];
+  const int c = blockIdx.x, t = threadIdx.x;
+  const int base = ct.base[c], Tc = ct.count[c];
+  unsigned long long off = 0;
+  for (int k = 0; k < c; k++) off += sw[SmallLayout::cam_pairs / 8 + k];
+  if (c == n_cams - 1 && t == 0) {
+    const unsigned long long P = off + sw[SmallLayout::cam_pairs / 8 + c];
+    sw[SmallLayout::total / 8] = P;
+    volatile uint32_t* hp = (volatile uint32_t*)host;
+    hp[0] = (uint32_t)P;
+    hp[1] = (uint32_t)(P >> 32);
+  }
+  if (t < 33) bcnt[t] = 0u;
+  __syncthreads();
+  uint32_t carry = (uint32_t)off;
+  for (int p0 = 0; p0 < Tc; p0 += kScanThreads * kScanItems) {
+    const int len = min(Tc - p0, kScanThreads * kScanItems);
+    const int q = (len + kScanThreads - 1) / kScanThreads;
+    const int b0 = p0 + t * q;
+    uint32_t v[kScanItems], sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+      const bool in = i < q && b0 + i < p0 + len;
+      v[i] = in ? ranges[base + b0 + i].y : 0u;
+      if (in) atomicAdd(&bcnt[__clz(v[i])], 1u);
+      sum += v[i];
+    }
+    uint32_t total;
+    uint32_t run = carry + block_scan_1024(sum, wsum, &total);
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+      if (i < q && b0 + i < p0 + len) ranges[base + b0 + i] = make_uint2(run, run + v[i]);
+      run += v[i];
+    }
+    carry += total;
+    __syncthreads();  // wsum is reused by the next piece
+  }
+  if (t == 0) {
+    unsigned acc = 0, big = 0, mid = 0;
+    for (int b = 0; b < 33; b++) {
+      bcur[b] = acc;
+      acc += bcnt[b];
+      if (b <= kBigBucket) big += bcnt[b];
+      if (b <= kMidBucket) mid += bcnt[b];
+    }
+    uint32_t* nb = (uint32_t*)((char*)sw + SmallLayout::nbig);
+    uint32_t* nm = (uint32_t*)((char*)sw + SmallLayout::nmid);
+    nb[c] = big;
+    nm[c] = mid;
+  }
+  __syncthreads();
+  for (int j = t; j < Tc; j += kScanThreads) {
+    const uint2 r = ranges[base + j];  // written before the barrier above
+    const unsigned pos = atomicAdd(&bcur[__clz(r.y - r.x)], 1u);
+    order[base + pos] = (uint32_t)j;
+  }
+}
+
+// ------------------------------------------------------------- list sort
+
+constexpr int kTSItems = 16;      // keys per thread in one LDS chunk
+constexpr uint32_t kTieRun = 32;  // longer runs of equal depth take the full sort
+
+// LDS of one sorting block of NT threads: a chunk of NT * 16 keys.
+template <int NT>
+struct TileSortSmem {
+  static constexpr int W = NT / 64;
+  unsigned long long stage[NT * kTSItems];
+  uint32_t wh[W][256];  // per-wave running digit counts, then wave prefixes
+  uint32_t lstart[256];  // start of digit d's run in the chunk
+  uint32_t dcnt[256];    // digit d's count in the chunk
+  uint32_t dbase[256];   // (lists over one chunk) next output position of digit d
+  uint32_t wsum[4];
+  unsigned long long wor[W];
+  uint32_t flag;
+};
+
+// Chunk position of item r of this thread: wave-major, then item, then lane.
+__device__ inline int ts_pos(int r) {
+  return (int)(threadIdx.x >> 6) * (64 * kTSItems) + r * 64 + (int)(threadIdx.x & 63);
+}
+
+__device__ inline uint32_t ts_digit(const uint32_t (&dg)[kTSItems / 4], int r) {
+  return (dg[r >> 2] >> (8 * (r & 3))) & 255u;
+}
+
+// Per digit: the per-wave counts in S.wh become exclusive prefixes over the
+// waves, S.dcnt the chunk's counts and S.lstart their exclusive prefix
+// (thread t handles digits [t Q, t Q + Q)).
+template <int NT>
+__device__ inline void digit_prefix(TileSortSmem<NT>& S) {
+  constexpr int W = NT / 64, Q = NT >= 256 ? 1 : 256 / NT, NS = 256 / Q;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  uint32_t cnt[Q], tot = 0;
+#pragma unroll
+  for (int q = 0; q < Q; q++) cnt[q] = 0u;
+  if (t < NS) {
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+      const int d = t * Q + q;
+      uint32_t sum = 0;
+#pragma unroll
+      for (int k = 0; k < W; k++) {
+        const uint32_t v = S.wh[k][d];
+        S.wh[k][d] = sum;
+        sum += v;
+      }
+      S.dcnt[d] = sum;
+      cnt[q] = sum;
+      tot += sum;
+    }
+  }
+  uint32_t x = tot;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (t < NS && lane == 63) S.wsum[w] = x;
+  __syncthreads();
+  if (t < NS) {
+    uint32_t run = x - tot;
+    for (int k = 0; k < w; k++) run += S.wsum[k];
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+      S.lstart[t * Q + q] = run;
+      run += cnt[q];
+    }
+  }
+  __syncthreads();
+}
+
+// Stable rank of the chunk's valid items by their digits (item r's digit is
+// byte r & 3 of dg[r >> 2]): within a wave with ballot peer masks and
+// per-wave running digit counts, across waves by the per-digit wave
+// prefixes.  Leaves the start and count of each digit's run in S.lstart /
+// S.dcnt and returns each item's place in the chunk's digit order.  Item
+// rows with no valid item are skipped (the check is uniform per wave).
+template <int NT>
+__device__ inline void chunk_rank(const uint32_t (&dg)[kTSItems / 4], uint32_t vmask, uint32_t (&lp)[kTSItems],
+                                  TileSortSmem<NT>& S) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int d = lane; d < 256; d += 64) S.wh[w][d] = 0u;
+  const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int r = 0; r < kTSItems; r++) {
+    const bool valid = (vmask >> r) & 1u;
+    lp[r] = 0u;
+    unsigned long long peers = __ballot(valid);
+    if (peers == 0ull) continue;
+    const uint32_t d = ts_digit(dg, r);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+      const bool bit = (d >> b) & 1u;
+      const unsigned long long bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const uint32_t before = (uint32_t)__popcll(peers & lt);
+    const uint32_t run = valid ? S.wh[w][d] : 0u;
+    if (valid && before == 0) S.wh[w][d] = run + (uint32_t)__popcll(peers);
+    lp[r] = run + before;  // rank within the wave's items of digit d so far
+  }
+  __syncthreads();
+  digit_prefix<NT>(S);
+#pragma unroll
+  for (int r = 0; r < kTSItems; r++) {
+    if (!((vmask >> r) & 1u)) continue;
+    const uint32_t d = ts_digit(dg, r);
+    lp[r] += S.lstart[d] + S.wh[w][d];
+  }
+}
+
+__device__ inline void ts_digits(const unsigned long long (&kk)[kTSItems], int shift,
+                                 uint32_t (&dg)[kTSItems / 4]) {
+#pragma unroll
+  for (int q = 0; q < kTSItems / 4; q++) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) v |= ((uint32_t)(kk[4 * q + j] >> shift) & 255u) << (8 * j);
+    dg[q] = v;
+  }
+}
+
+// OR over the block.
+template <int NT>
+__device__ inline unsigned long long block_or(unsigned long long x, TileSortSmem<NT>& S) {
+  for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, 64);
+  if ((threadIdx.x & 63) == 0) S.wor[threadIdx.x >> 6] = x;
+  __syncthreads();
+  unsigned long long m = 0;
+#pragma unroll
+  for (int k = 0; k < TileSortSmem<NT>::W; k++) m |= S.wor[k];
+  __syncthreads();
+  return m;
+}
+
+// One LSD pass over the byte at `shift` of the chunk's keys (registers, in
+// chunk positions); leaves them in their new order in kk.
+template <int NT>
+__device__ inline void lds_pass(unsigned long long (&kk)[kTSItems], uint32_t vmask, int shift,
+                                TileSortSmem<NT>& S) {
+  uint32_t dg[kTSItems / 4], lp[kTSItems];
+  ts_digits(kk, shift, dg);
+  chunk_rank<NT>(dg, vmask, lp, S);
+#pragma unroll
+  for (int r = 0; r < kTSItems; r++)
+    if ((vmask >> r) & 1u) S.stage[lp[r]] = kk[r];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kTSItems; r++)
+    if ((vmask >> r) & 1u) kk[r] = S.stage[ts_pos(r)];
+  __syncthreads();
+}
+
+// Sorts one list of L <= NT * 16 keys in LDS and writes its entry ids.  The
+// passes cover only the depth bytes that vary within the list, which orders
+// it by depth; runs of equal depth (rare) are then put in entry-id order by
+// the thread that owns their first key, or, if a run is longer than
+// kTieRun, the list is sorted again over every varying byte.
+template <int NT>
+__device__ inline void sort_list_lds(const unsigned long long* __restrict__ keys, uint32_t L,
+                                     uint32_t* __restrict__ ids, TileSortSmem<NT>& S) {
+  unsigned long long kk[kTSItems];
   uint32_t vmask = 0;
-  unsigned long long sum = 0;
+  const unsigned long long k0 = keys[0];
+  unsigned long long orv = 0;
 #pragma unroll
-  for (int r = 0; r < kRItems; r++) {
-    const int64_t g = base + r * kRWave + lane;
-    const uint32_t tl = g < E ? tiles[g] : 0u;
-    kk[r] = g < E ? __float_as_uint(depth[g]) : 0u;
-    vv[r] = (uint32_t)g;
-    if (rect) pp[r] = tl > 0 ? pack_rect(rect[g]) : 0u;
-    vmask |= (uint32_t)(tl > 0) << r;
-    sum += tl;
+  for (int r = 0; r < kTSItems; r++) {
+    const int p = ts_pos(r);
+    const bool v = (uint32_t)p < L;
+    kk[r] = v ? keys[p] : 0ull;
+    vmask |= (uint32_t)v << r;
+    if (v) orv |= kk[r] ^ k0;
   }
-  if (pairs) *pairs = sum;
-  return vmask;
-}
-
-// First depth pass, histogram: digit counts of the visible entries, and the
-// block's visible-entry and pair totals.  The blocks also set the tile ranges
-// to (~0u, 0), which the last tile pass lowers / raises with atomics.
-__global__ void __launch_bounds__(kRThreadsSort) entry_hist_kernel(
-    const uint32_t* __restrict__ tiles, const float* __restrict__ depth, int64_t E,
-    uint32_t* __restrict__ counts, int64_t nblocks, uint32_t* __restrict__ part_n,
-    unsigned long long* __restrict__ part_p, uint2* __restrict__ ranges, int64_t T) {
-  __shared__ uint32_t h[kRadix];
-  __shared__ unsigned long long wp[kRWaves];
-  __shared__ uint32_t wv[kRWaves];
-  for (int64_t i = (int64_t)blockIdx.x * kRThreadsSort + threadIdx.x; i < T;
-       i += nblocks * kRThreadsSort)
-    ranges[i] = make_uint2(~0u, 0u);
-  uint32_t kk[kRItems], vv[kRItems], pp[kRItems];
-  unsigned long long pairs;
-  const uint32_t vmask = load_entry_chunk(tiles, depth, E, kk, vv, &pairs, nullptr, pp, blockIdx.x);
-  uint32_t nv = (uint32_t)__popc(vmask);
-  for (int o = 32; o > 0; o >>= 1) {
-    pairs += __shfl_xor(pairs, o, 64);
-    nv += __shfl_xor(nv, o, 64);
-  }
-  if ((threadIdx.x & 63) == 0) { wp[threadIdx.x >> 6] = pairs; wv[threadIdx.x >> 6] = nv; }
-  radix_hist_store(kk, vmask, 0, kRadix - 1, h, counts, nblocks);  // synchronises the block
-  if (threadIdx.x == 0) {
-    unsigned long long sp = 0;
-    uint32_t sv = 0;
-    for (int k = 0; k < kRWaves; k++) { sp += wp[k]; sv += wv[k]; }
-    part_n[blockIdx.x] = sv;
-    part_p[blockIdx.x] = sp;
-  }
-}
-
-// First depth pass, scatter: places the visible entries only; with PACKED,
-// the packed rectangle travels with each entry.
-template <bool PACKED>
-__global__ void __launch_bounds__(kRThreadsSort) entry_scatter_kernel(
-    const uint32_t* __restrict__ tiles, const float* __restrict__ depth, const short4* __restrict__ rect,
-    int64_t E, KVSink sink, const uint32_t* __restrict__ offs, const uint32_t* __restrict__ totals,
-    int64_t nblocks) {
-  __shared__ RadixRankSmem S;
-  __shared__ uint32_t sk[kRChunk];
-  uint32_t kk[kRItems], vv[kRItems], pp[kRItems];
-  const int64_t chunk = radix_xcd_chunk(nblocks);
-  const uint32_t vmask =
-      load_entry_chunk(tiles, depth, E, kk, vv, nullptr, PACKED ? rect : nullptr, pp, chunk);
-  radix_scatter_chunk<PACKED>(kk, vv, pp, vmask, 0, kRadixBits, offs, totals, nblocks, chunk, sink, S, sk);
-}
-
-// Output of the last depth pass when the rectangles travel packed: the
-// entry ids, the packed rectangles and the tile counts, in depth order.
-struct EntryFinalSink {
-  uint32_t* ent;
-  uint32_t* rectp;
-  uint32_t* cnt;
-  __device__ uint2* bounds() const { return nullptr; }
-  __device__ void key(uint32_t, uint32_t) const {}
-  __device__ void vals(const uint32_t (&pos)[kRItems], const uint32_t (&v)[kRItems], int t,
-                       uint32_t count) const {
+  const unsigned long long mask = block_or<NT>(orv, S);
+  for (int shift = 32; shift < 64; shift += 8)
+    if ((mask >> shift) & 255ull) lds_pass<NT>(kk, vmask, shift, S);
+  // the depth-sorted keys in LDS (also when no pass ran), then the ties
 #pragma unroll
-    for (int i = 0; i < kRItems; i++)
-      if (t + i * kRThreadsSort < (int)count) ent[pos[i]] = v[i];
-  }
-  __device__ void pays(const uint32_t (&pos)[kRItems], const uint32_t (&p)[kRItems], int t,
-                       uint32_t count) const {
+  for (int r = 0; r < kTSItems; r++)
+    if ((vmask >> r) & 1u) S.stage[ts_pos(r)] = kk[r];
+  if (threadIdx.x == 0) S.flag = 0u;
+  __syncthreads();
+  bool tie = false;
 #pragma unroll
-    for (int i = 0; i < kRItems; i++) {
-      if (t + i * kRThreadsSort >= (int)count) continue;
-      rectp[pos[i]] = p[i];
-      cnt[pos[i]] = (((p[i] >> 16) & 255u) + 1u) * ((p[i] >> 24) + 1u);
+  for (int r = 0; r < kTSItems; r++) {
+    const uint32_t p = (uint32_t)ts_pos(r);
+    if (p + 1 < L && (S.stage[p] >> 32) == (S.stage[p + 1] >> 32)) tie = true;
+  }
+  if (__syncthreads_or(tie)) {
+#pragma unroll
+    for (int r = 0; r < kTSItems; r++) {
+      const uint32_t p = (uint32_t)ts_pos(r);
+      if (p + 1 >= L) continue;
+      const unsigned long long d = S.stage[p] >> 32;
+      if ((S.stage[p + 1] >> 32) != d || (p > 0 && (S.stage[p - 1] >> 32) == d)) continue;
+      uint32_t q = p + 1;  // the run of depth d is [p, q)
+      while (q < L && (S.stage[q] >> 32) == d) q++;
+      if (q - p > kTieRun) {
+        S.flag = 1u;
+        continue;
+      }
+      for (uint32_t i = p + 1; i < q; i++) {  // insertion sort by the whole key (the ids)
+        const unsigned long long x = S.stage[i];
+        uint32_t j = i;
+        while (j > p && S.stage[j - 1] > x) {
+          S.stage[j] = S.stage[j - 1];
+          j--;
+        }
+        S.stage[j] = x;
+      }
+    }
+    __syncthreads();
+    if (S.flag) {  // long runs of equal depth: sort again over every varying byte
+#pragma unroll
+      for (int r = 0; r < kTSItems; r++)
+        if ((vmask >> r) & 1u) kk[r] = S.stage[ts_pos(r)];
+      __syncthreads();
+      for (int shift = 0; shift < 64; shift += 8)
+        if ((mask >> shift) & 255ull) lds_pass<NT>(kk, vmask, shift, S);
+#pragma unroll
+      for (int r = 0; r < kTSItems; r++)
+        if ((vmask >> r) & 1u) S.stage[ts_pos(r)] = kk[r];
+      __syncthreads();
     }
   }
+#pragma unroll
+  for (int r = 0; r < kTSItems; r++) {
+    const int p = ts_pos(r);
+    if ((vmask >> r) & 1u) ids[p] = (uint32_t)S.stage[p];
+  }
+}
+
+// Sorts one list longer than a chunk over every byte that varies within it:
+// per byte, a histogram over all its chunks, then the chunks in order, each
+// ranked in LDS and written to its digit's next positions (stable across
+// chunks), ping-ponging between src and tmp; the last pass writes the entry
+// ids.  The chunk's keys wait in LDS while their digits are ranked.
+template <int NT>
+__device__ inline void sort_list_chunked(unsigned long long* __restrict__ src, unsigned long long* __restrict__ tmp,
+                                         uint32_t L, uint32_t* __restrict__ ids, TileSortSmem<NT>& S) {
+  constexpr uint32_t CH = NT * kTSItems;
+  const int t = threadIdx.x;
+  const unsigned long long k0 = src[0];
+  unsigned long long orv = 0;
+  for (uint32_t c0 = 0; c0 < L; c0 += CH)
+#pragma unroll
+    for (int r = 0; r < kTSItems; r++) {
+      const uint32_t p = c0 + (uint32_t)ts_pos(r);
+      if (p < L) orv |= src[p] ^ k0;
+    }
+  const unsigned long long mask = block_or<NT>(orv, S);
+  int last = -1;
+  for (int shift = 0; shift < 64; shift += 8)
+    if ((mask >> shift) & 255ull) last = shift;
+  if (last < 0) {  // all keys equal (cannot happen for distinct entries)
+    for (uint32_t p = t; p < L; p += NT) ids[p] = (uint32_t)src[p];
+    return;
+  }
+  unsigned long long *a = src, *b = tmp;
+  for (int shift = 0; shift <= last; shift += 8) {
+    if (!((mask >> shift) & 255ull)) continue;
+    if (t < 256) S.dbase[t] = 0u;
+    __syncthreads();
+    for (uint32_t c0 = 0; c0 < L; c0 += CH)
+#pragma unroll
+      for (int r = 0; r < kTSItems; r++) {
+        const uint32_t p = c0 + (uint32_t)ts_pos(r);
+        if (p < L) atomicAdd(&S.dbase[(uint32_t)(a[p] >> shift) & 255u], 1u);
+      }
+    __syncthreads();
+    // exclusive prefix of the histogram (S.wh[0] is free here)
+    if (t < 256) S.wh[0][t] = S.dbase[t];
+    __syncthreads();
+    if (t == 0) {
+      uint32_t run = 0;
+      for (int d = 0; d < 256; d++) {
+        S.dbase[d] = run;
+        run += S.wh[0][d];
+      }
+    }
+    __syncthreads();
+    const bool final_pass = shift == last;
+    for (uint32_t c0 = 0; c0 < L; c0 += CH) {
+      uint32_t vmask = 0, lp[kTSItems], dg[kTSItems / 4] = {};
+#pragma unroll
+      for (int r = 0; r < kTSItems; r++) {
+        const uint32_t p = c0 + (uint32_t)ts_pos(r);
+        const bool v = p < L;
+        const unsigned long long k = v ? a[p] : 0ull;
+        S.stage[ts_pos(r)] = k;
+        dg[r >> 2] |= ((uint32_t)(k >> shift) & 255u) << (8 * (r & 3));
+        vmask |= (uint32_t)v << r;
+      }
+      chunk_rank<NT>(dg, vmask, lp, S);
+#pragma unroll
+      for (int r = 0; r < kTSItems; r++) {
+        if (!((vmask >> r) & 1u)) continue;
+        const uint32_t d = ts_digit(dg, r);
+        const unsigned long long k = S.stage[ts_pos(r)];
+        const uint32_t pos = S.dbase[d] + (lp[r] - S.lstart[d]);
+        if (final_pass) ids[pos] = (uint32_t)k;
+        else b[pos] = k;
+      }
+      __syncthreads();
+      if (t < 256) S.dbase[t] += S.dcnt[t];
+      __syncthreads();
+    }
+    unsigned long long* sw = a;
+    a = b;
+    b = sw;
+  }
+}
+
+// Bucket sort of one list of L <= NT * 16 keys, the common path.  The keys
+// of a list agree on every bit above the highest one that varies within it,
+// so the next db bits from there down, taken as a digit, order the keys
+// (coarsely) as the keys themselves do.  The keys are counted per digit,
+// moved into their digit's bucket in LDS (in any order inside it), and each
+// key's place in the list is its bucket's start plus the number of keys of
+// its bucket below it: a direct comparison of the whole (depth, id) keys, so
+// equal depths need no second step.  db grows with the list (two bits more
+// than L needs, at most log2 NB): depths inside a tile bunch up, so the
+// buckets need to be much finer than L to stay small.  Returns false, before
+// touching ids, when a bucket holds more than kBucketMax keys (the
+// comparisons would cost more than the radix sort); the block then sorts the
+// list with sort_list_lds.
+constexpr uint32_t kBucketMax = 64;
+
+template <int NT, int NB>
+struct BucketSmem {
+  unsigned long long keys[NT * kTSItems];
+  uint32_t cnt[NB + NB / 32];  // at bk(d): keys per digit, then bucket starts, then bucket ends
+  uint32_t wsum[NT / 64];
+  uint32_t wmax[NT / 64];
+  unsigned long long wor[NT / 64];
 };
 
-__global__ void __launch_bounds__(kRThreadsSort) entry_final_kernel(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, const uint32_t* __restrict__ pin,
-    const uint32_t* n_dev, EntryFinalSink sink, int shift, int nbits, const uint32_t* __restrict__ offs,
-    const uint32_t* __restrict__ totals, int64_t nblocks) {
-  __shared__ RadixRankSmem S;
-  __shared__ uint32_t sk[kRChunk];
-  const int64_t n = *n_dev;
-  const int64_t chunk = radix_xcd_chunk((n + kRChunk - 1) / kRChunk);
-  if (chunk < 0) return;
-  uint32_t kk[kRItems], vv[kRItems], pp[kRItems];
-  const uint32_t vmask = radix_load_kv(kin, vin, pin, n, chunk, kk, vv, pp);
-  radix_scatter_chunk<true>(kk, vv, pp, vmask, shift, nbits, offs, totals, nblocks, chunk, sink, S, sk);
+template <int NT, int NB>
+union ListSortSmem {
+  TileSortSmem<NT> radix;
+  BucketSmem<NT, NB> bucket;
+};
+
+// LDS word of digit d's counter: one word of padding after every 32, so
+// that the scan's threads, each reading a run of consecutive digits, fall on
+// different banks.
+__device__ inline uint32_t bk(uint32_t d) { return d + (d >> 5); }
+
+template <int NT, int NB>
+__device__ inline bool sort_list_bucket(const unsigned long long* __restrict__ keys, uint32_t L,
+                                        uint32_t* __restrict__ ids, BucketSmem<NT, NB>& S) {
+  constexpr int W = NT / 64, QMAX = NB / NT;
+  static_assert((NB & (NB - 1)) == 0 && QMAX * NT == NB, "digits per thread");
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int lbits = 32 - __clz(L);  // bit length of L
+  const int db = min(31 - __clz(NB), lbits + 2);
+  const uint32_t nb = 1u << db;
+  const int q = nb > (uint32_t)NT ? (int)(nb / NT) : 1;  // digits per thread in the scan
+  unsigned long long kk[kTSItems];
+  const unsigned long long k0 = keys[0];
+  unsigned long long orv = 0;
+#pragma unroll
+  for (int r = 0; r < kTSItems; r++) {
+    const uint32_t p = (uint32_t)(r * NT + t);
+    kk[r] = p < L ? keys[p] : 0ull;
+    if (p < L) orv |= kk[r] ^ k0;
+  }
+  for (int o = 32; o > 0; o >>= 1) orv |= __shfl_xor(orv, o, 64);
+  if (lane == 0) S.wor[w] = orv;
+  for (uint32_t d = t; d < nb; d += NT) S.cnt[bk(d)] = 0u;
+  __syncthreads();
+  unsigned long long m = 0;
+#pragma unroll
+  for (int k = 0; k < W; k++) m |= S.wor[k];
+  const int hb = m ? 63 - __clzll((long long)m) : 0;
+  const int shift = hb >= db - 1 ? hb - (db - 1) : 0;
+  const unsigned long long dmask = nb - 1;
+#pragma unroll
+  for (int r = 0; r < kTSItems; r++)
+    if ((uint32_t)(r * NT + t) < L) atomicAdd(&S.cnt[bk((uint32_t)((kk[r] >> shift) & dmask))], 1u);
+  __syncthreads();
+  // bucket starts (an exclusive scan of the counts, q consecutive digits per
+  // thread) and the largest bucket
+  const uint32_t d0 = (uint32_t)(t * q);
+  const bool act = d0 < nb;
+  uint32_t c[QMAX], tot = 0, mx = 0;
+#pragma unroll
+  for (int j = 0; j < QMAX; j++) {
+    c[j] = act && j < q ? S.cnt[bk(d0 + j)] : 0u;
+    tot += c[j];
+    mx = max(mx, c[j]);
+  }
+  uint32_t x = tot;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
+  if (lane == 63) S.wsum[w] = x;
+  if (lane == 0) S.wmax[w] = mx;
+  __syncthreads();
+  uint32_t run = x - tot, mall = 0;
+#pragma unroll
+  for (int k = 0; k < W; k++) {
+    if (k < w) run += S.wsum[k];
+    mall = max(mall, S.wmax[k]);
+  }
+  if (mall > kBucketMax) {
+    __syncthreads();  // every thread has read S before the radix sort reuses it
+    return false;
+  }
+  if (act)
+#pragma unroll
+    for (int j = 0; j < QMAX; j++)
+      if (j < q) {
+        S.cnt[bk(d0 + j)] = run;
+        run += c[j];
+      }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kTSItems; r++)
+    if ((uint32_t)(r * NT + t) < L) {
+      const uint32_t at = atomicAdd(&S.cnt[bk((uint32_t)((kk[r] >> shift) & dmask))], 1u);
+      S.keys[at] = kk[r];
+    }
+  __syncthreads();
+  // S.cnt[d] is now the end of bucket d, and so the start of bucket d + 1
+#pragma unroll
+  for (int r = 0; r < kTSItems; r++)
+    if ((uint32_t)(r * NT + t) < L) {
+      const uint32_t d = (uint32_t)((kk[r] >> shift) & dmask);
+      const uint32_t e = S.cnt[bk(d)], b = d ? S.cnt[bk(d - 1)] : 0u;
+      uint32_t rank = b;
+      for (uint32_t j = b; j < e; j++) rank += S.keys[j] < kk[r] ? 1u : 0u;
+      ids[rank] = (uint32_t)kk[r];
+    }
+  return true;
 }
 
-// The depth-sorted entries' tile counts and geometry, gathered once by a
-// kernel with many waves in flight (the reads are random in the entry id):
-// cnt[j] = tiles[e], geo[j] = (first tile id, rectangle width | camera tiles
-// per row << 16) for e = ent[j]; each block also leaves the sum of its
-// 4096 counts for the offsets scan.
-__global__ void __launch_bounds__(kRThreadsSort) entry_gather_kernel(
-    const uint32_t* __restrict__ ent, int64_t m, const uint32_t* __restrict__ tiles,
-    const short4* __restrict__ rect, int n, CamTiles ct, uint32_t* __restrict__ cnt,
-    uint2* __restrict__ geo, uint32_t* __restrict__ sums) {
-  __shared__ uint32_t wsum[kRWaves];
-  const int t = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * kRChunk;
-  uint32_t e[kRItems], tl[kRItems];
-  short4 r[kRItems];
-#pragma unroll
-  for (int j = 0; j < kRItems; j++) {
-    const int64_t g = base + j * kRThreadsSort + t;
-    e[j] = g < m ? ent[g] : 0u;
+// K5 for lists below 1024 entries: one wave per tile.
+__global__ void __launch_bounds__(64) tile_sort_small_kernel(const uint2* __restrict__ ranges,
+                                                            const unsigned long long* __restrict__ keys,
+                                                            uint32_t* __restrict__ ids,
+                                                            const unsigned long long* __restrict__ P_dev,
+                                                            unsigned long long cap) {
+  __shared__ ListSortSmem<64, 2048> S;
+  const unsigned long long P = *P_dev;
+  const uint2 r = ranges[blockIdx.x];  // written by K3 whatever P is
+  if (P > cap) return;
+  const uint32_t L = r.y - r.x;
+  if (L == 0 || L >= 1024u || (unsigned long long)r.y > cap) return;
+  if (L == 1) {
+    if (threadIdx.x == 0) ids[r.x] = (uint32_t)keys[r.x];
+    return;
   }
-#pragma unroll
-  for (int j = 0; j < kRItems; j++) {
-    const int64_t g = base + j * kRThreadsSort + t;
-    tl[j] = g < m ? tiles[e[j]] : 0u;
-    r[j] = g < m ? rect[e[j]] : make_short4(0, 0, 0, 0);
-  }
-  uint32_t acc = 0;
-#pragma unroll
-  for (int j = 0; j < kRItems; j++) {
-    const int64_t g = base + j * kRThreadsSort + t;
-    if (g >= m) continue;
-    const int cam = (int)(e[j] / (uint32_t)n);
-    const uint32_t tx = (uint32_t)ct.tx[cam];
-    cnt[g] = tl[j];
-    geo[g] = make_uint2((uint32_t)ct.base[cam] + (uint32_t)r[j].y * tx + (uint32_t)r[j].x,
-                        (uint32_t)(r[j].z - r[j].x + 1) | (tx << 16));
-    acc += tl[j];
-  }
-  uint32_t total;
-  radix_block_scan(acc, wsum, &total);
-  if (t == 0) sums[blockIdx.x] = total;
+  if (!sort_list_bucket<64, 2048>(keys + r.x, L, ids + r.x, S.bucket)) sort_list_lds<64>(keys + r.x, L, ids + r.x, S.radix);
 }
 
-// Expands each visible entry (in depth order) into one (tile, entry) pair per
-// tile of its rectangle, row-major.  A block takes 256 consecutive entries
-// and spreads their contiguous output range evenly over its threads (each
-// output finds its entry by binary search of the block's offsets in LDS), so
-// the writes are coalesced whatever the rectangle sizes.  The rectangles come
-// packed (PACKED) or as gathered geometry.  Outputs stay below P and tile ids
-// below T whatever the inputs.
-constexpr int kDupThreads = 256;
-template <bool PACKED>
-__global__ void __launch_bounds__(kDupThreads) duplicate_kernel(
-    const uint32_t* __restrict__ ent, const uint32_t* __restrict__ offs, const uint32_t* __restrict__ rectp,
-    const uint2* __restrict__ geo, int n, CamTiles ct, int64_t m, uint64_t P, uint32_t T,
-    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  __shared__ uint32_t so[kDupThreads + 1];
-  __shared__ uint32_t se[kDupThreads];
-  __shared__ uint32_t st0[kDupThreads];  // first tile
-  __shared__ uint32_t sw[kDupThreads];   // rectangle width
-  __shared__ uint32_t stx[kDupThreads];  // camera tiles per row
-  __shared__ float sinv[kDupThreads];    // 1 / width
-  const int t = threadIdx.x;
-  const int64_t j0 = (int64_t)blockIdx.x * kDupThreads;
-  const int cnt = (int)min((int64_t)kDupThreads, m - j0);
-  if (t < cnt) {
-    const uint32_t e = ent[j0 + t];
-    uint32_t t0, w, tx;
-    if (PACKED) {
-      const uint32_t p = rectp[j0 + t];
-      const int cam = (int)(e / (uint32_t)n);
-      tx = (uint32_t)ct.tx[cam];
-      t0 = (uint32_t)ct.base[cam] + ((p >> 8) & 255u) * tx + (p & 255u);
-      w = ((p >> 16) & 255u) + 1u;
+// K5 for longer lists: a fixed grid of blocks takes them from the front of
+// each camera's render order (where the long lists are) -- block b the b-th,
+// (b + grid)-th, ... of the positions [n_from[c], n_to[c]) of every camera's
+// order (n_from null: from 0) -- and sorts each in LDS, or, past NT * 16
+// entries, in chunks.
+template <int NT>
+__global__ void __launch_bounds__(NT) tile_sort_long_kernel(const uint2* __restrict__ ranges,
+                                                           const uint32_t* __restrict__ order, CamTiles ct,
+                                                           int n_cams, const uint32_t* __restrict__ n_from,
+                                                           const uint32_t* __restrict__ n_to,
+                                                           unsigned long long* __restrict__ keys,
+                                                           unsigned long long* __restrict__ tmp,
+                                                           uint32_t* __restrict__ ids,
+                                                           const unsigned long long* __restrict__ P_dev,
+                                                           unsigned long long cap) {
+  __shared__ ListSortSmem<NT, 4096> S;
+  if (*P_dev > cap) return;
+  uint32_t total = 0;
+  for (int c = 0; c < n_cams; c++) total += n_to[c] - (n_from ? n_from[c] : 0u);
+  for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
+    uint32_t j = g;
+    int c = 0;
+    for (;;) {
+      const uint32_t lo = n_from ? n_from[c] : 0u, cnt = n_to[c] - lo;
+      if (j < cnt) {
+        j += lo;
+        break;
+      }
+      j -= cnt;
+      c++;
+    }
+    const uint32_t tile = (uint32_t)ct.base[c] + order[ct.base[c] + j];
+    const uint2 r = ranges[tile];
+    const uint32_t L = r.y - r.x;
+    if ((unsigned long long)r.y > cap) break;  // cannot happen: every list lies within [0, P)
+    if (L <= (uint32_t)NT * kTSItems) {
+      if (!sort_list_bucket<NT, 4096>(keys + r.x, L, ids + r.x, S.bucket))
+        sort_list_lds<NT>(keys + r.x, L, ids + r.x, S.radix);
     } else {
-      const uint2 g = geo[j0 + t];
-      t0 = g.x;
-      w = g.y & 0xffffu;
-      tx = g.y >> 16;
+      sort_list_chunked<NT>(keys + r.x, tmp + r.x, L, ids + r.x, S.radix);
     }
-    so[t] = offs[j0 + t];
-    se[t] = e;
-    st0[t] = t0;
-    sw[t] = w;
-    stx[t] = tx;
-    sinv[t] = 1.0f / (float)w;
-  }
-  if (t == 0) so[cnt] = j0 + cnt < m ? offs[j0 + cnt] : (uint32_t)P;
-  __syncthreads();
-  const uint32_t p1 = min(so[cnt], (uint32_t)P);
-  for (uint32_t p = so[0] + t; p < p1; p += kDupThreads) {
-    int lo = 0, hi = cnt - 1;  // last entry whose output starts at or before p
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (so[mid] <= p) lo = mid; else hi = mid - 1;
-    }
-    const uint32_t k = p - so[lo], w = sw[lo];
-    // k / w through the float reciprocal (k < 2^24), corrected by one step
-    uint32_t y = (uint32_t)((float)k * sinv[lo]);
-    int32_t x = (int32_t)(k - y * w);
-    if (x < 0) { y--; x += (int32_t)w; } else if (x >= (int32_t)w) { y++; x -= (int32_t)w; }
-    keys[p] = min(st0[lo] + y * stx[lo] + (uint32_t)x, T - 1u);
-    vals[p] = se[lo];
+    __syncthreads();  // the LDS is reused by the next list
   }
 }
 
-// Render order of one camera's tiles (one block per camera): a counting sort
-// of the tiles by bucket = bit length of the list length, longest first.
-// Only the schedule depends on it (every tile is rendered independently), so
-// the order within a bucket may vary from call to call.  Tiles that no pair
-// reached still hold (~0u, 0) from the initialisation and are set to [0, 0).
-constexpr int kOrderThreads = 1024;
-__global__ void __launch_bounds__(kOrderThreads) order_kernel(uint2* __restrict__ ranges, CamTiles ct,
-                                                             uint32_t* __restrict__ order) {
-  __shared__ unsigned cnt[33], cur[33];
-  const int c = blockIdx.x, base = ct.base[c], nt = ct.count[c];
-  for (int b = threadIdx.x; b < 33; b += blockDim.x) cnt[b] = 0;
-  __syncthreads();
-  for (int t = threadIdx.x; t < nt; t += blockDim.x) {
-    uint2 r = ranges[base + t];
-    if (r.x > r.y) {
-      r = make_uint2(0u, 0u);
-      ranges[base + t] = r;
-    }
-    const int key = __clz(r.y - r.x);  // 32 - bit length: 0 for the longest lists
-    atomicAdd(&cnt[key], 1u);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned acc = 0;
-    for (int b = 0; b < 33; b++) { cur[b] = acc; acc += cnt[b]; }
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < nt; t += blockDim.x) {
-    const uint2 r = ranges[base + t];  // as this thread left it above
-    const unsigned pos = atomicAdd(&cur[__clz(r.y - r.x)], 1u);
-    order[base + pos] = (uint32_t)t;
-  }
-}
+// ------------------------------------------------------------------ host
 
-// Pinned host slot for the count read-back and the event that marks it, one
-// per host thread.
+// Pinned host slot for the pair-count read-back and the event that marks
+// it, one per host thread.
 struct ReadbackSlot {
   void* p = nullptr;   // host address
   void* dp = nullptr;  // the same memory as the device sees it
@@ -349,9 +967,7 @@ struct ReadbackSlot {
 };
 static thread_local ReadbackSlot g_readback;
 
-static inline unsigned grid_for(int64_t m, int threads) {
-  return (unsigned)((m + threads - 1) / threads);
-}
+static inline unsigned grid_for(int64_t m, int threads) { return (unsigned)((m + threads - 1) / threads); }
 
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t m, uint32_t v) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -365,20 +981,6 @@ gut_status fill_u32(uint32_t* p, int64_t m, uint32_t v, hipStream_t st) {
   return GUT_OK;
 }
 
-// The depth sort's passes: the first writes (dkB, dvB[, pB]) and the others
-// ping-pong from B, so the sorted entry ids end in dvA; with packed
-// rectangles the last pass is entry_final_kernel, which also leaves the
-// packed rectangles in pA and the tile counts in dkA.
-static int depth_passes() { return radix_passes(32); }
-
-// The rectangles travel packed in 32 bits when every camera has at most 256
-// tiles per axis (4096 px); otherwise they are gathered after the sort.
-static bool rects_pack(const DevCam* dc, int n_cams) {
-  for (int c = 0; c < n_cams; c++)
-    if (dc[c].tiles_x > 256 || dc[c].tiles_y > 256) return false;
-  return true;
-}
-
 static CamTiles cam_tiles(const DevCam* dc, int n_cams) {
   CamTiles ct;
   for (int c = 0; c < n_cams; c++) {
@@ -389,132 +991,101 @@ static CamTiles cam_tiles(const DevCam* dc, int n_cams) {
   return ct;
 }
 
-gut_status bin_count(const gut_projected* proj, int n, const DevCam* dc, int n_cams, int64_t T, char* ews,
-                     uint32_t* tile_ranges, uint32_t* nvis_out, uint64_t* P_out, hipStream_t s) {
-  const int64_t E = (int64_t)n * n_cams;
-  EntryLayout L = entry_layout(E);
-  auto E32 = [&](size_t off) { return (uint32_t*)(ews + off); };
-  uint32_t* scal = E32(L.scalars);
-  *nvis_out = 0;
-  *P_out = 0;
-  gut_status st;
-  if (E == 0) return fill_u32(tile_ranges, 2 * T, 0u, s);
+static BinArgs bin_args(const gut_projected* proj, int n, const DevCam* dc, int n_cams, bool cull,
+                        size_t* lds_bytes) {
+  BinArgs a;
+  a.rect = (const short4*)proj->rect;
+  a.tiles = proj->tiles;
+  a.depth = proj->depth;
+  a.mean2d = (const float2*)proj->mean2d;
+  a.extent = (const float4*)proj->extent;
+  a.n = n;
+  a.bpc = (int)blocks_per_cam(n);
+  a.cull = cull ? 1 : 0;
+  a.n_cams = n_cams;
+  a.ct = cam_tiles(dc, n_cams);
+  int w = 0;  // LDS words of the largest window (with the count kernel's spare column)
+  for (int c = 0; c < n_cams; c++) {
+    const int txc = a.ct.tx[c], tyc = a.ct.count[c] / txc;
+    w = std::max(w, window_rows(txc, tyc) * (txc + 1));
+  }
+  *lds_bytes = (size_t)w * 4;
+  return a;
+}
+
+gut_status bin_count_launch(const gut_projected* proj, int n, const DevCam* dc, int n_cams, int64_t T,
+                            bool cull, char* cws, uint32_t* tile_ranges, hipStream_t s) {
   if (!g_readback.p) {
     GUT_HIP(hipHostMalloc(&g_readback.p, 64, hipHostMallocMapped | hipHostMallocCoherent));
     GUT_HIP(hipHostGetDevicePointer(&g_readback.dp, g_readback.p, 0));
   }
   if (!g_readback.ev) GUT_HIP(hipEventCreateWithFlags(&g_readback.ev, hipEventDisableTiming));
-  const int64_t nb = radix_blocks(E);
-  const RadixTemp rt = radix_temp(ews + L.radix_tmp, E);
-  entry_hist_kernel<<<(unsigned)nb, kRThreadsSort, 0, s>>>(
-      proj->tiles, proj->depth, E, rt.counts, nb, E32(L.part_n),
-      (unsigned long long*)(ews + L.part_p), (uint2*)tile_ranges, T);
+  std::memset(g_readback.p, 0xff, 8);  // a sentinel no total can equal
+  size_t lds = 0;
+  const BinArgs a = bin_args(proj, n, dc, n_cams, cull, &lds);
+  uint32_t* M = (uint32_t*)cws;
+  unsigned long long* sw = (unsigned long long*)(cws + al((size_t)((int64_t)a.bpc * T) * 4));
+  bin_init_kernel<<<1, 64, 0, s>>>(sw + SmallLayout::cam_pairs / 8);
   GUT_LAUNCH_CHECK();
-  // the rowscan's extra block totals N_vis and P into scal and the pinned
-  // slot; the slot starts as a sentinel no total can equal
-  std::memset(g_readback.p, 0xff, 16);
-  const RowscanTail tail = {E32(L.part_n), (const unsigned long long*)(ews + L.part_p), nb, scal,
-                            g_readback.dp};
-  if ((st = radix_rowscan(rt.counts, rt.offs, rt.totals, nb, s, &tail)) != GUT_OK) return st;
-  GUT_HIP(hipEventRecord(g_readback.ev, s));
-  const bool packed = rects_pack(dc, n_cams);
-  const KVSink sink0 = {E32(L.dkB), E32(L.dvB), nullptr, E32(L.pB)};
-  if (packed)
-    entry_scatter_kernel<true><<<(unsigned)nb, kRThreadsSort, 0, s>>>(
-        proj->tiles, proj->depth, (const short4*)proj->rect, E, sink0, rt.offs, rt.totals, nb);
-  else
-    entry_scatter_kernel<false><<<(unsigned)nb, kRThreadsSort, 0, s>>>(
-        proj->tiles, proj->depth, nullptr, E, sink0, rt.offs, rt.totals, nb);
-  GUT_LAUNCH_CHECK();
-  // the remaining passes take N_vis from the device
-  const int passes = depth_passes(), per = radix_per_pass(32);
-  int inB = 0;
-  if (!packed) {
-    if ((st = radix_sort_passes(E32(L.dkB), E32(L.dvB), E32(L.dkA), E32(L.dvA), E, scal, 32, 1, passes,
-                                ews + L.radix_tmp, s, &inB, nullptr)) != GUT_OK)
-      return st;
-  } else {
-    if ((st = radix_sort_passes(E32(L.dkB), E32(L.dvB), E32(L.dkA), E32(L.dvA), E, scal, 32, 1,
-                                passes - 1, ews + L.radix_tmp, s, &inB, nullptr, E32(L.pB), E32(L.pA))) !=
-        GUT_OK)
-      return st;
-    if (inB) {  // the middle passes are even in number: the last reads B
-      set_error("binning: depth sort ended in the wrong buffer");
-      return GUT_E_HIP;
-    }
-    const int shift = (passes - 1) * per, nbits = 32 - shift;
-    if ((st = radix_hist(E32(L.dkB), E, scal, shift, (1u << nbits) - 1u, rt.counts, nb, s)) != GUT_OK)
-      return st;
-    if ((st = radix_rowscan(rt.counts, rt.offs, rt.totals, nb, s)) != GUT_OK) return st;
-    const EntryFinalSink fin = {E32(L.dvA), E32(L.pA), E32(L.dkA)};
-    entry_final_kernel<<<(unsigned)nb, kRThreadsSort, 0, s>>>(E32(L.dkB), E32(L.dvB), E32(L.pB), scal, fin,
-                                                              shift, nbits, rt.offs, rt.totals, nb);
+  if (n > 0) {
+    bin_count_kernel<<<(unsigned)(a.bpc * n_cams), kBinThreads, lds, s>>>(a, M);
     GUT_LAUNCH_CHECK();
-    inB = 1;
+    bin_colscan_kernel<<<grid_for(T, kColThreads), kColThreads, 0, s>>>(
+        M, a.ct, n_cams, a.bpc, T, (uint2*)tile_ranges, sw + SmallLayout::cam_pairs / 8);
+    GUT_LAUNCH_CHECK();
+  } else {  // no entries: every count is zero
+    gut_status st = fill_u32(tile_ranges, 2 * T, 0u, s);
+    if (st != GUT_OK) return st;
   }
-  if (!inB) {
-    set_error("binning: depth sort ended in the wrong buffer");
-    return GUT_E_HIP;
-  }
-  // the one wait of the binning: for the totals, while the sort runs on
-  GUT_HIP(hipEventSynchronize(g_readback.ev));
-  uint32_t nvis;
-  unsigned long long P;
-  std::memcpy(&nvis, g_readback.p, 4);
-  std::memcpy(&P, (char*)g_readback.p + 8, 8);
-  if ((int64_t)nvis > E) {
-    set_error("binning: the visible-entry count did not reach the host");
-    return GUT_E_HIP;
-  }
-  *nvis_out = nvis;
-  *P_out = P;
+  bin_scan_kernel<<<n_cams, kScanThreads, 0, s>>>((uint2*)tile_ranges, tile_ranges + 2 * T, a.ct, n_cams, sw,
+                                                  g_readback.dp);
+  GUT_LAUNCH_CHECK();
+  GUT_HIP(hipEventRecord(g_readback.ev, s));
   return GUT_OK;
 }
 
-gut_status bin_sort(const gut_projected* proj, int n, const DevCam* dc, int n_cams, int64_t T,
-                    int64_t E, char* ews, uint32_t nvis, uint64_t P, char* pws,
-                    uint32_t* tile_ranges, uint32_t* sorted_ids, hipStream_t s) {
-  if (nvis == 0 || P == 0) return GUT_OK;
-  EntryLayout L = entry_layout(E);
-  PairLayout Lp = pair_layout((int64_t)P);
-  auto E32 = [&](size_t off) { return (uint32_t*)(ews + off); };
-  auto Q32 = [&](size_t off) { return (uint32_t*)(pws + off); };
-  gut_status st;
-  const CamTiles ct = cam_tiles(dc, n_cams);
-  const bool packed = rects_pack(dc, n_cams);
-  if (packed) {  // the depth sort left the tile counts in dkA
-    if ((st = exclusive_scan_u32(E32(L.dkA), E32(L.offs), nvis, ews + L.offs_tmp, s)) != GUT_OK) return st;
-  } else {
-    // tile counts (into dkA, free after the depth sort) and geometry, with
-    // the scan's block sums, then the rest of the offsets scan
-    entry_gather_kernel<<<(unsigned)radix_blocks(nvis), kRThreadsSort, 0, s>>>(
-        E32(L.dvA), nvis, proj->tiles, (const short4*)proj->rect, n, ct, E32(L.dkA),
-        (uint2*)(ews + L.geo), (uint32_t*)(ews + L.offs_tmp));
-    GUT_LAUNCH_CHECK();
-    if ((st = exclusive_scan_u32(E32(L.dkA), E32(L.offs), nvis, ews + L.offs_tmp, s, true)) != GUT_OK)
-      return st;
+gut_status bin_count_wait(uint64_t* P) {
+  GUT_HIP(hipEventSynchronize(g_readback.ev));
+  uint32_t w[2];
+  std::memcpy(w, g_readback.p, 8);
+  const uint64_t v = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+  if (v == ~0ull) {
+    set_error("binning: the pair count did not reach the host");
+    return GUT_E_HIP;
   }
-  int bits = 1;
-  while ((int64_t(1) << bits) < T) bits++;
-  const int passes = radix_passes(bits);
-  // the duplication lands so that the last pass writes (pkA, sorted_ids)
-  uint32_t *k0 = Q32(Lp.pkA), *v0 = sorted_ids, *k1 = Q32(Lp.pkB), *v1 = Q32(Lp.pvB);
-  if (passes % 2 == 1) { std::swap(k0, k1); std::swap(v0, v1); }
-  if (packed)
-    duplicate_kernel<true><<<grid_for(nvis, kDupThreads), kDupThreads, 0, s>>>(
-        E32(L.dvA), E32(L.offs), E32(L.pA), nullptr, n, ct, nvis, P, (uint32_t)T, k0, v0);
-  else
-    duplicate_kernel<false><<<grid_for(nvis, kDupThreads), kDupThreads, 0, s>>>(
-        E32(L.dvA), E32(L.offs), nullptr, (const uint2*)(ews + L.geo), n, ct, nvis, P, (uint32_t)T, k0, v0);
-  GUT_LAUNCH_CHECK();
-  int inB = 0;
-  return radix_sort_passes(k0, v0, k1, v1, (int64_t)P, nullptr, bits, 0, passes, pws + Lp.radix_tmp, s,
-                           &inB, (uint2*)tile_ranges);
+  *P = v;
+  return GUT_OK;
 }
 
-gut_status bin_order(const DevCam* dc, int n_cams, int64_t T, uint32_t* tile_ranges, hipStream_t s) {
-  const CamTiles ct = cam_tiles(dc, n_cams);
-  order_kernel<<<n_cams, kOrderThreads, 0, s>>>((uint2*)tile_ranges, ct, tile_ranges + 2 * T);
+constexpr int kMidThreads = 256, kMidBlocks = 1024;
+constexpr int kBigThreads = 512, kBigBlocks = 512;
+
+gut_status bin_sort_launch(const gut_projected* proj, int n, const DevCam* dc, int n_cams, int64_t T, bool cull,
+                           char* cws, int64_t cap, char* pws, uint32_t* tile_ranges, uint32_t* sorted_ids,
+                           hipStream_t s) {
+  size_t lds = 0;
+  const BinArgs a = bin_args(proj, n, dc, n_cams, cull, &lds);
+  const uint32_t* M = (const uint32_t*)cws;
+  char* swb = cws + al((size_t)((int64_t)a.bpc * T) * 4);
+  const unsigned long long* P_dev = (const unsigned long long*)(swb + SmallLayout::total);
+  const uint32_t* nbig = (const uint32_t*)(swb + SmallLayout::nbig);
+  const uint32_t* nmid = (const uint32_t*)(swb + SmallLayout::nmid);
+  unsigned long long* keys = (unsigned long long*)pws;
+  unsigned long long* tmp = (unsigned long long*)(pws + al((size_t)(cap > 0 ? cap : 1) * 8));
+  const unsigned long long ucap = (unsigned long long)cap;
+  if (n > 0) {
+    bin_scatter_kernel<<<(unsigned)(a.bpc * n_cams), kBinThreads, lds, s>>>(a, M, (const uint2*)tile_ranges,
+                                                                             P_dev, ucap, keys);
+    GUT_LAUNCH_CHECK();
+  }
+  tile_sort_small_kernel<<<(unsigned)T, 64, 0, s>>>((const uint2*)tile_ranges, keys, sorted_ids, P_dev, ucap);
+  GUT_LAUNCH_CHECK();
+  tile_sort_long_kernel<kMidThreads><<<kMidBlocks, kMidThreads, 0, s>>>(
+      (const uint2*)tile_ranges, tile_ranges + 2 * T, a.ct, n_cams, nbig, nmid, keys, tmp, sorted_ids, P_dev, ucap);
+  GUT_LAUNCH_CHECK();
+  tile_sort_long_kernel<kBigThreads><<<kBigBlocks, kBigThreads, 0, s>>>(
+      (const uint2*)tile_ranges, tile_ranges + 2 * T, a.ct, n_cams, nullptr, nbig, keys, tmp, sorted_ids, P_dev,
+      ucap);
   GUT_LAUNCH_CHECK();
   return GUT_OK;
 }
@@ -523,9 +1094,15 @@ gut_status bin_order(const DevCam* dc, int n_cams, int64_t T, uint32_t* tile_ran
 
 using namespace gut;
 
-extern "C" size_t gut_bin_workspace_bytes(int64_t n, int32_t n_cams, int64_t pair_capacity) {
-  if (n < 0 || n_cams <= 0 || pair_capacity < 0) return 0;
-  return bin_entry_bytes(n * n_cams) + bin_pair_bytes(pair_capacity);
+extern "C" size_t gut_bin_workspace_bytes(int64_t n, const gut_camera* cams, int32_t n_cams,
+                                          int64_t pair_capacity) {
+  if (n < 0 || !cams || n_cams <= 0 || n_cams > kMaxCams || pair_capacity < 0) return 0;
+  int64_t T = 0;
+  for (int c = 0; c < n_cams; c++) {
+    if (cams[c].width <= 0 || cams[c].height <= 0) return 0;
+    T += (int64_t)((cams[c].width + kTile - 1) / kTile) * ((cams[c].height + kTile - 1) / kTile);
+  }
+  return bin_count_bytes(n, T) + bin_pair_bytes(pair_capacity);
 }
 
 extern "C" gut_status gut_bin(const gut_projected* proj, int64_t n, const gut_camera* cams,
@@ -538,8 +1115,14 @@ extern "C" gut_status gut_bin(const gut_projected* proj, int64_t n, const gut_ca
     set_error("projected rect, tiles and depth are required");
     return GUT_E_INVALID;
   }
-  if (((uintptr_t)proj->rect & 7) || ((uintptr_t)tile_ranges & 7)) {
-    set_error("rect and tile_ranges must be 8-byte aligned");
+  const bool cull = p->tile_cull != 0;
+  if (cull && n > 0 && (!proj->mean2d || !proj->extent)) {
+    set_error("tile culling needs the projected mean2d and extent");
+    return GUT_E_INVALID;
+  }
+  if (((uintptr_t)proj->rect & 7) || ((uintptr_t)tile_ranges & 7) || ((uintptr_t)proj->mean2d & 7) ||
+      ((uintptr_t)proj->extent & 15)) {
+    set_error("rect, mean2d and tile_ranges must be 8-byte, extent 16-byte aligned");
     return GUT_E_INVALID;
   }
   if (n < 0 || pair_capacity < 0 || !tile_ranges || (pair_capacity > 0 && !sorted_ids)) {
@@ -555,25 +1138,26 @@ extern "C" gut_status gut_bin(const gut_projected* proj, int64_t n, const gut_ca
   if ((st = prepare_cams(cams, n_cams, *p, dc, &T, nullptr)) != GUT_OK) return st;
   const int64_t E = n * n_cams;
   if (E >= (int64_t(1) << 31)) { set_error("n * n_cams must be below 2^31"); return GUT_E_INVALID; }
-  const size_t eb = bin_entry_bytes(E), need = eb + bin_pair_bytes(pair_capacity);
+  const size_t cb = bin_count_bytes(n, T), need = cb + bin_pair_bytes(pair_capacity);
   if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) {
     set_error("workspace must be 256-byte aligned and hold %zu bytes (got %zu)", need, ws_bytes);
     return GUT_E_INVALID;
   }
   hipStream_t s = (hipStream_t)stream;
-  char* ews = (char*)ws;
-  char* pws = ews + eb;
-  uint32_t nvis = 0;
+  char* cws = (char*)ws;
+  char* pws = cws + cb;
+  if ((st = bin_count_launch(proj, (int)n, dc, n_cams, T, cull, cws, tile_ranges, s)) != GUT_OK) return st;
+  // the sort is queued before the one wait: it checks the capacity on the device
+  if ((st = bin_sort_launch(proj, (int)n, dc, n_cams, T, cull, cws, pair_capacity, pws, tile_ranges, sorted_ids,
+                            s)) != GUT_OK)
+    return st;
   uint64_t P = 0;
-  if ((st = bin_count(proj, (int)n, dc, n_cams, T, ews, tile_ranges, &nvis, &P, s)) != GUT_OK) return st;
+  if ((st = bin_count_wait(&P)) != GUT_OK) return st;
   if (n_pairs) *n_pairs = (int64_t)P;
   if ((int64_t)P > pair_capacity) {
-    (void)bin_order(dc, n_cams, T, tile_ranges, s);  // leaves every tile empty
+    (void)fill_u32(tile_ranges, 2 * T, 0u, s);  // every tile empty
     set_error("pair capacity %lld < required %llu", (long long)pair_capacity, (unsigned long long)P);
     return GUT_E_CAPACITY;
   }
-  if ((st = bin_sort(proj, (int)n, dc, n_cams, T, E, ews, nvis, P, pws, tile_ranges, sorted_ids,
-                     s)) != GUT_OK)
-    return st;
-  return bin_order(dc, n_cams, T, tile_ranges, s);
+  return GUT_OK;
 }

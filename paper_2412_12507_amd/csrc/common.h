@@ -107,41 +107,20 @@ gut_status render_batch_launch(const DevCam* d_cams, const DevCam* h_cams, int n
                                const float* rgb, float* const* d_outs, unsigned* d_counters,
                                int* d_lists, int* h_lists, int n_blocks, hipStream_t s);
 gut_status record_launch(const gut_scene* scene, float* record, hipStream_t s);
-size_t bin_entry_bytes(int64_t E);
+// Binning in two phases.  The count phase (bin_count_bytes(n, T) of
+// workspace for n particles and T tiles over the cameras) queues the
+// per-tile counts, the list starts, the render order and the pair total P,
+// whose read-back bin_count_wait waits for; the sort phase (with
+// bin_pair_bytes(cap) more) queues the pairs' scatter and the per-list
+// sorts, which write nothing when P exceeds cap.
+size_t bin_count_bytes(int64_t n, int64_t T);
 size_t bin_pair_bytes(int64_t cap);
-// Binning, phase 1 (E = n * n_cams entries): initialises the tile ranges,
-// compacts the visible entries and queues their depth sort; returns (N_vis,
-// P) to the host without waiting for the sort.
-gut_status bin_count(const gut_projected* proj, int n, const DevCam* dc, int n_cams, int64_t T, char* ews,
-                     uint32_t* tile_ranges, uint32_t* nvis_out, uint64_t* P_out, hipStream_t s);
-// Phase 2 (P within the pair workspace): duplicate, tile sort, ranges.
-gut_status bin_sort(const gut_projected* proj, int n, const DevCam* dc, int n_cams, int64_t T,
-                    int64_t E, char* ews, uint32_t nvis, uint64_t P, char* pws,
-                    uint32_t* tile_ranges, uint32_t* sorted_ids, hipStream_t s);
-// Render order after the ranges (tile_ranges[2T .. 3T)); also turns the
-// ranges of empty tiles into [0, 0).  Always follows bin_count.
-gut_status bin_order(const DevCam* dc, int n_cams, int64_t T, uint32_t* tile_ranges, hipStream_t s);
-
-// Radix sort / scan building blocks (sort.hip).
-size_t scan_temp_bytes(int64_t n);
-// Exclusive scan of in[0, n) into out.  have_sums: the caller has already
-// written the sums of in's 4096-element blocks at the start of temp.
-gut_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* temp, hipStream_t st,
-                              bool have_sums = false);
-int64_t radix_blocks(int64_t n);
-size_t radix_temp_bytes(int64_t n);
-// Stable LSD sort of (key, value) pairs over key bits [0, bits): passes
-// pass0 .. pass_end-1 of the ceil(bits/8) (bits spread evenly), ping-ponging
-// between (kA, vA) and (kB, vB) starting from A; *result_in_b tells which
-// pair holds the result.  The item count is *n_dev when n_dev is given (at
-// most n_max, which sizes the grids and temp), else n_max.  ranges
-// (nullable): the sort's last pass also writes each key's [start, end), over
-// entries initialised to (~0u, 0), and then leaves the sorted keys unwritten.
-// pA / pB (both or neither): a 32-bit payload carried with each key.
-gut_status radix_sort_passes(uint32_t* kA, uint32_t* vA, uint32_t* kB, uint32_t* vB, int64_t n_max,
-                             const uint32_t* n_dev, int bits, int pass0, int pass_end, void* temp,
-                             hipStream_t st, int* result_in_b, uint2* ranges,
-                             uint32_t* pA = nullptr, uint32_t* pB = nullptr);
+gut_status bin_count_launch(const gut_projected* proj, int n, const DevCam* dc, int n_cams, int64_t T,
+                            bool cull, char* cws, uint32_t* tile_ranges, hipStream_t s);
+gut_status bin_count_wait(uint64_t* P);
+gut_status bin_sort_launch(const gut_projected* proj, int n, const DevCam* dc, int n_cams, int64_t T, bool cull,
+                           char* cws, int64_t cap, char* pws, uint32_t* tile_ranges, uint32_t* sorted_ids,
+                           hipStream_t s);
 
 // ---------------------------------------------------------------- device math
 __host__ __device__ inline float3 f3(float x, float y, float z) { return make_float3(x, y, z); }

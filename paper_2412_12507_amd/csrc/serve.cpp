@@ -24,12 +24,15 @@ namespace gut {
 
 constexpr size_t kStage = 64 * 1024;
 
-// Device memory one batch needs before its pair count is known.
+// Device memory one batch needs before its pair count is known: the
+// projection (rect, tiles, depth, rgb, mean, extent ellipse), the count
+// phase's workspace, ranges and render order, and the launch tables.
 static size_t batch_entry_bytes(int64_t n, int n_cams, int64_t T) {
   const int64_t E = n * (int64_t)n_cams;
-  return al256(E * 8) + al256(E * 4) * 2 + al256(E * 12) + al256(bin_entry_bytes(E)) +
-         al256(T * 12) + al256(n_cams * sizeof(DevCam)) + al256(n_cams * sizeof(float*)) +
-         al256(2 * (2 * kMaxCams + 1) * sizeof(int)) + al256(16 * sizeof(unsigned)) + 4096;
+  return al256(E * 8) + al256(E * 4) * 2 + al256(E * 12) + al256(E * 8) + al256(E * 16) +
+         al256(bin_count_bytes(n, T)) + al256(T * 12) + al256(n_cams * sizeof(DevCam)) +
+         al256(n_cams * sizeof(float*)) + al256(2 * (2 * kMaxCams + 1) * sizeof(int)) +
+         al256(16 * sizeof(unsigned)) + 4096;
 }
 
 static size_t batch_pair_bytes(int64_t P) { return al256(P * 4) + al256(bin_pair_bytes(P)); }
@@ -48,7 +51,6 @@ class HipBackend {
     // state of the batch between count() and finish()
     std::vector<DevCam> dc;
     int64_t T = 0;
-    uint32_t nvis = 0;
   };
   std::vector<Slot> slots;
 
@@ -70,7 +72,7 @@ class HipBackend {
 
   struct EntryMem {
     gut_projected proj;
-    char* ews;
+    char* cws;
     uint32_t* ranges;  // [T,2] ranges, then the render order
     DevCam* d_cams;
     float** d_outs;
@@ -87,8 +89,10 @@ class HipBackend {
     m.proj.tiles = (uint32_t*)take(E * 4);
     m.proj.depth = (float*)take(E * 4);
     m.proj.rgb = (float*)take(E * 12);
+    m.proj.mean2d = (float*)take(E * 8);
+    m.proj.extent = (float*)take(E * 16);
     m.proj.record = (float*)(base + record_off);
-    m.ews = take(bin_entry_bytes(E));
+    m.cws = take(bin_count_bytes(scene.n, T));
     m.ranges = (uint32_t*)take(T * 12);
     m.d_cams = (DevCam*)take(nc * sizeof(DevCam));
     m.d_outs = (float**)take(nc * sizeof(float*));
@@ -115,7 +119,10 @@ class HipBackend {
     if ((st = project_launch(&scene, W.dc.data(), nc, make_ut(params), make_thresholds(params), &m.proj,
                              false, s)) != GUT_OK)
       return st;
-    return bin_count(&m.proj, (int)scene.n, W.dc.data(), nc, W.T, m.ews, m.ranges, &W.nvis, P, s);
+    if ((st = bin_count_launch(&m.proj, (int)scene.n, W.dc.data(), nc, W.T, params.tile_cull != 0, m.cws,
+                               m.ranges, s)) != GUT_OK)
+      return st;
+    return bin_count_wait(P);
   }
 
   gut_status finish(int slot, const std::vector<gut_camera>& cams, const std::vector<float*>&,
@@ -124,15 +131,13 @@ class HipBackend {
     const int nc = (int)cams.size();
     EntryMem m = carve(off_entry, nc, W.T);
     hipStream_t s = W.stream;
-    const int64_t E = scene.n * (int64_t)nc;
     char* pb = base + off_pair;
     uint32_t* ids = (uint32_t*)pb;
     char* pws = pb + al256((P > 0 ? P : 1) * 4);
     int* h_lists = (int*)((char*)W.pinned + 49152);
     gut_status st;
-    if ((st = bin_sort(&m.proj, (int)scene.n, W.dc.data(), nc, W.T, E, m.ews, W.nvis, P, pws, m.ranges, ids,
-                       s)) != GUT_OK ||
-        (st = bin_order(W.dc.data(), nc, W.T, m.ranges, s)) != GUT_OK ||
+    if ((st = bin_sort_launch(&m.proj, (int)scene.n, W.dc.data(), nc, W.T, params.tile_cull != 0, m.cws,
+                              (int64_t)P, pws, m.ranges, ids, s)) != GUT_OK ||
         (st = render_batch_launch(m.d_cams, W.dc.data(), nc, make_thresholds(params), (int)scene.n, m.ranges,
                                   m.ranges + 2 * W.T, ids, m.proj.record, m.proj.rgb, m.d_outs,
                                   m.d_counters, m.d_lists, h_lists, n_blocks, s)) != GUT_OK)
@@ -145,8 +150,7 @@ class HipBackend {
     return GUT_OK;
   }
 
-  // queued work may still use the memory (bin_count returns while the depth
-  // sort runs)
+  // queued work may still use the memory
   void quiesce(int slot) { (void)hipStreamSynchronize(slots[slot].stream); }
 };
 

@@ -63,14 +63,15 @@ class Projection:
     depth: torch.Tensor    # [C*n]   float32
     rgb: torch.Tensor      # [C*n,3] float32
     record: torch.Tensor   # [n,16]  float32
-    mean2d: torch.Tensor | None = None
-    cov2d: torch.Tensor | None = None
+    mean2d: torch.Tensor | None = None  # [C*n,2] UT mean (tile culling reads it)
+    cov2d: torch.Tensor | None = None   # [C*n,3] UT covariance (debug)
+    extent: torch.Tensor | None = None  # [C*n,4] extent ellipse k^2 Sigma' and k (tile culling)
     n: int = 0
     n_cams: int = 1
 
     def struct(self) -> L.Projected:
         p = L.Projected()
-        for k in ("rect", "tiles", "depth", "rgb", "record", "mean2d", "cov2d"):
+        for k in ("rect", "tiles", "depth", "rgb", "record", "mean2d", "cov2d", "extent"):
             t = getattr(self, k)
             setattr(p, k, None if t is None else t.data_ptr())
         return p
@@ -121,7 +122,7 @@ def alloc_projection(n, n_cams, device="cuda", debug=False) -> Projection:
     mk = lambda *s, dt=torch.float32: torch.empty(*s, dtype=dt, device=device)
     return Projection(rect=mk(E, 4, dt=torch.int16), tiles=mk(E, dt=torch.int32), depth=mk(E),
                       rgb=mk(E, 3), record=mk(max(n, 1), 16),
-                      mean2d=mk(E, 2) if debug else None, cov2d=mk(E, 3) if debug else None,
+                      mean2d=mk(E, 2), cov2d=mk(E, 3) if debug else None, extent=mk(E, 4),
                       n=n, n_cams=n_cams)
 
 
@@ -160,7 +161,7 @@ def bin_tiles(proj: Projection, cams, params=None, bins: Bins | None = None,
     for _ in range(3):
         if ids is None or ids.shape[0] < cap:
             ids = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
-        need = lib.gut_bin_workspace_bytes(n, nc, ids.shape[0])
+        need = lib.gut_bin_workspace_bytes(n, arr, nc, ids.shape[0])
         if ws is None or ws.numel() < need:
             ws = torch.empty(max(int(need), 256), dtype=torch.uint8, device=dev)
         npairs = C.c_int64(0)

@@ -34,12 +34,14 @@ def test_default_params_and_helpers():
     assert p.ut_alpha == 1.0 and p.ut_beta == 2.0 and p.ut_kappa == 0.0
     assert p.alpha_min == np.float32(1 / 255) and p.alpha_max == np.float32(0.99)
     assert p.t_min == np.float32(1e-4) and p.tile == 16 and p.rs_iters == 3
-    assert p.kernel_degree == 2
+    assert p.kernel_degree == 2 and p.tile_cull == 1
     cams = G.config2_cameras()
     arr = L.camera_array(cams)
     assert lib.gut_num_tiles(arr, 2, L.ref(p)) == 2 * 120 * 68
     assert lib.gut_num_pixels(arr, 2) == 2 * 1920 * 1080
-    assert lib.gut_bin_workspace_bytes(1000, 1, 5000) > 5000 * 12
+    a1 = L.camera_array([cams[0]])
+    assert lib.gut_bin_workspace_bytes(1000, a1, 1, 5000) >= 4096 + 8160 * 4 + 5000 * 16  # counts + keys
+    assert lib.gut_bin_workspace_bytes(1000, None, 1, 5000) == 0
     assert lib.gut_render_bwd_workspace_bytes(1000, 2) >= 1000 * 80 + 2000 * 24  # FP64 sums
     assert lib.gut_status_string(2) == b"GUT_E_CAPACITY"
 
@@ -114,11 +116,16 @@ def test_bin_and_render_validation_without_launch():
     arr = L.camera_array([cam])
     pj = L.Projected()
     pj.rect = pj.tiles = pj.depth = pj.rgb = pj.record = 4096
+    # tile culling reads the mean and the extent ellipse
+    st = lib.gut_bin(L.ref(pj), 10, arr, 1, L.ref(p), C.c_void_p(4096), 1 << 20, 100, C.c_void_p(4096),
+                     C.c_void_p(4096), None, None)
+    assert st == L.GUT_E_INVALID and b"mean2d and extent" in lib.gut_last_error()
+    pj.mean2d = pj.extent = 4096
     # workspace too small / misaligned
     st = lib.gut_bin(L.ref(pj), 10, arr, 1, L.ref(p), C.c_void_p(4096), 16, 100, C.c_void_p(4096),
                      C.c_void_p(4096), None, None)
     assert st == L.GUT_E_INVALID
-    need = lib.gut_bin_workspace_bytes(10, 1, 100)
+    need = lib.gut_bin_workspace_bytes(10, arr, 1, 100)
     st = lib.gut_bin(L.ref(pj), 10, arr, 1, L.ref(p), C.c_void_p(4097), need, 100, C.c_void_p(4096),
                      C.c_void_p(4096), None, None)
     assert st == L.GUT_E_INVALID
@@ -128,6 +135,16 @@ def test_bin_and_render_validation_without_launch():
                      C.c_void_p(4096), None, None)
     assert st == L.GUT_E_INVALID and b"8-byte" in lib.gut_last_error()
     pj.rect = 4096
+    pj.extent = 4104  # read as 16-byte vectors
+    st = lib.gut_bin(L.ref(pj), 10, arr, 1, L.ref(p), C.c_void_p(4096), need, 100, C.c_void_p(4096),
+                     C.c_void_p(4096), None, None)
+    assert st == L.GUT_E_INVALID and b"16-byte" in lib.gut_last_error()
+    pj.extent = 4096
+    # the tile rule is 0 or 1
+    p2 = L.params_struct(dict(tile_cull=2))
+    st = lib.gut_bin(L.ref(pj), 10, arr, 1, L.ref(p2), C.c_void_p(4096), need, 100, C.c_void_p(4096),
+                     C.c_void_p(4096), None, None)
+    assert st == L.GUT_E_INVALID and b"tile_cull" in lib.gut_last_error()
     st = lib.gut_bin(L.ref(pj), 10, arr, 1, L.ref(p), C.c_void_p(4096), need, 100, C.c_void_p(4100),
                      C.c_void_p(4096), None, None)
     assert st == L.GUT_E_INVALID and b"8-byte" in lib.gut_last_error()

@@ -239,7 +239,7 @@ def test_edge_cases():
     arr, ps = L.camera_array([cam2]), L.params_struct()
     ranges = torch.empty(3 * R.num_tiles([cam2]), dtype=torch.int32, device="cuda")
     ids = torch.empty(1, dtype=torch.int32, device="cuda")
-    need = lib.gut_bin_workspace_bytes(gs.n, 1, 1)
+    need = lib.gut_bin_workspace_bytes(gs.n, arr, 1, 1)
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     npairs = C.c_int64(0)
     pj = proj.struct()
