@@ -49,14 +49,16 @@ constexpr int kBinChunk = kBinThreads * kBinItems;  // entries per block, at mos
 constexpr int kLdsTiles = 16000;  // tiles counted in LDS at once (64 KB); larger cameras go in windows
 
 // Small per-call values after the count matrix: per-camera pair totals, the
-// total P, and per camera the number of lists of at least 4096 and of at
-// least 1024 entries (the front of its render order).
+// total P, per camera the number of lists of at least 4096 and of at least
+// 1024 entries (the front of its render order), and the number of short
+// lists left to the radix sort; then that list of tiles (u32 [T]).
 struct SmallLayout {
   static constexpr size_t cam_pairs = 0;                     // u64 [kMaxCams]
   static constexpr size_t total = cam_pairs + 8 * kMaxCams;  // u64
   static constexpr size_t nbig = total + 256;                // u32 [kMaxCams]
   static constexpr size_t nmid = nbig + 4 * kMaxCams;        // u32 [kMaxCams]
-  static constexpr size_t bytes = nmid + 4 * kMaxCams + 256;
+  static constexpr size_t nfall = nmid + 4 * kMaxCams;       // u32
+  static constexpr size_t bytes = nfall + 256;
 };
 constexpr size_t kSmallBytes = 4096;
 static_assert(SmallLayout::bytes <= kSmallBytes, "small workspace");
@@ -64,8 +66,10 @@ static_assert(SmallLayout::bytes <= kSmallBytes, "small workspace");
 static int64_t blocks_per_cam(int64_t n) { return n > 0 ? (n + kBinChunk - 1) / kBinChunk : 0; }
 
 // Count phase: the (block x tile) matrix (blocks_per_cam x tiles of every
-// camera, u32) and the small values.
-size_t bin_count_bytes(int64_t n, int64_t T) { return al((size_t)(blocks_per_cam(n) * T) * 4) + kSmallBytes; }
+// camera, u32), the small values and the radix sort's list of tiles.
+size_t bin_count_bytes(int64_t n, int64_t T) {
+  return al((size_t)(blocks_per_cam(n) * T) * 4) + kSmallBytes + al((size_t)T * 4);
+}
 // Pair phase: the pairs' keys and a ping-pong copy for lists longer than one
 // LDS chunk.
 size_t bin_pair_bytes(int64_t cap) { return 2 * al((size_t)(cap > 0 ? cap : 1) * 8); }
@@ -297,9 +301,11 @@ __global__ void __launch_bounds__(kColThreads) bin_colscan_kernel(uint32_t* __re
   if (threadIdx.x < n_cams && cs[threadIdx.x]) atomicAdd(&cam_pairs[threadIdx.x], cs[threadIdx.x]);
 }
 
-// Clears the per-camera totals K2 adds into.
-__global__ void bin_init_kernel(unsigned long long* __restrict__ cam_pairs) {
-  if (threadIdx.x < kMaxCams) cam_pairs[threadIdx.x] = 0ull;
+// Clears the per-camera totals K2 adds into and the count of lists left to
+// the radix sort.
+__global__ void bin_init_kernel(unsigned long long* __restrict__ sw) {
+  if (threadIdx.x < kMaxCams) sw[SmallLayout::cam_pairs / 8 + threadIdx.x] = 0ull;
+  if (threadIdx.x == 0) *(uint32_t*)((char*)sw + SmallLayout::nfall) = 0u;
 }
 
 // K4: each pair's key at its place: the tile's list start plus the block's
@@ -761,82 +767,89 @@ __device__ inline void sort_list_chunked(unsigned long long* __restrict__ src, u
   }
 }
 
-// Bucket sort of one list of L <= NT * 16 keys, the common path.  The keys
-// of a list agree on every bit above the highest one that varies within it,
-// so the next db bits from there down, taken as a digit, order the keys
-// (coarsely) as the keys themselves do.  The keys are counted per digit,
-// moved into their digit's bucket in LDS (in any order inside it), and each
-// key's place in the list is its bucket's start plus the number of keys of
-// its bucket below it: a direct comparison of the whole (depth, id) keys, so
-// equal depths need no second step.  db grows with the list (two bits more
-// than L needs, at most log2 NB): depths inside a tile bunch up, so the
-// buckets need to be much finer than L to stay small.  Returns false, before
-// touching ids, when a bucket holds more than kBucketMax keys (the
-// comparisons would cost more than the radix sort); the block then sorts the
-// list with sort_list_lds.
+// Bucket sort of one list, the common path.  The keys of a list agree on
+// every bit above the highest one that varies within it, so the next db
+// bits from there down, taken as a digit, order the keys (coarsely) as the
+// keys themselves do.  The keys are counted per digit, moved into their
+// digit's bucket in LDS (in any order inside it), and each key's place in
+// the list is its bucket's start plus the number of keys of its bucket below
+// it: a direct comparison of the whole (depth, id) keys, so equal depths
+// need no second step.  db grows with the list: depths inside a tile bunch
+// up, so the buckets need to be much finer than L to stay small.  When a
+// bucket holds more than kBucketMax keys (the comparisons would cost more
+// than a radix sort) the sort gives up before touching ids, and the list
+// goes to the radix sort.
 constexpr uint32_t kBucketMax = 64;
 
-template <int NT, int NB>
-struct BucketSmem {
-  unsigned long long keys[NT * kTSItems];
-  uint32_t cnt[NB + NB / 32];  // at bk(d): keys per digit, then bucket starts, then bucket ends
+// A block of NT threads sorts one list of L <= NT ROWS keys with the bucket
+// sort above: item r of thread t is list position NT r + t, the rows are
+// unrolled and the rank counts run without branches, so that their LDS reads
+// overlap.  nb = 2^db buckets, db two bits above the bit length of L, at most
+// BF NT ROWS; thread t owns the q = nb / NT consecutive digits from t q on (in
+// the scan), kept at word j NT + t for its j-th digit so that the scan's
+// reads do not collide in the banks.
+template <int NT, int ROWS, int BF = 2>
+struct BlockSortSmem {
+  unsigned long long keys[NT * ROWS];
+  uint32_t cnt[BF * NT * ROWS];
   uint32_t wsum[NT / 64];
   uint32_t wmax[NT / 64];
   unsigned long long wor[NT / 64];
 };
 
-template <int NT, int NB>
-union ListSortSmem {
-  TileSortSmem<NT> radix;
-  BucketSmem<NT, NB> bucket;
-};
-
-// LDS word of digit d's counter: one word of padding after every 32, so
-// that the scan's threads, each reading a run of consecutive digits, fall on
-// different banks.
-__device__ inline uint32_t bk(uint32_t d) { return d + (d >> 5); }
-
-template <int NT, int NB>
-__device__ inline bool sort_list_bucket(const unsigned long long* __restrict__ keys, uint32_t L,
-                                        uint32_t* __restrict__ ids, BucketSmem<NT, NB>& S) {
-  constexpr int W = NT / 64, QMAX = NB / NT;
-  static_assert((NB & (NB - 1)) == 0 && QMAX * NT == NB, "digits per thread");
+template <int NT, int ROWS, int BF>
+__device__ inline bool block_bucket_sort(const unsigned long long* __restrict__ keys, uint32_t L,
+                                         uint32_t* __restrict__ ids, BlockSortSmem<NT, ROWS, BF>& S) {
+  constexpr int W = NT / 64, QM = BF * ROWS;  // waves; most digits per thread
+  constexpr int LNT = NT == 64 ? 6 : NT == 128 ? 7 : NT == 256 ? 8 : 9;
+  constexpr int DBM = LNT + (BF == 2 ? 1 : 0) + (ROWS == 1 ? 0 : ROWS == 2 ? 1 : ROWS == 4 ? 2 : ROWS == 8 ? 3 : 4);
+  static_assert((1 << LNT) == NT && (1 << DBM) == BF * NT * ROWS, "bucket count");
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int lbits = 32 - __clz(L);  // bit length of L
-  const int db = min(31 - __clz(NB), lbits + 2);
+  unsigned long long kk[ROWS];
+  bool ok[ROWS];
+#pragma unroll
+  for (int r = 0; r < ROWS; r++) {
+    const uint32_t p = (uint32_t)(r * NT + t);
+    ok[r] = p < L;
+    kk[r] = ok[r] ? keys[p] : 0ull;
+  }
+  const int db = min(DBM, 34 - __clz(L));  // bit length of L, plus two
   const uint32_t nb = 1u << db;
-  const int q = nb > (uint32_t)NT ? (int)(nb / NT) : 1;  // digits per thread in the scan
-  unsigned long long kk[kTSItems];
+  const int lq = db > LNT ? db - LNT : 0;
+  const uint32_t q = 1u << lq;  // digits per thread
+  const bool own = (uint32_t)t < nb;  // thread owns digits (all once nb >= NT)
+  // the bits that vary within the list (any of its keys is a reference)
   const unsigned long long k0 = keys[0];
   unsigned long long orv = 0;
 #pragma unroll
-  for (int r = 0; r < kTSItems; r++) {
-    const uint32_t p = (uint32_t)(r * NT + t);
-    kk[r] = p < L ? keys[p] : 0ull;
-    if (p < L) orv |= kk[r] ^ k0;
-  }
+  for (int r = 0; r < ROWS; r++) orv |= ok[r] ? kk[r] ^ k0 : 0ull;
   for (int o = 32; o > 0; o >>= 1) orv |= __shfl_xor(orv, o, 64);
-  if (lane == 0) S.wor[w] = orv;
-  for (uint32_t d = t; d < nb; d += NT) S.cnt[bk(d)] = 0u;
-  __syncthreads();
-  unsigned long long m = 0;
+  if (W > 1 && lane == 0) S.wor[w] = orv;
 #pragma unroll
-  for (int k = 0; k < W; k++) m |= S.wor[k];
-  const int hb = m ? 63 - __clzll((long long)m) : 0;
+  for (int j = 0; j < QM; j++)
+    if ((uint32_t)j < q && own) S.cnt[j * NT + t] = 0u;
+  __syncthreads();
+  if (W > 1) {
+    orv = 0;
+#pragma unroll
+    for (int k = 0; k < W; k++) orv |= S.wor[k];
+  }
+  const int hb = orv ? 63 - __clzll((long long)orv) : 0;
   const int shift = hb >= db - 1 ? hb - (db - 1) : 0;
-  const unsigned long long dmask = nb - 1;
+  uint32_t sl[ROWS];
 #pragma unroll
-  for (int r = 0; r < kTSItems; r++)
-    if ((uint32_t)(r * NT + t) < L) atomicAdd(&S.cnt[bk((uint32_t)((kk[r] >> shift) & dmask))], 1u);
+  for (int r = 0; r < ROWS; r++) {
+    const uint32_t d = (uint32_t)(kk[r] >> shift) & (nb - 1);
+    sl[r] = ((d & (q - 1)) << LNT) | (d >> lq);
+  }
+#pragma unroll
+  for (int r = 0; r < ROWS; r++)
+    if (ok[r]) atomicAdd(&S.cnt[sl[r]], 1u);
   __syncthreads();
-  // bucket starts (an exclusive scan of the counts, q consecutive digits per
-  // thread) and the largest bucket
-  const uint32_t d0 = (uint32_t)(t * q);
-  const bool act = d0 < nb;
-  uint32_t c[QMAX], tot = 0, mx = 0;
+  uint32_t c[QM], tot = 0, mx = 0;
 #pragma unroll
-  for (int j = 0; j < QMAX; j++) {
-    c[j] = act && j < q ? S.cnt[bk(d0 + j)] : 0u;
+  for (int j = 0; j < QM; j++) {
+    c[j] = (uint32_t)j < q && own ? S.cnt[j * NT + t] : 0u;
     tot += c[j];
     mx = max(mx, c[j]);
   }
@@ -847,107 +860,166 @@ __device__ inline bool sort_list_bucket(const unsigned long long* __restrict__ k
     if (lane >= o) x += y;
   }
   for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
-  if (lane == 63) S.wsum[w] = x;
-  if (lane == 0) S.wmax[w] = mx;
-  __syncthreads();
-  uint32_t run = x - tot, mall = 0;
+  uint32_t run = x - tot;
+  if (W > 1) {
+    if (lane == 63) S.wsum[w] = x;
+    if (lane == 0) S.wmax[w] = mx;
+    __syncthreads();
 #pragma unroll
-  for (int k = 0; k < W; k++) {
-    if (k < w) run += S.wsum[k];
-    mall = max(mall, S.wmax[k]);
+    for (int k = 0; k < W; k++) {
+      if (k < w) run += S.wsum[k];
+      mx = max(mx, S.wmax[k]);
+    }
   }
-  if (mall > kBucketMax) {
-    __syncthreads();  // every thread has read S before the radix sort reuses it
+  if (mx > kBucketMax) {
+    __syncthreads();  // every thread has read S before it is reused
     return false;
   }
-  if (act)
 #pragma unroll
-    for (int j = 0; j < QMAX; j++)
-      if (j < q) {
-        S.cnt[bk(d0 + j)] = run;
-        run += c[j];
-      }
+  for (int j = 0; j < QM; j++) {
+    if ((uint32_t)j < q && own) S.cnt[j * NT + t] = run;
+    run += c[j];
+  }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kTSItems; r++)
-    if ((uint32_t)(r * NT + t) < L) {
-      const uint32_t at = atomicAdd(&S.cnt[bk((uint32_t)((kk[r] >> shift) & dmask))], 1u);
-      S.keys[at] = kk[r];
-    }
+  for (int r = 0; r < ROWS; r++)
+    if (ok[r]) S.keys[atomicAdd(&S.cnt[sl[r]], 1u)] = kk[r];
   __syncthreads();
-  // S.cnt[d] is now the end of bucket d, and so the start of bucket d + 1
+  // S.cnt now holds each bucket's end, which is the next bucket's start
+  uint32_t base[ROWS], len[ROWS], most = 0;
 #pragma unroll
-  for (int r = 0; r < kTSItems; r++)
-    if ((uint32_t)(r * NT + t) < L) {
-      const uint32_t d = (uint32_t)((kk[r] >> shift) & dmask);
-      const uint32_t e = S.cnt[bk(d)], b = d ? S.cnt[bk(d - 1)] : 0u;
-      uint32_t rank = b;
-      for (uint32_t j = b; j < e; j++) rank += S.keys[j] < kk[r] ? 1u : 0u;
-      ids[rank] = (uint32_t)kk[r];
+  for (int r = 0; r < ROWS; r++) {
+    const uint32_t d = (uint32_t)(kk[r] >> shift) & (nb - 1), dp = d ? d - 1 : 0u;
+    const uint32_t e = S.cnt[sl[r]], s0 = S.cnt[((dp & (q - 1)) << LNT) | (dp >> lq)];
+    base[r] = d ? s0 : 0u;
+    len[r] = ok[r] ? e - base[r] : 0u;
+    most = max(most, len[r]);
+  }
+  for (int o = 32; o > 0; o >>= 1) most = max(most, (uint32_t)__shfl_xor(most, o, 64));
+  uint32_t rank[ROWS];
+#pragma unroll
+  for (int r = 0; r < ROWS; r++) rank[r] = base[r];
+  for (uint32_t j = 0; j < most; j++)
+#pragma unroll
+    for (int r = 0; r < ROWS; r++) {
+      const unsigned long long v = S.keys[min(base[r] + j, L - 1)];
+      rank[r] += (j < len[r]) & (v < kk[r]) ? 1u : 0u;
     }
+#pragma unroll
+  for (int r = 0; r < ROWS; r++)
+    if (ok[r]) ids[rank[r]] = (uint32_t)kk[r];
   return true;
 }
 
-// K5 for lists below 1024 entries: one wave per tile.
+// K5 for lists of 1 to 1023 entries, one wave per tile, in two launches by
+// length (the LDS a wave holds, and so how many waves fit a CU, follows the
+// longest list of the launch): ROWS_MAX 4 takes lists below 256 entries,
+// ROWS_MAX 16 the others.  A list whose largest bucket is too large goes on
+// the list for tile_sort_fallback_kernel.
+template <int ROWS_MAX>
 __global__ void __launch_bounds__(64) tile_sort_small_kernel(const uint2* __restrict__ ranges,
                                                             const unsigned long long* __restrict__ keys,
                                                             uint32_t* __restrict__ ids,
                                                             const unsigned long long* __restrict__ P_dev,
-                                                            unsigned long long cap) {
-  __shared__ ListSortSmem<64, 2048> S;
+                                                            unsigned long long cap, uint32_t* __restrict__ nfall,
+                                                            uint32_t* __restrict__ fall) {
+  constexpr uint32_t lo = ROWS_MAX == 4 ? 1u : 256u, hi = 64u * ROWS_MAX;
+  __shared__ BlockSortSmem<64, ROWS_MAX> S;
   const unsigned long long P = *P_dev;
   const uint2 r = ranges[blockIdx.x];  // written by K3 whatever P is
-  if (P > cap) return;
+  if (P > cap) return;                 // the keys were not written
   const uint32_t L = r.y - r.x;
-  if (L == 0 || L >= 1024u || (unsigned long long)r.y > cap) return;
+  if (L < lo || L >= hi || (unsigned long long)r.y > cap) return;
+  bool done;
   if (L == 1) {
     if (threadIdx.x == 0) ids[r.x] = (uint32_t)keys[r.x];
-    return;
+    done = true;
+  } else if (L <= 64u) {
+    done = block_bucket_sort<64, 1>(keys + r.x, L, ids + r.x, *(BlockSortSmem<64, 1>*)&S);
+  } else if (L <= 128u) {
+    done = block_bucket_sort<64, 2>(keys + r.x, L, ids + r.x, *(BlockSortSmem<64, 2>*)&S);
+  } else if (ROWS_MAX == 4 || L <= 256u) {
+    done = block_bucket_sort<64, 4>(keys + r.x, L, ids + r.x, *(BlockSortSmem<64, 4>*)&S);
+  } else if (L <= 512u) {
+    done = block_bucket_sort<64, 8>(keys + r.x, L, ids + r.x, *(BlockSortSmem<64, 8>*)&S);
+  } else {
+    done = block_bucket_sort<64, ROWS_MAX>(keys + r.x, L, ids + r.x, S);
   }
-  if (!sort_list_bucket<64, 2048>(keys + r.x, L, ids + r.x, S.bucket)) sort_list_lds<64>(keys + r.x, L, ids + r.x, S.radix);
+  if (!done && threadIdx.x == 0) fall[atomicAdd(nfall, 1u)] = blockIdx.x;
 }
 
-// K5 for longer lists: a fixed grid of blocks takes them from the front of
-// each camera's render order (where the long lists are) -- block b the b-th,
-// (b + grid)-th, ... of the positions [n_from[c], n_to[c]) of every camera's
-// order (n_from null: from 0) -- and sorts each in LDS, or, past NT * 16
-// entries, in chunks.
-template <int NT>
-__global__ void __launch_bounds__(NT) tile_sort_long_kernel(const uint2* __restrict__ ranges,
-                                                           const uint32_t* __restrict__ order, CamTiles ct,
-                                                           int n_cams, const uint32_t* __restrict__ n_from,
-                                                           const uint32_t* __restrict__ n_to,
-                                                           unsigned long long* __restrict__ keys,
-                                                           unsigned long long* __restrict__ tmp,
-                                                           uint32_t* __restrict__ ids,
-                                                           const unsigned long long* __restrict__ P_dev,
-                                                           unsigned long long cap) {
-  __shared__ ListSortSmem<NT, 4096> S;
-  if (*P_dev > cap) return;
+// The lists whose buckets came out too large, by the stable LSD radix sort.
+constexpr int kFallThreads = 256, kFallBlocks = 64;
+__global__ void __launch_bounds__(kFallThreads) tile_sort_fallback_kernel(const uint2* __restrict__ ranges,
+                                                                         const unsigned long long* __restrict__ keys,
+                                                                         uint32_t* __restrict__ ids,
+                                                                         const uint32_t* __restrict__ nfall,
+                                                                         const uint32_t* __restrict__ fall) {
+  __shared__ TileSortSmem<kFallThreads> S;
+  const uint32_t m = *nfall;
+  for (uint32_t i = blockIdx.x; i < m; i += gridDim.x) {
+    const uint2 r = ranges[fall[i]];
+    sort_list_lds<kFallThreads>(keys + r.x, r.y - r.x, ids + r.x, S);
+    __syncthreads();  // the LDS is reused by the next list
+  }
+}
+
+// The t-th tile of the positions [n_from[c], n_to[c]) of the cameras' render
+// orders (n_from null: from 0), counted across the cameras in turn.
+__device__ inline uint32_t order_tile(uint32_t g, const uint32_t* __restrict__ order, const CamTiles& ct,
+                                      const uint32_t* __restrict__ n_from, const uint32_t* __restrict__ n_to) {
+  int c = 0;
+  for (;;) {
+    const uint32_t lo = n_from ? n_from[c] : 0u, cnt = n_to[c] - lo;
+    if (g < cnt) return (uint32_t)ct.base[c] + order[ct.base[c] + lo + g];
+    g -= cnt;
+    c++;
+  }
+}
+
+__device__ inline uint32_t order_count(int n_cams, const uint32_t* __restrict__ n_from,
+                                       const uint32_t* __restrict__ n_to) {
   uint32_t total = 0;
   for (int c = 0; c < n_cams; c++) total += n_to[c] - (n_from ? n_from[c] : 0u);
+  return total;
+}
+
+// K5 for lists of 1024 to 4095 entries (the positions [nbig, nmid) of each
+// camera's render order): a fixed grid of 256-thread blocks, block b taking
+// the b-th, (b + grid)-th, ... of them, by the bucket sort; a list whose
+// largest bucket is too large goes on the list for tile_sort_fallback_kernel.
+constexpr int kMidThreads = 256, kMidBlocks = 1024;
+__global__ void __launch_bounds__(kMidThreads) tile_sort_mid_kernel(
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ order, CamTiles ct, int n_cams,
+    const uint32_t* __restrict__ nbig, const uint32_t* __restrict__ nmid, const unsigned long long* __restrict__ keys,
+    uint32_t* __restrict__ ids, const unsigned long long* __restrict__ P_dev, unsigned long long cap,
+    uint32_t* __restrict__ nfall, uint32_t* __restrict__ fall) {
+  __shared__ BlockSortSmem<kMidThreads, kTSItems, 1> S;
+  if (*P_dev > cap) return;
+  const uint32_t total = order_count(n_cams, nbig, nmid);
   for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
-    uint32_t j = g;
-    int c = 0;
-    for (;;) {
-      const uint32_t lo = n_from ? n_from[c] : 0u, cnt = n_to[c] - lo;
-      if (j < cnt) {
-        j += lo;
-        break;
-      }
-      j -= cnt;
-      c++;
-    }
-    const uint32_t tile = (uint32_t)ct.base[c] + order[ct.base[c] + j];
+    const uint32_t tile = order_tile(g, order, ct, nbig, nmid);
     const uint2 r = ranges[tile];
-    const uint32_t L = r.y - r.x;
-    if ((unsigned long long)r.y > cap) break;  // cannot happen: every list lies within [0, P)
-    if (L <= (uint32_t)NT * kTSItems) {
-      if (!sort_list_bucket<NT, 4096>(keys + r.x, L, ids + r.x, S.bucket))
-        sort_list_lds<NT>(keys + r.x, L, ids + r.x, S.radix);
-    } else {
-      sort_list_chunked<NT>(keys + r.x, tmp + r.x, L, ids + r.x, S.radix);
+    if (!block_bucket_sort<kMidThreads, kTSItems, 1>(keys + r.x, r.y - r.x, ids + r.x, S)) {
+      if (threadIdx.x == 0) fall[atomicAdd(nfall, 1u)] = tile;
     }
+    __syncthreads();  // the LDS is reused by the next list
+  }
+}
+
+// K5 for lists of 4096 entries and more (the positions [0, nbig)): a fixed
+// grid of 512-thread blocks, by the radix sort in chunks.
+constexpr int kBigThreads = 512, kBigBlocks = 512;
+__global__ void __launch_bounds__(kBigThreads) tile_sort_big_kernel(
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ order, CamTiles ct, int n_cams,
+    const uint32_t* __restrict__ nbig, unsigned long long* __restrict__ keys, unsigned long long* __restrict__ tmp,
+    uint32_t* __restrict__ ids, const unsigned long long* __restrict__ P_dev, unsigned long long cap) {
+  __shared__ TileSortSmem<kBigThreads> S;
+  if (*P_dev > cap) return;
+  const uint32_t total = order_count(n_cams, nullptr, nbig);
+  for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
+    const uint2 r = ranges[order_tile(g, order, ct, nullptr, nbig)];
+    sort_list_chunked<kBigThreads>(keys + r.x, tmp + r.x, r.y - r.x, ids + r.x, S);
     __syncthreads();  // the LDS is reused by the next list
   }
 }
@@ -1025,7 +1097,7 @@ gut_status bin_count_launch(const gut_projected* proj, int n, const DevCam* dc, 
   const BinArgs a = bin_args(proj, n, dc, n_cams, cull, &lds);
   uint32_t* M = (uint32_t*)cws;
   unsigned long long* sw = (unsigned long long*)(cws + al((size_t)((int64_t)a.bpc * T) * 4));
-  bin_init_kernel<<<1, 64, 0, s>>>(sw + SmallLayout::cam_pairs / 8);
+  bin_init_kernel<<<1, 64, 0, s>>>(sw);
   GUT_LAUNCH_CHECK();
   if (n > 0) {
     bin_count_kernel<<<(unsigned)(a.bpc * n_cams), kBinThreads, lds, s>>>(a, M);
@@ -1057,9 +1129,6 @@ gut_status bin_count_wait(uint64_t* P) {
   return GUT_OK;
 }
 
-constexpr int kMidThreads = 256, kMidBlocks = 1024;
-constexpr int kBigThreads = 512, kBigBlocks = 512;
-
 gut_status bin_sort_launch(const gut_projected* proj, int n, const DevCam* dc, int n_cams, int64_t T, bool cull,
                            char* cws, int64_t cap, char* pws, uint32_t* tile_ranges, uint32_t* sorted_ids,
                            hipStream_t s) {
@@ -1078,14 +1147,23 @@ gut_status bin_sort_launch(const gut_projected* proj, int n, const DevCam* dc, i
                                                                              P_dev, ucap, keys);
     GUT_LAUNCH_CHECK();
   }
-  tile_sort_small_kernel<<<(unsigned)T, 64, 0, s>>>((const uint2*)tile_ranges, keys, sorted_ids, P_dev, ucap);
+  uint32_t* nfall = (uint32_t*)(swb + SmallLayout::nfall);
+  uint32_t* fall = (uint32_t*)(swb + kSmallBytes);
+  tile_sort_small_kernel<4><<<(unsigned)T, 64, 0, s>>>((const uint2*)tile_ranges, keys, sorted_ids, P_dev, ucap, nfall,
+                                                       fall);
   GUT_LAUNCH_CHECK();
-  tile_sort_long_kernel<kMidThreads><<<kMidBlocks, kMidThreads, 0, s>>>(
-      (const uint2*)tile_ranges, tile_ranges + 2 * T, a.ct, n_cams, nbig, nmid, keys, tmp, sorted_ids, P_dev, ucap);
+  tile_sort_small_kernel<16><<<(unsigned)T, 64, 0, s>>>((const uint2*)tile_ranges, keys, sorted_ids, P_dev, ucap,
+                                                        nfall, fall);
   GUT_LAUNCH_CHECK();
-  tile_sort_long_kernel<kBigThreads><<<kBigBlocks, kBigThreads, 0, s>>>(
-      (const uint2*)tile_ranges, tile_ranges + 2 * T, a.ct, n_cams, nullptr, nbig, keys, tmp, sorted_ids, P_dev,
-      ucap);
+  tile_sort_mid_kernel<<<kMidBlocks, kMidThreads, 0, s>>>((const uint2*)tile_ranges, tile_ranges + 2 * T, a.ct,
+                                                          n_cams, nbig, nmid, keys, sorted_ids, P_dev, ucap, nfall,
+                                                          fall);
+  GUT_LAUNCH_CHECK();
+  tile_sort_fallback_kernel<<<kFallBlocks, kFallThreads, 0, s>>>((const uint2*)tile_ranges, keys, sorted_ids, nfall,
+                                                                 fall);
+  GUT_LAUNCH_CHECK();
+  tile_sort_big_kernel<<<kBigBlocks, kBigThreads, 0, s>>>((const uint2*)tile_ranges, tile_ranges + 2 * T, a.ct,
+                                                          n_cams, nbig, keys, tmp, sorted_ids, P_dev, ucap);
   GUT_LAUNCH_CHECK();
   return GUT_OK;
 }
