@@ -112,6 +112,59 @@ def test_full_size_sampled(which):
     assert rep["n_fail"] == 0
 
 
+def test_full_size_timed_launch():
+    """The benchmark's exact step: the 1M-particle scene, both 1920x1080 views
+    in one gut_render call, Gaussian response, no n_eval (the
+    render_multi_kernel<false, false, false, false> instance the benchmark
+    times).  Every particle's projection in both views, every tile list, and
+    sampled tiles of both views (the longest lists plus random ones) against
+    the oracle; n_eval comes from a second call with n_eval on, whose colour,
+    T and n_contrib must equal the timed call's bit for bit.  The share of
+    checked pixels that match only one of the oracle's single-decision
+    alternatives is reported and bounded."""
+    say("[full size, timed launch] 1M particles, pinhole + fisheye 1920x1080 in one call")
+    scene = G.config2_scene()
+    cams = G.config2_cameras()
+    p = O.default_params()
+    gs = to_torch_scene(scene)
+    proj = R.project(gs, cams, p, debug=True)
+    bins = R.bin_tiles(proj, cams, p)
+    img = R.render(proj, bins, cams, p, with_eval=False)
+    img_e = R.render(proj, bins, cams, p, with_eval=True)
+    torch.cuda.synchronize()
+    assert img.n_eval is None
+    for key in ("rgb", "T", "n_contrib"):
+        assert torch.equal(getattr(img, key), getattr(img_e, key)), key
+    n = scene.n
+    tile_base = 0
+    checked = alt = 0
+    for ci, cam in enumerate(cams):
+        pr = O.project(scene, cam, p)
+        rep = compare_projection(proj, pr, ci, n)
+        say(f"  view {ci} projection", rep)
+        assert rep["cull_mismatch_unexplained"] == 0 and rep["rect_mismatch_unexplained"] == 0
+        assert rep["tiles_mismatch_unexplained"] == 0
+        assert rep["depth_rel_err"] <= 4e-6 and rep["rgb_abs_err"] <= 1e-5
+        assert rep["mean_abs_err_px"] <= 2e-3 and rep["cov_rel_err"] <= 1e-2
+        ob = O.bin_tiles(pr, cam, p)
+        tx, ty = O.tiles_xy(cam, p)
+        bad = compare_bins(bins, ob, pr, ci, n, tile_base, tx * ty)
+        say(f"  view {ci} bins: bad tiles", bad[:5])
+        assert not bad
+        lens = np.diff(ob[0])
+        rng = np.random.default_rng(11 + ci)
+        tiles = np.unique(np.concatenate([np.argsort(lens)[-6:], rng.choice(tx * ty, 18, replace=False)]))
+        res = O.render(scene, pr, cam, ob, p, tiles=tiles.astype(np.int32))
+        rep = compare_pixels(image_np(img_e, ci), res, cam, p)
+        say(f"  view {ci} pixels", {k: v for k, v in rep.items() if k != "fails"}, rep["fails"][:3])
+        assert rep["n_fail"] == 0
+        checked += rep["n_checked"]
+        alt += rep["n_alt_used"]
+        tile_base += tx * ty
+    say(f"  alternatives used on {alt} of {checked} checked pixels ({100.0 * alt / checked:.3f}%)")
+    assert alt <= 0.01 * checked
+
+
 @pytest.mark.parametrize("which", ["c2-pinhole", "c2-fisheye", "c3-rolling"])
 def test_full_size_backward_sampled(which):
     """Backward parity on the full workloads in the benchmark's launch
