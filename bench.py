@@ -39,6 +39,7 @@ Also reported on the same line:
 from __future__ import annotations
 
 import argparse
+import collections
 import gc
 import json
 import os
@@ -254,13 +255,34 @@ def bench_fwd_bwd(scene, cam, steps, warmup, R, G, torch, params=None):
                 ms_max=float(np.max(walls)), gpu_ms_median=per[len(per) // 2])
 
 
-def bench_serving(n_requests, rates, R, G, torch, n_particles=3_000_000, warm=8):
+def _replay_sequential(gs, reqs, arr, render_sequential):
+    """Serve the trace one request at a time, at its arrival times: a request
+    starts when it has arrived and the previous one has finished, its cameras
+    are rendered one after another, synchronously.  Returns per-request
+    latencies (s) and the time the last one finished."""
+    lat = np.empty(len(reqs))
+    t0 = time.perf_counter()
+    for i, (a, cams) in enumerate(zip(arr, reqs)):
+        d = t0 + a - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        render_sequential(gs, cams)
+        lat[i] = time.perf_counter() - t0 - a
+    return lat, time.perf_counter() - t0
+
+
+def bench_serving(n_requests, rates, R, G, torch, n_particles=3_000_000, warm=8, check_every=0,
+                  check_load=0.9, check_tiles=4, save_checks=None):
     """Serving workload: the 3M-Gaussian scene resident in HBM, Poisson
     arrivals of requests with 1-8 cameras (half pinhole 640x480..3840x2160,
-    half 1600x1200 rolling-shutter fisheye).  The baseline renders the same
-    trace one request at a time, cameras one after another, synchronously;
-    its latencies at a given arrival rate follow from its measured service
-    times by the FIFO recursion start = max(arrival, previous finish)."""
+    half 1600x1200 rolling-shutter fisheye).  Capacity is the inverse of the
+    sequential baseline's mean service time over the whole trace.  At each
+    load the trace is served twice at the same arrival times: by the
+    continuous-batching server, and by the sequential baseline replayed on
+    the GPU (one request at a time, cameras one after another).  With
+    check_every > 0, every check_every-th camera served at check_load keeps
+    check_tiles random tiles of its image (with the camera) for an offline
+    comparison with the oracle (tests/serve_oracle_check.py)."""
     from paper_2412_12507_amd.serve import Server, render_sequential
     scene = G.config3_scene(n_particles)
     gs = R.GaussianScene.from_host(scene)
@@ -276,7 +298,11 @@ def bench_serving(n_requests, rates, R, G, torch, n_particles=3_000_000, warm=8)
     service = np.array(service)
     cap = 1.0 / service.mean()
     n_cams = np.array([len(c) for c in reqs])
-    out = dict(capacity_req_per_s=cap, mean_cameras_per_request=float(n_cams.mean()), rates=[])
+    log(f"[bench] serving: {len(reqs)} requests, sequential capacity {cap:.1f} req/s")
+    out = dict(capacity_req_per_s=cap, mean_cameras_per_request=float(n_cams.mean()),
+               requests_per_rate=len(reqs), warmup_requests=warm, rates=[])
+    checks = []
+    rng = np.random.default_rng(3006)
     srv = Server(gs, mem_budget_bytes=48 << 30, max_slots=4, max_batch_cams=8)
     try:
         for cams in warm_reqs:
@@ -285,35 +311,62 @@ def bench_serving(n_requests, rates, R, G, torch, n_particles=3_000_000, warm=8)
         for f in rates:
             lam = f * cap
             arr = G.poisson_arrivals(len(reqs), lam, seed=3005 + int(100 * f))
-            # sequential server at these arrivals
-            fin, lat = 0.0, []
-            for a, sv in zip(arr, service):
-                start = max(a, fin)
-                fin = start + sv
-                lat.append(fin - a)
-            lat = np.array(lat) * 1e3
-            seq = dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                       frames_per_s=float(n_cams.sum() / fin))
+            keep = check_every > 0 and abs(f - check_load) < 1e-9
             srv.reset_stats()
+            pending, picks, lat_s = collections.deque(), {}, []
+
+            def finish(block):
+                # collect finished requests in order (their images are freed)
+                while pending and (block or srv.poll(pending[0])):
+                    rid = pending.popleft()
+                    outs = srv.wait(rid)
+                    for j, cam in picks.pop(rid, []):
+                        tx, ty = -(-int(cam["width"]) // 16), -(-int(cam["height"]) // 16)
+                        tiles = np.sort(rng.choice(tx * ty, check_tiles, replace=False))
+                        px = [outs[j][(int(t) // tx) * 16:(int(t) // tx) * 16 + 16,
+                                      (int(t) % tx) * 16:(int(t) % tx) * 16 + 16].cpu().numpy() for t in tiles]
+                        checks.append(dict(cam=cam, tiles=tiles, pixels=px))
+                    lat_s.append(srv.latency_ms(rid))
+
             t0 = time.perf_counter()
-            ids = []
+            cam_no = 0
             for a, cams in zip(arr, reqs):
-                d = t0 + a - time.perf_counter()
-                if d > 0:
-                    time.sleep(d)
-                ids.append(srv.submit(cams)[0])
-            for rid in ids:
-                srv.wait(rid)
+                while True:
+                    finish(False)
+                    d = t0 + a - time.perf_counter()
+                    if d <= 0:
+                        break
+                    time.sleep(min(d, 1e-3))
+                rid, _ = srv.submit(cams)
+                pending.append(rid)
+                if keep:
+                    sel = [(j, cam) for j, cam in enumerate(cams) if (cam_no + j) % check_every == 0]
+                    if sel:
+                        picks[rid] = sel
+                cam_no += len(cams)
+            finish(True)
             st = srv.stats()
+            lat_s = np.array(lat_s)
+            log(f"[bench] serving load {f}: server p50 {np.percentile(lat_s, 50):.1f} "
+                f"p99 {np.percentile(lat_s, 99):.1f} ms, {st['frames_per_s']:.0f} fps")
+            lat_q, span = _replay_sequential(gs, reqs, arr, render_sequential)
+            lat_q *= 1e3
+            seq = dict(p50_ms=float(np.percentile(lat_q, 50)), p99_ms=float(np.percentile(lat_q, 99)),
+                       frames_per_s=float(n_cams.sum() / span))
+            log(f"[bench] serving load {f}: sequential replay p50 {seq['p50_ms']:.1f} "
+                f"p99 {seq['p99_ms']:.1f} ms")
             out["rates"].append(dict(load=f, arrival_req_per_s=lam,
-                                     server=dict(p50_ms=st["p50_ms"], p99_ms=st["p99_ms"],
-                                                 frames_per_s=st["frames_per_s"],
-                                                 batches=st["batches"]),
+                                     server=dict(p50_ms=float(np.percentile(lat_s, 50)),
+                                                 p99_ms=float(np.percentile(lat_s, 99)),
+                                                 frames_per_s=st["frames_per_s"], batches=st["batches"]),
                                      sequential=seq))
-            log(f"[bench] serving load {f}: server p50 {st['p50_ms']:.1f} p99 {st['p99_ms']:.1f} ms, "
-                f"{st['frames_per_s']:.0f} fps; sequential p50 {seq['p50_ms']:.1f} p99 {seq['p99_ms']:.1f}")
     finally:
         srv.close()
+    if save_checks and checks:
+        import pickle
+        with open(save_checks, "wb") as fh:
+            pickle.dump(dict(n_particles=n_particles, load=check_load, every=check_every, checks=checks), fh)
+        out["oracle_check"] = dict(cameras=len(checks), tiles_per_camera=check_tiles, file=save_checks)
     return out
 
 
@@ -410,8 +463,12 @@ def main():
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the 3M-particle rolling-shutter fisheye stage timings")
     ap.add_argument("--serve-requests", type=int, default=120)
-    ap.add_argument("--serve-loads", default="0.5,0.9,1.5,3.0",
+    ap.add_argument("--serve-loads", default="0.25,0.5,0.75,0.9,1.1",
                     help="arrival rates as fractions of the sequential baseline's capacity")
+    ap.add_argument("--serve-protocol", metavar="OUT_JSON", default=None,
+                    help="run only the serving protocol (2000 requests per load after 100 warm-up, "
+                         "1 in 50 cameras at load 0.9 kept for the oracle check), write its "
+                         "results to OUT_JSON and exit")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.traffic_json, args.pmc_command)
@@ -427,6 +484,13 @@ def main():
     from paper_2412_12507_amd import raster as R, _lib
     _lib.load()
     torch.cuda.set_device(0)
+    if args.serve_protocol:
+        res = bench_serving(2000, [float(x) for x in args.serve_loads.split(",")], R, G, torch, warm=100,
+                            check_every=50, save_checks=os.path.splitext(args.serve_protocol)[0] + "_checks.pkl")
+        with open(args.serve_protocol, "w") as fh:
+            json.dump(res, fh, indent=1)
+        print(json.dumps(res), flush=True)
+        return
     if args.calib_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

@@ -67,6 +67,28 @@ def test_serve_mix_equals_alone():
     assert np.abs(img - rgb_o)[~amb].max() <= 1e-4
 
 
+def test_serve_full_size_mix_equals_alone():
+    """The serving workload's own sizes: the 3M-particle scene and requests of
+    the serving trace (pinhole 640x480 .. 3840x2160, rolling-shutter fisheye
+    1600x1200, up to 8 cameras each), served together in merged batches; each
+    image equals the request rendered alone, bit for bit."""
+    say("[serve mix vs alone, full size]")
+    scene = G.config3_scene()
+    gs = R.GaussianScene.from_host(scene)
+    reqs = G.config5_requests(5, seed=3007)
+    say("  cameras", [[(c["model"], c["width"], c["height"]) for c in cams] for cams in reqs])
+    with Server(gs, mem_budget_bytes=48 << 30, max_slots=4, max_batch_cams=8) as srv:
+        ids = [srv.submit(cams)[0] for cams in reqs]
+        outs = {rid: srv.wait(rid) for rid in ids}
+        st = srv.stats()
+        say("  stats", st)
+        assert st["completed"] == len(reqs)
+        for rid, cams in zip(ids, reqs):
+            alone = render_sequential(gs, cams)
+            for a, b in zip(outs[rid], alone):
+                assert torch.equal(a, b)
+
+
 def test_serve_admission_and_growth():
     say("[serve admission]")
     scene = G.clustered_scene(30000, seed=1003)
