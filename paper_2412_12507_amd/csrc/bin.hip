@@ -903,7 +903,7 @@ __device__ inline bool block_bucket_sort(const unsigned long long* __restrict__ 
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
       const unsigned long long v = S.keys[min(base[r] + j, L - 1)];
-      rank[r] += (j < len[r]) & (v < kk[r]) ? 1u : 0u;
+      rank[r] += ((j < len[r]) && (v < kk[r])) ? 1u : 0u;
     }
 #pragma unroll
   for (int r = 0; r < ROWS; r++)

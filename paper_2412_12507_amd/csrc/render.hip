@@ -15,7 +15,10 @@
 // pixels have stopped, and the block stops when no pixel is still going.
 // Blocks take tiles in the render order from gut_bin (longest lists first)
 // and waves of long lists raise their issue priority, so the longest tiles
-// neither start last nor crawl behind short ones.
+// neither start last nor crawl behind short ones.  The walk is bound by
+// latency more than by issue, so the kernels ask for five waves per SIMD
+// (96 VGPRs): the FP64 pair setup then keeps a few values in scratch, which
+// costs less than the fifth wave gains.
 #include "tile_eval.h"
 
 namespace gut {
@@ -162,7 +165,7 @@ __device__ __forceinline__ void render_tile(
 // One block per tile, taken in the render order (longest lists first).  NE:
 // also count each pixel's evaluated entries (out_ne non-null).
 template <bool RS, bool NE, bool GEN, bool CLIP>
-__global__ void __launch_bounds__(kRThreads, 4) render_kernel(
+__global__ void __launch_bounds__(kRThreads, 5) render_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
     const float4* __restrict__ record, const float* __restrict__ rgb, const float* __restrict__ clip,
@@ -191,7 +194,7 @@ struct MultiCams {
 };
 
 template <bool RS, bool NE, bool GEN, bool CLIP>
-__global__ void __launch_bounds__(kRThreads, 4) render_multi_kernel(
+__global__ void __launch_bounds__(kRThreads, 5) render_multi_kernel(
     MultiCams mc, Thresholds th, int n, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
     const float4* __restrict__ record, const float* __restrict__ rgb, const float* __restrict__ clip,
@@ -315,6 +318,12 @@ gut_status render_batch_launch(const DevCam* d_cams, const DevCam* h_cams, int n
 // nearest first.  Colours are read by entry id when a hit is blended.
 constexpr int kKBuf = 16;
 constexpr int kKThreads = 256;
+// Four waves per SIMD (128 VGPRs, some of the buffer in scratch): the walk
+// waits on LDS and on the colour fetches of evicted hits, and a fourth wave
+// hides more of that than the spills cost.  (Keeping the hits' payloads in an
+// LDS table instead, so that only 32-bit keys move, cuts the VALU work of an
+// insertion by two thirds but takes so much LDS that two waves per SIMD fit,
+// and is slower.)
 
 __device__ __forceinline__ void kbuf_blend(float a, uint32_t e, const float* __restrict__ rgb,
                                            float t_min, float& T, double (&C)[3], uint32_t& nc,
@@ -331,7 +340,7 @@ __device__ __forceinline__ void kbuf_blend(float a, uint32_t e, const float* __r
 }
 
 template <bool RS, bool NE, bool GEN, bool CLIP>
-__global__ void __launch_bounds__(kKThreads, 2) render_kbuffer_kernel(
+__global__ void __launch_bounds__(kKThreads, 4) render_kbuffer_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, int kcap, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
     const float4* __restrict__ record, const float* __restrict__ rgb, const float* __restrict__ clip,

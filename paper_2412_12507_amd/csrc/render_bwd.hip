@@ -262,8 +262,11 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
 // dL/dalpha there.  The geometric factors a blend needs -- the closest-point
 // vector p and rho = alpha_raw / sigma -- are formed when the hit enters the
 // buffer (its pair is then in LDS) and travel with it; rho carries the sign
-// of the alpha_max clamp.  Blended hits of one wave belong to different
-// particles, so each lane adds its 13 values with its own FP64 atomics.
+// of the alpha_max clamp.  Each step's blended values go to FP64 atomics,
+// summed across the wave per particle first (kbuf_add_wave).  The buffer alone takes 128 registers a lane; the kernel asks for two waves per
+// SIMD all the same (part of it then lives in scratch), since the replay
+// waits on memory far more than it computes and one wave per SIMD leaves the
+// SIMD idle (this halves the kernel's time).
 constexpr int kKBufB = 16;
 constexpr int kKThreadsB = 256;
 
@@ -338,7 +341,7 @@ __device__ __forceinline__ void kbuf_add_wave(bool valid, uint32_t e, const floa
 }
 
 template <bool RS, bool GEN, bool CLIP>
-__global__ void __launch_bounds__(kKThreadsB, 1) render_kbuffer_bwd_kernel(
+__global__ void __launch_bounds__(kKThreadsB, 2) render_kbuffer_bwd_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, int kcap, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
     const float4* __restrict__ record, const float* __restrict__ rgb, const float* __restrict__ clip,
