@@ -20,10 +20,11 @@
 //                           bits << 32 | entry id) at its offsets in the lists
 //   K5 tile_sort_*_kernel   per list, in LDS: a bucket sort on the highest
 //                           bits that vary within it with a direct rank
-//                           count inside each bucket, or, if a bucket is
-//                           large, a stable LSD radix sort; one wave per
-//                           list below 1024 entries, 256 threads up to 4095,
-//                           512 (radix, in chunks) beyond
+//                           count inside each bucket; one wave per list
+//                           below 1024 entries, 256 threads up to 4095, 1024
+//                           threads beyond (cutting lists over 16384 into
+//                           runs first); lists with a large bucket take a
+//                           stable LSD radix sort instead
 // Nothing needs a device-wide atomic per pair or per touched tile: blocks on
 // different XCDs meet only in the count matrix, whose columns K2 scans.
 // The (depth bits, id) key orders exactly as a full (tile, depth, id) sort
@@ -613,7 +614,7 @@ __device__ inline void lds_pass(unsigned long long (&kk)[kTSItems], uint32_t vma
 // the thread that owns their first key, or, if a run is longer than
 // kTieRun, the list is sorted again over every varying byte.
 template <int NT>
-__device__ inline void sort_list_lds(const unsigned long long* __restrict__ keys, uint32_t L,
+__device__ __forceinline__ void sort_list_lds(const unsigned long long* __restrict__ keys, uint32_t L,
                                      uint32_t* __restrict__ ids, TileSortSmem<NT>& S) {
   unsigned long long kk[kTSItems];
   uint32_t vmask = 0;
@@ -692,7 +693,7 @@ __device__ inline void sort_list_lds(const unsigned long long* __restrict__ keys
 // chunks), ping-ponging between src and tmp; the last pass writes the entry
 // ids.  The chunk's keys wait in LDS while their digits are ranked.
 template <int NT>
-__device__ inline void sort_list_chunked(unsigned long long* __restrict__ src, unsigned long long* __restrict__ tmp,
+__device__ __forceinline__ void sort_list_chunked(unsigned long long* __restrict__ src, unsigned long long* __restrict__ tmp,
                                          uint32_t L, uint32_t* __restrict__ ids, TileSortSmem<NT>& S) {
   constexpr uint32_t CH = NT * kTSItems;
   const int t = threadIdx.x;
@@ -785,25 +786,45 @@ constexpr uint32_t kBucketMax = 64;
 // sort above: item r of thread t is list position NT r + t, the rows are
 // unrolled and the rank counts run without branches, so that their LDS reads
 // overlap.  nb = 2^db buckets, db two bits above the bit length of L, at most
-// BF NT ROWS; thread t owns the q = nb / NT consecutive digits from t q on (in
-// the scan), kept at word j NT + t for its j-th digit so that the scan's
-// reads do not collide in the banks.
-template <int NT, int ROWS, int BF = 2>
+// DBM; thread t owns the q = nb / NT consecutive digits from t q on (in the
+// scan), kept at counter j NT + t for its j-th digit so that the scan's
+// reads do not collide in the banks.  P16: the counters are 16-bit halves of
+// 32-bit words (every count and position is at most L <= 65535), counted and
+// claimed with word atomics that add 1 to one half, which halves their LDS.
+template <int NT, int ROWS, int DBM, bool P16 = false>
 struct BlockSortSmem {
   unsigned long long keys[NT * ROWS];
-  uint32_t cnt[BF * NT * ROWS];
+  uint32_t cnt[P16 ? (1 << DBM) / 2 : (1 << DBM)];
   uint32_t wsum[NT / 64];
   uint32_t wmax[NT / 64];
   unsigned long long wor[NT / 64];
 };
 
-template <int NT, int ROWS, int BF>
-__device__ inline bool block_bucket_sort(const unsigned long long* __restrict__ keys, uint32_t L,
-                                         uint32_t* __restrict__ ids, BlockSortSmem<NT, ROWS, BF>& S) {
-  constexpr int W = NT / 64, QM = BF * ROWS;  // waves; most digits per thread
-  constexpr int LNT = NT == 64 ? 6 : NT == 128 ? 7 : NT == 256 ? 8 : 9;
-  constexpr int DBM = LNT + (BF == 2 ? 1 : 0) + (ROWS == 1 ? 0 : ROWS == 2 ? 1 : ROWS == 4 ? 2 : ROWS == 8 ? 3 : 4);
-  static_assert((1 << LNT) == NT && (1 << DBM) == BF * NT * ROWS, "bucket count");
+template <bool P16>
+__device__ inline uint32_t ctr_get(const uint32_t* c, uint32_t i) {
+  return P16 ? (uint32_t)reinterpret_cast<const unsigned short*>(c)[i] : c[i];
+}
+template <bool P16>
+__device__ inline void ctr_set(uint32_t* c, uint32_t i, uint32_t v) {
+  if (P16) reinterpret_cast<unsigned short*>(c)[i] = (unsigned short)v;
+  else c[i] = v;
+}
+// Adds 1 to counter i and returns its old value.
+template <bool P16>
+__device__ inline uint32_t ctr_inc(uint32_t* c, uint32_t i) {
+  if (!P16) return atomicAdd(&c[i], 1u);
+  const uint32_t sh = 16u * (i & 1u);
+  return (atomicAdd(&c[i >> 1], 1u << sh) >> sh) & 0xffffu;
+}
+
+template <int NT, int ROWS, int DBM, bool P16>
+__device__ __forceinline__ bool block_bucket_sort(const unsigned long long* __restrict__ keys, uint32_t L,
+                                         uint32_t* __restrict__ ids, BlockSortSmem<NT, ROWS, DBM, P16>& S,
+                                         uint32_t bucket_max = kBucketMax) {
+  constexpr int W = NT / 64;
+  constexpr int LNT = NT == 64 ? 6 : NT == 128 ? 7 : NT == 256 ? 8 : NT == 512 ? 9 : 10;
+  constexpr int QM = (1 << DBM) / NT > 0 ? (1 << DBM) / NT : 1;  // most digits per thread
+  static_assert((1 << LNT) == NT, "threads");
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   unsigned long long kk[ROWS];
   bool ok[ROWS];
@@ -825,9 +846,7 @@ __device__ inline bool block_bucket_sort(const unsigned long long* __restrict__ 
   for (int r = 0; r < ROWS; r++) orv |= ok[r] ? kk[r] ^ k0 : 0ull;
   for (int o = 32; o > 0; o >>= 1) orv |= __shfl_xor(orv, o, 64);
   if (W > 1 && lane == 0) S.wor[w] = orv;
-#pragma unroll
-  for (int j = 0; j < QM; j++)
-    if ((uint32_t)j < q && own) S.cnt[j * NT + t] = 0u;
+  for (uint32_t i = t; i < (P16 ? (nb + 1) / 2 : nb); i += NT) S.cnt[i] = 0u;
   __syncthreads();
   if (W > 1) {
     orv = 0;
@@ -844,12 +863,12 @@ __device__ inline bool block_bucket_sort(const unsigned long long* __restrict__ 
   }
 #pragma unroll
   for (int r = 0; r < ROWS; r++)
-    if (ok[r]) atomicAdd(&S.cnt[sl[r]], 1u);
+    if (ok[r]) (void)ctr_inc<P16>(S.cnt, sl[r]);
   __syncthreads();
   uint32_t c[QM], tot = 0, mx = 0;
 #pragma unroll
   for (int j = 0; j < QM; j++) {
-    c[j] = (uint32_t)j < q && own ? S.cnt[j * NT + t] : 0u;
+    c[j] = (uint32_t)j < q && own ? ctr_get<P16>(S.cnt, j * NT + t) : 0u;
     tot += c[j];
     mx = max(mx, c[j]);
   }
@@ -871,40 +890,58 @@ __device__ inline bool block_bucket_sort(const unsigned long long* __restrict__ 
       mx = max(mx, S.wmax[k]);
     }
   }
-  if (mx > kBucketMax) {
+  if (mx > bucket_max) {
     __syncthreads();  // every thread has read S before it is reused
     return false;
   }
 #pragma unroll
   for (int j = 0; j < QM; j++) {
-    if ((uint32_t)j < q && own) S.cnt[j * NT + t] = run;
+    if ((uint32_t)j < q && own) ctr_set<P16>(S.cnt, j * NT + t, run);
     run += c[j];
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < ROWS; r++)
-    if (ok[r]) S.keys[atomicAdd(&S.cnt[sl[r]], 1u)] = kk[r];
+    if (ok[r]) S.keys[ctr_inc<P16>(S.cnt, sl[r])] = kk[r];
   __syncthreads();
-  // S.cnt now holds each bucket's end, which is the next bucket's start
+  // the counters now hold each bucket's end, which is the next bucket's start
   uint32_t base[ROWS], len[ROWS], most = 0;
 #pragma unroll
   for (int r = 0; r < ROWS; r++) {
     const uint32_t d = (uint32_t)(kk[r] >> shift) & (nb - 1), dp = d ? d - 1 : 0u;
-    const uint32_t e = S.cnt[sl[r]], s0 = S.cnt[((dp & (q - 1)) << LNT) | (dp >> lq)];
+    const uint32_t e = ctr_get<P16>(S.cnt, sl[r]);
+    const uint32_t s0 = ctr_get<P16>(S.cnt, ((dp & (q - 1)) << LNT) | (dp >> lq));
     base[r] = d ? s0 : 0u;
     len[r] = ok[r] ? e - base[r] : 0u;
     most = max(most, len[r]);
   }
-  for (int o = 32; o > 0; o >>= 1) most = max(most, (uint32_t)__shfl_xor(most, o, 64));
   uint32_t rank[ROWS];
 #pragma unroll
   for (int r = 0; r < ROWS; r++) rank[r] = base[r];
-  for (uint32_t j = 0; j < most; j++)
+  if (ROWS * NT <= 4096) {
+    // all rows advance together (their reads overlap), as far as the wave's
+    // largest bucket
+    for (int o = 32; o > 0; o >>= 1) most = max(most, (uint32_t)__shfl_xor(most, o, 64));
+    for (uint32_t j = 0; j < most; j++)
+#pragma unroll
+      for (int r = 0; r < ROWS; r++) {
+        const unsigned long long v = S.keys[min(base[r] + j, L - 1)];
+        rank[r] += ((j < len[r]) & (v < kk[r])) ? 1u : 0u;  // no short circuit: no branch in the loop
+      }
+  } else {
+    // long lists: a row at a time, as far as the wave's largest bucket in
+    // that row (a few buckets are long, most are short, and reading every
+    // row to the longest would swamp the LDS)
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
-      const unsigned long long v = S.keys[min(base[r] + j, L - 1)];
-      rank[r] += ((j < len[r]) && (v < kk[r])) ? 1u : 0u;
+      uint32_t lm = len[r];
+      for (int o = 32; o > 0; o >>= 1) lm = max(lm, (uint32_t)__shfl_xor(lm, o, 64));
+      for (uint32_t j = 0; j < lm; j++) {
+        const unsigned long long v = S.keys[min(base[r] + j, L - 1)];
+        rank[r] += ((j < len[r]) & (v < kk[r])) ? 1u : 0u;
+      }
     }
+  }
 #pragma unroll
   for (int r = 0; r < ROWS; r++)
     if (ok[r]) ids[rank[r]] = (uint32_t)kk[r];
@@ -924,7 +961,7 @@ __global__ void __launch_bounds__(64) tile_sort_small_kernel(const uint2* __rest
                                                             unsigned long long cap, uint32_t* __restrict__ nfall,
                                                             uint32_t* __restrict__ fall) {
   constexpr uint32_t lo = ROWS_MAX == 4 ? 1u : 256u, hi = 64u * ROWS_MAX;
-  __shared__ BlockSortSmem<64, ROWS_MAX> S;
+  __shared__ BlockSortSmem<64, ROWS_MAX, ROWS_MAX == 4 ? 9 : 11> S;
   const unsigned long long P = *P_dev;
   const uint2 r = ranges[blockIdx.x];  // written by K3 whatever P is
   if (P > cap) return;                 // the keys were not written
@@ -935,23 +972,25 @@ __global__ void __launch_bounds__(64) tile_sort_small_kernel(const uint2* __rest
     if (threadIdx.x == 0) ids[r.x] = (uint32_t)keys[r.x];
     done = true;
   } else if (L <= 64u) {
-    done = block_bucket_sort<64, 1>(keys + r.x, L, ids + r.x, *(BlockSortSmem<64, 1>*)&S);
+    done = block_bucket_sort<64, 1, 7, false>(keys + r.x, L, ids + r.x, *(BlockSortSmem<64, 1, 7>*)&S);
   } else if (L <= 128u) {
-    done = block_bucket_sort<64, 2>(keys + r.x, L, ids + r.x, *(BlockSortSmem<64, 2>*)&S);
+    done = block_bucket_sort<64, 2, 8, false>(keys + r.x, L, ids + r.x, *(BlockSortSmem<64, 2, 8>*)&S);
   } else if (ROWS_MAX == 4 || L <= 256u) {
-    done = block_bucket_sort<64, 4>(keys + r.x, L, ids + r.x, *(BlockSortSmem<64, 4>*)&S);
+    done = block_bucket_sort<64, 4, 9, false>(keys + r.x, L, ids + r.x, *(BlockSortSmem<64, 4, 9>*)&S);
   } else if (L <= 512u) {
-    done = block_bucket_sort<64, 8>(keys + r.x, L, ids + r.x, *(BlockSortSmem<64, 8>*)&S);
+    done = block_bucket_sort<64, 8, 10, false>(keys + r.x, L, ids + r.x, *(BlockSortSmem<64, 8, 10>*)&S);
   } else {
-    done = block_bucket_sort<64, ROWS_MAX>(keys + r.x, L, ids + r.x, S);
+    done = block_bucket_sort<64, ROWS_MAX, ROWS_MAX == 4 ? 9 : 11, false>(keys + r.x, L, ids + r.x, S);
   }
   if (!done && threadIdx.x == 0) fall[atomicAdd(nfall, 1u)] = blockIdx.x;
 }
 
-// The lists whose buckets came out too large, by the stable LSD radix sort.
-constexpr int kFallThreads = 256, kFallBlocks = 64;
+// The lists whose buckets came out too large, by the stable LSD radix sort:
+// in LDS up to 4096 entries, else in chunks through the ping-pong buffer.
+constexpr int kFallThreads = 256, kFallBlocks = 256;
 __global__ void __launch_bounds__(kFallThreads) tile_sort_fallback_kernel(const uint2* __restrict__ ranges,
-                                                                         const unsigned long long* __restrict__ keys,
+                                                                         unsigned long long* __restrict__ keys,
+                                                                         unsigned long long* __restrict__ tmp,
                                                                          uint32_t* __restrict__ ids,
                                                                          const uint32_t* __restrict__ nfall,
                                                                          const uint32_t* __restrict__ fall) {
@@ -959,7 +998,11 @@ __global__ void __launch_bounds__(kFallThreads) tile_sort_fallback_kernel(const 
   const uint32_t m = *nfall;
   for (uint32_t i = blockIdx.x; i < m; i += gridDim.x) {
     const uint2 r = ranges[fall[i]];
-    sort_list_lds<kFallThreads>(keys + r.x, r.y - r.x, ids + r.x, S);
+    const uint32_t L = r.y - r.x;
+    if (L <= (uint32_t)kFallThreads * kTSItems)
+      sort_list_lds<kFallThreads>(keys + r.x, L, ids + r.x, S);
+    else
+      sort_list_chunked<kFallThreads>(keys + r.x, tmp + r.x, L, ids + r.x, S);
     __syncthreads();  // the LDS is reused by the next list
   }
 }
@@ -987,20 +1030,22 @@ __device__ inline uint32_t order_count(int n_cams, const uint32_t* __restrict__ 
 // K5 for lists of 1024 to 4095 entries (the positions [nbig, nmid) of each
 // camera's render order): a fixed grid of 256-thread blocks, block b taking
 // the b-th, (b + grid)-th, ... of them, by the bucket sort; a list whose
-// largest bucket is too large goes on the list for tile_sort_fallback_kernel.
+// largest bucket holds more than 128 entries goes on the list for
+// tile_sort_fallback_kernel.
 constexpr int kMidThreads = 256, kMidBlocks = 1024;
+constexpr uint32_t kMidBucketMax = 128;
 __global__ void __launch_bounds__(kMidThreads) tile_sort_mid_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ order, CamTiles ct, int n_cams,
     const uint32_t* __restrict__ nbig, const uint32_t* __restrict__ nmid, const unsigned long long* __restrict__ keys,
     uint32_t* __restrict__ ids, const unsigned long long* __restrict__ P_dev, unsigned long long cap,
     uint32_t* __restrict__ nfall, uint32_t* __restrict__ fall) {
-  __shared__ BlockSortSmem<kMidThreads, kTSItems, 1> S;
+  __shared__ BlockSortSmem<kMidThreads, kTSItems, 12> S;
   if (*P_dev > cap) return;
   const uint32_t total = order_count(n_cams, nbig, nmid);
   for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
     const uint32_t tile = order_tile(g, order, ct, nbig, nmid);
     const uint2 r = ranges[tile];
-    if (!block_bucket_sort<kMidThreads, kTSItems, 1>(keys + r.x, r.y - r.x, ids + r.x, S)) {
+    if (!block_bucket_sort<kMidThreads, kTSItems, 12, false>(keys + r.x, r.y - r.x, ids + r.x, S, kMidBucketMax)) {
       if (threadIdx.x == 0) fall[atomicAdd(nfall, 1u)] = tile;
     }
     __syncthreads();  // the LDS is reused by the next list
@@ -1008,18 +1053,115 @@ __global__ void __launch_bounds__(kMidThreads) tile_sort_mid_kernel(
 }
 
 // K5 for lists of 4096 entries and more (the positions [0, nbig)): a fixed
-// grid of 512-thread blocks, by the radix sort in chunks.
-constexpr int kBigThreads = 512, kBigBlocks = 512;
+// grid of 1024-thread blocks, one per CU, by the bucket sort with up to 8192
+// buckets (16-bit counters) for lists of up to 16384 entries.  A longer list
+// is first cut into runs of at most 16384 by the 8 bits below its highest
+// varying bit (runs of whole digit values, so every key of a run is below
+// every key of the next), moved run by run into the ping-pong buffer, and
+// each run is bucket-sorted there.  A list with a run or bucket of more than
+// 128 entries, or a digit value of more than 16384, goes on the list for
+// tile_sort_fallback_kernel.
+constexpr int kBigThreads = 1024, kBigBlocks = 256, kBigRows = 16;
+constexpr uint32_t kBigMax = kBigThreads * kBigRows;
+constexpr uint32_t kBigBucketMax = 128;
+constexpr int kMaxRuns = 256;
+struct SplitSmem {
+  uint32_t hist[256];
+  uint32_t run_of[256];  // the run of each digit value
+  uint32_t fill[kMaxRuns];
+  unsigned long long wor[kBigThreads / 64];
+  uint32_t ok;
+};
+union BigSortSmem {
+  BlockSortSmem<kBigThreads, kBigRows, 13, true> bucket;
+  SplitSmem split;
+};
+
+// Cuts the L > kBigMax keys of src into runs of at most kBigMax (see above)
+// and moves them to dst; the runs' bounds go to bounds[0 .. *nrun].  Returns
+// false (and moves nothing) when one digit value holds more than kBigMax.
+__device__ inline bool split_list(const unsigned long long* __restrict__ src, uint32_t L,
+                                  unsigned long long* __restrict__ dst, SplitSmem& S, uint32_t* bounds,
+                                  uint32_t* nrun) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const unsigned long long k0 = src[0];
+  unsigned long long orv = 0;
+  for (uint32_t p = t; p < L; p += kBigThreads) orv |= src[p] ^ k0;
+  for (int o = 32; o > 0; o >>= 1) orv |= __shfl_xor(orv, o, 64);
+  if (lane == 0) S.wor[w] = orv;
+  if (t < 256) S.hist[t] = 0u;
+  __syncthreads();
+  orv = 0;
+#pragma unroll
+  for (int k = 0; k < kBigThreads / 64; k++) orv |= S.wor[k];
+  const int hb = orv ? 63 - __clzll((long long)orv) : 0;
+  const int shift = hb >= 7 ? hb - 7 : 0;
+  for (uint32_t p = t; p < L; p += kBigThreads) atomicAdd(&S.hist[(uint32_t)(src[p] >> shift) & 255u], 1u);
+  __syncthreads();
+  if (t == 0) {  // greedy cut at digit boundaries
+    uint32_t run = 0, acc = 0, start = 0, ok = 1;
+    bounds[0] = 0;
+    for (int d = 0; d < 256; d++) {
+      const uint32_t c = S.hist[d];
+      if (c > kBigMax) ok = 0;
+      if (acc + c > kBigMax) {
+        run++;
+        bounds[run] = start;
+        acc = 0;
+      }
+      S.run_of[d] = run;
+      acc += c;
+      start += c;
+    }
+    *nrun = run + 1;
+    bounds[run + 1] = L;
+    S.ok = ok;
+  }
+  __syncthreads();
+  if (!S.ok) {
+    __syncthreads();
+    return false;
+  }
+  if ((uint32_t)t < *nrun) S.fill[t] = bounds[t];
+  __syncthreads();
+  for (uint32_t p = t; p < L; p += kBigThreads) {
+    const unsigned long long k = src[p];
+    dst[atomicAdd(&S.fill[S.run_of[(uint32_t)(k >> shift) & 255u]], 1u)] = k;
+  }
+  __syncthreads();  // the runs are in dst for the whole block
+  return true;
+}
+
 __global__ void __launch_bounds__(kBigThreads) tile_sort_big_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ order, CamTiles ct, int n_cams,
-    const uint32_t* __restrict__ nbig, unsigned long long* __restrict__ keys, unsigned long long* __restrict__ tmp,
-    uint32_t* __restrict__ ids, const unsigned long long* __restrict__ P_dev, unsigned long long cap) {
-  __shared__ TileSortSmem<kBigThreads> S;
+    const uint32_t* __restrict__ nbig, const unsigned long long* __restrict__ keys,
+    unsigned long long* __restrict__ tmp, uint32_t* __restrict__ ids, const unsigned long long* __restrict__ P_dev,
+    unsigned long long cap, uint32_t* __restrict__ nfall, uint32_t* __restrict__ fall) {
+  __shared__ BigSortSmem S;
+  __shared__ uint32_t bounds[kMaxRuns + 1];
+  __shared__ uint32_t nrun;
   if (*P_dev > cap) return;
   const uint32_t total = order_count(n_cams, nullptr, nbig);
   for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
-    const uint2 r = ranges[order_tile(g, order, ct, nullptr, nbig)];
-    sort_list_chunked<kBigThreads>(keys + r.x, tmp + r.x, r.y - r.x, ids + r.x, S);
+    const uint32_t tile = order_tile(g, order, ct, nullptr, nbig);
+    const uint2 r = ranges[tile];
+    const uint32_t L = r.y - r.x;
+    bool done = false;
+    if (L <= kBigMax) {
+      done = block_bucket_sort<kBigThreads, kBigRows, 13, true>(keys + r.x, L, ids + r.x, S.bucket, kBigBucketMax);
+    } else if (L <= kBigMax * (kMaxRuns / 2) && split_list(keys + r.x, L, tmp + r.x, S.split, bounds, &nrun)) {
+      const uint32_t m = nrun;
+      done = true;
+      for (uint32_t k = 0; k < m && done; k++) {
+        const uint32_t a = bounds[k], n = bounds[k + 1] - a;
+        if (n > 0)
+          done = block_bucket_sort<kBigThreads, kBigRows, 13, true>(tmp + r.x + a, n, ids + r.x + a, S.bucket,
+                                                                    kBigBucketMax);
+        __syncthreads();
+      }
+    }
+    // the list's keys are still whole in keys: the radix sort takes it over
+    if (!done && threadIdx.x == 0) fall[atomicAdd(nfall, 1u)] = tile;
     __syncthreads();  // the LDS is reused by the next list
   }
 }
@@ -1159,11 +1301,12 @@ gut_status bin_sort_launch(const gut_projected* proj, int n, const DevCam* dc, i
                                                           n_cams, nbig, nmid, keys, sorted_ids, P_dev, ucap, nfall,
                                                           fall);
   GUT_LAUNCH_CHECK();
-  tile_sort_fallback_kernel<<<kFallBlocks, kFallThreads, 0, s>>>((const uint2*)tile_ranges, keys, sorted_ids, nfall,
-                                                                 fall);
-  GUT_LAUNCH_CHECK();
   tile_sort_big_kernel<<<kBigBlocks, kBigThreads, 0, s>>>((const uint2*)tile_ranges, tile_ranges + 2 * T, a.ct,
-                                                          n_cams, nbig, keys, tmp, sorted_ids, P_dev, ucap);
+                                                          n_cams, nbig, keys, tmp, sorted_ids, P_dev, ucap, nfall,
+                                                          fall);
+  GUT_LAUNCH_CHECK();
+  tile_sort_fallback_kernel<<<kFallBlocks, kFallThreads, 0, s>>>((const uint2*)tile_ranges, keys, tmp, sorted_ids,
+                                                                 nfall, fall);
   GUT_LAUNCH_CHECK();
   return GUT_OK;
 }
