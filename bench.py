@@ -460,6 +460,9 @@ def main():
                     help="skip the k-buffer (\"Ours (sorted)\", Sec. 4.3) timing")
     ap.add_argument("--no-clip", action="store_true",
                     help="skip the hybrid-rendering depth-clip timing (Sec. 6.2)")
+    ap.add_argument("--warm-only", action="store_true",
+                    help="skip the cold-cache and tile-culling-off repeats of the forward step "
+                         "(for counter runs, whose per-dispatch means should see warm steps only)")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the 3M-particle rolling-shutter fisheye stage timings")
     ap.add_argument("--serve-requests", type=int, default=120)
@@ -536,27 +539,29 @@ def main():
         for k, b, ms in (("project", proj_bytes, fw["stage_ms"][0]), ("bin", bin_bytes, fw["stage_ms"][1]))}
     stage_roofline["bin"]["kernels"] = BIN_KERNELS
 
-    # the same step with every stage cold: a 512 MB write before each step
-    # evicts the scene and the buffers from the 256 MB Infinity Cache
-    log("[bench] forward steps, cold (Infinity Cache flushed before each step)")
-    flush = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
-    fcold = bench_forward(gs, cams, max(3, args.steps // 2), 2, R, torch, flush=flush)
-    del flush
-    cold = dict(ms_per_step=fcold["ms_per_step"],
-                stages_ms={"project": fcold["stage_ms"][0], "bin": fcold["stage_ms"][1],
-                           "render": fcold["stage_ms"][2]},
-                project_frac=proj_bytes / (fcold["stage_ms"][0] * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                bin_frac=bin_bytes / (fcold["stage_ms"][1] * 1e-3) / 1e9 / PEAK_HBM_GBS)
-    del fcold
+    cold = rect_only = None
+    if not args.warm_only:
+        # the same step with every stage cold: a 512 MB write before each step
+        # evicts the scene and the buffers from the 256 MB Infinity Cache
+        log("[bench] forward steps, cold (Infinity Cache flushed before each step)")
+        flush = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
+        fcold = bench_forward(gs, cams, max(3, args.steps // 2), 2, R, torch, flush=flush)
+        del flush
+        cold = dict(ms_per_step=fcold["ms_per_step"],
+                    stages_ms={"project": fcold["stage_ms"][0], "bin": fcold["stage_ms"][1],
+                               "render": fcold["stage_ms"][2]},
+                    project_frac=proj_bytes / (fcold["stage_ms"][0] * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                    bin_frac=bin_bytes / (fcold["stage_ms"][1] * 1e-3) / 1e9 / PEAK_HBM_GBS)
+        del fcold
 
-    # the rectangle-only tile lists (tile culling off), for comparison
-    log("[bench] forward steps without tile culling")
-    frect = bench_forward(gs, cams, max(3, args.steps // 2), 2, R, torch, dict(tile_cull=0))
-    rect_only = dict(mpix_per_s=npx / (frect["ms_per_step"] * 1e-3) / 1e6, n_pairs=frect["n_pairs"],
-                     e_eval=frect["e_eval"],
-                     stages_ms={"project": frect["stage_ms"][0], "bin": frect["stage_ms"][1],
-                                "render": frect["stage_ms"][2]})
-    del frect
+        # the rectangle-only tile lists (tile culling off), for comparison
+        log("[bench] forward steps without tile culling")
+        frect = bench_forward(gs, cams, max(3, args.steps // 2), 2, R, torch, dict(tile_cull=0))
+        rect_only = dict(mpix_per_s=npx / (frect["ms_per_step"] * 1e-3) / 1e6, n_pairs=frect["n_pairs"],
+                         e_eval=frect["e_eval"],
+                         stages_ms={"project": frect["stage_ms"][0], "bin": frect["stage_ms"][1],
+                                    "render": frect["stage_ms"][2]})
+        del frect
 
     # the generalized Gaussian responses of Supp. A on the same forward step
     # (its table trades quality for speed across degrees 2..8)

@@ -15,10 +15,10 @@
 // pixels have stopped, and the block stops when no pixel is still going.
 // Blocks take tiles in the render order from gut_bin (longest lists first)
 // and waves of long lists raise their issue priority, so the longest tiles
-// neither start last nor crawl behind short ones.  The walk is bound by
-// latency more than by issue, so the kernels ask for five waves per SIMD
-// (96 VGPRs): the FP64 pair setup then keeps a few values in scratch, which
-// costs less than the fifth wave gains.
+// neither start last nor crawl behind short ones.  The kernels run four waves
+// per SIMD (124 VGPRs).  Five (96 VGPRs) are 4% faster, but the FP64 pair
+// setup then keeps 27 values in scratch, whose spills and reloads add about
+// 450 MB of memory traffic per two-view launch to the 620 MB it moves.
 #include "tile_eval.h"
 
 namespace gut {
@@ -165,7 +165,7 @@ __device__ __forceinline__ void render_tile(
 // One block per tile, taken in the render order (longest lists first).  NE:
 // also count each pixel's evaluated entries (out_ne non-null).
 template <bool RS, bool NE, bool GEN, bool CLIP>
-__global__ void __launch_bounds__(kRThreads, 5) render_kernel(
+__global__ void __launch_bounds__(kRThreads, 4) render_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
     const float4* __restrict__ record, const float* __restrict__ rgb, const float* __restrict__ clip,
@@ -194,7 +194,7 @@ struct MultiCams {
 };
 
 template <bool RS, bool NE, bool GEN, bool CLIP>
-__global__ void __launch_bounds__(kRThreads, 5) render_multi_kernel(
+__global__ void __launch_bounds__(kRThreads, 4) render_multi_kernel(
     MultiCams mc, Thresholds th, int n, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
     const float4* __restrict__ record, const float* __restrict__ rgb, const float* __restrict__ clip,
