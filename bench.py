@@ -142,7 +142,7 @@ def pmc_summary(fetch_dir, write_dir, out_path, command):
 # 4 B depth by the scatter; per pair 8 B of key written and read back, 4 B of
 # id written; per tile 24 B of counts, starts, ranges and order.
 PROJ_CAMS_PER_LAUNCH = 4
-BIN_KERNELS = 8  # init, count, column scan, list scan, scatter, sorts (lists < 1024, < 4096, longer)
+BIN_KERNELS = 10  # init, count, column scan, list scan, scatter, 5 sorts (by list length, and the radix fallback)
 
 
 def project_bytes(n, n_cams):
