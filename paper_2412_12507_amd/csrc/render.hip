@@ -83,10 +83,12 @@ __device__ __forceinline__ void render_tile(
   float T[2] = {1.0f, 1.0f};
   double C[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
   uint32_t last[2] = {0u, 0u}, nev[2] = {active[0] ? len : 0u, active[1] ? len : 0u};
-  bool done0 = !active[0], done1 = !active[1];
+  // stopped pixels as 0/1 in vector registers: kept as lane masks, the
+  // flags cost a merge with the exec mask at every divergent step
+  uint32_t done0 = active[0] ? 0u : 1u, done1 = active[1] ? 0u : 1u;
   for (uint32_t b = 0; b < len; b += kRBatch) {
     // (also publishes wb before the first setup)
-    if (__syncthreads_count(!(done0 && done1)) == 0) break;
+    if (__syncthreads_count((done0 & done1) == 0u) == 0) break;
     uint32_t fl = 0u;
     if (b + t < len) {
       uint32_t e = ids[rg.x + b + t];
@@ -102,7 +104,7 @@ __device__ __forceinline__ void render_tile(
     for (int h = 0; h < 2 && !wave_done; h++) {
       unsigned long long m = h ? m1 : m0;
       while (m) {
-        if (!wave_any(!(done0 && done1))) { wave_done = true; break; }
+        if (!wave_any((done0 & done1) == 0u)) { wave_done = true; break; }
         const uint32_t q = 64u * h + (uint32_t)__builtin_ctzll(m);
         m &= m - 1ull;
         const uint32_t idx1 = b + q + 1;  // the entry's 1-based place in the list
@@ -115,7 +117,7 @@ __device__ __forceinline__ void render_tile(
           eval_test<RS>(r, P, u[k], v[k], dt[k], &ev[k]);
           if (CLIP) ev[k].ok = ev[k].ok && !behind_clip<RS>(r, P, u[k], v[k], dt[k], dlen[k], clipv[k], ev[k].dd);
         }
-        const bool live0 = ev[0].ok && !done0, live1 = ev[1].ok && !done1;
+        const bool live0 = ev[0].ok && done0 == 0u, live1 = ev[1].ok && done1 == 0u;
         if (!wave_any(live0 || live1)) continue;  // nothing reaches alpha_min here
         bool contrib[2];
         float wgt[2];
@@ -132,7 +134,7 @@ __device__ __forceinline__ void render_tile(
           T[k] = fmaf(-ae, T[k], T[k]);  // Tn, or T itself when not contributing
           last[k] = contrib[k] ? idx1 : last[k];
           if (NE) nev[k] = stop ? idx1 : nev[k];
-          if (k) done1 = done1 || stop; else done0 = done0 || stop;
+          if (k) done1 |= stop ? 1u : 0u; else done0 |= stop ? 1u : 0u;
         }
         // some lane passed the alpha_min test, so almost always some lane
         // contributes: accumulate unconditionally (zero weights add nothing)

@@ -265,19 +265,24 @@ class GutRender(torch.autograd.Function):
         ctx.cams, ctx.params, ctx.sh_degree, ctx.clip = cams, params, int(sh_degree), clip
         ctx.recompute = bool(recompute_projection)
         ctx.bins = bins
-        ctx.img = img
+        ctx.shapes = img.shapes
         ctx.proj = None if ctx.recompute else proj
-        ctx.save_for_backward(scene.means, scene.scales, scene.quats, scene.opacities, scene.sh)
+        # the outputs go through save_for_backward, so that an in-place edit of
+        # a returned image is caught by autograd's version check instead of
+        # silently changing the gradients
+        ctx.save_for_backward(scene.means, scene.scales, scene.quats, scene.opacities, scene.sh,
+                              img.rgb, img.T, img.n_contrib)
         return img.rgb, img.T
 
     @staticmethod
     def backward(ctx, d_rgb, d_T):
-        means, scales, quats, opacities, sh = ctx.saved_tensors
+        means, scales, quats, opacities, sh, rgb, T, n_contrib = ctx.saved_tensors
         scene = GaussianScene(means, scales, quats, opacities, sh, ctx.sh_degree)
+        img = Image(rgb=rgb, T=T, n_contrib=n_contrib, n_eval=None, shapes=ctx.shapes)
         proj = ctx.proj if ctx.proj is not None else project(scene, ctx.cams, ctx.params)
         if d_rgb is None:
-            d_rgb = torch.zeros_like(ctx.img.rgb)
-        g = render_backward(scene, proj, ctx.bins, ctx.cams, ctx.img, d_rgb, d_T, ctx.params,
+            d_rgb = torch.zeros_like(rgb)
+        g = render_backward(scene, proj, ctx.bins, ctx.cams, img, d_rgb, d_T, ctx.params,
                             clip=ctx.clip)
         return g["means"], g["scales"], g["quats"], g["opacities"], g["sh"], None, None, None, None, None
 

@@ -369,3 +369,12 @@ def test_autograd_function_matches_direct_call():
     ((imgs2[0] * w).sum() + Ts2[0].sum()).backward()
     for a, b in zip(leaves, leaves2):
         assert close(a.grad, b.grad)
+    # the returned images are saved for the backward: editing one in place
+    # must be caught by autograd's version check, not change the gradients
+    leaves3 = [t.clone().requires_grad_(True) for t in (gs.means, gs.scales, gs.quats, gs.opacities, gs.sh)]
+    imgs3, Ts3 = R.render_gaussians(*leaves3, gs.sh_degree, [cam])
+    loss3 = (imgs3[0] * w).sum()
+    with torch.no_grad():
+        imgs3[0].clamp_(0.0, 0.5)
+    with pytest.raises(RuntimeError):
+        loss3.backward()
