@@ -329,10 +329,10 @@ constexpr int kKThreads = 256;
 
 __device__ __forceinline__ void kbuf_blend(float a, uint32_t e, const float* __restrict__ rgb,
                                            float t_min, float& T, double (&C)[3], uint32_t& nc,
-                                           bool& done) {
+                                           uint32_t& done) {
   if (a <= 0.0f || done) return;  // a sentinel or a wall, or the pixel has stopped
   const float Tn = fmaf(-a, T, T);
-  if (Tn < t_min) { done = true; return; }
+  if (Tn < t_min) { done = 1u; return; }
   const double w = (double)(a * T);
   C[0] = fma(w, (double)rgb[3 * (size_t)e], C[0]);
   C[1] = fma(w, (double)rgb[3 * (size_t)e + 1], C[1]);
@@ -389,9 +389,9 @@ __global__ void __launch_bounds__(kKThreads, 4) render_kbuffer_kernel(
   float T = 1.0f;
   double C[3] = {0.0, 0.0, 0.0};
   uint32_t nc = 0u, nev = active ? len : 0u;
-  bool done = !active;
+  uint32_t done = active ? 0u : 1u;  // a 0/1 vector register, as in render_tile
   for (uint32_t b = 0; b < len; b += kKThreads) {
-    if (__syncthreads_count(!done) == 0) break;  // (also publishes wb before the first setup)
+    if (__syncthreads_count(done == 0u) == 0) break;  // (also publishes wb before the first setup)
     uint32_t fl = 0u;
     if (b + t < len) {
       const uint32_t e = ids[rg.x + b + t];
@@ -406,7 +406,7 @@ __global__ void __launch_bounds__(kKThreads, 4) render_kbuffer_kernel(
     for (int h = 0; h < kKThreads / 64 && !wave_done; h++) {
       unsigned long long m = __builtin_amdgcn_ballot_w64((pf[lane + 64 * h] >> wv) & 1u);
       while (m) {
-        if (!wave_any(!done)) { wave_done = true; break; }
+        if (!wave_any(done == 0u)) { wave_done = true; break; }
         const uint32_t q = 64u * h + (uint32_t)__builtin_ctzll(m);
         m &= m - 1ull;
         const float4* P = &pd[q * S];
@@ -415,7 +415,7 @@ __global__ void __launch_bounds__(kKThreads, 4) render_kbuffer_kernel(
         Eval ev;
         eval_test<RS>(r, P, u, v, dt, &ev);
         if (CLIP) ev.ok = ev.ok && !behind_clip<RS>(r, P, u, v, dt, dlen, clipv, ev.dd);
-        const bool live = ev.ok && !done;
+        const bool live = ev.ok && done == 0u;
         if (!wave_any(live)) continue;
         eval_alpha<RS, GEN>(r, th, &ev);
         if (live) {

@@ -285,13 +285,13 @@ struct KBufGrad {
 __device__ __forceinline__ bool kbuf_blend_bwd(float a, uint32_t e, float px_, float py_, float pz_,
                                                float rho, float fg, const KBufGrad& K, const float (&gC)[3],
                                                const double (&gCd)[3], float gTT, float& T, double& Z,
-                                               bool& done, float (&v)[16]) {
+                                               uint32_t& done, float (&v)[16]) {
 #pragma unroll
   for (int k = 0; k < 16; k++) v[k] = 0.0f;
   if (a <= 0.0f || done) return false;
   const float Tb = T;
   const float Tn = fmaf(-a, Tb, Tb);
-  if (Tn < K.t_min) { done = true; return false; }
+  if (Tn < K.t_min) { done = 1u; return false; }
   T = Tn;
   const float wgt = a * Tb;
   const double c0 = K.rgb[3 * (size_t)e], c1 = K.rgb[3 * (size_t)e + 1], c2 = K.rgb[3 * (size_t)e + 2];
@@ -401,9 +401,9 @@ __global__ void __launch_bounds__(kKThreadsB, 2) render_kbuffer_bwd_kernel(
     bi[j] = 0u;
   }
   float T = 1.0f;
-  bool done = !active;
+  uint32_t done = active ? 0u : 1u;  // a 0/1 vector register, as in render_tile
   for (uint32_t b = 0; b < len; b += kKThreadsB) {
-    if (__syncthreads_count(!done) == 0) break;
+    if (__syncthreads_count(done == 0u) == 0) break;
     uint32_t fl = 0u;
     if (b + t < len) {
       const uint32_t e = ids[rg.x + b + t];
@@ -418,7 +418,7 @@ __global__ void __launch_bounds__(kKThreadsB, 2) render_kbuffer_bwd_kernel(
     for (int h = 0; h < kKThreadsB / 64 && !wave_done; h++) {
       unsigned long long m = __builtin_amdgcn_ballot_w64((pf[lane + 64 * h] >> wv) & 1u);
       while (m) {
-        if (!wave_any(!done)) { wave_done = true; break; }
+        if (!wave_any(done == 0u)) { wave_done = true; break; }
         const uint32_t q = 64u * h + (uint32_t)__builtin_ctzll(m);
         m &= m - 1ull;
         const float4* P = &pd[q * S];
@@ -427,7 +427,7 @@ __global__ void __launch_bounds__(kKThreadsB, 2) render_kbuffer_bwd_kernel(
         Eval ev;
         eval_test<RS>(r, P, u, v, dt, &ev);
         if (CLIP) ev.ok = ev.ok && !behind_clip<RS>(r, P, u, v, dt, dlen, clipv, ev.dd);
-        const bool live = ev.ok && !done;
+        const bool live = ev.ok && done == 0u;
         if (!wave_any(live)) continue;
         eval_alpha<RS, GEN>(r, th, &ev);
         bool valid = false;
