@@ -264,39 +264,69 @@ __global__ void __launch_bounds__(kBinThreads) bin_count_kernel(BinArgs a, uint3
   }
 }
 
-// K2: for each tile (one thread per tile of every camera), the exclusive
-// prefix of its column of the count matrix, in place, and its count into
-// ranges[t].y; each block adds its tiles' counts to their cameras' totals
-// (one atomic per camera a block touches; the totals start at zero from the
-// init kernel).
+// K2: for each tile, the exclusive prefix of its column of the count matrix,
+// in place, and its count into ranges[t].y; each block adds its tiles'
+// counts to their cameras' totals (one atomic per camera a block touches; the
+// totals start at zero from the init kernel).  A block takes 32 tiles, and
+// each tile's column is cut into kColSegs segments of rows, one per thread:
+// a thread sums its segment, the segments' sums are scanned in LDS, and the
+// thread writes its segment's prefixes, so a long column (many blocks of
+// entries) is not walked by one thread alone.
 constexpr int kColThreads = 256;
-constexpr int kColUnroll = 8;
+constexpr int kColTiles = 32;
+constexpr int kColSegs = kColThreads / kColTiles;
+constexpr int kColUnroll = 4;
 __global__ void __launch_bounds__(kColThreads) bin_colscan_kernel(uint32_t* __restrict__ M, CamTiles ct,
                                                                   int n_cams, int bpc, int64_t T,
                                                                   uint2* __restrict__ ranges,
                                                                   unsigned long long* __restrict__ cam_pairs) {
   __shared__ unsigned long long cs[kMaxCams];
-  const int64_t g = (int64_t)blockIdx.x * kColThreads + threadIdx.x;
+  __shared__ uint32_t ssum[kColSegs][kColTiles];
+  const int tl = threadIdx.x % kColTiles, seg = threadIdx.x / kColTiles;
+  const int64_t g = (int64_t)blockIdx.x * kColTiles + tl;
   if (threadIdx.x < kMaxCams) cs[threadIdx.x] = 0ull;
-  __syncthreads();
+  const int chunk = (bpc + kColSegs - 1) / kColSegs;
+  const int r0 = min(bpc, seg * chunk), r1 = min(bpc, r0 + chunk);
+  int c = 0;
+  uint32_t* col = nullptr;
+  int Tc = 0;
+  uint32_t sum = 0;
   if (g < T) {
-    int c = 0;
     while (c + 1 < n_cams && ct.base[c + 1] <= g) c++;
-    const int Tc = ct.count[c], t = (int)(g - ct.base[c]);
-    uint32_t* col = M + (int64_t)bpc * ct.base[c] + t;
-    uint32_t run = 0;
-    for (int b0 = 0; b0 < bpc; b0 += kColUnroll) {
+    Tc = ct.count[c];
+    col = M + (int64_t)bpc * ct.base[c] + (g - ct.base[c]);
+    for (int r = r0; r < r1; r += kColUnroll) {
       uint32_t v[kColUnroll];
 #pragma unroll
-      for (int k = 0; k < kColUnroll; k++) v[k] = b0 + k < bpc ? col[(int64_t)(b0 + k) * Tc] : 0u;
+      for (int k = 0; k < kColUnroll; k++) v[k] = r + k < r1 ? col[(int64_t)(r + k) * Tc] : 0u;
+#pragma unroll
+      for (int k = 0; k < kColUnroll; k++) sum += v[k];
+    }
+  }
+  ssum[seg][tl] = sum;
+  __syncthreads();
+  uint32_t run = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kColSegs; k++) {
+    const uint32_t x = ssum[k][tl];
+    if (k < seg) run += x;
+    tot += x;
+  }
+  if (g < T) {
+    for (int r = r0; r < r1; r += kColUnroll) {
+      uint32_t v[kColUnroll];
+#pragma unroll
+      for (int k = 0; k < kColUnroll; k++) v[k] = r + k < r1 ? col[(int64_t)(r + k) * Tc] : 0u;
 #pragma unroll
       for (int k = 0; k < kColUnroll; k++) {
-        if (b0 + k < bpc) col[(int64_t)(b0 + k) * Tc] = run;
+        if (r + k < r1) col[(int64_t)(r + k) * Tc] = run;
         run += v[k];
       }
     }
-    ranges[g].y = run;
-    atomicAdd(&cs[c], (unsigned long long)run);
+    if (seg == 0) {
+      ranges[g].y = tot;
+      atomicAdd(&cs[c], (unsigned long long)tot);
+    }
   }
   __syncthreads();
   if (threadIdx.x < n_cams && cs[threadIdx.x]) atomicAdd(&cam_pairs[threadIdx.x], cs[threadIdx.x]);
@@ -1244,7 +1274,7 @@ gut_status bin_count_launch(const gut_projected* proj, int n, const DevCam* dc, 
   if (n > 0) {
     bin_count_kernel<<<(unsigned)(a.bpc * n_cams), kBinThreads, lds, s>>>(a, M);
     GUT_LAUNCH_CHECK();
-    bin_colscan_kernel<<<grid_for(T, kColThreads), kColThreads, 0, s>>>(
+    bin_colscan_kernel<<<grid_for(T, kColTiles), kColThreads, 0, s>>>(
         M, a.ct, n_cams, a.bpc, T, (uint2*)tile_ranges, sw + SmallLayout::cam_pairs / 8);
     GUT_LAUNCH_CHECK();
   } else {  // no entries: every count is zero
