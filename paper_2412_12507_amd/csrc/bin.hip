@@ -934,12 +934,19 @@ __device__ __forceinline__ bool block_bucket_sort(const unsigned long long* __re
   for (int r = 0; r < ROWS; r++)
     if (ok[r]) S.keys[ctr_inc<P16>(S.cnt, sl[r])] = kk[r];
   __syncthreads();
-  // the counters now hold each bucket's end, which is the next bucket's start
+  // The counters now hold each bucket's end, which is the next bucket's
+  // start.  The rank counts run over the keys in their bucket order (item r
+  // of thread t is the key at place NT r + t of the moved list), so the 64
+  // lanes of a wave mostly share a few neighbouring buckets and the count of
+  // a row stops at the longest of those, not at the longest bucket that 64
+  // keys from anywhere in the list would meet.
+#pragma unroll
+  for (int r = 0; r < ROWS; r++) kk[r] = ok[r] ? S.keys[r * NT + t] : 0ull;
   uint32_t base[ROWS], len[ROWS], most = 0;
 #pragma unroll
   for (int r = 0; r < ROWS; r++) {
     const uint32_t d = (uint32_t)(kk[r] >> shift) & (nb - 1), dp = d ? d - 1 : 0u;
-    const uint32_t e = ctr_get<P16>(S.cnt, sl[r]);
+    const uint32_t e = ctr_get<P16>(S.cnt, ((d & (q - 1)) << LNT) | (d >> lq));
     const uint32_t s0 = ctr_get<P16>(S.cnt, ((dp & (q - 1)) << LNT) | (dp >> lq));
     base[r] = d ? s0 : 0u;
     len[r] = ok[r] ? e - base[r] : 0u;
@@ -960,8 +967,7 @@ __device__ __forceinline__ bool block_bucket_sort(const unsigned long long* __re
       }
   } else {
     // long lists: a row at a time, as far as the wave's largest bucket in
-    // that row (a few buckets are long, most are short, and reading every
-    // row to the longest would swamp the LDS)
+    // that row
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
       uint32_t lm = len[r];
@@ -1114,9 +1120,16 @@ __device__ inline bool split_list(const unsigned long long* __restrict__ src, ui
                                   unsigned long long* __restrict__ dst, SplitSmem& S, uint32_t* bounds,
                                   uint32_t* nrun) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  constexpr int U = 8;  // loads in flight per thread
   const unsigned long long k0 = src[0];
   unsigned long long orv = 0;
-  for (uint32_t p = t; p < L; p += kBigThreads) orv |= src[p] ^ k0;
+  for (uint32_t p0 = t; p0 < L; p0 += U * kBigThreads) {
+    unsigned long long k[U];
+#pragma unroll
+    for (int j = 0; j < U; j++) k[j] = p0 + j * kBigThreads < L ? src[p0 + j * kBigThreads] : k0;
+#pragma unroll
+    for (int j = 0; j < U; j++) orv |= k[j] ^ k0;
+  }
   for (int o = 32; o > 0; o >>= 1) orv |= __shfl_xor(orv, o, 64);
   if (lane == 0) S.wor[w] = orv;
   if (t < 256) S.hist[t] = 0u;
@@ -1126,7 +1139,14 @@ __device__ inline bool split_list(const unsigned long long* __restrict__ src, ui
   for (int k = 0; k < kBigThreads / 64; k++) orv |= S.wor[k];
   const int hb = orv ? 63 - __clzll((long long)orv) : 0;
   const int shift = hb >= 7 ? hb - 7 : 0;
-  for (uint32_t p = t; p < L; p += kBigThreads) atomicAdd(&S.hist[(uint32_t)(src[p] >> shift) & 255u], 1u);
+  for (uint32_t p0 = t; p0 < L; p0 += U * kBigThreads) {
+    unsigned long long k[U];
+#pragma unroll
+    for (int j = 0; j < U; j++) k[j] = p0 + j * kBigThreads < L ? src[p0 + j * kBigThreads] : 0ull;
+#pragma unroll
+    for (int j = 0; j < U; j++)
+      if (p0 + j * kBigThreads < L) atomicAdd(&S.hist[(uint32_t)(k[j] >> shift) & 255u], 1u);
+  }
   __syncthreads();
   if (t == 0) {  // greedy cut at digit boundaries
     uint32_t run = 0, acc = 0, start = 0, ok = 1;
@@ -1154,9 +1174,13 @@ __device__ inline bool split_list(const unsigned long long* __restrict__ src, ui
   }
   if ((uint32_t)t < *nrun) S.fill[t] = bounds[t];
   __syncthreads();
-  for (uint32_t p = t; p < L; p += kBigThreads) {
-    const unsigned long long k = src[p];
-    dst[atomicAdd(&S.fill[S.run_of[(uint32_t)(k >> shift) & 255u]], 1u)] = k;
+  for (uint32_t p0 = t; p0 < L; p0 += U * kBigThreads) {
+    unsigned long long k[U];
+#pragma unroll
+    for (int j = 0; j < U; j++) k[j] = p0 + j * kBigThreads < L ? src[p0 + j * kBigThreads] : 0ull;
+#pragma unroll
+    for (int j = 0; j < U; j++)
+      if (p0 + j * kBigThreads < L) dst[atomicAdd(&S.fill[S.run_of[(uint32_t)(k[j] >> shift) & 255u]], 1u)] = k[j];
   }
   __syncthreads();  // the runs are in dst for the whole block
   return true;
