@@ -80,15 +80,15 @@ __device__ __forceinline__ void render_tile(
   else __builtin_amdgcn_s_setprio(0);
   // Colour accumulates in FP64 (three FMAs per contributing entry) so that
   // the backward can form suffix sums C - C_<=j without FP32 cancellation.
-  float T[2] = {1.0f, 1.0f};
+  // A stopped pixel keeps -T (T >= t_min > 0 while it runs): the stop is
+  // then one select on T instead of a flag of its own.
+  float T[2] = {active[0] ? 1.0f : -1.0f, active[1] ? 1.0f : -1.0f};
   double C[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
   uint32_t last[2] = {0u, 0u}, nev[2] = {active[0] ? len : 0u, active[1] ? len : 0u};
-  // stopped pixels as 0/1 in vector registers: kept as lane masks, the
-  // flags cost a merge with the exec mask at every divergent step
-  uint32_t done0 = active[0] ? 0u : 1u, done1 = active[1] ? 0u : 1u;
   for (uint32_t b = 0; b < len; b += kRBatch) {
     // (also publishes wb before the first setup)
-    if (__syncthreads_count((done0 & done1) == 0u) == 0) break;
+    if (__syncthreads_count(T[0] > 0.0f || T[1] > 0.0f) == 0) break;
+    b = __builtin_amdgcn_readfirstlane(b);
     uint32_t fl = 0u;
     if (b + t < len) {
       uint32_t e = ids[rg.x + b + t];
@@ -98,27 +98,32 @@ __device__ __forceinline__ void render_tile(
     pf[t] = fl;
     __syncthreads();
     // the batch's pairs that may reach alpha_min somewhere in this wave's half-tile
-    const unsigned long long m0 = __builtin_amdgcn_ballot_w64((pf[lane] >> wv) & 1u);
-    const unsigned long long m1 = __builtin_amdgcn_ballot_w64((pf[lane + 64] >> wv) & 1u);
+    const uint32_t f0 = pf[lane], f1 = pf[lane + 64];
+    const unsigned long long m0 = __builtin_amdgcn_ballot_w64((f0 >> wv) & 1u);
+    const unsigned long long m1 = __builtin_amdgcn_ballot_w64((f1 >> wv) & 1u);
+    const unsigned long long x0 = __builtin_amdgcn_ballot_w64((f0 & kMixedBit) != 0u);
+    const unsigned long long x1 = __builtin_amdgcn_ballot_w64((f1 & kMixedBit) != 0u);
     bool wave_done = false;
     for (int h = 0; h < 2 && !wave_done; h++) {
       unsigned long long m = h ? m1 : m0;
+      const unsigned long long xm = h ? x1 : x0;
       while (m) {
-        if (!wave_any((done0 & done1) == 0u)) { wave_done = true; break; }
-        const uint32_t q = 64u * h + (uint32_t)__builtin_ctzll(m);
+        if (!wave_any(T[0] > 0.0f || T[1] > 0.0f)) { wave_done = true; break; }
+        const uint32_t ql = (uint32_t)__builtin_ctzll(m), q = 64u * h + ql;
         m &= m - 1ull;
         const uint32_t idx1 = b + q + 1;  // the entry's 1-based place in the list
         const float4* P = &pd[q * S];
         PairRegs<RS> r;
         load_pair<RS>(P, r);
+        r.mixed = (xm >> ql) & 1ull;  // (from the flags: no wait on the LDS read)
         Eval ev[2];
 #pragma unroll
         for (int k = 0; k < 2; k++) {
           eval_test<RS>(r, P, u[k], v[k], dt[k], &ev[k]);
           if (CLIP) ev[k].ok = ev[k].ok && !behind_clip<RS>(r, P, u[k], v[k], dt[k], dlen[k], clipv[k], ev[k].dd);
         }
-        const bool live0 = ev[0].ok && done0 == 0u, live1 = ev[1].ok && done1 == 0u;
-        if (!wave_any(live0 || live1)) continue;  // nothing reaches alpha_min here
+        const bool live0 = ev[0].ok & (T[0] > 0.0f), live1 = ev[1].ok & (T[1] > 0.0f);
+        if (!wave_any(live0 | live1)) continue;  // nothing reaches alpha_min here
         bool contrib[2];
         float wgt[2];
 #pragma unroll
@@ -131,10 +136,10 @@ __device__ __forceinline__ void render_tile(
           contrib[k] = live & !below;
           const float ae = contrib[k] ? ev[k].a : 0.0f;
           wgt[k] = ae * T[k];
-          T[k] = fmaf(-ae, T[k], T[k]);  // Tn, or T itself when not contributing
+          const float Tk = fmaf(-ae, T[k], T[k]);  // Tn, or T itself when not contributing
+          T[k] = stop ? -T[k] : Tk;
           last[k] = contrib[k] ? idx1 : last[k];
           if (NE) nev[k] = stop ? idx1 : nev[k];
-          if (k) done1 |= stop ? 1u : 0u; else done0 |= stop ? 1u : 0u;
         }
         // some lane passed the alpha_min test, so almost always some lane
         // contributes: accumulate unconditionally (zero weights add nothing)
@@ -155,10 +160,11 @@ __device__ __forceinline__ void render_tile(
     if (!inside[k]) continue;
     const int py = py0 + 4 * k;
     long long pix = pix_base + (long long)py * cam.W + px;
-    out_rgb[3 * pix] = (float)fma((double)T[k], (double)th.bg[0], C[k][0]);
-    out_rgb[3 * pix + 1] = (float)fma((double)T[k], (double)th.bg[1], C[k][1]);
-    out_rgb[3 * pix + 2] = (float)fma((double)T[k], (double)th.bg[2], C[k][2]);
-    if (out_T) out_T[pix] = T[k];
+    const float Tf = fabsf(T[k]);
+    out_rgb[3 * pix] = (float)fma((double)Tf, (double)th.bg[0], C[k][0]);
+    out_rgb[3 * pix + 1] = (float)fma((double)Tf, (double)th.bg[1], C[k][1]);
+    out_rgb[3 * pix + 2] = (float)fma((double)Tf, (double)th.bg[2], C[k][2]);
+    if (out_T) out_T[pix] = Tf;
     if (out_nc) out_nc[pix] = last[k];
     if (NE) out_ne[pix] = nev[k];
   }
@@ -184,10 +190,17 @@ __global__ void __launch_bounds__(kRThreads, 4) render_kernel(
 }
 
 // Several cameras of one shutter type and one tile count in one launch
-// (kMultiCams at most, passed by value): block b takes tile b / n of camera
-// b % n in that camera's render order, so the cameras' longest tiles start
+// (kMultiCams at most, passed by value).  Blocks take the cameras' tiles in
+// their render orders, 32 tiles of every camera per run of 32 n blocks (the
+// run's j-th 32 blocks take camera j), so the cameras' longest tiles start
 // together and one camera's tail overlaps the others' work instead of ending
-// a launch of its own.
+// a launch of its own.  Blocks are dealt in order to 32 queues, one per
+// shader engine (XCD b % 8, then engine (b / 8) % 4 in it), and an engine
+// waits for its own queue: with 32 blocks per camera in a row every queue
+// holds all cameras alike.  (With block b on camera b % n each XCD rendered
+// one camera, and the XCDs of a fisheye view finished a tenth after those of
+// a pinhole view; with the camera changing every 8 blocks whole engines
+// idled behind the queues of the longer view.)
 constexpr int kMultiCams = 4;
 struct MultiCams {
   DevCam cam[kMultiCams];
@@ -207,7 +220,16 @@ __global__ void __launch_bounds__(kRThreads, 4) render_multi_kernel(
   __shared__ TileFrameD F;
   __shared__ WaveBoxes wb;
   __shared__ float red[6];
-  const int c = (int)(blockIdx.x % (unsigned)mc.n), k = (int)(blockIdx.x / (unsigned)mc.n);
+  const unsigned nc = (unsigned)mc.n, T = (unsigned)(mc.cam[0].tiles_x * mc.cam[0].tiles_y);
+  const unsigned g = blockIdx.x / (32u * nc), r = blockIdx.x % (32u * nc);
+  unsigned c, k;
+  if (32u * g + 32u <= T) {
+    c = r >> 5;
+    k = 32u * g + (r & 31u);
+  } else {  // the last, partial run
+    c = r % nc;
+    k = 32u * g + r / nc;
+  }
   const DevCam& cam = mc.cam[c];
   const int tile = (int)order[cam.tile_base + k];
   render_tile<RS, NE, GEN, CLIP>(cam, th, n, mc.idx[c], tile, ranges, ids, record, rgb, clip, out_rgb,

@@ -262,38 +262,91 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
 // dL/dalpha there.  The geometric factors a blend needs -- the closest-point
 // vector p and rho = alpha_raw / sigma -- are formed when the hit enters the
 // buffer (its pair is then in LDS) and travel with it; rho carries the sign
-// of the alpha_max clamp.  Each step's blended values go to FP64 atomics,
-// summed across the wave per particle first (kbuf_add_wave).  The buffer alone takes 128 registers a lane; the kernel asks for two waves per
-// SIMD all the same (part of it then lives in scratch), since the replay
-// waits on memory far more than it computes and one wave per SIMD leaves the
-// SIMD idle (this halves the kernel's time).
+// of the alpha_max clamp.  The buffer alone takes 128 registers a lane; the
+// kernel asks for two waves per SIMD all the same (part of it then lives in
+// scratch), since the replay waits on memory far more than it computes and
+// one wave per SIMD leaves the SIMD idle.
+//
+// Sums.  A lane blends the nearest hit of its own buffer, so the hits one
+// step blends are mostly different particles across the wave (about seven
+// per step on a 1M-particle view), and summing them across the wave one
+// particle at a time cost more than the rest of the kernel.  Instead every
+// blended value goes to an FP32 LDS row of its hit's list position, with LDS
+// atomics, over a window of the two latest batches (positions [b - 256,
+// b + 256) while batch b runs).  A row is added to the FP64 per-particle sums
+// when its batch leaves the window, 13 atomics per (tile, particle).  The
+// buffer holds list positions; a hit that has stayed longer than the window
+// (a buffer usually turns over within a batch) adds its values to the FP64
+// sums itself.
 constexpr int kKBufB = 16;
 constexpr int kKThreadsB = 256;
+constexpr int kWin = 2 * kKThreadsB;  // list positions with an LDS row
+constexpr int kRow = kAcc + 3;        // values per row (13: an odd stride spreads rows over the banks)
 
 struct KBufGrad {
   double* acc;
   double* acc_rgb;
   const float* rgb;
+  const uint32_t* lids;  // the tile's sorted entry ids
+  const uint32_t* pew;   // entry ids of the window's positions (LDS)
+  float* accw;           // the window's rows (LDS)
   int n, cam_idx;
   float t_min;
+  uint32_t wlo;  // lowest list position in the window
 };
 
-// One blend of the replay (Eq. 5 with the t_min stop, as kbuf_blend) and the
-// hit's 13 gradient values: G (6), h (3), dL/dsigma, then dL/dc (3).
-// Returns false (values zero) for a sentinel, a wall, a stopped pixel or a
-// hit that would cross t_min.
-__device__ __forceinline__ bool kbuf_blend_bwd(float a, uint32_t e, float px_, float py_, float pz_,
+__device__ __forceinline__ uint32_t kbuf_entry(uint32_t pos, const KBufGrad& K) {
+  return pos >= K.wlo ? K.pew[pos & (kWin - 1)] : K.lids[pos];
+}
+
+// Adds one lane's blended values (hit at list position pos, entry e) to the
+// sums: its LDS row inside the window, else the FP64 sums.
+__device__ __forceinline__ void kbuf_add(uint32_t pos, uint32_t e, const float (&v)[kRow],
+                                         const KBufGrad& K) {
+  if (pos >= K.wlo) {
+    float* row = K.accw + (pos & (kWin - 1)) * kRow;
+#pragma unroll
+    for (int k = 0; k < kRow; k++) atomicAdd(&row[k], v[k]);
+  } else {
+    const long long i = (long long)(e - (uint32_t)K.cam_idx * (uint32_t)K.n);
+#pragma unroll
+    for (int k = 0; k < kAcc; k++) atomicAdd(&K.acc[i * kAcc + k], (double)v[k]);
+#pragma unroll
+    for (int k = 0; k < 3; k++) atomicAdd(&K.acc_rgb[3 * (long long)e + k], (double)v[kAcc + k]);
+  }
+}
+
+// Adds row r of the window to the FP64 sums of its entry and clears it.
+__device__ __forceinline__ void kbuf_flush_row(int r, const KBufGrad& K) {
+  float* row = K.accw + r * kRow;
+  const uint32_t e = K.pew[r];
+  const long long i = (long long)(e - (uint32_t)K.cam_idx * (uint32_t)K.n);
+#pragma unroll
+  for (int k = 0; k < kRow; k++) {
+    const float x = row[k];
+    if (x != 0.0f) {
+      if (k < kAcc) atomicAdd(&K.acc[i * kAcc + k], (double)x);
+      else atomicAdd(&K.acc_rgb[3 * (long long)e + (k - kAcc)], (double)x);
+      row[k] = 0.0f;
+    }
+  }
+}
+
+// One blend of the replay (Eq. 5 with the t_min stop, as kbuf_blend) of the
+// hit at list position pos, and its 13 gradient values into the sums: G (6),
+// h (3), dL/dsigma, then dL/dc (3).  Nothing for a sentinel, a wall, a
+// stopped pixel or a hit that would cross t_min.
+__device__ __forceinline__ void kbuf_blend_bwd(float a, uint32_t pos, float px_, float py_, float pz_,
                                                float rho, float fg, const KBufGrad& K, const float (&gC)[3],
                                                const double (&gCd)[3], float gTT, float& T, double& Z,
-                                               uint32_t& done, float (&v)[16]) {
-#pragma unroll
-  for (int k = 0; k < 16; k++) v[k] = 0.0f;
-  if (a <= 0.0f || done) return false;
+                                               uint32_t& done) {
+  if (a <= 0.0f || done) return;
   const float Tb = T;
   const float Tn = fmaf(-a, Tb, Tb);
-  if (Tn < K.t_min) { done = 1u; return false; }
+  if (Tn < K.t_min) { done = 1u; return; }
   T = Tn;
   const float wgt = a * Tb;
+  const uint32_t e = kbuf_entry(pos, K);
   const double c0 = K.rgb[3 * (size_t)e], c1 = K.rgb[3 * (size_t)e + 1], c2 = K.rgb[3 * (size_t)e + 2];
   const double D = fma(gCd[0], c0, fma(gCd[1], c1, gCd[2] * c2));
   Z = fma(-(double)wgt, D, Z);
@@ -301,43 +354,13 @@ __device__ __forceinline__ bool kbuf_blend_bwd(float a, uint32_t e, float px_, f
   float gA = fmaf(Tb, (float)D, -inv1m * ((float)Z + gTT));
   if (rho < 0.0f) gA = 0.0f;  // alpha = alpha_max carries no gradient
   const float c = -a * gA * fg;  // 2 dL/domega^2 (fg: a degree-n response's chain factor, else 1)
+  float v[kRow];
   v[0] = c * px_ * px_; v[1] = c * px_ * py_; v[2] = c * px_ * pz_;
   v[3] = c * py_ * py_; v[4] = c * py_ * pz_; v[5] = c * pz_ * pz_;
   v[6] = c * px_; v[7] = c * py_; v[8] = c * pz_;
   v[9] = gA * fabsf(rho);
   v[10] = wgt * gC[0]; v[11] = wgt * gC[1]; v[12] = wgt * gC[2];
-  return true;
-}
-
-// Adds the wave's blended values to the per-particle sums.  Lanes that
-// blended the same entry in this step (neighbouring pixels usually blend the
-// same particle together) are summed across the wave first, one entry at a
-// time, so each distinct entry costs 13 atomics instead of 13 per lane.
-// Called by the whole wave.
-__device__ __forceinline__ void kbuf_add_wave(bool valid, uint32_t e, const float (&v)[16],
-                                              const KBufGrad& K) {
-  const int lane = threadIdx.x & 63;
-  uint32_t key = valid ? e : 0xffffffffu;
-  while (true) {
-    const unsigned long long m = __builtin_amdgcn_ballot_w64(key != 0xffffffffu);
-    if (!m) break;
-    const uint32_t e0 = (uint32_t)__builtin_amdgcn_readlane((int)key, (int)__builtin_ctzll(m));
-    const bool mine = key == e0;
-    float g[16];
-#pragma unroll
-    for (int k = 0; k < 16; k++) g[k] = mine ? v[k] : 0.0f;
-    const float tot = wave_reduce16(g);  // lane 4k holds value k
-    const int k = lane >> 2;
-    if ((lane & 3) == 0 && k < kAcc + 3 && tot != 0.0f) {
-      if (k < kAcc) {
-        const int i = (int)(e0 - (uint32_t)K.cam_idx * (uint32_t)K.n);
-        atomicAdd(&K.acc[(long long)i * kAcc + k], (double)tot);
-      } else {
-        atomicAdd(&K.acc_rgb[3 * (long long)e0 + (k - kAcc)], (double)tot);
-      }
-    }
-    if (mine) key = 0xffffffffu;
-  }
+  kbuf_add(pos, e, v, K);
 }
 
 template <bool RS, bool GEN, bool CLIP>
@@ -351,7 +374,8 @@ __global__ void __launch_bounds__(kKThreadsB, 2) render_kbuffer_bwd_kernel(
   constexpr int S = Slots<RS, true>::N;
   __shared__ float4 pd[kKThreadsB * S];
   __shared__ uint32_t pf[kKThreadsB];
-  __shared__ uint32_t pe[kKThreadsB];
+  __shared__ uint32_t pew[kWin];
+  __shared__ float accw[kWin * kRow];
   __shared__ TileFrameD F;
   __shared__ WaveBoxes wb;
   __shared__ float red[12];
@@ -361,6 +385,7 @@ __global__ void __launch_bounds__(kKThreadsB, 2) render_kbuffer_bwd_kernel(
   const int px = tx * kTile + (lane & (kTile - 1));
   const int py = ty * kTile + 4 * wv + (lane >> 4);
   if (t == 0) tile_frame(cam, tx, ty, &F);
+  for (int i = t; i < kWin * kRow; i += kKThreadsB) accw[i] = 0.0f;
   __syncthreads();
   const bool inside = px < cam.W && py < cam.H;
   float u = 0.f, v = 0.f, dt = 0.f;
@@ -388,12 +413,12 @@ __global__ void __launch_bounds__(kKThreadsB, 2) render_kbuffer_bwd_kernel(
       Z = fma(gCd[c], (double)out_rgb[3 * pix + c], Z);
     }
   }
-  const KBufGrad K = {acc, acc_rgb, rgb, n, cam_idx, th.t_min};
-
   const uint2 rg = ranges[cam.tile_base + tile];
   const uint32_t len = __builtin_amdgcn_readfirstlane(rg.y - rg.x);
+  KBufGrad K = {acc, acc_rgb, rgb, ids + rg.x, pew, accw, n, cam_idx, th.t_min, 0u};
+
   float bd[kKBufB], ba[kKBufB], bx[kKBufB], by[kKBufB], bz[kKBufB], br[kKBufB], bf[kKBufB];
-  uint32_t bi[kKBufB];
+  uint32_t bi[kKBufB];  // list positions
 #pragma unroll
   for (int j = 0; j < kKBufB; j++) {
     bd[j] = j < kcap ? -INFINITY : INFINITY;
@@ -404,10 +429,15 @@ __global__ void __launch_bounds__(kKThreadsB, 2) render_kbuffer_bwd_kernel(
   uint32_t done = active ? 0u : 1u;  // a 0/1 vector register, as in render_tile
   for (uint32_t b = 0; b < len; b += kKThreadsB) {
     if (__syncthreads_count(done == 0u) == 0) break;
+    const int half = (int)(b & (uint32_t)kKThreadsB);  // this batch's rows: b mod kWin
+    // the rows of batch b - kWin leave the window (their batch's eval ended
+    // before the barrier above)
+    if (b >= (uint32_t)kWin) kbuf_flush_row(half + t, K);
+    K.wlo = b >= (uint32_t)kKThreadsB ? b - kKThreadsB : 0u;
     uint32_t fl = 0u;
     if (b + t < len) {
       const uint32_t e = ids[rg.x + b + t];
-      pe[t] = e;
+      pew[half + t] = e;
       fl = pair_setup<RS, true, GEN, CLIP>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n),
                                            F, cam, umax, vmax, dtmax, th, l2amin, wb, kKThreadsB / 64,
                                            &pd[t * S]);
@@ -430,11 +460,6 @@ __global__ void __launch_bounds__(kKThreadsB, 2) render_kbuffer_bwd_kernel(
         const bool live = ev.ok && done == 0u;
         if (!wave_any(live)) continue;
         eval_alpha<RS, GEN>(r, th, &ev);
-        bool valid = false;
-        uint32_t be = 0u;
-        float vals[16];
-#pragma unroll
-        for (int k = 0; k < 16; k++) vals[k] = 0.0f;
         if (live) {
           float odg;
           if (!RS) {
@@ -445,7 +470,7 @@ __global__ void __launch_bounds__(kKThreadsB, 2) render_kbuffer_bwd_kernel(
             odg = fmaf(dt, fmaf(v, r.p9.w, fmaf(u, r.p8.w, r.p7.w)), odg);
           }
           const float dist = -odg * dlen * ev.idd;
-          const uint32_t e = pe[q];
+          const uint32_t pos = b + q;  // the hit's list position
           // the closest point p = d_g x (o_g x d_g) / |d_g|^2 and rho, as in render_bwd_kernel
           float3 dg, cr;
           pair_vectors<RS>(P, ev, u, v, &dg, &cr);
@@ -456,18 +481,15 @@ __global__ void __launch_bounds__(kKThreadsB, 2) render_kbuffer_bwd_kernel(
           // degree n: d alpha / d omega^2 relative to the Gaussian's (as in render_bwd_kernel)
           const float fg = GEN ? __builtin_amdgcn_exp2f(fmaf(th.k_h - 1.0f, ev.lq, th.k_f)) : 1.0f;
           if (dist <= bd[0]) {
-            valid = kbuf_blend_bwd(ev.a, e, pv.x, pv.y, pv.z, rho, fg, K, gC, gCd, gTT, T, Z, done, vals);
-            be = e;
+            kbuf_blend_bwd(ev.a, pos, pv.x, pv.y, pv.z, rho, fg, K, gC, gCd, gTT, T, Z, done);
           } else {
-            valid = kbuf_blend_bwd(ba[0], bi[0], bx[0], by[0], bz[0], br[0], bf[0], K, gC, gCd, gTT, T, Z,
-                                   done, vals);
-            be = bi[0];
+            kbuf_blend_bwd(ba[0], bi[0], bx[0], by[0], bz[0], br[0], bf[0], K, gC, gCd, gTT, T, Z, done);
 #pragma unroll
             for (int j = 0; j < kKBufB - 1; j++) {
               const bool nx = bd[j + 1] < dist, here = j == 0 || bd[j] < dist;
               bd[j] = nx ? bd[j + 1] : (here ? dist : bd[j]);
               ba[j] = nx ? ba[j + 1] : (here ? ev.a : ba[j]);
-              bi[j] = nx ? bi[j + 1] : (here ? e : bi[j]);
+              bi[j] = nx ? bi[j + 1] : (here ? pos : bi[j]);
               bx[j] = nx ? bx[j + 1] : (here ? pv.x : bx[j]);
               by[j] = nx ? by[j + 1] : (here ? pv.y : by[j]);
               bz[j] = nx ? bz[j + 1] : (here ? pv.z : bz[j]);
@@ -477,7 +499,7 @@ __global__ void __launch_bounds__(kKThreadsB, 2) render_kbuffer_bwd_kernel(
             const int L = kKBufB - 1;
             const bool last = bd[L] < dist;
             ba[L] = last ? ev.a : ba[L];
-            bi[L] = last ? e : bi[L];
+            bi[L] = last ? pos : bi[L];
             bx[L] = last ? pv.x : bx[L];
             by[L] = last ? pv.y : by[L];
             bz[L] = last ? pv.z : bz[L];
@@ -486,17 +508,15 @@ __global__ void __launch_bounds__(kKThreadsB, 2) render_kbuffer_bwd_kernel(
             bd[L] = last ? dist : bd[L];
           }
         }
-        kbuf_add_wave(valid, be, vals, K);  // the whole wave, after the divergent part
       }
     }
   }
 #pragma unroll
-  for (int j = 0; j < kKBufB; j++) {
-    float vals[16];
-    const bool valid = kbuf_blend_bwd(ba[j], bi[j], bx[j], by[j], bz[j], br[j], bf[j], K, gC, gCd, gTT,
-                                      T, Z, done, vals);
-    kbuf_add_wave(valid, bi[j], vals, K);
-  }
+  for (int j = 0; j < kKBufB; j++)
+    kbuf_blend_bwd(ba[j], bi[j], bx[j], by[j], bz[j], br[j], bf[j], K, gC, gCd, gTT, T, Z, done);
+  __syncthreads();
+  kbuf_flush_row(t, K);
+  kbuf_flush_row(t + kKThreadsB, K);
 }
 
 // K7a: camera-independent part of the per-particle chain (FP64: the

@@ -102,6 +102,10 @@ constexpr double kHalfLog2e = 0.72134752044448170368;
 // Kp = log2(sigma / alpha_min) (-1: never contributes), so that
 //   alpha = min(2^(lsig - omega'^2), alpha_max),  alpha >= alpha_min <=> omega'^2 <= Kp
 // with omega'^2 = omega^2 log2(e) / 2.
+// Bit of pair_setup's result set when the sign of o_g . d_g varies over the
+// tile (the per-pixel tau_max > 0 test is needed); the low bits are per wave.
+constexpr unsigned kMixedBit = 1u << 8;
+
 template <bool RS, bool BWD>
 struct Slots {
   static constexpr int N = RS ? 11 : (BWD ? 12 : 7);
@@ -254,6 +258,7 @@ __device__ inline unsigned pair_setup(const float4* __restrict__ record,
     for (int k = 0; k < nwaves; k++)
       if (lb > (double)wb.cmax[k] * (1.0 + 1e-4)) flags &= ~(1u << k);
   }
+  if (mixed && flags) flags |= kMixedBit;
   const float* c = rgb + 3 * e;
   const float mflag = mixed ? -1.0f : 1.0f;
   if (!RS) {
