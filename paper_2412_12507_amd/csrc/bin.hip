@@ -823,11 +823,15 @@ constexpr uint32_t kBucketMax = 64;
 // claimed with word atomics that add 1 to one half, which halves their LDS.
 template <int NT, int ROWS, int DBM, bool P16 = false>
 struct BlockSortSmem {
-  unsigned long long keys[NT * ROWS];
+  union {
+    unsigned long long keys[NT * ROWS];
+    struct {
+      uint32_t wsum[NT / 64];
+      uint32_t wmax[NT / 64];
+      unsigned long long wor[NT / 64];
+    } w;  // the waves' partials, read only before the keys move in
+  };
   uint32_t cnt[P16 ? (1 << DBM) / 2 : (1 << DBM)];
-  uint32_t wsum[NT / 64];
-  uint32_t wmax[NT / 64];
-  unsigned long long wor[NT / 64];
 };
 
 template <bool P16>
@@ -875,13 +879,13 @@ __device__ __forceinline__ bool block_bucket_sort(const unsigned long long* __re
 #pragma unroll
   for (int r = 0; r < ROWS; r++) orv |= ok[r] ? kk[r] ^ k0 : 0ull;
   for (int o = 32; o > 0; o >>= 1) orv |= __shfl_xor(orv, o, 64);
-  if (W > 1 && lane == 0) S.wor[w] = orv;
+  if (W > 1 && lane == 0) S.w.wor[w] = orv;
   for (uint32_t i = t; i < (P16 ? (nb + 1) / 2 : nb); i += NT) S.cnt[i] = 0u;
   __syncthreads();
   if (W > 1) {
     orv = 0;
 #pragma unroll
-    for (int k = 0; k < W; k++) orv |= S.wor[k];
+    for (int k = 0; k < W; k++) orv |= S.w.wor[k];
   }
   const int hb = orv ? 63 - __clzll((long long)orv) : 0;
   const int shift = hb >= db - 1 ? hb - (db - 1) : 0;
@@ -911,13 +915,13 @@ __device__ __forceinline__ bool block_bucket_sort(const unsigned long long* __re
   for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
   uint32_t run = x - tot;
   if (W > 1) {
-    if (lane == 63) S.wsum[w] = x;
-    if (lane == 0) S.wmax[w] = mx;
+    if (lane == 63) S.w.wsum[w] = x;
+    if (lane == 0) S.w.wmax[w] = mx;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < W; k++) {
-      if (k < w) run += S.wsum[k];
-      mx = max(mx, S.wmax[k]);
+      if (k < w) run += S.w.wsum[k];
+      mx = max(mx, S.w.wmax[k]);
     }
   }
   if (mx > bucket_max) {
@@ -987,8 +991,9 @@ __device__ __forceinline__ bool block_bucket_sort(const unsigned long long* __re
 // K5 for lists of 1 to 1023 entries, one wave per tile, in two launches by
 // length (the LDS a wave holds, and so how many waves fit a CU, follows the
 // longest list of the launch): ROWS_MAX 4 takes lists below 256 entries,
-// ROWS_MAX 16 the others.  A list whose largest bucket is too large goes on
-// the list for tile_sort_fallback_kernel.
+// ROWS_MAX 16 the others (with 16-bit counters: 12 KB of LDS a wave instead
+// of 16, so 13 waves fit a CU instead of 10).  A list whose largest bucket
+// is too large goes on the list for tile_sort_fallback_kernel.
 template <int ROWS_MAX>
 __global__ void __launch_bounds__(64) tile_sort_small_kernel(const uint2* __restrict__ ranges,
                                                             const unsigned long long* __restrict__ keys,
@@ -997,7 +1002,7 @@ __global__ void __launch_bounds__(64) tile_sort_small_kernel(const uint2* __rest
                                                             unsigned long long cap, uint32_t* __restrict__ nfall,
                                                             uint32_t* __restrict__ fall) {
   constexpr uint32_t lo = ROWS_MAX == 4 ? 1u : 256u, hi = 64u * ROWS_MAX;
-  __shared__ BlockSortSmem<64, ROWS_MAX, ROWS_MAX == 4 ? 9 : 11> S;
+  __shared__ BlockSortSmem<64, ROWS_MAX, ROWS_MAX == 4 ? 9 : 11, ROWS_MAX == 16> S;
   const unsigned long long P = *P_dev;
   const uint2 r = ranges[blockIdx.x];  // written by K3 whatever P is
   if (P > cap) return;                 // the keys were not written
@@ -1016,7 +1021,7 @@ __global__ void __launch_bounds__(64) tile_sort_small_kernel(const uint2* __rest
   } else if (L <= 512u) {
     done = block_bucket_sort<64, 8, 10, false>(keys + r.x, L, ids + r.x, *(BlockSortSmem<64, 8, 10>*)&S);
   } else {
-    done = block_bucket_sort<64, ROWS_MAX, ROWS_MAX == 4 ? 9 : 11, false>(keys + r.x, L, ids + r.x, S);
+    done = block_bucket_sort<64, ROWS_MAX, ROWS_MAX == 4 ? 9 : 11, ROWS_MAX == 16>(keys + r.x, L, ids + r.x, S);
   }
   if (!done && threadIdx.x == 0) fall[atomicAdd(nfall, 1u)] = blockIdx.x;
 }
@@ -1065,23 +1070,25 @@ __device__ inline uint32_t order_count(int n_cams, const uint32_t* __restrict__ 
 
 // K5 for lists of 1024 to 4095 entries (the positions [nbig, nmid) of each
 // camera's render order): a fixed grid of 256-thread blocks, block b taking
-// the b-th, (b + grid)-th, ... of them, by the bucket sort; a list whose
+// the b-th, (b + grid)-th, ... of them, by the bucket sort (16-bit counters
+// and the waves' partials inside the key array: 40 KB of LDS and 128 VGPRs,
+// four blocks a CU instead of three); a list whose
 // largest bucket holds more than 128 entries goes on the list for
 // tile_sort_fallback_kernel.
 constexpr int kMidThreads = 256, kMidBlocks = 1024;
 constexpr uint32_t kMidBucketMax = 128;
-__global__ void __launch_bounds__(kMidThreads) tile_sort_mid_kernel(
+__global__ void __launch_bounds__(kMidThreads, 4) tile_sort_mid_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ order, CamTiles ct, int n_cams,
     const uint32_t* __restrict__ nbig, const uint32_t* __restrict__ nmid, const unsigned long long* __restrict__ keys,
     uint32_t* __restrict__ ids, const unsigned long long* __restrict__ P_dev, unsigned long long cap,
     uint32_t* __restrict__ nfall, uint32_t* __restrict__ fall) {
-  __shared__ BlockSortSmem<kMidThreads, kTSItems, 12> S;
+  __shared__ BlockSortSmem<kMidThreads, kTSItems, 12, true> S;
   if (*P_dev > cap) return;
   const uint32_t total = order_count(n_cams, nbig, nmid);
   for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
     const uint32_t tile = order_tile(g, order, ct, nbig, nmid);
     const uint2 r = ranges[tile];
-    if (!block_bucket_sort<kMidThreads, kTSItems, 12, false>(keys + r.x, r.y - r.x, ids + r.x, S, kMidBucketMax)) {
+    if (!block_bucket_sort<kMidThreads, kTSItems, 12, true>(keys + r.x, r.y - r.x, ids + r.x, S, kMidBucketMax)) {
       if (threadIdx.x == 0) fall[atomicAdd(nfall, 1u)] = tile;
     }
     __syncthreads();  // the LDS is reused by the next list

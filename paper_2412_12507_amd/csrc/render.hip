@@ -131,12 +131,11 @@ __device__ __forceinline__ void render_tile(
           eval_alpha<RS, GEN>(r, th, &ev[k]);
           const bool live = k ? live1 : live0;
           const float Tn = fmaf(-ev[k].a, T[k], T[k]);  // T (1 - alpha)
-          const bool below = Tn < th.t_min;
-          const bool stop = live & below;  // stop before adding this particle
-          contrib[k] = live & !below;
+          const bool stop = live & (Tn < th.t_min);  // stop before adding this particle
+          contrib[k] = live ^ stop;
           const float ae = contrib[k] ? ev[k].a : 0.0f;
           wgt[k] = ae * T[k];
-          const float Tk = fmaf(-ae, T[k], T[k]);  // Tn, or T itself when not contributing
+          const float Tk = contrib[k] ? Tn : T[k];
           T[k] = stop ? -T[k] : Tk;
           last[k] = contrib[k] ? idx1 : last[k];
           if (NE) nev[k] = stop ? idx1 : nev[k];
@@ -190,17 +189,15 @@ __global__ void __launch_bounds__(kRThreads, 4) render_kernel(
 }
 
 // Several cameras of one shutter type and one tile count in one launch
-// (kMultiCams at most, passed by value).  Blocks take the cameras' tiles in
-// their render orders, 32 tiles of every camera per run of 32 n blocks (the
-// run's j-th 32 blocks take camera j), so the cameras' longest tiles start
+// (kMultiCams at most, passed by value): block b takes tile b / n of camera
+// b % n in that camera's render order, so the cameras' longest tiles start
 // together and one camera's tail overlaps the others' work instead of ending
-// a launch of its own.  Blocks are dealt in order to 32 queues, one per
-// shader engine (XCD b % 8, then engine (b / 8) % 4 in it), and an engine
-// waits for its own queue: with 32 blocks per camera in a row every queue
-// holds all cameras alike.  (With block b on camera b % n each XCD rendered
-// one camera, and the XCDs of a fisheye view finished a tenth after those of
-// a pinhole view; with the camera changing every 8 blocks whole engines
-// idled behind the queues of the longer view.)
+// a launch of its own.  Blocks are dealt to the 8 XCDs round-robin, so with
+// two cameras each XCD renders one of them and its L2 holds that camera's
+// records only.  The XCDs of the heavier view then finish later (a fisheye
+// view's about a tenth after a pinhole view's); dealing 32 tiles of each
+// camera in turn balances the XCDs but mixes the cameras in every L2, and
+// took as long with 18% more memory traffic.
 constexpr int kMultiCams = 4;
 struct MultiCams {
   DevCam cam[kMultiCams];
@@ -220,16 +217,7 @@ __global__ void __launch_bounds__(kRThreads, 4) render_multi_kernel(
   __shared__ TileFrameD F;
   __shared__ WaveBoxes wb;
   __shared__ float red[6];
-  const unsigned nc = (unsigned)mc.n, T = (unsigned)(mc.cam[0].tiles_x * mc.cam[0].tiles_y);
-  const unsigned g = blockIdx.x / (32u * nc), r = blockIdx.x % (32u * nc);
-  unsigned c, k;
-  if (32u * g + 32u <= T) {
-    c = r >> 5;
-    k = 32u * g + (r & 31u);
-  } else {  // the last, partial run
-    c = r % nc;
-    k = 32u * g + r / nc;
-  }
+  const int c = (int)(blockIdx.x % (unsigned)mc.n), k = (int)(blockIdx.x / (unsigned)mc.n);
   const DevCam& cam = mc.cam[c];
   const int tile = (int)order[cam.tile_base + k];
   render_tile<RS, NE, GEN, CLIP>(cam, th, n, mc.idx[c], tile, ranges, ids, record, rgb, clip, out_rgb,
@@ -339,7 +327,9 @@ gut_status render_batch_launch(const DevCam* d_cams, const DevCam* h_cams, int n
 // nothing) and the hit is merged into the remaining sorted slots by a fixed
 // compare-select chain; a hit at or before slot 0 is blended at once.  Blending
 // is Eq. 5 with the t_min stop; at the end of the list the buffer is blended
-// nearest first.  Colours are read by entry id when a hit is blended.
+// nearest first.  The buffer keeps each hit's list position; the colour a
+// blend needs comes from an LDS copy of the two latest batches' colours
+// (a buffer usually turns over within a batch), else through the list.
 constexpr int kKBuf = 16;
 constexpr int kKThreads = 256;
 // Four waves per SIMD (128 VGPRs, some of the buffer in scratch): the walk
@@ -349,16 +339,35 @@ constexpr int kKThreads = 256;
 // insertion by two thirds but takes so much LDS that two waves per SIMD fit,
 // and is slower.)
 
-__device__ __forceinline__ void kbuf_blend(float a, uint32_t e, const float* __restrict__ rgb,
+// Colours of the hits at list positions [wlo, wlo + kKWin) (the two latest
+// batches) are kept in LDS, row pos mod kKWin; an older hit's colour is read
+// through the list.
+constexpr int kKWin = 2 * kKThreads;
+struct KbufColours {
+  const float* cw;         // LDS rows of 3
+  const uint32_t* lids;    // the tile's sorted entry ids
+  const float* rgb;
+  uint32_t wlo;
+};
+
+__device__ __forceinline__ void kbuf_blend(float a, uint32_t pos, const KbufColours& K,
                                            float t_min, float& T, double (&C)[3], uint32_t& nc,
                                            uint32_t& done) {
   if (a <= 0.0f || done) return;  // a sentinel or a wall, or the pixel has stopped
   const float Tn = fmaf(-a, T, T);
   if (Tn < t_min) { done = 1u; return; }
   const double w = (double)(a * T);
-  C[0] = fma(w, (double)rgb[3 * (size_t)e], C[0]);
-  C[1] = fma(w, (double)rgb[3 * (size_t)e + 1], C[1]);
-  C[2] = fma(w, (double)rgb[3 * (size_t)e + 2], C[2]);
+  float c0, c1, c2;
+  if (pos >= K.wlo) {
+    const float* c = K.cw + 3 * (pos & (kKWin - 1));
+    c0 = c[0]; c1 = c[1]; c2 = c[2];
+  } else {
+    const float* c = K.rgb + 3 * (size_t)K.lids[pos];
+    c0 = c[0]; c1 = c[1]; c2 = c[2];
+  }
+  C[0] = fma(w, (double)c0, C[0]);
+  C[1] = fma(w, (double)c1, C[1]);
+  C[2] = fma(w, (double)c2, C[2]);
   T = Tn;
   nc++;
 }
@@ -373,7 +382,7 @@ __global__ void __launch_bounds__(kKThreads, 4) render_kbuffer_kernel(
   constexpr int S = Slots<RS, false>::N;
   __shared__ float4 pd[kKThreads * S];
   __shared__ uint32_t pf[kKThreads];
-  __shared__ uint32_t pe[kKThreads];
+  __shared__ float cw[kKWin * 3];
   __shared__ TileFrameD F;
   __shared__ WaveBoxes wb;
   __shared__ float red[12];
@@ -412,12 +421,15 @@ __global__ void __launch_bounds__(kKThreads, 4) render_kbuffer_kernel(
   double C[3] = {0.0, 0.0, 0.0};
   uint32_t nc = 0u, nev = active ? len : 0u;
   uint32_t done = active ? 0u : 1u;  // a 0/1 vector register, as in render_tile
+  KbufColours K = {cw, ids + rg.x, rgb, 0u};
   for (uint32_t b = 0; b < len; b += kKThreads) {
     if (__syncthreads_count(done == 0u) == 0) break;  // (also publishes wb before the first setup)
+    K.wlo = b >= (uint32_t)kKThreads ? b - kKThreads : 0u;
     uint32_t fl = 0u;
     if (b + t < len) {
       const uint32_t e = ids[rg.x + b + t];
-      pe[t] = e;
+      float* c = cw + 3 * ((b + t) & (kKWin - 1));
+      c[0] = rgb[3 * (size_t)e]; c[1] = rgb[3 * (size_t)e + 1]; c[2] = rgb[3 * (size_t)e + 2];
       fl = pair_setup<RS, false, GEN, CLIP>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n),
                                             F, cam, umax, vmax, dtmax, th, l2amin, wb, kKThreads / 64,
                                             &pd[t * S]);
@@ -451,12 +463,12 @@ __global__ void __launch_bounds__(kKThreads, 4) render_kbuffer_kernel(
             odg = fmaf(dt, fmaf(v, r.p9.w, fmaf(u, r.p8.w, r.p7.w)), odg);
           }
           const float dist = -odg * dlen * ev.idd;
-          const uint32_t e = pe[q];
+          const uint32_t e = b + q;  // the hit's list position
           const uint32_t idx1 = b + q + 1;
           if (dist <= bd[0]) {
-            kbuf_blend(ev.a, e, rgb, th.t_min, T, C, nc, done);
+            kbuf_blend(ev.a, e, K, th.t_min, T, C, nc, done);
           } else {
-            kbuf_blend(ba[0], bi[0], rgb, th.t_min, T, C, nc, done);
+            kbuf_blend(ba[0], bi[0], K, th.t_min, T, C, nc, done);
             // merge the hit into slots 1 .. kKBuf-1 (sorted), dropping slot 0
 #pragma unroll
             for (int j = 0; j < kKBuf - 1; j++) {
@@ -478,7 +490,7 @@ __global__ void __launch_bounds__(kKThreads, 4) render_kbuffer_kernel(
   }
   // the buffer, nearest first
 #pragma unroll
-  for (int j = 0; j < kKBuf; j++) kbuf_blend(ba[j], bi[j], rgb, th.t_min, T, C, nc, done);
+  for (int j = 0; j < kKBuf; j++) kbuf_blend(ba[j], bi[j], K, th.t_min, T, C, nc, done);
   if (!inside) return;
   const long long pix = cam.pixel_base + (long long)py * cam.W + px;
   out_rgb[3 * pix] = (float)fma((double)T, (double)th.bg[0], C[0]);
