@@ -15,10 +15,11 @@
 // pixels have stopped, and the block stops when no pixel is still going.
 // Blocks take tiles in the render order from gut_bin (longest lists first)
 // and waves of long lists raise their issue priority, so the longest tiles
-// neither start last nor crawl behind short ones.  The kernels run four waves
-// per SIMD (124 VGPRs).  Five (96 VGPRs) are 4% faster, but the FP64 pair
-// setup then keeps 27 values in scratch, whose spills and reloads add about
-// 450 MB of memory traffic per two-view launch to the 620 MB it moves.
+// neither start last nor crawl behind short ones.  The compositing kernels
+// run five waves per SIMD (96 VGPRs; the FP64 pair setup keeps 12 values in
+// scratch): 8% faster than four waves without spills (114 VGPRs).  The walk
+// is a chain of dependent LDS reads, compares and transcendentals, and a
+// fifth wave hides more of it than the setup's spills cost.
 #include "tile_eval.h"
 
 namespace gut {
@@ -58,7 +59,15 @@ __device__ __forceinline__ void render_tile(
   }
   float umax, vmax, dtmax;
   tile_bounds<2>(u, v, dt, active, red, &umax, &vmax, &dtmax);
-  const float l2amin = log2f(th.alpha_min);
+  // The pair setup reads the tile's bounds from LDS at each batch (published
+  // by the batch's first barrier): kept in registers across the walk, they
+  // were among the values the setup spilled at five waves per SIMD.
+  if (t == 0) {
+    F.umax = umax;
+    F.vmax = vmax;
+    F.dtmax = dtmax;
+    F.l2amin = log2f(th.alpha_min);
+  }
   wave_box<2>(u, v, active, &wb);
   float clipv[2] = {0.f, 0.f}, dlen[2] = {1.f, 1.f};
   if (CLIP) {
@@ -93,7 +102,8 @@ __device__ __forceinline__ void render_tile(
     if (b + t < len) {
       uint32_t e = ids[rg.x + b + t];
       fl = pair_setup<RS, false, GEN, CLIP>(record, rgb, e, (int)(e - (uint32_t)cam_idx * (uint32_t)n), F,
-                                      cam, umax, vmax, dtmax, th, l2amin, wb, kRThreads / 64, &pd[t * S]);
+                                      cam, F.umax, F.vmax, F.dtmax, th, F.l2amin, wb, kRThreads / 64,
+                                      &pd[t * S]);
     }
     pf[t] = fl;
     __syncthreads();
@@ -172,7 +182,7 @@ __device__ __forceinline__ void render_tile(
 // One block per tile, taken in the render order (longest lists first).  NE:
 // also count each pixel's evaluated entries (out_ne non-null).
 template <bool RS, bool NE, bool GEN, bool CLIP>
-__global__ void __launch_bounds__(kRThreads, 4) render_kernel(
+__global__ void __launch_bounds__(kRThreads, 5) render_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
     const float4* __restrict__ record, const float* __restrict__ rgb, const float* __restrict__ clip,
@@ -206,7 +216,7 @@ struct MultiCams {
 };
 
 template <bool RS, bool NE, bool GEN, bool CLIP>
-__global__ void __launch_bounds__(kRThreads, 4) render_multi_kernel(
+__global__ void __launch_bounds__(kRThreads, 5) render_multi_kernel(
     MultiCams mc, Thresholds th, int n, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
     const float4* __restrict__ record, const float* __restrict__ rgb, const float* __restrict__ clip,

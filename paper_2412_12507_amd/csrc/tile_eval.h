@@ -29,6 +29,7 @@ namespace gut {
 // FP64 tile frame kept in LDS: origin, anchor direction, tangent basis, time.
 struct TileFrameD {
   double o[3], n[3], e1[3], e2[3], tT;
+  float umax, vmax, dtmax, l2amin;  // compositing: the tile's |u|, |v|, |dt| bounds and log2(alpha_min)
 };
 
 __device__ inline void tile_frame(const DevCam& cam, int tx, int ty, TileFrameD* F) {
@@ -111,17 +112,26 @@ struct Slots {
   static constexpr int N = RS ? 11 : (BWD ? 12 : 7);
 };
 
+// 1 / sqrt(x) for a normal x > 0: the hardware estimate (relative error
+// below 2^-22) and one Newton step, ~1e-13 relative: the factorisation below
+// needs ~1e-7.
+__device__ __forceinline__ double rsq64(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  return fma(0.5 * r, fma(-x * r, r, 1.0), r);
+}
+
 // QR of the affine map (u, v) -> c0 + u c1 + v c2 (FP64 Gram-Schmidt; one
 // pass keeps the form to ~1e-7 of the alpha_min decision scale, below the
 // FP32 rounding the coefficients then take): |c0 + u c1 + v c2|^2 =
 // (q[0] + q[1] u + q[2] v)^2 + (q[3] + q[4] v)^2 + q[5].
 __device__ inline void affine_qr(d3 c0, d3 c1, d3 c2, double q[6]) {
-  const double n11 = dot(c1, c1), i11 = n11 > 0.0 ? rsqrt(n11) : 0.0;
+  // (a norm below 1e-300 counts as zero: the estimate is not made for denormals)
+  const double n11 = dot(c1, c1), i11 = n11 > 1e-300 ? rsq64(n11) : 0.0;
   const double r11 = n11 * i11;
   const d3 a1 = scl(c1, i11);
   const double r12 = dot(c2, a1);
   const d3 b = axpy(-r12, a1, c2);
-  const double n22 = dot(b, b), i22 = n22 > 0.0 ? rsqrt(n22) : 0.0;
+  const double n22 = dot(b, b), i22 = n22 > 1e-300 ? rsq64(n22) : 0.0;
   const double r22 = n22 * i22;
   const d3 a2 = scl(b, i22);
   const double f1 = dot(c0, a1), f2 = dot(c0, a2);
@@ -197,6 +207,7 @@ __device__ inline unsigned pair_setup(const float4* __restrict__ record,
     spread = fma(dtmax, fma(umax, fabs(ta2), fma(vmax, fabs(tb2), fabs(s2))), spread);
     mlen = sqrt(dot(m, m));
   }
+  const double oo = dot(og, og);
   const float sigma = r0.w;
   bool never = false, mixed = false;
   if (s + spread < 0.0) {
@@ -210,30 +221,71 @@ __device__ inline unsigned pair_setup(const float4* __restrict__ record,
   float Kp = (!never && sigma >= amin) ? lsig - log2_amin : -1.0f;
   // degree n: 2^(k_h log2 q + k_l) <= Kp  <=>  q <= 2^((log2 Kp - k_l) / k_h)
   if (GEN && Kp > 0.0f) Kp = exp2f((log2f(Kp) - th.k_l) * th.k_inv_h);
+  const float mflag = mixed ? -1.0f : 1.0f;
+  // the per-pixel test uses this FP32 Kp; cull with it in natural units
+  double Kc = (double)Kp / kHalfLog2e * (1.0 + 1e-3) + 1e-5;
+  if (RS) {
+    const double r = sqrt(Kc) + dtmax * mlen * (1.0 + 1e-6);
+    Kc = r * r;
+  }
+  // The culling ellipse's matrix N (below).  Without a rolling shutter the
+  // slots' factorised forms are made first and N is read off them, so that
+  // the FP64 vectors are dead before the culling: from
+  // |c0 + u c1 + v c2|^2 = (q0 + q1 u + q2 v)^2 + (q3 + q4 v)^2 + q5,
+  // |c0|^2 = q0^2 + q3^2 + q5, c0.c1 = q0 q1, c0.c2 = q0 q2 + q3 q4,
+  // |c1|^2 = q1^2, c1.c2 = q1 q2, |c2|^2 = q2^2 + q4^2.  qc carries the
+  // factor log2(e)/2, so N comes scaled by it, which leaves the ellipse.
+  double N00 = 0.0, N01 = 0.0, N02 = 0.0, N11 = 0.0, N12 = 0.0, N22 = 0.0;
+  if (!RS) {
+    double qc[6], qd[6];
+    const double sc = sqrt(kHalfLog2e);
+    affine_qr(scl(w, sc), scl(A, sc), scl(B, sc), qc);
+    affine_qr(dn, da, db, qd);
+    out[0] = make_float4((float)qc[0], (float)qc[1], (float)qc[2], Kp);
+    out[1] = make_float4((float)qc[3], (float)qc[4], (float)qc[5], lsig);
+    out[2] = make_float4((float)qd[0], (float)qd[1], (float)qd[2], mflag);
+    out[3] = make_float4((float)qd[3], (float)qd[4], (float)qd[5], 0.0f);
+    out[5] = make_float4((float)s, (float)ta, (float)tb, 0.0f);
+    if (BWD) {
+      out[7] = make_float4((float)dn.x, (float)dn.y, (float)dn.z, (float)w.x);
+      out[8] = make_float4((float)da.x, (float)da.y, (float)da.z, (float)w.y);
+      out[9] = make_float4((float)db.x, (float)db.y, (float)db.z, (float)w.z);
+      out[10] = make_float4((float)A.x, (float)A.y, (float)A.z, (float)B.x);
+      out[11] = make_float4((float)B.y, (float)B.z, 0.0f, 0.0f);
+    }
+    const double K2 = Kc * kHalfLog2e;
+    N00 = fma(-K2, fma(qd[0], qd[0], fma(qd[3], qd[3], qd[5])), fma(qc[0], qc[0], fma(qc[3], qc[3], qc[5])));
+    N01 = fma(-K2, qd[0] * qd[1], qc[0] * qc[1]);
+    N02 = fma(-K2, fma(qd[0], qd[2], qd[3] * qd[4]), fma(qc[0], qc[2], qc[3] * qc[4]));
+    N11 = fma(-K2, qd[1] * qd[1], qc[1] * qc[1]);
+    N12 = fma(-K2, qd[1] * qd[2], qc[1] * qc[2]);
+    N22 = fma(-K2, fma(qd[2], qd[2], qd[4] * qd[4]), fma(qc[2], qc[2], qc[4] * qc[4]));
+  }
   unsigned flags = 0;
   if (Kp >= 0.0f) {
-    // the per-pixel test uses this FP32 Kp; cull with it in natural units
-    double Kc = (double)Kp / kHalfLog2e * (1.0 + 1e-3) + 1e-5;
-    if (RS) {
-      const double r = sqrt(Kc) + dtmax * mlen * (1.0 + 1e-6);
-      Kc = r * r;
-    }
     const unsigned all = (1u << nwaves) - 1u;
-    if (dot(og, og) <= Kc) {
+    if (oo <= Kc) {
       flags = all;  // the ray origin is inside the particle's alpha_min ellipsoid
     } else {
-      const double N00 = fma(-Kc, dot(dn, dn), dot(w, w)), N01 = fma(-Kc, dot(dn, da), dot(w, A));
-      const double N02 = fma(-Kc, dot(dn, db), dot(w, B)), N11 = fma(-Kc, dot(da, da), dot(A, A));
-      const double N12 = fma(-Kc, dot(da, db), dot(A, B)), N22 = fma(-Kc, dot(db, db), dot(B, B));
+      if (RS) {
+        N00 = fma(-Kc, dot(dn, dn), dot(w, w));
+        N01 = fma(-Kc, dot(dn, da), dot(w, A));
+        N02 = fma(-Kc, dot(dn, db), dot(w, B));
+        N11 = fma(-Kc, dot(da, da), dot(A, A));
+        N12 = fma(-Kc, dot(da, db), dot(A, B));
+        N22 = fma(-Kc, dot(db, db), dot(B, B));
+      }
       const double det = fma(N11, N22, -N12 * N12);
       if (!(N11 > 0.0) || !(N22 > 0.0) || !(det > 1e-9 * N11 * N22)) {
         flags = all;  // not a well-conditioned ellipse in the tile plane: no culling
       } else {
-        const double idet = 1.0 / det;
+        // 1/det, 1/N11 and 1/N22 from one division
+        const double p11 = N11 * N22, rq = 1.0 / (det * p11);
+        const double idet = p11 * rq;
         const double uc = fma(N02, N12, -N01 * N22) * idet, vc = fma(N01, N12, -N02 * N11) * idet;
         const double qmin = fma(N02, vc, fma(N01, uc, N00));
         if (qmin < 0.0) {
-          const double iN11 = 1.0 / N11, iN22 = 1.0 / N22;
+          const double iN11 = det * N22 * rq, iN22 = det * N11 * rq;
           for (int k = 0; k < nwaves; k++)
             if (ellipse_meets_box(qmin, N11, N12, N22, iN11, iN22, wb.u0[k] - uc, wb.u1[k] - uc,
                                   wb.v0[k] - vc, wb.v1[k] - vc))
@@ -249,37 +301,20 @@ __device__ inline unsigned pair_setup(const float4* __restrict__ record,
     // under a rolling shutter moves up to dtmax |c1 - c0| from o_T.  The
     // per-pixel test carries ~1e-6 relative error: a 1e-4 margin keeps every
     // culled pair clipped there too.
-    const double Kc = (double)Kp / kHalfLog2e * (1.0 + 1e-3) + 1e-5;
+    const double Kc0 = (double)Kp / kHalfLog2e * (1.0 + 1e-3) + 1e-5;
     double rmin = 3e300;
     for (int k = 0; k < 3; k++) rmin = fmin(rmin, M[3 * k] * M[3 * k] + M[3 * k + 1] * M[3 * k + 1] +
                                                       M[3 * k + 2] * M[3 * k + 2]);
-    double lb = sqrt(dot(rel, rel)) - sqrt(Kc / rmin);
+    double lb = sqrt(dot(rel, rel)) - sqrt(Kc0 / rmin);
     if (RS) lb -= (double)dtmax * sqrt(cam.dc[0] * cam.dc[0] + cam.dc[1] * cam.dc[1] + cam.dc[2] * cam.dc[2]);
     for (int k = 0; k < nwaves; k++)
       if (lb > (double)wb.cmax[k] * (1.0 + 1e-4)) flags &= ~(1u << k);
   }
   if (mixed && flags) flags |= kMixedBit;
   const float* c = rgb + 3 * e;
-  const float mflag = mixed ? -1.0f : 1.0f;
   if (!RS) {
-    const double sc = sqrt(kHalfLog2e);
-    double qc[6], qd[6];
-    affine_qr(scl(w, sc), scl(A, sc), scl(B, sc), qc);
-    affine_qr(dn, da, db, qd);
-    out[0] = make_float4((float)qc[0], (float)qc[1], (float)qc[2], Kp);
-    out[1] = make_float4((float)qc[3], (float)qc[4], (float)qc[5], lsig);
-    out[2] = make_float4((float)qd[0], (float)qd[1], (float)qd[2], mflag);
-    out[3] = make_float4((float)qd[3], (float)qd[4], (float)qd[5], 0.0f);
     reinterpret_cast<double2*>(out + 4)[0] = make_double2(c[0], c[1]);
-    out[5] = make_float4((float)s, (float)ta, (float)tb, 0.0f);
     reinterpret_cast<double2*>(out + 6)[0] = make_double2(c[2], 0.0);
-    if (BWD) {
-      out[7] = make_float4((float)dn.x, (float)dn.y, (float)dn.z, (float)w.x);
-      out[8] = make_float4((float)da.x, (float)da.y, (float)da.z, (float)w.y);
-      out[9] = make_float4((float)db.x, (float)db.y, (float)db.z, (float)w.z);
-      out[10] = make_float4((float)A.x, (float)A.y, (float)A.z, (float)B.x);
-      out[11] = make_float4((float)B.y, (float)B.z, 0.0f, 0.0f);
-    }
   } else {
     out[0] = make_float4((float)dn.x, (float)dn.y, (float)dn.z, mflag);
     out[1] = make_float4((float)da.x, (float)da.y, (float)da.z, lsig);
