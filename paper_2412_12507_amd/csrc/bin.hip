@@ -418,7 +418,8 @@ __device__ inline uint32_t block_scan_1024(uint32_t v, uint32_t* wsum, uint32_t*
 // bit length of the list length, longest first; within a bucket the order
 // may vary from call to call), the number of lists of at least 4096 and of
 // at least 1024 entries (the front of that order), and from the last
-// camera's block the total P for the device and the host.
+// camera's block the total P for the device and the host (with each
+// camera's count of long lists).
 __global__ void __launch_bounds__(kScanThreads) bin_scan_kernel(uint2* __restrict__ ranges,
                                                                 uint32_t* __restrict__ order, CamTiles ct,
                                                                 int n_cams, unsigned long long* __restrict__ sw,
@@ -473,6 +474,7 @@ __global__ void __launch_bounds__(kScanThreads) bin_scan_kernel(uint2* __restric
     uint32_t* nm = (uint32_t*)((char*)sw + SmallLayout::nmid);
     nb[c] = big;
     nm[c] = mid;
+    ((volatile uint32_t*)host)[2 + c] = big;  // for the host: whether the long-list sort has work
   }
   __syncthreads();
   for (int j = t; j < Tc; j += kScanThreads) {
@@ -1232,9 +1234,10 @@ __global__ void __launch_bounds__(kBigThreads) tile_sort_big_kernel(
 // Pinned host slot for the pair-count read-back and the event that marks
 // it, one per host thread.
 struct ReadbackSlot {
-  void* p = nullptr;   // host address
+  void* p = nullptr;   // host address: P (2 words), then each camera's long lists
   void* dp = nullptr;  // the same memory as the device sees it
   hipEvent_t ev = nullptr;
+  int n_cams = 0;      // cameras of the last count phase
   ~ReadbackSlot() {
     if (p) (void)hipHostFree(p);
     if (ev) (void)hipEventDestroy(ev);
@@ -1291,11 +1294,12 @@ static BinArgs bin_args(const gut_projected* proj, int n, const DevCam* dc, int 
 gut_status bin_count_launch(const gut_projected* proj, int n, const DevCam* dc, int n_cams, int64_t T,
                             bool cull, char* cws, uint32_t* tile_ranges, hipStream_t s) {
   if (!g_readback.p) {
-    GUT_HIP(hipHostMalloc(&g_readback.p, 64, hipHostMallocMapped | hipHostMallocCoherent));
+    GUT_HIP(hipHostMalloc(&g_readback.p, 4 * (2 + kMaxCams), hipHostMallocMapped | hipHostMallocCoherent));
     GUT_HIP(hipHostGetDevicePointer(&g_readback.dp, g_readback.p, 0));
   }
   if (!g_readback.ev) GUT_HIP(hipEventCreateWithFlags(&g_readback.ev, hipEventDisableTiming));
   std::memset(g_readback.p, 0xff, 8);  // a sentinel no total can equal
+  g_readback.n_cams = n_cams;
   size_t lds = 0;
   const BinArgs a = bin_args(proj, n, dc, n_cams, cull, &lds);
   uint32_t* M = (uint32_t*)cws;
@@ -1319,22 +1323,27 @@ gut_status bin_count_launch(const gut_projected* proj, int n, const DevCam* dc, 
   return GUT_OK;
 }
 
-gut_status bin_count_wait(uint64_t* P) {
+gut_status bin_count_wait(uint64_t* P, uint32_t* n_long) {
   GUT_HIP(hipEventSynchronize(g_readback.ev));
-  uint32_t w[2];
-  std::memcpy(w, g_readback.p, 8);
+  uint32_t w[2 + kMaxCams];
+  std::memcpy(w, g_readback.p, 4 * (2 + g_readback.n_cams));
   const uint64_t v = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
   if (v == ~0ull) {
     set_error("binning: the pair count did not reach the host");
     return GUT_E_HIP;
   }
   *P = v;
+  if (n_long) {
+    uint32_t m = 0;
+    for (int c = 0; c < g_readback.n_cams; c++) m += w[2 + c];
+    *n_long = m;
+  }
   return GUT_OK;
 }
 
 gut_status bin_sort_launch(const gut_projected* proj, int n, const DevCam* dc, int n_cams, int64_t T, bool cull,
                            char* cws, int64_t cap, char* pws, uint32_t* tile_ranges, uint32_t* sorted_ids,
-                           hipStream_t s) {
+                           hipStream_t s, int phases) {
   size_t lds = 0;
   const BinArgs a = bin_args(proj, n, dc, n_cams, cull, &lds);
   const uint32_t* M = (const uint32_t*)cws;
@@ -1345,30 +1354,36 @@ gut_status bin_sort_launch(const gut_projected* proj, int n, const DevCam* dc, i
   unsigned long long* keys = (unsigned long long*)pws;
   unsigned long long* tmp = (unsigned long long*)(pws + al((size_t)(cap > 0 ? cap : 1) * 8));
   const unsigned long long ucap = (unsigned long long)cap;
-  if (n > 0) {
-    bin_scatter_kernel<<<(unsigned)(a.bpc * n_cams), kBinThreads, lds, s>>>(a, M, (const uint2*)tile_ranges,
-                                                                             P_dev, ucap, keys);
-    GUT_LAUNCH_CHECK();
-  }
   uint32_t* nfall = (uint32_t*)(swb + SmallLayout::nfall);
   uint32_t* fall = (uint32_t*)(swb + kSmallBytes);
-  tile_sort_small_kernel<4><<<(unsigned)T, 64, 0, s>>>((const uint2*)tile_ranges, keys, sorted_ids, P_dev, ucap, nfall,
-                                                       fall);
-  GUT_LAUNCH_CHECK();
-  tile_sort_small_kernel<16><<<(unsigned)T, 64, 0, s>>>((const uint2*)tile_ranges, keys, sorted_ids, P_dev, ucap,
-                                                        nfall, fall);
-  GUT_LAUNCH_CHECK();
-  tile_sort_mid_kernel<<<kMidBlocks, kMidThreads, 0, s>>>((const uint2*)tile_ranges, tile_ranges + 2 * T, a.ct,
-                                                          n_cams, nbig, nmid, keys, sorted_ids, P_dev, ucap, nfall,
-                                                          fall);
-  GUT_LAUNCH_CHECK();
-  tile_sort_big_kernel<<<kBigBlocks, kBigThreads, 0, s>>>((const uint2*)tile_ranges, tile_ranges + 2 * T, a.ct,
-                                                          n_cams, nbig, keys, tmp, sorted_ids, P_dev, ucap, nfall,
-                                                          fall);
-  GUT_LAUNCH_CHECK();
-  tile_sort_fallback_kernel<<<kFallBlocks, kFallThreads, 0, s>>>((const uint2*)tile_ranges, keys, tmp, sorted_ids,
-                                                                 nfall, fall);
-  GUT_LAUNCH_CHECK();
+  if (phases & kSortLists) {
+    if (n > 0) {
+      bin_scatter_kernel<<<(unsigned)(a.bpc * n_cams), kBinThreads, lds, s>>>(a, M, (const uint2*)tile_ranges,
+                                                                               P_dev, ucap, keys);
+      GUT_LAUNCH_CHECK();
+    }
+    tile_sort_small_kernel<4><<<(unsigned)T, 64, 0, s>>>((const uint2*)tile_ranges, keys, sorted_ids, P_dev, ucap,
+                                                         nfall, fall);
+    GUT_LAUNCH_CHECK();
+    tile_sort_small_kernel<16><<<(unsigned)T, 64, 0, s>>>((const uint2*)tile_ranges, keys, sorted_ids, P_dev, ucap,
+                                                          nfall, fall);
+    GUT_LAUNCH_CHECK();
+    tile_sort_mid_kernel<<<kMidBlocks, kMidThreads, 0, s>>>((const uint2*)tile_ranges, tile_ranges + 2 * T, a.ct,
+                                                            n_cams, nbig, nmid, keys, sorted_ids, P_dev, ucap, nfall,
+                                                            fall);
+    GUT_LAUNCH_CHECK();
+  }
+  if (phases & kSortLong) {
+    tile_sort_big_kernel<<<kBigBlocks, kBigThreads, 0, s>>>((const uint2*)tile_ranges, tile_ranges + 2 * T, a.ct,
+                                                            n_cams, nbig, keys, tmp, sorted_ids, P_dev, ucap, nfall,
+                                                            fall);
+    GUT_LAUNCH_CHECK();
+  }
+  if (phases & kSortFallback) {
+    tile_sort_fallback_kernel<<<kFallBlocks, kFallThreads, 0, s>>>((const uint2*)tile_ranges, keys, tmp, sorted_ids,
+                                                                   nfall, fall);
+    GUT_LAUNCH_CHECK();
+  }
   return GUT_OK;
 }
 
@@ -1429,12 +1444,18 @@ extern "C" gut_status gut_bin(const gut_projected* proj, int64_t n, const gut_ca
   char* cws = (char*)ws;
   char* pws = cws + cb;
   if ((st = bin_count_launch(proj, (int)n, dc, n_cams, T, cull, cws, tile_ranges, s)) != GUT_OK) return st;
-  // the sort is queued before the one wait: it checks the capacity on the device
-  if ((st = bin_sort_launch(proj, (int)n, dc, n_cams, T, cull, cws, pair_capacity, pws, tile_ranges, sorted_ids,
-                            s)) != GUT_OK)
+  // The scatter and the sorts up to 4095 entries are queued before the one
+  // wait (they check the capacity on the device); the long lists' sort is
+  // queued after it, only if there are long lists, and the fallback last.
+  if ((st = bin_sort_launch(proj, (int)n, dc, n_cams, T, cull, cws, pair_capacity, pws, tile_ranges, sorted_ids, s,
+                            kSortLists)) != GUT_OK)
     return st;
   uint64_t P = 0;
-  if ((st = bin_count_wait(&P)) != GUT_OK) return st;
+  uint32_t n_long = 0;
+  if ((st = bin_count_wait(&P, &n_long)) != GUT_OK) return st;
+  if ((st = bin_sort_launch(proj, (int)n, dc, n_cams, T, cull, cws, pair_capacity, pws, tile_ranges, sorted_ids, s,
+                            (n_long ? kSortLong : 0) | kSortFallback)) != GUT_OK)
+    return st;
   if (n_pairs) *n_pairs = (int64_t)P;
   if ((int64_t)P > pair_capacity) {
     (void)fill_u32(tile_ranges, 2 * T, 0u, s);  // every tile empty

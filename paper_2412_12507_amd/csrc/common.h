@@ -117,10 +117,15 @@ size_t bin_count_bytes(int64_t n, int64_t T);
 size_t bin_pair_bytes(int64_t cap);
 gut_status bin_count_launch(const gut_projected* proj, int n, const DevCam* dc, int n_cams, int64_t T,
                             bool cull, char* cws, uint32_t* tile_ranges, hipStream_t s);
-gut_status bin_count_wait(uint64_t* P);
+// bin_count_wait also returns the number of lists of 4096 entries or more
+// (n_long, when not null); the sort phase's parts can be queued separately:
+// the scatter and the sorts of shorter lists, the long lists' sort, and the
+// fallback sort of lists whose buckets came out too large, in that order.
+gut_status bin_count_wait(uint64_t* P, uint32_t* n_long = nullptr);
+constexpr int kSortLists = 1, kSortLong = 2, kSortFallback = 4, kSortAll = 7;
 gut_status bin_sort_launch(const gut_projected* proj, int n, const DevCam* dc, int n_cams, int64_t T, bool cull,
                            char* cws, int64_t cap, char* pws, uint32_t* tile_ranges, uint32_t* sorted_ids,
-                           hipStream_t s);
+                           hipStream_t s, int phases = kSortAll);
 
 // ---------------------------------------------------------------- device math
 __host__ __device__ inline float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
