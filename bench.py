@@ -142,7 +142,10 @@ def pmc_summary(fetch_dir, write_dir, out_path, command):
 # 4 B depth by the scatter; per pair 8 B of key written and read back, 4 B of
 # id written; per tile 24 B of counts, starts, ranges and order.
 PROJ_CAMS_PER_LAUNCH = 4
-BIN_KERNELS = 10  # init, count, column scan, list scan, scatter, 5 sorts (by list length, and the radix fallback)
+# init, count, column scan, list scan, scatter, 4 sorts (three list lengths and the radix fallback); the
+# sort of lists of 4096 entries or more is launched only when there are such lists, and the two-view
+# benchmark batch has none
+BIN_KERNELS = 9
 
 
 def project_bytes(n, n_cams):
