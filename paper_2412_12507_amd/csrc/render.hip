@@ -367,11 +367,13 @@ __device__ __forceinline__ void kbuf_blend(float a, uint32_t pos, const KbufColo
   const float Tn = fmaf(-a, T, T);
   if (Tn < t_min) { done = 1u; return; }
   const double w = (double)(a * T);
-  float c0, c1, c2;
-  if (pos >= K.wlo) {
-    const float* c = K.cw + 3 * (pos & (kKWin - 1));
-    c0 = c[0]; c1 = c[1]; c2 = c[2];
-  } else {
+  // the LDS row is read in any case and an older hit's colour then replaces
+  // it; the empty register constraint keeps the compiler from folding the two
+  // reads into one flat read through a selected pointer
+  const float* cl = K.cw + 3 * (pos & (kKWin - 1));
+  float c0 = cl[0], c1 = cl[1], c2 = cl[2];
+  asm volatile("" : "+v"(c0), "+v"(c1), "+v"(c2));
+  if (pos < K.wlo) {
     const float* c = K.rgb + 3 * (size_t)K.lids[pos];
     c0 = c[0]; c1 = c[1]; c2 = c[2];
   }
@@ -483,7 +485,9 @@ __global__ void __launch_bounds__(kKThreads, 4) render_kbuffer_kernel(
 #pragma unroll
             for (int j = 0; j < kKBuf - 1; j++) {
               const bool nx = bd[j + 1] < dist, here = j == 0 || bd[j] < dist;
-              const float od = nx ? bd[j + 1] : (here ? dist : bd[j]);
+              // the buffer is sorted and dist > bd[0]: the slot's new distance is
+              // the middle one of bd[j], dist, bd[j + 1]
+              const float od = __builtin_amdgcn_fmed3f(bd[j], dist, bd[j + 1]);
               const float oa = nx ? ba[j + 1] : (here ? ev.a : ba[j]);
               const uint32_t oi = nx ? bi[j + 1] : (here ? e : bi[j]);
               bd[j] = od; ba[j] = oa; bi[j] = oi;

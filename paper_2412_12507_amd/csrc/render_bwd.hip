@@ -296,7 +296,13 @@ struct KBufGrad {
 };
 
 __device__ __forceinline__ uint32_t kbuf_entry(uint32_t pos, const KBufGrad& K) {
-  return pos >= K.wlo ? K.pew[pos & (kWin - 1)] : K.lids[pos];
+  // the LDS copy is read in any case and an older hit's entry then replaces
+  // it; the empty register constraint keeps the compiler from folding the two
+  // reads into one flat read through a selected pointer
+  uint32_t e = K.pew[pos & (kWin - 1)];
+  asm volatile("" : "+v"(e));
+  if (pos < K.wlo) e = K.lids[pos];
+  return e;
 }
 
 // Adds one lane's blended values (hit at list position pos, entry e) to the
@@ -487,7 +493,8 @@ __global__ void __launch_bounds__(kKThreadsB, 2) render_kbuffer_bwd_kernel(
 #pragma unroll
             for (int j = 0; j < kKBufB - 1; j++) {
               const bool nx = bd[j + 1] < dist, here = j == 0 || bd[j] < dist;
-              bd[j] = nx ? bd[j + 1] : (here ? dist : bd[j]);
+              // sorted buffer and dist > bd[0]: the middle one of bd[j], dist, bd[j + 1]
+              bd[j] = __builtin_amdgcn_fmed3f(bd[j], dist, bd[j + 1]);
               ba[j] = nx ? ba[j + 1] : (here ? ev.a : ba[j]);
               bi[j] = nx ? bi[j + 1] : (here ? pos : bi[j]);
               bx[j] = nx ? bx[j + 1] : (here ? pv.x : bx[j]);
