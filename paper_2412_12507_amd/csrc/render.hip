@@ -335,9 +335,13 @@ gut_status render_batch_launch(const DevCam* d_cams, const DevCam* h_cams, int n
 // capacity k < kKBuf leaves kKBuf - k +inf walls at the far end.  A hit no
 // nearer than slot 0 evicts it -- slot 0 is blended (a sentinel blends to
 // nothing) and the hit is merged into the remaining sorted slots by a fixed
-// compare-select chain; a hit at or before slot 0 is blended at once.  Blending
-// is Eq. 5 with the t_min stop; at the end of the list the buffer is blended
-// nearest first.  The buffer keeps each hit's list position; the colour a
+// compare-select chain; a hit at or before slot 0 is blended at once.  With a
+// full-size buffer (k = kKBuf) the slots instead move one place nearer, the
+// hit takes the last one and moves nearer level by level while some lane of
+// the wave still moves: hits arrive nearly in depth order, so a third of the
+// insertion steps need no level and the wave's deepest move averages about
+// two.  Blending is Eq. 5 with the t_min stop; at the end of the list the
+// buffer is blended nearest first.  The buffer keeps each hit's list position; the colour a
 // blend needs comes from an LDS copy of the two latest batches' colours
 // (a buffer usually turns over within a batch), else through the list.
 constexpr int kKBuf = 16;
@@ -359,6 +363,52 @@ struct KbufColours {
   const float* rgb;
   uint32_t wlo;
 };
+
+// Slot 0 leaves on the lanes with ins set: slots J.. move one place nearer and
+// the hit takes the last slot.  Written as a recursion so that every slot
+// index is a constant from the start: in a loop the compiler folds each
+// select of two slots into one read through a lane-dependent address, and the
+// whole buffer then lives in scratch memory.
+template <int J>
+__device__ __forceinline__ void kbuf_shift(float (&bd)[kKBuf], float (&ba)[kKBuf],
+                                           uint32_t (&bi)[kKBuf], bool ins, float dist, float a,
+                                           uint32_t e) {
+  if constexpr (J < kKBuf - 1) {
+    bd[J] = ins ? bd[J + 1] : bd[J];
+    ba[J] = ins ? ba[J + 1] : ba[J];
+    bi[J] = ins ? bi[J + 1] : bi[J];
+    kbuf_shift<J + 1>(bd, ba, bi, ins, dist, a, e);
+  } else {
+    bd[J] = ins ? dist : bd[J];
+    ba[J] = ins ? a : ba[J];
+    bi[J] = ins ? e : bi[J];
+  }
+}
+
+// One level of the move nearer: on the lanes whose hit (now in slot I + 1)
+// lies at or before slot I, the two swap; the next level runs while some
+// lane of the wave still moves.
+template <int I>
+__device__ __forceinline__ void kbuf_bubble(float (&bd)[kKBuf], float (&ba)[kKBuf],
+                                            uint32_t (&bi)[kKBuf], bool mv, unsigned long long mm,
+                                            float dist, float a, uint32_t e) {
+  // mm: the moving lanes as a wave mask, kept from ballots of the bare
+  // compare (a ballot of a combined lane flag goes through a vector register)
+  const bool ge = bd[I] >= dist;
+  mv = mv && ge;
+  mm &= __builtin_amdgcn_ballot_w64(ge);
+  if (mm == 0ull) return;
+  // an empty statement with side effects: without it the compiler turns the
+  // wave-uniform early exits into straight-line selects over all 15 levels
+  asm volatile("");
+  bd[I + 1] = mv ? bd[I] : bd[I + 1];
+  ba[I + 1] = mv ? ba[I] : ba[I + 1];
+  bi[I + 1] = mv ? bi[I] : bi[I + 1];
+  bd[I] = mv ? dist : bd[I];
+  ba[I] = mv ? a : ba[I];
+  bi[I] = mv ? e : bi[I];
+  if constexpr (I > 0) kbuf_bubble<I - 1>(bd, ba, bi, mv, mm, dist, a, e);
+}
 
 __device__ __forceinline__ void kbuf_blend(float a, uint32_t pos, const KbufColours& K,
                                            float t_min, float& T, double (&C)[3], uint32_t& nc,
@@ -384,7 +434,7 @@ __device__ __forceinline__ void kbuf_blend(float a, uint32_t pos, const KbufColo
   nc++;
 }
 
-template <bool RS, bool NE, bool GEN, bool CLIP>
+template <bool RS, bool NE, bool GEN, bool CLIP, bool FULL>
 __global__ void __launch_bounds__(kKThreads, 4) render_kbuffer_kernel(
     DevCam cam, Thresholds th, int n, int cam_idx, int kcap, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
@@ -464,7 +514,30 @@ __global__ void __launch_bounds__(kKThreads, 4) render_kbuffer_kernel(
         const bool live = ev.ok && done == 0u;
         if (!wave_any(live)) continue;
         eval_alpha<RS, GEN>(r, th, &ev);
-        if (live) {
+        if (FULL) {
+          // the hit's distance tau' |d|, tau' = -(o_g . d_g) / |d_g|^2 (the clip test's form)
+          float odg;
+          if (!RS) {
+            const float4 p5 = P[5];
+            odg = fmaf(v, p5.z, fmaf(u, p5.y, p5.x));
+          } else {
+            odg = fmaf(v, r.p4.w, fmaf(u, r.p3.w, r.p5.w));
+            odg = fmaf(dt, fmaf(v, r.p9.w, fmaf(u, r.p8.w, r.p7.w)), odg);
+          }
+          const float dist = -odg * dlen * ev.idd;
+          const uint32_t e = b + q;  // the hit's list position
+          const bool ins = live && !(dist <= bd[0]);
+          if (live && !ins) kbuf_blend(ev.a, e, K, th.t_min, T, C, nc, done);
+          if (ins) kbuf_blend(ba[0], bi[0], K, th.t_min, T, C, nc, done);
+          // slot 0 leaves: the other slots move one place nearer and the hit
+          // takes the last one, then moves nearer past every slot at or beyond
+          // its distance (so it goes before equal ones), level by level for as
+          // long as a lane of the wave still moves (hits arrive nearly in depth
+          // order: most steps need no level or a few)
+          kbuf_shift<0>(bd, ba, bi, ins, dist, ev.a, e);
+          kbuf_bubble<kKBuf - 2>(bd, ba, bi, ins, __builtin_amdgcn_ballot_w64(ins), dist, ev.a, e);
+          if (NE && live && done) nev = b + q + 1;
+        } else if (live) {
           // the hit's distance tau' |d|, tau' = -(o_g . d_g) / |d_g|^2 (the clip test's form)
           float odg;
           if (!RS) {
@@ -521,11 +594,13 @@ static gut_status launch_render_kbuffer(const DevCam& cam, const Thresholds& th,
                                         const float* clip, float* out_rgb, float* out_T,
                                         uint32_t* out_nc, uint32_t* out_ne, hipStream_t s) {
   dim3 grid(cam.tiles_x * cam.tiles_y), block(kKThreads);
-#define GUT_RKB(RS, NE, GEN, CLIP)                                                                  \
-  render_kbuffer_kernel<RS, NE, GEN, CLIP><<<grid, block, 0, s>>>(cam, th, n, cam_idx, kcap,           \
-                                                                  (const uint2*)ranges, order, ids,       \
-                                                                  (const float4*)record, rgb, clip,       \
-                                                                  out_rgb, out_T, out_nc, out_ne)
+#define GUT_RKB2(RS, NE, GEN, CLIP, FULL)                                                          \
+  render_kbuffer_kernel<RS, NE, GEN, CLIP, FULL><<<grid, block, 0, s>>>(cam, th, n, cam_idx, kcap,     \
+                                                                        (const uint2*)ranges, order, ids, \
+                                                                        (const float4*)record, rgb, clip, \
+                                                                        out_rgb, out_T, out_nc, out_ne)
+#define GUT_RKB(RS, NE, GEN, CLIP) \
+  do { if (kcap == kKBuf) GUT_RKB2(RS, NE, GEN, CLIP, true); else GUT_RKB2(RS, NE, GEN, CLIP, false); } while (0)
 #define GUT_RKB0(RS, NE, GEN) \
   do { if (clip) GUT_RKB(RS, NE, GEN, true); else GUT_RKB(RS, NE, GEN, false); } while (0)
 #define GUT_RKB1(RS, NE) \
@@ -536,6 +611,7 @@ static gut_status launch_render_kbuffer(const DevCam& cam, const Thresholds& th,
 #undef GUT_RKB1
 #undef GUT_RKB0
 #undef GUT_RKB
+#undef GUT_RKB2
   GUT_LAUNCH_CHECK();
   return GUT_OK;
 }
