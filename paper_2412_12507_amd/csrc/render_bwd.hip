@@ -256,7 +256,9 @@ __global__ void __launch_bounds__(kBwThreads, 3) render_bwd_kernel(
 
 // Backward of the k-buffer render ("Ours (sorted)", Sec. 4.3).  It replays
 // render_kbuffer_kernel bit for bit (same blocks, pixels, pair setup, tests,
-// distances and buffer chain) and differentiates each hit when it is blended,
+// distances, and the same buffer after every insertion: the merge chain here
+// and the forward's shift-and-move for a full-size buffer order the slots
+// alike, ties included) and differentiates each hit when it is blended,
 // in blend order: the Supp. B recursion of render_bwd_kernel (T and
 // Z = gC . (C - C_<=j) carried forward from the forward's outputs) gives
 // dL/dalpha there.  The geometric factors a blend needs -- the closest-point
