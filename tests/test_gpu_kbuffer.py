@@ -196,3 +196,36 @@ def test_kbuffer_with_degree4_forward_and_backward():
     say("  grads", {k: (v["rel"], v["elem_fail"]) for k, v in rep.items()})
     for key, v in rep.items():
         assert v["rel"] <= 1e-3 and v["elem_fail"] == 0, (key, v)
+
+
+@pytest.mark.parametrize("k", [16, 4])
+def test_kbuffer_exact_ties_follow_the_insertion_rule(k):
+    """Every particle twice, same geometry, another colour: the two hits of a
+    copy pair lie at exactly the same distance on both sides, so the order
+    the buffer gives equal hits (a new hit goes before equal ones, the
+    sorted insertion of Sec. 4.3 as read here) decides thousands of pixels.
+    The full-size buffer (k = 16: slots shift, the hit moves nearer) and the
+    merge chain (k = 4) must both give the oracle's own order there: with
+    the opposite rule nearly every such pixel would match only an order
+    alternative, while the GPU takes one only where FP32 rounding decides
+    (a few per thousand pixels)."""
+    say(f"[k-buffer exact ties] k={k}")
+    base = G.clustered_scene(1500, seed=1107)
+    sh2 = base.sh.copy()
+    sh2[:, 0, :] = 1.6 - sh2[:, 0, :]  # a clearly different colour per copy
+    dup = lambda a: np.concatenate([a, a])
+    scene = G.scene_from_raw(dup(base.means), dup(base.log_scales), dup(base.quats),
+                             dup(base.logit_opacities), np.concatenate([base.sh, sh2]), base.sh_degree)
+    cam = G.config2_cameras(160, 120)[0]
+    p = O.default_params(kbuffer=k)
+    _, _, _, img = gpu_forward(scene, [cam], p)
+    pr = O.project(scene, cam, p)
+    ob = O.bin_tiles(pr, cam, p)
+    res = O.render(scene, pr, cam, ob, p)
+    n_tie = int((res["n_alt"] > 0).sum())  # pixels with an order alternative
+    rep = compare_pixels(image_np(img), res, cam, p)
+    say("  pixels with an order alternative", n_tie, {kk: v for kk, v in rep.items() if kk != "fails"},
+        rep["fails"][:3])
+    assert n_tie > 2000
+    assert rep["n_fail"] == 0
+    assert rep["n_alt_used"] <= n_tie // 20
